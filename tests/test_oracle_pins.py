@@ -1,0 +1,388 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+The paper prints no worked values of u, V, phi or the marginal errors, so the oracle is
+pinned by identities, closed forms, brute force and invariants instead:
+
+* dense definition == separable evaluation (Sec. 3, Eq. 6-8 with the factorisation after Eq. 6)
+* product measures reduce to two independent one-dimensional Sinkhorn runs
+* Gaussian -> Gaussian has a closed-form entropic barycentric map (affine)
+* linear-programming brute force bounds the entropic transport cost (Sec. 2, Eq. 2)
+* dual ascent, weak duality and the exact column marginal after a V-update
+* symmetries (transposition, mirroring) and the eps -> infinity limit
+* a hand-worked 2 x 2 first iteration (Algorithm 1 from u = V = 1/n^2)
+* the continuum closed form of the integrated phase (Sec. 2, Eq. 4-5 and R9)
+* central finite differences of the dense definition for the reverse sweep
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2512_19072_amd import workloads as W
+
+RNG = np.random.default_rng(12345)
+
+
+def _rand_images(n, rng, zeros=True):
+    g = rng.uniform(0.05, 1.0, (n, n))
+    G = rng.uniform(0.05, 1.0, (n, n))
+    if zeros:
+        G[0, :] = 0.0          # a whole zero row in the target
+        G[n // 2, 1] = 0.0     # an isolated zero
+        g[-1, -1] = 0.0        # a zero input pixel
+    return g, G
+
+
+def _finite_close(x, y, tol):
+    mx, my = np.isfinite(x), np.isfinite(y)
+    assert np.array_equal(mx, my), "different -inf patterns"
+    if mx.any():
+        assert np.max(np.abs(x[mx] - y[my])) <= tol
+
+
+# ---------------------------------------------------------------- P1: dense == separable
+@pytest.mark.parametrize("n", [4, 7, 12])
+@pytest.mark.parametrize("eps", [1e-1, 1e-2])
+def test_dense_equals_separable(n, eps):
+    g, G = _rand_images(n, np.random.default_rng(n))
+    T = 12
+    r1 = O.solve_dense(g, G, eps, T)
+    r2 = O.solve_sep(g, G, eps, T)
+    _finite_close(r1.f, r2.f, 1e-12)
+    _finite_close(r1.psi, r2.psi, 1e-12)
+    # histories: O1 evaluates the plan by definition, O2 by the fused identity
+    np.testing.assert_allclose(r1.err_a_hist, r2.err_a_hist, rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(r1.err_b_hist, r2.err_b_hist, rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(r1.dual_hist, r2.dual_hist, rtol=1e-12, atol=1e-14)
+    for name in ("err_a", "dual", "cost", "mass"):
+        assert abs(getattr(r1, name) - getattr(r2, name)) <= 1e-12
+    assert r1.err_b < 1e-13 and r2.err_b < 1e-13
+    np.testing.assert_allclose(r1.Tx, r2.Tx, atol=1e-12)
+    np.testing.assert_allclose(r1.Ty, r2.Ty, atol=1e-12)
+    np.testing.assert_allclose(r1.phase, r2.phase, atol=1e-12)
+
+
+def test_dense_equals_separable_annealed():
+    n, T = 8, 10
+    g, G = _rand_images(n, np.random.default_rng(7))
+    e = W.anneal_schedule(5e-2, 4e-3, T)
+    r1 = O.solve_dense(g, G, e, T)
+    r2 = O.solve_sep(g, G, e, T)
+    _finite_close(r1.f, r2.f, 1e-12)
+    _finite_close(r1.psi, r2.psi, 1e-12)
+    np.testing.assert_allclose(r1.err_a_hist, r2.err_a_hist, rtol=1e-10)
+    np.testing.assert_allclose(r1.phase, r2.phase, atol=1e-12)
+    assert abs(r1.dual - r2.dual) < 1e-12
+
+
+def test_first_error_counts_zero_mass_pixels():
+    """u^0 = 1/n^2 puts mass on zero-intensity pixels; the first error must include it."""
+    n = 6
+    g, G = _rand_images(n, np.random.default_rng(3))
+    r1 = O.solve_dense(g, G, 5e-2, 2)
+    r2 = O.solve_sep(g, G, 5e-2, 2)
+    assert r1.err_a_hist[0] == pytest.approx(r2.err_a_hist[0], rel=1e-12)
+    assert r1.err_b_hist[0] == pytest.approx(r2.err_b_hist[0], rel=1e-12)
+
+
+# ---------------------------------------------------------------- P2: product measures
+def _sinkhorn_1d(a, b, eps, T):
+    """Plain one-dimensional Sinkhorn in the scaling form, u = V = 1/n at start."""
+    n = a.size
+    lam = [[math.exp(-((i - k) ** 2) / (2.0 * n * n * eps)) for k in range(n)] for i in range(n)]
+    u = [1.0 / n] * n
+    v = [1.0 / n] * n
+    for _ in range(T):
+        u = [a[i] / sum(lam[i][k] * v[k] for k in range(n)) for i in range(n)]
+        v = [b[k] / sum(lam[i][k] * u[i] for i in range(n)) for k in range(n)]
+    return np.array(u), np.array(v)
+
+
+def test_product_measures_factorise():
+    """a = a1 (x) a2, b = b1 (x) b2: every iterate is u1 (x) u2 with 1-D Sinkhorns.
+
+    The 2-D grid has n points per axis, so the cost's 1/(2 n^2) matches the 1-D runs."""
+    n, eps, T = 10, 2e-2, 25
+    rng = np.random.default_rng(5)
+    a1, a2, b1, b2 = (rng.uniform(0.1, 1, n) for _ in range(4))
+    a1, a2, b1, b2 = (v / v.sum() for v in (a1, a2, b1, b2))
+    g = np.sqrt(np.outer(a1, a2))
+    G = np.sqrt(np.outer(b1, b2))
+    u1, v1 = _sinkhorn_1d(a1, b1, eps, T)
+    u2, v2 = _sinkhorn_1d(a2, b2, eps, T)
+    r = O.solve_sep(g, G, eps, T)
+    np.testing.assert_allclose(r.f, eps * np.log(np.outer(u1, u2)), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r.psi, eps * np.log(np.outer(v1, v2)), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- P3: Gaussian closed form
+def test_gaussian_to_gaussian_affine_map():
+    """Entropic OT between 1-D Gaussians N(0,s1^2) -> N(0,s2^2) with cost |x-y|^2/2 has an
+    affine barycentric map of slope kappa/s1^2, kappa = (sqrt(eps^2 + 4 s1^2 s2^2) - eps)/2.
+    On the grid the cost is (j-L)^2/(2n^2), so s is the intensity std in pixels / n, and
+    Tx = slope * x (both coordinates scaled by sqrt(n)).  Axis-aligned anisotropic Gaussians
+    are products, so each axis has its own slope."""
+    n, eps = 128, 1e-3
+    c = n // 2
+    sx1, sy1, sx2, sy2 = 8.0, 6.0, 12.0, 10.0          # intensity std in pixels
+    r2 = math.sqrt(2.0)                                  # amplitude sigma = sqrt(2) * intensity std
+    g = W.gaussian(n, c, c, sx1 * r2, sy1 * r2)
+    G = W.gaussian(n, c, c, sx2 * r2, sy2 * r2)
+    r = O.solve_sep(g, G, eps, 500)
+
+    def slope(s1px, s2px):
+        s1, s2 = s1px / n, s2px / n
+        kappa = (math.sqrt(eps * eps + 4 * s1 * s1 * s2 * s2) - eps) / 2
+        return kappa / s1 ** 2
+
+    x = (np.arange(n) - c) / math.sqrt(n)              # the paper's x_j, written out here
+    sel = np.abs(np.arange(n) - c) <= 8
+    slope_x = np.polyfit(x[sel], r.Tx[sel, c], 1)[0]
+    slope_y = np.polyfit(x[sel], r.Ty[c, sel], 1)[0]
+    assert slope_x == pytest.approx(slope(sx1, sx2), rel=5e-6)
+    assert slope_y == pytest.approx(slope(sy1, sy2), rel=5e-6)
+    # Tx does not depend on k, Ty not on j (product structure)
+    assert np.ptp(r.Tx[c - 8:c + 9, c - 8:c + 9], axis=1).max() < 1e-9
+    # the entropic bias is visible: the unregularised slope s2/s1 is clearly different
+    assert abs(slope_x - sx2 / sx1) > 1e-2
+
+
+# ---------------------------------------------------------------- P4: LP brute force
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 2e-3])
+def test_lp_bound(eps):
+    """0 <= <Gamma_eps, c> - OT_0 <= eps min(H(a), H(b)) for the converged entropic plan."""
+    n = 4
+    g, G = _rand_images(n, np.random.default_rng(11), zeros=False)
+    a, b = O.normalise(g).ravel(), O.normalise(G).ravel()
+    ot0 = O.lp_ot_cost(a, b, O.cost_dense(n))
+    r = O.solve_dense(g, G, eps, 4000)
+    assert r.err_a < 1e-9
+    gap = r.cost - ot0
+    assert gap >= -1e-10
+    assert gap <= eps * min(O.entropy(a), O.entropy(b)) + 1e-10
+    # weak duality with the LP optimum as the feasible plan: D <= <G0,c> - eps (H(G0) + 1) <= OT_0
+    assert r.dual <= ot0 + 1e-12
+
+
+def test_lp_limit_small_eps():
+    n = 4
+    g, G = _rand_images(n, np.random.default_rng(2), zeros=False)
+    a, b = O.normalise(g).ravel(), O.normalise(G).ravel()
+    ot0 = O.lp_ot_cost(a, b, O.cost_dense(n))
+    r = O.solve_dense(g, G, 5e-4, 20000)
+    assert abs(r.cost - ot0) < 5e-4 * math.log(n * n)
+
+
+# ---------------------------------------------------------------- P6/P7: invariants
+def test_dual_ascent_and_weak_duality():
+    n, eps = 8, 1e-2
+    g, G = _rand_images(n, np.random.default_rng(4))
+    r = O.solve_dense(g, G, eps, 60)
+    d = r.dual_hist
+    assert np.all(np.diff(d) >= -1e-15)
+    a, b = O.normalise(g).ravel(), O.normalise(G).ravel()
+    C = O.cost_dense(n)
+    # any feasible plan bounds the dual from above: the product a (x) b
+    assert d[-1] <= O.primal_entropic(np.outer(a, b), C, eps) + 1e-14
+    # the duality gap at the final plan is <f, r - a> and vanishes at convergence
+    r_long = O.solve_dense(g, G, eps, 3000)
+    Gam = np.exp((r_long.f.ravel()[:, None] + r_long.psi.ravel()[None, :] - C) / eps)
+    assert O.primal_entropic(Gam, C, eps) - r_long.dual == pytest.approx(0.0, abs=1e-11)
+
+
+def test_column_marginal_exact_after_v_update():
+    n = 16
+    g, G = W.gauss_to_disk(n)
+    r = O.solve_sep(g, G, 1e-2, 30)
+    assert r.err_b < 1e-14
+    assert r.err_a_hist[-1] > 0
+
+
+# ---------------------------------------------------------------- P8: symmetries
+def test_transpose_symmetry():
+    n, eps, T = 12, 1e-2, 20
+    g, G = _rand_images(n, np.random.default_rng(8))
+    r = O.solve_sep(g, G, eps, T)
+    rt = O.solve_sep(g.T, G.T, eps, T)
+    _finite_close(rt.f, r.f.T, 1e-13)
+    _finite_close(rt.psi, r.psi.T, 1e-13)
+    np.testing.assert_allclose(rt.Tx, r.Ty.T, atol=1e-13)
+    np.testing.assert_allclose(rt.Ty, r.Tx.T, atol=1e-13)
+
+
+def test_mirror_symmetry():
+    """j -> n-1-j on both images mirrors the potentials; X maps to -X - 1/sqrt(n) (n even).
+
+    The constant -1/sqrt(n) is weighted by the row mass / a, so the comparison of the
+    gradients is made at convergence (row mass = a)."""
+    n, eps, T = 12, 1e-2, 400
+    g, G = _rand_images(n, np.random.default_rng(9))
+    r = O.solve_sep(g, G, eps, T)
+    rm = O.solve_sep(g[::-1], G[::-1], eps, T)
+    assert r.err_a < 1e-12
+    _finite_close(rm.f, r.f[::-1], 1e-13)
+    _finite_close(rm.psi, r.psi[::-1], 1e-13)
+    np.testing.assert_allclose(rm.Tx, -r.Tx[::-1] - 1.0 / math.sqrt(n), atol=1e-12)
+    np.testing.assert_allclose(rm.Ty, r.Ty[::-1], atol=1e-12)
+
+
+# ---------------------------------------------------------------- P9: eps -> infinity
+def test_large_eps_limit():
+    """As eps -> infinity the plan tends to a (x) b and Tx to the b-mean of X."""
+    n = 10
+    g, G = _rand_images(n, np.random.default_rng(10), zeros=False)
+    r = O.solve_sep(g, G, 1e5, 5)
+    b = O.normalise(G)
+    X = O.coords(n)
+    np.testing.assert_allclose(r.Tx, np.sum(b * X[:, None]), atol=1e-4)
+    np.testing.assert_allclose(r.Ty, np.sum(b * X[None, :]), atol=1e-4)
+
+
+# ---------------------------------------------------------------- P10: 2 x 2 by hand
+def test_two_by_two_first_iteration():
+    """n = 2, eps = 1/8: Lambda = [[1, r], [r, 1]] with r = exp(-(1/8)/eps) = e^-1.
+    From V = 1/4, K V = (1 + r)^2 / 4 at every pixel, so u = 4 a / (1 + r)^2; then
+    (K^T u)_{LM} = sum_jk Lambda_Lj u_jk Lambda_kM, written out term by term."""
+    eps = 1.0 / 8.0
+    r = math.exp(-1.0)
+    g = np.array([[1.0, 2.0], [3.0, 4.0]])
+    G = np.array([[2.0, 1.0], [1.0, 3.0]])
+    a = np.array([[1.0, 4.0], [9.0, 16.0]]) / 30.0
+    b = np.array([[4.0, 1.0], [1.0, 9.0]]) / 15.0
+    u = 4.0 * a / (1.0 + r) ** 2
+    lam = [[1.0, r], [r, 1.0]]
+    Su = np.array([[sum(lam[L][j] * u[j, k] * lam[k][M] for j in range(2) for k in range(2))
+                    for M in range(2)] for L in range(2)])
+    V = b / Su
+    res = O.solve_dense(g, G, eps, 1)
+    np.testing.assert_allclose(res.f, eps * np.log(u), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(res.psi, eps * np.log(V), rtol=0, atol=1e-15)
+    # explicit: u_00 = 4 (1/30) / (1 + e^-1)^2
+    assert math.exp(res.f[0, 0] / eps) == pytest.approx(4.0 / 30.0 / (1.0 + math.exp(-1.0)) ** 2,
+                                                        rel=1e-14)
+
+
+# ---------------------------------------------------------------- P11: phase closed form
+def test_phase_matches_continuum_closed_form():
+    """In the continuum the barycentric map is x + eps grad ln S, so with the paper's
+    coordinates phi = n[((j-c)^2 + (k-c)^2)/(2n^2) + eps ln S] + const, up to the O(h^2)
+    error of trapezoid integration."""
+    n, eps = 64, 1e-2
+    c = n // 2
+    g, G = W.gauss_to_disk(n)
+    G = np.sqrt(np.maximum(G * G, 1e-6))
+    r = O.solve_sep(g, G, eps, 300)
+    lam = O.gibbs_1d(n, eps)
+    lnS, _ = O.sep_log_apply(r.psi / eps, lam, lam)
+    j, k = W.grid(n)
+    closed = n * (((j - c) ** 2 + (k - c) ** 2) / (2.0 * n * n) + eps * lnS)
+    a = O.normalise(g)
+    closed = closed - np.sum(a * closed)
+    m = a > 1e-3 * a.max()
+    rng = r.phase[m].max() - r.phase[m].min()
+    assert rng > 3.0
+    assert np.max(np.abs(closed - r.phase)[m]) < 5e-4 * rng
+    # a wrong sign of the phase, or swapped axes, would be far off
+    assert np.max(np.abs(closed + r.phase)[m]) > 0.1 * rng
+
+
+# ---------------------------------------------------------------- integration transpose
+def test_integrate_adjoint_is_transpose():
+    n = 7
+    rng = np.random.default_rng(0)
+    a = rng.uniform(0, 1, (n, n))
+    a /= a.sum()
+    # explicit matrix of the linear map (Tx, Ty) -> phi
+    cols = []
+    for which in range(2):
+        for p in range(n * n):
+            e = np.zeros(n * n)
+            e[p] = 1.0
+            Tx = e.reshape(n, n) if which == 0 else np.zeros((n, n))
+            Ty = e.reshape(n, n) if which == 1 else np.zeros((n, n))
+            cols.append(O.integrate(Tx, Ty, a).ravel())
+    M = np.array(cols).T                                   # [n^2][2 n^2]
+    pb = rng.standard_normal((n, n))
+    Txb, Tyb = O.integrate_adjoint(pb, a)
+    np.testing.assert_allclose(np.concatenate([Txb.ravel(), Tyb.ravel()]), M.T @ pb.ravel(),
+                               atol=1e-13)
+
+
+def test_integrate_linear_phase():
+    """A constant gradient (X0, Y0) integrates to X0 x + Y0 y up to a constant."""
+    n = 9
+    X = O.coords(n)
+    a = np.full((n, n), 1.0 / (n * n))
+    phi = O.integrate(np.full((n, n), 0.7), np.full((n, n), -0.3), a)
+    ref = 0.7 * X[:, None] - 0.3 * X[None, :]
+    ref -= ref.mean()
+    np.testing.assert_allclose(phi, ref, atol=1e-13)
+
+
+# ---------------------------------------------------------------- P12: reverse sweep vs FD
+def _loss_dense(g, G, eps, T, dD, dphi):
+    r = O.solve_dense(g, G, eps, T)
+    return dD * r.dual + float(np.sum(dphi * r.phase))
+
+
+@pytest.mark.parametrize("with_zero", [False, True])
+def test_grad_matches_central_fd_dense(with_zero):
+    n, eps, T = 4, 3e-2, 12
+    rng = np.random.default_rng(21)
+    g = rng.uniform(0.2, 1.0, (n, n))
+    G = rng.uniform(0.2, 1.0, (n, n))
+    if with_zero:
+        G[1, 2] = 0.0
+    dD = 0.7
+    dphi = rng.standard_normal((n, n))
+    grad = O.grad_G(g, G, eps, T, dD, dphi)
+    h = 1e-6
+    fd = np.zeros((n, n))
+    for p in range(n * n):
+        jj, kk = divmod(p, n)
+        if G[jj, kk] == 0.0:
+            continue
+        Gp, Gm = G.copy(), G.copy()
+        Gp[jj, kk] += h
+        Gm[jj, kk] -= h
+        fd[jj, kk] = (_loss_dense(g, Gp, eps, T, dD, dphi) - _loss_dense(g, Gm, eps, T, dD, dphi)) / (2 * h)
+    scale = np.max(np.abs(fd))
+    np.testing.assert_allclose(grad, fd, atol=2e-8 * max(scale, 1.0))
+    if with_zero:
+        assert grad[1, 2] == 0.0
+
+
+def test_grad_annealed_and_dual_only():
+    n, T = 5, 8
+    rng = np.random.default_rng(22)
+    g = rng.uniform(0.2, 1.0, (n, n))
+    G = rng.uniform(0.2, 1.0, (n, n))
+    e = W.anneal_schedule(8e-2, 1e-2, T)
+    for dD, dphi in ((1.0, None), (0.0, rng.standard_normal((n, n)))):
+        grad = O.grad_G(g, G, e, T, dD, dphi)
+        dp = np.zeros((n, n)) if dphi is None else dphi
+        h = 1e-6
+        for p in (0, 7, 13, 24):
+            jj, kk = divmod(p, n)
+            Gp, Gm = G.copy(), G.copy()
+            Gp[jj, kk] += h
+            Gm[jj, kk] -= h
+            fd = (_loss_dense(g, Gp, e, T, dD, dp) - _loss_dense(g, Gm, e, T, dD, dp)) / (2 * h)
+            assert grad[jj, kk] == pytest.approx(fd, abs=1e-8)
+
+
+def test_grad_envelope_limit():
+    """For a converged solve dD/db is the gauge-fixed psi (envelope theorem), so the
+    gradient with respect to G is (2G/Z)(psi - <psi, b>)."""
+    n, eps = 6, 5e-2
+    rng = np.random.default_rng(23)
+    g = rng.uniform(0.2, 1.0, (n, n))
+    G = rng.uniform(0.2, 1.0, (n, n))
+    T = 600
+    grad = O.grad_G(g, G, eps, T, 1.0, None)
+    r = O.solve_sep(g, G, eps, T)
+    Z = float(np.sum(G * G))
+    b = G * G / Z
+    env = (2 * G / Z) * (r.psi - np.sum(r.psi * b))
+    np.testing.assert_allclose(grad, env, atol=1e-9)
