@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Benchmark of the FOT hot path on one MI355X.
+
+A step is one full fot_solve of the 1024 x 1024 two-Gaussian -> ellipses-and-rings workload
+(FP32 operands, eps 5e-3, 200 iterations of Algorithm 1, then the phase read-out of Eq. 9-10
+and the final reductions), with inputs resident in HBM.  The value is whole-job throughput in
+Mpixel.iterations/s = n^2 * iterations * steps / elapsed.
+
+Also reported:
+  roofline      the contraction GEMM kernel (the dominant kernel): 2 n^3 flop per launch over
+                its HIP-event-timed average launch duration on the solve's stream, against the
+                FP32 MFMA peak (157.3 TFLOP/s).
+  cpu_baseline  the FP64 oracle (separable form) timed on the host cores on a bounded sample
+                of the same workload (first `--cpu-iters` iterations).
+  variants      the same workload with BF16 and FP16 operands, and the BF16/FP32 speed ratio
+                at equal marginal L1 error (first iteration reaching the common error level).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel·iter/s at 1024²; %MFMA/HBM peak; BF16 vs FP32 at equal marginal L1"
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "f64": 78.6}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True):
+    n = g.shape[-1]
+    dev = torch.device("cuda", 0)
+    gd = torch.tensor(g, dtype=torch.float64, device=dev)
+    Gd = torch.tensor(G, dtype=torch.float64, device=dev)
+    plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile)
+    for _ in range(warmup):
+        plan.solve(gd, Gd, eps, iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(steps):
+        _, rep, _ = plan.solve(gd, Gd, eps, iters)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plan.close()
+    return elapsed, reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=100, help="oracle iterations in the CPU sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the FOT solve is measured on one "
+              "MI355X; multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2512_19072_amd import fot as F
+    from paper_2512_19072_amd import workloads as W
+
+    wl = W.workload(1)
+    n, iters, eps = wl.n, wl.iters, float(wl.eps[0])
+    g, G = wl.images()
+    log(f"bench: workload {wl.name} n={n} iters={iters} eps={eps} f32, steps={args.steps} warmup={args.warmup}")
+    elapsed, reps = run_variant(F, W, torch, "f32", g, G, eps, iters, args.steps, args.warmup)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n * n * iters * args.steps / elapsed / 1e6
+    ms_gemm = sum(r.ms_contract for r in reps) / max(1, sum(r.n_contract for r in reps))
+    flop = 2.0 * n ** 3
+    achieved = flop / (ms_gemm * 1e-3) / 1e12
+    err_a_f32 = reps[-1].err_a_history[:, 0].copy()
+    ms_iter_f32 = float(np.median([r.ms_iterations for r in reps])) / iters
+    log(f"bench: f32 {value:.1f} Mpx.it/s, {ms_per_step:.2f} ms/step, gemm {ms_gemm * 1e3:.1f} us "
+        f"({achieved:.1f} TFLOP/s), iteration loop {ms_iter_f32 * 1e3:.1f} us/it")
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mpixel·iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "twogauss_to_shapes", "n": n, "iters": iters, "eps": eps, "batch": 1,
+                   "precision": "f32", "seed": 0},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32"], 4), "traffic": None,
+                     "kernel": "fot::k_gemm<float,*> (contraction GEMM, 2 n^3 flop per launch)",
+                     "avg_launch_us": round(ms_gemm * 1e3, 3)},
+    }
+
+    if not args.no_variants:
+        variants = {}
+        for prec in ("bf16", "f16"):
+            el, rp = run_variant(F, W, torch, prec, g, G, eps, iters, args.steps, args.warmup)
+            v = n * n * iters * args.steps / el / 1e6
+            msg = sum(r.ms_contract for r in rp) / max(1, sum(r.n_contract for r in rp))
+            ach = flop / (msg * 1e-3) / 1e12
+            hist = rp[-1].err_a_history[:, 0]
+            ms_it = float(np.median([r.ms_iterations for r in rp])) / iters
+            target = max(float(np.min(hist)), float(err_a_f32[-1]))
+            t_lp = int(np.argmax(hist <= target)) if np.any(hist <= target) else None
+            t_32 = int(np.argmax(err_a_f32 <= target)) if np.any(err_a_f32 <= target) else None
+            equal_l1 = None
+            if t_lp is not None and t_32 is not None:
+                equal_l1 = round(((t_32 + 1) * ms_iter_f32) / ((t_lp + 1) * ms_it), 3)
+            variants[prec] = {"value": round(v, 3), "ms_per_step": round(1e3 * el / args.steps, 4),
+                              "speedup_vs_f32_per_iteration": round(ms_iter_f32 / ms_it, 3),
+                              "equal_marginal_l1": {"err_level": target, "iter_f32": t_32, "iter_lowp": t_lp,
+                                                    "speedup_vs_f32": equal_l1},
+                              "final_err_a": float(hist[-1]),
+                              "gemm_avg_launch_us": round(msg * 1e3, 3),
+                              "gemm_tflops": round(ach, 2),
+                              "gemm_frac_of_peak": round(ach / PEAK_TFLOPS[prec], 4)}
+            log(f"bench: {prec} {v:.1f} Mpx.it/s, gemm {msg * 1e3:.1f} us, final err {hist[-1]:.2e}")
+        out["variants"] = variants
+        out["final_err_a_f32"] = float(err_a_f32[-1])
+
+    if not args.no_cpu_baseline:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count()
+        k = args.cpu_iters
+        t0 = time.perf_counter()
+        oracle.solve_sep(g, G[0], eps, k)
+        t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n * n * k / t_cpu / 1e6, 3), "unit": "Mpixel·iter/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"{wl.name} {n}x{n}, eps {eps}: first {k} of {iters} iterations plus "
+                                         f"read-out, FP64 separable oracle (numpy/OpenBLAS), {t_cpu:.1f} s"}
+        log(f"bench: cpu oracle {out['cpu_baseline']['value']} Mpx.it/s on {cores} threads ({t_cpu:.1f} s)")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

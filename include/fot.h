@@ -1,0 +1,132 @@
+/*
+ * fot.h -- C ABI of the MI355X (gfx950) Fast Optimal Transport library (libfot.so).
+ *
+ * The library solves the entropic optimal-transport problem of holographic beam shaping
+ * of arXiv 2512.19072: given an input-beam amplitude g_jk and target amplitudes G_LM on
+ * n x n grids (Sec. 2), it runs the Sinkhorn-Knopp dual iteration of Algorithm 1 with the
+ * separable Gibbs kernel exp(-c/eps) = Lambda_jL Lambda_kM (Sec. 3, Eq. 6-8), returns the
+ * dual potentials, the marginal errors, the dual value and transport cost, and the phase
+ * obtained from the first moments of the plan (Sec. 3, Eq. 9-10) by trapezoid integration.
+ * fot_backward differentiates the dual value and the phase with respect to G through the
+ * unrolled iterations (reverse mode with checkpoints).
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are row-major [n][n] per image, j (row) = x axis, k (column) = y axis;
+ *     batches are [batch][n][n].  X_L = (L - floor(n/2)) / sqrt(n) (Sec. 2).
+ *   - Every array argument except the fot_report fields is a DEVICE pointer owned by the
+ *     caller (for example a torch tensor's data pointer); the library never frees it.
+ *     The plan owns all its workspace, allocated once in fot_plan.
+ *   - Potentials are FP64: f = eps ln u and psi = eps ln V (Eq. 6), -inf at zero-mass pixels.
+ *   - Work is issued on the plan's stream in stream order.  fot_solve synchronises once at
+ *     its end to fill the report; fot_backward synchronises once at its end to report errors.
+ *   - Every call returns a status; nothing aborts or throws across the ABI.  On failure,
+ *     fot_last_error() gives a message (thread-local, valid until the next call on the
+ *     same thread).
+ *   - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef FOT_H
+#define FOT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fot_plan_s* fot_plan_t;
+
+typedef enum {
+  FOT_OK = 0,
+  FOT_E_INVALID = 1,     /* bad argument: size, eps <= 0, negative/non-finite amplitude, zero mass */
+  FOT_E_NOMEM = 2,       /* device allocation failed in fot_plan */
+  FOT_E_HIP = 3,         /* a HIP runtime call failed */
+  FOT_E_NONFINITE = 4,   /* a potential of a positive-mass pixel became non-finite */
+  FOT_E_STATE = 5,       /* call order violated (e.g. backward without a taped solve) */
+  FOT_E_UNSUPPORTED = 6  /* option not available in this build */
+} fot_status;
+
+/* Element type of the contraction operands (the Gibbs factor and the shifted exponentials
+ * that the per-axis matrix products consume).  Accumulation is FP32 (FP64 for FOT_F64);
+ * potentials, logarithms of the marginals, and all reductions are FP64 in every mode. */
+typedef enum { FOT_F64 = 0, FOT_F32 = 1, FOT_BF16 = 2, FOT_F16 = 3 } fot_precision;
+
+enum {
+  FOT_FLAG_PROFILE = 1   /* time every contraction launch with HIP events (fot_report.ms_contract) */
+};
+
+typedef struct {
+  int n;                 /* grid side, 1 <= n <= 8192 */
+  int batch;             /* number of targets sharing one input amplitude, >= 1 */
+  int precision;         /* fot_precision */
+  int max_iters;         /* largest iteration count fot_solve will be given, >= 1 */
+  int checkpoint_every;  /* > 0: keep psi every k iterations so fot_backward can replay;
+                            0: no tape (fot_backward then returns FOT_E_STATE) */
+  int flags;             /* FOT_FLAG_* */
+} fot_plan_desc;
+
+/* Results of fot_solve.  All pointers are HOST arrays owned by the caller; any may be NULL. */
+typedef struct {
+  double* err_a;          /* [batch] sum_p |sum_q Gamma_pq - a_p| of the final plan (Sec. 3, conv. criterion) */
+  double* err_b;          /* [batch] sum_q |sum_p Gamma_pq - b_q| of the final plan */
+  double* dual;           /* [batch] <f,a> + <psi,b> - eps sum Gamma, a = g^2/sum g^2, b = G^2/sum G^2 */
+  double* transport_cost; /* [batch] sum Gamma_pq c_pq (Sec. 2, Eq. 2-3) */
+  double* err_a_history;  /* [iters][batch] row-marginal L1 of the plan entering each u-update */
+  double* err_b_history;  /* [iters][batch] column-marginal L1 of the plan entering each V-update */
+  int iters_done;         /* iterations run */
+  int nonfinite;          /* 1 if a non-finite potential appeared (status FOT_E_NONFINITE) */
+  double ms_total;        /* HIP-event time of the whole solve on the plan's stream */
+  double ms_iterations;   /* HIP-event time of the iteration loop only */
+  double ms_contract;     /* FOT_FLAG_PROFILE: summed HIP-event time of contraction launches */
+  int n_contract;         /* FOT_FLAG_PROFILE: number of contraction launches timed */
+} fot_report;
+
+/* Create a plan: validates desc, allocates O(n^2 * batch) device workspace once (no later
+ * allocation in fot_solve or fot_backward), and binds it to `stream` (a hipStream_t; NULL
+ * = the null stream) on the current device.  *out is set only on FOT_OK. */
+fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out);
+
+/* Run Algorithm 1 (Sec. 3): normalise a = g^2/sum g^2 and b = G^2/sum G^2 (Eq. 2 marginals,
+ * unit mass), start from u = V = 1/n^2 (or, with warm_start != 0, from the potentials the
+ * plan holds), do `iters` iterations of the u-update (Eq. 7) then the V-update (Eq. 8), then
+ * compute Eq. 9-10 with the final u and V, integrate by the trapezoid rule from phi_00 = 0
+ * (along j at k = 0, then along k), remove the a-weighted mean, and fill `rep`.
+ *   g         device [n][n] FP64 input amplitude, finite, >= 0, positive total
+ *   G         device [batch][n][n] FP64 target amplitudes, same requirements per target
+ *   eps       HOST array of n_eps values: n_eps == 1 (constant) or n_eps == iters (eps_t of
+ *             iteration t; the potentials are carried across changes), each finite and > 0
+ *   iters     1 <= iters <= max_iters
+ *   phase_out device [batch][n][n] FP64 phase in cycles, or NULL to skip writing it
+ *   rep       host report, or NULL
+ * Returns FOT_E_INVALID for bad arguments or amplitudes (nothing is run),
+ * FOT_E_NONFINITE if a positive-mass potential overflowed (outputs undefined, the plan
+ * stays usable), FOT_E_HIP on a runtime error. */
+fot_status fot_solve(fot_plan_t plan, const double* g, const double* G,
+                     const double* eps, int n_eps, int iters, int warm_start,
+                     double* phase_out, fot_report* rep);
+
+/* Read and/or write the potentials held by the plan (device [batch][n][n] FP64 each).
+ * Outputs are written before inputs are read, so the same call can swap states.
+ * Any pointer may be NULL to skip it.  Writing potentials invalidates the backward tape. */
+fot_status fot_potentials(fot_plan_t plan, double* f_out, double* psi_out,
+                          const double* f_in, const double* psi_in);
+
+/* Reverse mode of the last fot_solve (which must have run with checkpoint_every > 0 and
+ * without warm_start changes since): given dL/dD per target (HOST [batch], NULL = 0) and
+ * dL/dphase (device [batch][n][n] FP64, NULL = 0), write dL/dG (device [batch][n][n] FP64).
+ * The iterations are replayed from the stored checkpoints segment by segment; the replay is
+ * bit-identical to the forward solve.  Zero-amplitude target pixels get gradient 0. */
+fot_status fot_backward(fot_plan_t plan, const double* dL_dDual, const double* dL_dphase,
+                        double* dL_dG);
+
+/* Release the plan and all its device memory (after finishing its stream's work). */
+fot_status fot_destroy(fot_plan_t plan);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* fot_last_error(void);
+
+/* Library version string, e.g. "fot 0.1 gfx950". */
+const char* fot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOT_H */

@@ -1,0 +1,525 @@
+// Host side of libfot: plan/workspace management, the iteration schedule of Algorithm 1
+// (arXiv 2512.19072, Sec. 3), the phase read-out (Eq. 9-10) and the C ABI of fot.h.
+#include "fot.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fot_kernels.hpp"
+
+using namespace fot;
+
+namespace {
+
+thread_local std::string g_err;
+
+fot_status fail(fot_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(FOT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK()                                                                       \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess) return fail(FOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int READOUT_BLOCKS = 256;
+
+}  // namespace
+
+struct fot_plan_s {
+  fot_plan_desc d{};
+  int n = 0, np = 0, B = 0, prec = 0, tiles = 0;
+  size_t esz = 0, zsz = 0, plane = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // FP64 state and scratch
+  double *f = nullptr, *psi = nullptr, *lna = nullptr, *lnb = nullptr, *lnS = nullptr, *lnSp = nullptr;
+  double *mrow = nullptr, *Tx = nullptr, *Ty = nullptr, *phi = nullptr;
+  double *rowsum_g = nullptr, *rowsum_G = nullptr, *rowpart = nullptr, *partials = nullptr;
+  double *hist_a = nullptr, *hist_b = nullptr, *rparts = nullptr, *rsums = nullptr;
+  unsigned *colkey = nullptr, *counters = nullptr;
+  int* flag = nullptr;
+  // contraction operands (element type of the precision) and pass outputs (float / double)
+  void *lam = nullptr, *lamH = nullptr, *opA = nullptr, *opA2 = nullptr;
+  void *opB = nullptr, *opBx = nullptr, *opBy = nullptr, *opBc = nullptr;
+  void *Z = nullptr, *Zy = nullptr, *Zc = nullptr;
+  void *S = nullptr, *Sx = nullptr, *Sy = nullptr, *Scx = nullptr, *Scy = nullptr;
+  double* tape = nullptr;
+  int n_ckpt = 0;
+  double lam_eps = -1.0;
+  bool lamH_valid = false;
+  bool has_state = false;
+  bool tape_valid = false;
+  int last_iters = 0;
+  std::vector<double> last_eps;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> prof;
+  int prof_used = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+fot_status dalloc(fot_plan_s* p, void** out, size_t bytes) {
+  void* ptr = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) return fail(FOT_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  p->allocs.push_back(ptr);
+  *out = ptr;
+  return FOT_OK;
+}
+
+template <typename Ptr>
+fot_status dalloc_t(fot_plan_s* p, Ptr** out, size_t count) {
+  void* v = nullptr;
+  fot_status s = dalloc(p, &v, count * sizeof(Ptr));
+  *out = (Ptr*)v;
+  return s;
+}
+
+void release(fot_plan_s* p) {
+  for (void* a : p->allocs) (void)hipFree(a);
+  p->allocs.clear();
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : p->prof) (void)hipEventDestroy(e);
+  p->prof.clear();
+}
+
+// ------------------------------------------------------------------ launch helpers
+template <typename T>
+struct Ops {
+  typedef typename Mma<T>::out_t zt;
+
+  static fot_status gemm_launch(fot_plan_s* p, int epi, const GemmArgs& a) {
+    dim3 grid(p->np / TILE, p->np / TILE, p->B);
+    const bool prof = (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
+    if (prof) HIP_TRY(hipEventRecord(p->prof[p->prof_used], p->stream));
+    switch (epi) {
+      case EPI_LOGROW: hipLaunchKernelGGL((k_gemm<T, EPI_LOGROW>), grid, dim3(NTHREADS), 0, p->stream, a); break;
+      case EPI_UPDATE: hipLaunchKernelGGL((k_gemm<T, EPI_UPDATE>), grid, dim3(NTHREADS), 0, p->stream, a); break;
+      default: hipLaunchKernelGGL((k_gemm<T, EPI_RAW>), grid, dim3(NTHREADS), 0, p->stream, a); break;
+    }
+    LAUNCH_CHECK();
+    if (prof) {
+      HIP_TRY(hipEventRecord(p->prof[p->prof_used + 1], p->stream));
+      p->prof_used += 2;
+    }
+    return FOT_OK;
+  }
+
+  static GemmArgs base_args(fot_plan_s* p, const void* A, long long sA, const void* Bm, long long sB) {
+    GemmArgs a{};
+    a.A = A;
+    a.B = Bm;
+    a.sA = sA;
+    a.sB = sB;
+    a.n = p->n;
+    a.np = p->np;
+    a.nk = (int)((size_t)p->np * sizeof(T) / ROWB);
+    a.xcd_swizzle = 1;
+    return a;
+  }
+
+  static fot_status fill_lambda(fot_plan_s* p, double eps, bool withH) {
+    const size_t total = p->plane;
+    const int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_fill_lambda<T>, dim3(blocks), dim3(256), 0, p->stream, (T*)p->lam,
+                       withH ? (T*)p->lamH : (T*)nullptr, p->n, p->np, 1.0 / eps);
+    LAUNCH_CHECK();
+    p->lam_eps = eps;
+    p->lamH_valid = withH;
+    return FOT_OK;
+  }
+
+  // One half-step: Pout = eps (lnm - ln(Lambda . exp(Pin/eps) . Lambda)) with the fused
+  // marginal error of the entering plan written to hist[batch].
+  static fot_status half(fot_plan_s* p, const double* Pin, double* Pout, const double* lnm, long long sMarg,
+                         double* hist, double* lnS_out, double eps) {
+    const long long plane = (long long)p->plane;
+    hipLaunchKernelGGL(k_rowexp<T>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, Pin, p->n, p->np, 1.0 / eps,
+                       p->mrow, (T*)p->opA, (T*)nullptr, p->colkey);
+    LAUNCH_CHECK();
+    GemmArgs g1 = base_args(p, p->opA, plane, p->lam, 0);
+    g1.out = p->Z;
+    g1.sOut = plane;
+    g1.mrow = p->mrow;
+    g1.colkey = p->colkey;
+    fot_status s = gemm_launch(p, EPI_LOGROW, g1);
+    if (s != FOT_OK) return s;
+    dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
+    hipLaunchKernelGGL((k_colexpT<T, zt, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Z, p->mrow,
+                       p->colkey, p->n, p->np, (T*)p->opB);
+    LAUNCH_CHECK();
+    GemmArgs g2 = base_args(p, p->lam, 0, p->opB, plane);
+    g2.colkey = p->colkey;
+    g2.lnmarg = lnm;
+    g2.sMarg = sMarg;
+    g2.pot = Pout;
+    g2.lnS_out = lnS_out;
+    g2.eps = eps;
+    g2.inv_eps = 1.0 / eps;
+    g2.partials = p->partials;
+    g2.counters = p->counters;
+    g2.hist = hist;
+    g2.flag = p->flag;
+    return gemm_launch(p, EPI_UPDATE, g2);
+  }
+
+  // Phase read-out (Eq. 9-10), final marginals, dual value and transport cost.
+  static fot_status readout(fot_plan_s* p, double eps, double* phase_out) {
+    const long long plane = (long long)p->plane;
+    fot_status s;
+    if (p->lam_eps != eps || !p->lamH_valid) {
+      s = fill_lambda(p, eps, true);
+      if (s != FOT_OK) return s;
+    }
+    hipLaunchKernelGGL(k_rowexp<T>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np, 1.0 / eps,
+                       p->mrow, (T*)p->opA, (T*)p->opA2, p->colkey);
+    LAUNCH_CHECK();
+    GemmArgs g1 = base_args(p, p->opA, plane, p->lam, 0);
+    g1.out = p->Z;
+    g1.sOut = plane;
+    g1.mrow = p->mrow;
+    g1.colkey = p->colkey;
+    if ((s = gemm_launch(p, EPI_LOGROW, g1)) != FOT_OK) return s;
+    GemmArgs gy = base_args(p, p->opA2, plane, p->lam, 0);
+    gy.out = p->Zy;
+    gy.sOut = plane;
+    if ((s = gemm_launch(p, EPI_RAW, gy)) != FOT_OK) return s;
+    GemmArgs gc = base_args(p, p->opA, plane, p->lamH, 0);
+    gc.out = p->Zc;
+    gc.sOut = plane;
+    if ((s = gemm_launch(p, EPI_RAW, gc)) != FOT_OK) return s;
+    dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
+    hipLaunchKernelGGL((k_colexpT<T, zt, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Z, p->mrow,
+                       p->colkey, p->n, p->np, (T*)p->opB);
+    hipLaunchKernelGGL((k_colexpT<T, zt, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Z, p->mrow,
+                       p->colkey, p->n, p->np, (T*)p->opBx);
+    hipLaunchKernelGGL((k_colexpT<T, zt, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Zy, p->mrow,
+                       p->colkey, p->n, p->np, (T*)p->opBy);
+    hipLaunchKernelGGL((k_colexpT<T, zt, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Zc, p->mrow,
+                       p->colkey, p->n, p->np, (T*)p->opBc);
+    LAUNCH_CHECK();
+    struct Job { const void* A; const void* Bm; void* out; } jobs[5] = {
+        {p->lam, p->opB, p->S}, {p->lam, p->opBx, p->Sx}, {p->lam, p->opBy, p->Sy},
+        {p->lamH, p->opB, p->Scx}, {p->lam, p->opBc, p->Scy}};
+    for (auto& j : jobs) {
+      GemmArgs g = base_args(p, j.A, 0, j.Bm, plane);
+      g.out = j.out;
+      g.sOut = plane;
+      if ((s = gemm_launch(p, EPI_RAW, g)) != FOT_OK) return s;
+    }
+    hipLaunchKernelGGL((k_readout<zt>), dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream,
+                       (const zt*)p->S, (const zt*)p->Sx, (const zt*)p->Sy, (const zt*)p->Scx, (const zt*)p->Scy,
+                       p->colkey, p->lnS, p->lna, p->lnb, p->f, p->psi, p->lnSp, p->n, p->np, eps, p->Tx, p->Ty,
+                       p->rparts);
+    hipLaunchKernelGGL(k_sum_parts, dim3(5, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS,
+                       p->rsums);
+    hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->Tx, p->Ty, p->lna, p->n,
+                       p->np, p->phi, p->rowpart);
+    if (phase_out)
+      hipLaunchKernelGGL(k_center, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->phi, p->rowpart, p->n,
+                         p->np, phase_out);
+    LAUNCH_CHECK();
+    return FOT_OK;
+  }
+};
+
+template <typename F>
+fot_status dispatch(int prec, F&& fn) {
+  switch (prec) {
+    case FOT_F64: return fn((double)0);
+    case FOT_F32: return fn((float)0);
+    case FOT_BF16: return fn((__bf16)0);
+    case FOT_F16: return fn((_Float16)0);
+    default: return fail(FOT_E_UNSUPPORTED, "unknown precision");
+  }
+}
+
+bool finite_positive(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* fot_last_error(void) { return g_err.c_str(); }
+
+const char* fot_version(void) { return "fot 0.1 gfx950"; }
+
+fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
+  g_err.clear();
+  if (!desc || !out) return fail(FOT_E_INVALID, "fot_plan: null argument");
+  const fot_plan_desc d = *desc;
+  if (d.n < 1 || d.n > 8192) return fail(FOT_E_INVALID, "fot_plan: n must be in [1, 8192]");
+  if (d.batch < 1 || d.batch > 65535) return fail(FOT_E_INVALID, "fot_plan: batch must be in [1, 65535]");
+  if (d.precision < FOT_F64 || d.precision > FOT_F16) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
+  if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
+  if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
+  fot_plan_s* p = new (std::nothrow) fot_plan_s();
+  if (!p) return fail(FOT_E_NOMEM, "fot_plan: host allocation failed");
+  p->d = d;
+  p->n = d.n;
+  p->np = ((d.n + TILE - 1) / TILE) * TILE;
+  p->B = d.batch;
+  p->prec = d.precision;
+  p->tiles = (p->np / TILE) * (p->np / TILE);
+  p->esz = d.precision == FOT_F64 ? 8 : d.precision == FOT_F32 ? 4 : 2;
+  p->zsz = d.precision == FOT_F64 ? 8 : 4;
+  p->plane = (size_t)p->np * p->np;
+  p->stream = (hipStream_t)stream;
+  auto bail = [&](fot_status s) {
+    std::string msg = g_err;
+    release(p);
+    delete p;
+    g_err = msg;
+    return s;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: no HIP device"));
+  const size_t BP = (size_t)p->B * p->plane;
+  fot_status s = FOT_OK;
+#define ALLOC(ptr, cnt)                                       \
+  if ((s = dalloc_t(p, &(ptr), (cnt))) != FOT_OK) return bail(s);
+#define ALLOCV(ptr, bytes)                                    \
+  if ((s = dalloc(p, &(ptr), (bytes))) != FOT_OK) return bail(s);
+  ALLOC(p->f, BP);
+  ALLOC(p->psi, BP);
+  ALLOC(p->lna, p->plane);
+  ALLOC(p->lnb, BP);
+  ALLOC(p->lnS, BP);
+  ALLOC(p->lnSp, BP);
+  ALLOC(p->mrow, (size_t)p->B * p->np);
+  ALLOC(p->Tx, BP);
+  ALLOC(p->Ty, BP);
+  ALLOC(p->phi, BP);
+  ALLOC(p->rowsum_g, (size_t)p->n);
+  ALLOC(p->rowsum_G, (size_t)p->B * p->n);
+  ALLOC(p->rowpart, (size_t)p->B * p->n);
+  ALLOC(p->partials, (size_t)p->B * p->tiles);
+  ALLOC(p->hist_a, (size_t)d.max_iters * p->B);
+  ALLOC(p->hist_b, (size_t)d.max_iters * p->B);
+  ALLOC(p->rparts, (size_t)5 * p->B * READOUT_BLOCKS);
+  ALLOC(p->rsums, (size_t)5 * p->B);
+  ALLOC(p->colkey, (size_t)p->B * p->np);
+  ALLOC(p->counters, (size_t)p->B);
+  ALLOC(p->flag, (size_t)1);
+  ALLOCV(p->lam, p->plane * p->esz);
+  ALLOCV(p->lamH, p->plane * p->esz);
+  ALLOCV(p->opA, BP * p->esz);
+  ALLOCV(p->opA2, BP * p->esz);
+  ALLOCV(p->opB, BP * p->esz);
+  ALLOCV(p->opBx, BP * p->esz);
+  ALLOCV(p->opBy, BP * p->esz);
+  ALLOCV(p->opBc, BP * p->esz);
+  ALLOCV(p->Z, BP * p->zsz);
+  ALLOCV(p->Zy, BP * p->zsz);
+  ALLOCV(p->Zc, BP * p->zsz);
+  ALLOCV(p->S, BP * p->zsz);
+  ALLOCV(p->Sx, BP * p->zsz);
+  ALLOCV(p->Sy, BP * p->zsz);
+  ALLOCV(p->Scx, BP * p->zsz);
+  ALLOCV(p->Scy, BP * p->zsz);
+  if (d.checkpoint_every > 0) {
+    p->n_ckpt = (d.max_iters + d.checkpoint_every - 1) / d.checkpoint_every;
+    ALLOC(p->tape, (size_t)p->n_ckpt * BP);
+  }
+#undef ALLOC
+#undef ALLOCV
+  if (hipMemsetAsync(p->counters, 0, sizeof(unsigned) * p->B, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->flag, 0, sizeof(int), p->stream) != hipSuccess)
+    return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
+  for (auto& e : p->ev)
+    if (hipEventCreate(&e) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: event create failed"));
+  if (d.flags & FOT_FLAG_PROFILE) {
+    const size_t ne = 2 * ((size_t)d.max_iters * 4 + 16);
+    p->prof.resize(ne, nullptr);
+    for (auto& e : p->prof)
+      if (hipEventCreate(&e) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: event create failed"));
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: sync failed"));
+  *out = p;
+  return FOT_OK;
+}
+
+fot_status fot_destroy(fot_plan_t p) {
+  g_err.clear();
+  if (!p) return fail(FOT_E_INVALID, "fot_destroy: null plan");
+  (void)hipStreamSynchronize(p->stream);
+  release(p);
+  delete p;
+  return FOT_OK;
+}
+
+fot_status fot_potentials(fot_plan_t p, double* f_out, double* psi_out, const double* f_in, const double* psi_in) {
+  g_err.clear();
+  if (!p) return fail(FOT_E_INVALID, "fot_potentials: null plan");
+  const size_t n = p->n, np = p->np;
+  const size_t rows = (size_t)p->B * n;
+  // the padded planes are stacked, so one 2-D copy per batch entry keeps the pitches simple
+  for (int b = 0; b < p->B; ++b) {
+    const size_t po = (size_t)b * p->plane, co = (size_t)b * n * n;
+    if (f_out)
+      HIP_TRY(hipMemcpy2DAsync(f_out + co, n * 8, p->f + po, np * 8, n * 8, n, hipMemcpyDeviceToDevice, p->stream));
+    if (psi_out)
+      HIP_TRY(hipMemcpy2DAsync(psi_out + co, n * 8, p->psi + po, np * 8, n * 8, n, hipMemcpyDeviceToDevice,
+                               p->stream));
+  }
+  (void)rows;
+  if (f_in || psi_in) {
+    if (!p->has_state) {
+      const size_t total = (size_t)p->B * p->plane;
+      const int blocks = (int)((total + 255) / 256);
+      const double v0 = -INFINITY;
+      if (!f_in) hipLaunchKernelGGL(k_fill_pot, dim3(blocks), dim3(256), 0, p->stream, p->f, p->n, p->np, p->B, v0);
+      if (!psi_in)
+        hipLaunchKernelGGL(k_fill_pot, dim3(blocks), dim3(256), 0, p->stream, p->psi, p->n, p->np, p->B, v0);
+      LAUNCH_CHECK();
+    }
+    for (int b = 0; b < p->B; ++b) {
+      const size_t po = (size_t)b * p->plane, co = (size_t)b * n * n;
+      if (f_in)
+        HIP_TRY(hipMemcpy2DAsync(p->f + po, np * 8, f_in + co, n * 8, n * 8, n, hipMemcpyDeviceToDevice, p->stream));
+      if (psi_in)
+        HIP_TRY(hipMemcpy2DAsync(p->psi + po, np * 8, psi_in + co, n * 8, n * 8, n, hipMemcpyDeviceToDevice,
+                                 p->stream));
+    }
+    p->has_state = true;
+    p->tape_valid = false;
+  }
+  return FOT_OK;
+}
+
+fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const double* eps, int n_eps, int iters,
+                     int warm_start, double* phase_out, fot_report* rep) {
+  g_err.clear();
+  if (!p || !g || !G || !eps) return fail(FOT_E_INVALID, "fot_solve: null argument");
+  if (iters < 1 || iters > p->d.max_iters) return fail(FOT_E_INVALID, "fot_solve: iters must be in [1, max_iters]");
+  if (n_eps != 1 && n_eps != iters) return fail(FOT_E_INVALID, "fot_solve: n_eps must be 1 or iters");
+  for (int i = 0; i < n_eps; ++i)
+    if (!finite_positive(eps[i])) return fail(FOT_E_INVALID, "fot_solve: eps must be finite and > 0");
+  if (warm_start && !p->has_state) return fail(FOT_E_STATE, "fot_solve: warm start without potentials");
+  std::vector<double> e(iters);
+  for (int t = 0; t < iters; ++t) e[t] = eps[n_eps == 1 ? 0 : t];
+  const int n = p->n, np = p->np, B = p->B;
+  p->prof_used = 0;
+  p->tape_valid = false;
+
+  HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+  HIP_TRY(hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
+  hipLaunchKernelGGL(k_rowsumsq, dim3(n, 1), dim3(NTHREADS), 0, p->stream, g, n, p->rowsum_g, p->flag);
+  hipLaunchKernelGGL(k_logmarg, dim3(np, 1), dim3(NTHREADS), 0, p->stream, g, p->rowsum_g, n, np, p->lna, p->flag);
+  hipLaunchKernelGGL(k_rowsumsq, dim3(n, B), dim3(NTHREADS), 0, p->stream, G, n, p->rowsum_G, p->flag);
+  hipLaunchKernelGGL(k_logmarg, dim3(np, B), dim3(NTHREADS), 0, p->stream, G, p->rowsum_G, n, np, p->lnb, p->flag);
+  LAUNCH_CHECK();
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (hflag & 2) return fail(FOT_E_INVALID, "fot_solve: amplitudes must be finite and >= 0");
+  if (hflag & 4) return fail(FOT_E_INVALID, "fot_solve: an image has zero (or non-finite) total intensity");
+
+  if (!warm_start) {
+    const double v0 = e[0] * std::log(1.0 / ((double)n * (double)n));  // u = V = 1/n^2
+    const size_t total = (size_t)B * p->plane;
+    const int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_fill_pot, dim3(blocks), dim3(256), 0, p->stream, p->f, n, np, B, v0);
+    hipLaunchKernelGGL(k_fill_pot, dim3(blocks), dim3(256), 0, p->stream, p->psi, n, np, B, v0);
+    LAUNCH_CHECK();
+  }
+
+  fot_status st = dispatch(p->prec, [&](auto tag) -> fot_status {
+    typedef decltype(tag) T;
+    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+    const long long plane = (long long)p->plane;
+    for (int t = 0; t < iters; ++t) {
+      const double ep = e[t];
+      fot_status s;
+      if (p->lam_eps != ep)
+        if ((s = Ops<T>::fill_lambda(p, ep, false)) != FOT_OK) return s;
+      if (p->tape && (t % p->d.checkpoint_every) == 0)
+        HIP_TRY(hipMemcpyAsync(p->tape + (size_t)(t / p->d.checkpoint_every) * B * p->plane, p->psi,
+                               sizeof(double) * B * p->plane, hipMemcpyDeviceToDevice, p->stream));
+      const bool last = (t == iters - 1);
+      if ((s = Ops<T>::half(p, p->psi, p->f, p->lna, 0, p->hist_a + (size_t)t * B, last ? p->lnS : nullptr, ep)) !=
+          FOT_OK)
+        return s;
+      if ((s = Ops<T>::half(p, p->f, p->psi, p->lnb, plane, p->hist_b + (size_t)t * B, last ? p->lnSp : nullptr,
+                            ep)) != FOT_OK)
+        return s;
+    }
+    HIP_TRY(hipEventRecord(p->ev[2], p->stream));
+    fot_status s = Ops<T>::readout(p, e[iters - 1], phase_out);
+    if (s != FOT_OK) return s;
+    HIP_TRY(hipEventRecord(p->ev[3], p->stream));
+    return FOT_OK;
+  });
+  if (st != FOT_OK) return st;
+
+  std::vector<double> ha((size_t)iters * B), hb((size_t)iters * B), rs((size_t)5 * B);
+  HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(ha.data(), p->hist_a, ha.size() * 8, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(hb.data(), p->hist_b, hb.size() * 8, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(rs.data(), p->rsums, rs.size() * 8, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->has_state = true;
+  p->last_iters = iters;
+  p->last_eps = e;
+  p->tape_valid = (p->tape != nullptr);
+
+  if (rep) {
+    const double epT = e[iters - 1];
+    for (int b = 0; b < B; ++b) {
+      const double err_a = rs[0 * B + b], mass = rs[1 * B + b], cost = rs[2 * B + b], dots = rs[3 * B + b],
+                   err_b = rs[4 * B + b];
+      if (rep->err_a) rep->err_a[b] = err_a;
+      if (rep->err_b) rep->err_b[b] = err_b;
+      if (rep->dual) rep->dual[b] = dots - epT * mass;
+      if (rep->transport_cost) rep->transport_cost[b] = cost;
+    }
+    if (rep->err_a_history) std::memcpy(rep->err_a_history, ha.data(), ha.size() * 8);
+    if (rep->err_b_history) std::memcpy(rep->err_b_history, hb.data(), hb.size() * 8);
+    rep->iters_done = iters;
+    rep->nonfinite = (hflag & 1) ? 1 : 0;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[3]));
+    rep->ms_total = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[1], p->ev[2]));
+    rep->ms_iterations = ms;
+    double tot = 0.0;
+    int cnt = 0;
+    for (int i = 0; i + 1 < p->prof_used; i += 2) {
+      HIP_TRY(hipEventElapsedTime(&ms, p->prof[i], p->prof[i + 1]));
+      tot += ms;
+      ++cnt;
+    }
+    rep->ms_contract = tot;
+    rep->n_contract = cnt;
+  }
+  if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_solve: a potential became non-finite");
+  return FOT_OK;
+}
+
+fot_status fot_backward(fot_plan_t p, const double* dL_dDual, const double* dL_dphase, double* dL_dG) {
+  g_err.clear();
+  (void)dL_dDual;
+  (void)dL_dphase;
+  (void)dL_dG;
+  if (!p) return fail(FOT_E_INVALID, "fot_backward: null plan");
+  return fail(FOT_E_UNSUPPORTED, "fot_backward: not available yet");
+}
+
+}  // extern "C"

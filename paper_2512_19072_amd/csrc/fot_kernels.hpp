@@ -1,0 +1,643 @@
+// Device code of the FOT library for gfx950 (CDNA4).
+//
+// The hot loop of Algorithm 1 (arXiv 2512.19072, Sec. 3) is the Gibbs-kernel application
+// S = Lambda . V . Lambda of Eq. 7 (and Lambda . u . Lambda of Eq. 8).  Here it runs in the
+// log domain as two dense per-axis products, each an MFMA GEMM C = A . B^T with both
+// operands stored K-contiguous:
+//
+//   pass 1  W[L][k]   = sum_M  At[L][M] * Lambda[k][M]    At = exp(psi/eps - m_L)  (row shift m_L)
+//   pass 2  S[j][k]   = sum_L  Lambda[j][L] * Bt[k][L]    Bt = exp(ln W - m'_k)^T  (column shift m'_k)
+//
+// so ln S = m'_k + ln(C).  The potential update f = eps (ln a - ln S) and the row-marginal
+// error of the entering plan are fused into the pass-2 epilogue (Sec. 3, convergence
+// criterion), reduced per workgroup and finished in fixed order by the last workgroup, so
+// every result is bit-reproducible.  Arrays are padded to np = ceil(n / 64) * 64 with
+// zeros in the operands, so tiles never need bounds checks inside the main loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+namespace fot {
+
+constexpr int TILE = 64;          // output tile edge of one workgroup
+constexpr int NTHREADS = 256;     // 4 wave64s, each owning a 32 x 32 quarter of the tile
+constexpr int ROWB = 128;         // bytes of one operand row per K stage
+constexpr int LDS_RS = 144;       // LDS row stride in bytes (16 B of padding: conflict-free b128 reads)
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ element conversions
+template <typename T> __device__ __forceinline__ T from_float(float x);
+template <> __device__ __forceinline__ float from_float<float>(float x) { return x; }
+template <> __device__ __forceinline__ __bf16 from_float<__bf16>(float x) { return (__bf16)x; }
+template <> __device__ __forceinline__ _Float16 from_float<_Float16>(float x) { return (_Float16)x; }
+
+// exp of a non-positive log-weight, rounded to the operand type.  FP64 operands use the
+// FP64 exponential; the others evaluate expf on the FP32-rounded argument (the argument is
+// <= 0 and near 0 for the entries that matter, so its rounding is harmless).
+template <typename T> __device__ __forceinline__ T exp_op(double x) {
+  return from_float<T>(expf((float)x));
+}
+template <> __device__ __forceinline__ double exp_op<double>(double x) { return exp(x); }
+
+// w * exp(x), rounded once to the operand type.
+template <typename T> __device__ __forceinline__ T scaled_exp_op(double x, double w) {
+  return from_float<T>(expf((float)x) * (float)w);
+}
+template <> __device__ __forceinline__ double scaled_exp_op<double>(double x, double w) { return exp(x) * w; }
+
+template <typename T> __device__ __forceinline__ T signed_exp_op(double mag_log, bool neg) {
+  T v = exp_op<T>(mag_log);
+  return neg ? (T)(-v) : v;
+}
+
+// ------------------------------------------------------------------ ordered float keys
+// Column maxima across workgroups use atomicMax on an order-preserving encoding of float.
+// Key 0 means "no finite value seen" (it decodes to no shift).
+__device__ __forceinline__ unsigned float_key(float f) {
+  unsigned u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ double key_to_shift(unsigned key) {
+  if (key == 0u) return 0.0;
+  unsigned u = (key & 0x80000000u) ? (key & 0x7fffffffu) : ~key;
+  float f = __uint_as_float(u);
+  return (f > -INFINITY && f < INFINITY) ? (double)f : 0.0;
+}
+
+// ------------------------------------------------------------------ MFMA traits
+// One 16-byte LDS fragment per lane holds 16/sizeof(T) consecutive K elements.  A and B
+// fragments use the same K mapping, so the products pair up correctly whatever order the
+// instruction assigns to K inside the fragment.
+template <typename T> struct Mma;
+
+template <> struct Mma<float> {
+  typedef f32x4 acc_t;
+  typedef float out_t;
+  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+    const f32x4 av = __builtin_bit_cast(f32x4, a);
+    const f32x4 bv = __builtin_bit_cast(f32x4, b);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], bv[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], bv[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], bv[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], bv[3], c, 0, 0, 0);
+  }
+};
+
+template <> struct Mma<double> {
+  typedef f64x4 acc_t;
+  typedef double out_t;
+  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 av = __builtin_bit_cast(d2, a);
+    const d2 bv = __builtin_bit_cast(d2, b);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], c, 0, 0, 0);
+  }
+};
+
+template <> struct Mma<__bf16> {
+  typedef f32x4 acc_t;
+  typedef float out_t;
+  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  }
+};
+
+template <> struct Mma<_Float16> {
+  typedef f32x4 acc_t;
+  typedef float out_t;
+  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                               __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  }
+};
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block-wide sum of one double per thread in a fixed order (deterministic).
+__device__ __forceinline__ double block_sum(double v, double* scratch /* >= 4 */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) s += scratch[w];
+  return s;
+}
+__device__ __forceinline__ double block_max(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double s = -INFINITY;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) s = fmax(s, scratch[w]);
+  return s;
+}
+
+__device__ __forceinline__ double load_acquire_relaxed(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every workgroup writes its partial; the last one to arrive (per batch entry) sums all
+// partials in index order and stores the total.  The counter is reset for the next launch.
+__device__ void finish_partials(double part, double* partials, unsigned* counter, int nparts,
+                                int slot, double* out, double* scratch, int* s_last) {
+  if (threadIdx.x == 0) {
+    partials[slot] = part;
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    *s_last = (prev == (unsigned)(nparts - 1));
+  }
+  __syncthreads();
+  if (*s_last) {
+    __threadfence();
+    const double* base = partials + (slot - (slot % nparts));
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += load_acquire_relaxed(base + i);
+    const double total = block_sum(v, scratch);
+    if (threadIdx.x == 0) {
+      *out = total;
+      *counter = 0u;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ GEMM (C = A . B^T)
+enum Epilogue { EPI_LOGROW = 0, EPI_UPDATE = 1, EPI_RAW = 2 };
+
+struct GemmArgs {
+  const void* A;            // [batch][np][np] (row i, K contiguous); sA = 0 shares it
+  const void* B;            // [batch][np][np] (row j, K contiguous)
+  long long sA, sB;         // batch strides in elements
+  int n, np, nk;            // valid size, padded size, number of K stages
+  int xcd_swizzle;          // remap workgroups so each XCD works on a compact block of tiles
+  // EPI_LOGROW / EPI_RAW output (Z type, [batch][np][np])
+  void* out;
+  long long sOut;
+  const double* mrow;       // [batch][np] row shifts of the pass-1 operand
+  unsigned* colkey;         // [batch][np] column-max keys (pass 1 writes, pass 2 reads)
+  // EPI_UPDATE
+  const double* lnmarg;     // ln a or ln b, [np][np] with batch stride sMarg
+  long long sMarg;
+  double* pot;              // potential updated in place, [batch][np][np]
+  double* lnS_out;          // optional copy of ln S
+  double eps, inv_eps;
+  double* partials;         // [batch][tiles]
+  unsigned* counters;       // [batch]
+  double* hist;             // [batch] error of the entering plan
+  int* flag;                // bit 0: non-finite potential
+};
+
+// Map the linear workgroup id to a tile so that the workgroups that land on one XCD
+// (hardware round-robin: id % 8) cover a compact block of tiles that shares A rows and
+// B columns in that XCD's L2.
+__device__ __forceinline__ void tile_of(int tiles_x, int tiles_y, int swz, int* tr, int* tc) {
+  const int total = tiles_x * tiles_y;
+  int w = blockIdx.x + tiles_x * blockIdx.y;
+  if (swz && (total % 8) == 0) {
+    const int per = total / 8;
+    w = (w % 8) * per + (w / 8);
+  }
+  const int GROUP = 4;
+  const int per_group = GROUP * tiles_x;
+  const int grp = w / per_group;
+  const int first = grp * GROUP;
+  const int gsz = min(tiles_y - first, GROUP);
+  const int in = w % per_group;
+  *tr = first + in % gsz;
+  *tc = in / gsz;
+}
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
+  typedef typename Mma<T>::acc_t acc_t;
+  typedef typename Mma<T>::out_t zt;           // float, or double for FP64
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][TILE * LDS_RS];
+  __shared__ double red[4];
+  __shared__ float cmax[2][TILE];
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int bz = blockIdx.z;
+  int tr, tc;
+  tile_of(gridDim.x, gridDim.y, p.xcd_swizzle, &tr, &tc);
+  const int row0 = tr * TILE, col0 = tc * TILE;
+  const size_t pitch = (size_t)p.np * sizeof(T);
+  const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
+  const unsigned char* Bb = (const unsigned char*)p.B + ((size_t)bz * p.sB) * sizeof(T) + (size_t)col0 * pitch;
+
+  // each thread moves two 16-byte chunks of A and two of B per K stage
+  const int ra0 = tid >> 3, qa = tid & 7, ra1 = ra0 + 32;
+  uint4 ga0, ga1, gb0, gb1;
+  auto gload = [&](int kt) {
+    const size_t ko = (size_t)kt * ROWB + (size_t)qa * 16;
+    ga0 = *(const uint4*)(Ab + (size_t)ra0 * pitch + ko);
+    ga1 = *(const uint4*)(Ab + (size_t)ra1 * pitch + ko);
+    gb0 = *(const uint4*)(Bb + (size_t)ra0 * pitch + ko);
+    gb1 = *(const uint4*)(Bb + (size_t)ra1 * pitch + ko);
+  };
+  auto sstore = [&](int s) {
+    *(uint4*)(&lds[s][0][ra0 * LDS_RS + qa * 16]) = ga0;
+    *(uint4*)(&lds[s][0][ra1 * LDS_RS + qa * 16]) = ga1;
+    *(uint4*)(&lds[s][1][ra0 * LDS_RS + qa * 16]) = gb0;
+    *(uint4*)(&lds[s][1][ra1 * LDS_RS + qa * 16]) = gb1;
+  };
+
+  acc_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{};
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < p.nk; ++kt) {
+    const int s = kt & 1;
+    if (kt + 1 < p.nk) gload(kt + 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint4 af[2], bf[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        af[rb] = *(const uint4*)(&lds[s][0][(wm * 32 + rb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+        bf[cb] = *(const uint4*)(&lds[s][1][(wn * 32 + cb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) Mma<T>::run(af[rb], bf[cb], acc[rb][cb]);
+    }
+    if (kt + 1 < p.nk) sstore(s ^ 1);
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------------- epilogues
+  // acc[rb][cb][e] is C[row0 + wm*32 + rb*16 + g*4 + e][col0 + wn*32 + cb*16 + r16]
+  const int n = p.n, np = p.np;
+  if constexpr (EPI == EPI_RAW) {
+    zt* out = (zt*)p.out + (size_t)bz * p.sOut;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = row0 + wm * 32 + rb * 16 + g * 4 + e;
+          const int j = col0 + wn * 32 + cb * 16 + r16;
+          if (i < n && j < n) out[(size_t)i * np + j] = (zt)acc[rb][cb][e];
+        }
+  } else if constexpr (EPI == EPI_LOGROW) {
+    zt* out = (zt*)p.out + (size_t)bz * p.sOut;
+    const double* mrow = p.mrow + (size_t)bz * np;
+    double cm[2] = {-INFINITY, -INFINITY};
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = row0 + wm * 32 + rb * 16 + g * 4 + e;
+          const int j = col0 + wn * 32 + cb * 16 + r16;
+          if (i < n && j < n) {
+            const zt z = log((zt)acc[rb][cb][e]);
+            out[(size_t)i * np + j] = z;
+            cm[cb] = fmax(cm[cb], mrow[i] + (double)z);
+          }
+        }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      cm[cb] = fmax(cm[cb], __shfl_xor(cm[cb], 16, 64));
+      cm[cb] = fmax(cm[cb], __shfl_xor(cm[cb], 32, 64));
+      if (g == 0) cmax[wm][wn * 32 + cb * 16 + r16] = (float)cm[cb];
+    }
+    __syncthreads();
+    if (tid < TILE) {
+      const float m = fmaxf(cmax[0][tid], cmax[1][tid]);
+      const int j = col0 + tid;
+      if (j < n && m > -INFINITY) atomicMax(p.colkey + (size_t)bz * np + j, float_key(m));
+    }
+  } else {  // EPI_UPDATE
+    const double eps = p.eps, inv_eps = p.inv_eps;
+    const double* lnm = p.lnmarg + (size_t)bz * p.sMarg;
+    double* pot = p.pot + (size_t)bz * (size_t)np * np;
+    double* lns = p.lnS_out ? p.lnS_out + (size_t)bz * (size_t)np * np : nullptr;
+    const unsigned* ck = p.colkey + (size_t)bz * np;
+    double err = 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int j = col0 + wn * 32 + cb * 16 + r16;
+      const double shift = (j < n) ? key_to_shift(ck[j]) : 0.0;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = row0 + wm * 32 + rb * 16 + g * 4 + e;
+          if (i < n && j < n) {
+            const size_t o = (size_t)i * np + j;
+            const double lnS = shift + log((double)acc[rb][cb][e]);
+            const double la = lnm[o];
+            const double fold = pot[o];
+            double fnew;
+            if (la == -INFINITY) {
+              fnew = -INFINITY;
+              // entering plan's mass on a zero-mass pixel: u_old * S
+              err += exp(fold * inv_eps + lnS);
+            } else {
+              fnew = eps * (la - lnS);
+              err += fabs(exp(la + (fold - fnew) * inv_eps) - exp(la));
+              bad |= !(fabs(fnew) < INFINITY);
+            }
+            pot[o] = fnew;
+            if (lns) lns[o] = lnS;
+          }
+        }
+    }
+    if (bad) atomicOr(p.flag, 1);
+    const double part = block_sum(err, red);
+    const int tiles = gridDim.x * gridDim.y;
+    finish_partials(part, p.partials, p.counters + bz, tiles, bz * tiles + blockIdx.x + gridDim.x * blockIdx.y,
+                    p.hist + bz, red, &s_last);
+  }
+}
+
+// ------------------------------------------------------------------ operand preparation
+// Row shift and shifted exponentials of a potential (pass-1 operand):
+//   m_i = max_k P_ik / eps (0 if the row has no finite entry), out_ik = exp(P_ik/eps - m_i).
+// Optionally out2_ik = out_ik * Y_k with Y_k = (k - floor(n/2)) / sqrt(n) (Eq. 10 moment).
+// Also clears the column-max keys that the following pass 1 fills.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int np, double inv_eps,
+                                                     double* mrow, T* out, T* out2, unsigned* colkey) {
+  __shared__ double red[4];
+  const int i = blockIdx.x, bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  T* o = out + bz * plane + (size_t)i * np;
+  T* o2 = out2 ? out2 + bz * plane + (size_t)i * np : nullptr;
+  if (threadIdx.x == 0) colkey[(size_t)bz * np + i] = 0u;
+  if (i >= n) {
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      o[k] = (T)0;
+      if (o2) o2[k] = (T)0;
+    }
+    if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = 0.0;
+    return;
+  }
+  const double* row = P + bz * plane + (size_t)i * np;
+  double m = -INFINITY;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmax(m, row[k] * inv_eps);
+  m = block_max(m, red);
+  if (!(m > -INFINITY && m < INFINITY)) m = 0.0;
+  if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = m;
+  const double ysc = 1.0 / sqrt((double)n);
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    T v = (T)0, v2 = (T)0;
+    if (k < n) {
+      const double x = row[k] * inv_eps - m;
+      v = exp_op<T>(x);
+      if (o2) v2 = scaled_exp_op<T>(x, (double)(k - n / 2) * ysc);
+    }
+    o[k] = v;
+    if (o2) o2[k] = v2;
+  }
+}
+
+// Pass-2 operand, transposed: outT[k][L] = weight * exp(m_L - m'_k) * W[L][k] where
+//   MODE 0: Z = ln W (from EPI_LOGROW), weight 1
+//   MODE 1: Z = ln W, weight X_L = (L - floor(n/2)) / sqrt(n)   (Eq. 9 moment)
+//   MODE 2: Z = W itself (signed, from EPI_RAW), weight 1
+template <typename T, typename ZT, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_colexpT(const ZT* Z, const double* mrow, const unsigned* colkey,
+                                                      int n, int np, T* outT) {
+  __shared__ T tile[TILE][TILE + 2];
+  const int bz = blockIdx.z;
+  const int L0 = blockIdx.y * TILE, k0 = blockIdx.x * TILE;
+  const size_t plane = (size_t)np * np;
+  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int gk = k0 + c;
+  const double mk = (gk < n) ? key_to_shift(colkey[(size_t)bz * np + gk]) : 0.0;
+  const double xsc = 1.0 / sqrt((double)n);
+#pragma unroll 4
+  for (int r = rg; r < TILE; r += 4) {
+    const int gL = L0 + r;
+    T v = (T)0;
+    if (gL < n && gk < n) {
+      const double z = (double)Z[bz * plane + (size_t)gL * np + gk];
+      const double ml = mrow[(size_t)bz * np + gL];
+      if (MODE == 2) {
+        v = (z == 0.0) ? (T)0 : signed_exp_op<T>(log(fabs(z)) + (ml - mk), z < 0.0);
+      } else {
+        if (MODE == 1)
+          v = scaled_exp_op<T>((ml - mk) + z, (double)(gL - n / 2) * xsc);
+        else
+          v = exp_op<T>((ml - mk) + z);
+      }
+    }
+    tile[c][r] = v;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int r = rg; r < TILE; r += 4) outT[bz * plane + (size_t)(k0 + r) * np + L0 + c] = tile[r][c];
+}
+
+// Gibbs factor Lambda[i][k] = exp(-(i-k)^2 / (2 n^2 eps)) (Sec. 3, after Eq. 6), optionally
+// times the axis cost H = (i-k)^2 / (2 n^2) for the transport-cost moments.  Padded rows and
+// columns are filled by the same formula; they only ever meet zero operands.
+template <typename T>
+__global__ void k_fill_lambda(T* lam, T* lamH, int n, int np, double inv_eps) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)np * np) return;
+  const int i = (int)(idx / np), k = (int)(idx % np);
+  const double d = (double)(i - k);
+  const double h = d * d / (2.0 * (double)n * (double)n);
+  const double v = exp(-h * inv_eps);
+  lam[idx] = (T)v;
+  if (lamH) lamH[idx] = (T)(v * h);
+}
+
+// ------------------------------------------------------------------ marginals (Eq. 2)
+// Row sums of squared amplitudes (one block per row), with input validation.
+__global__ void k_rowsumsq(const double* x, int n, double* rowsum, int* flag) {
+  __shared__ double red[4];
+  const int i = blockIdx.x, bz = blockIdx.y;
+  const double* row = x + ((size_t)bz * n + i) * n;
+  double s = 0.0;
+  int bad = 0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double v = row[k];
+    bad |= !(v >= 0.0 && v < INFINITY);
+    s += v * v;
+  }
+  if (bad) atomicOr(flag, 2);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) rowsum[(size_t)bz * n + i] = s;
+}
+
+// ln of the normalised intensity x^2 / sum x^2 into the padded layout (-inf at zeros and
+// in the padding).  Every block re-sums the row sums in the same order.
+__global__ void k_logmarg(const double* x, const double* rowsum, int n, int np, double* lnm, int* flag) {
+  __shared__ double red[4];
+  const int i = blockIdx.x, bz = blockIdx.y;
+  double t = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) t += rowsum[(size_t)bz * n + r];
+  t = block_sum(t, red);
+  if (!(t > 0.0 && t < INFINITY)) {
+    if (threadIdx.x == 0) atomicOr(flag, 4);
+    t = 1.0;
+  }
+  const double lt = log(t);
+  double* o = lnm + ((size_t)bz * np + i) * np;
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    double v = -INFINITY;
+    if (i < n && k < n) {
+      const double a = x[((size_t)bz * n + i) * n + k];
+      if (a > 0.0) v = 2.0 * log(a) - lt;
+    }
+    o[k] = v;
+  }
+}
+
+__global__ void k_fill_pot(double* pot, int n, int np, int batch, double value) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t plane = (size_t)np * np;
+  if (idx >= plane * batch) return;
+  const size_t r = idx % plane;
+  const int i = (int)(r / np), k = (int)(r % np);
+  pot[idx] = (i < n && k < n) ? value : -INFINITY;
+}
+
+// ------------------------------------------------------------------ read-out (Eq. 9-10)
+// Inputs per pixel p = (j,k): S, Sx, Sy, Scx, Scy are the pass-2 outputs for V_T divided by
+// exp(m'_k); lnS_prev = ln(Lambda V_{T-1} Lambda) from the final u-update.  u/a = 1/S_prev.
+// Writes Tx, Ty and per-block partial sums of: |row mass - a|, row mass, transport cost,
+// <f,a> + <psi,b>, column-mass error.
+template <typename ZT>
+__global__ __launch_bounds__(NTHREADS) void k_readout(
+    const ZT* S, const ZT* Sx, const ZT* Sy, const ZT* Scx, const ZT* Scy, const unsigned* colkey,
+    const double* lnS_prev, const double* lna, const double* lnb, const double* f, const double* psi,
+    const double* lnSp, int n, int np, double eps, double* Tx, double* Ty, double* part /*[5][batch][blocks]*/) {
+  __shared__ double red[4];
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  const int nblk = gridDim.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  const double inv_eps = 1.0 / eps;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)nblk * blockDim.x) {
+    const int j = (int)(idx / n), k = (int)(idx % n);
+    const size_t o = bz * plane + (size_t)j * np + k;
+    const size_t oa = (size_t)j * np + k;
+    const double scale = exp(key_to_shift(colkey[(size_t)bz * np + k]) - lnS_prev[o]);
+    Tx[o] = (double)Sx[o] * scale;
+    Ty[o] = (double)Sy[o] * scale;
+    const double la = lna[oa];
+    if (la > -INFINITY) {
+      const double a = exp(la);
+      const double rm = a * (double)S[o] * scale;
+      acc[0] += fabs(rm - a);
+      acc[1] += rm;
+      acc[2] += a * scale * ((double)Scx[o] + (double)Scy[o]);
+      acc[3] += a * f[o];
+    }
+    const double lb = lnb[o];
+    const double cmass = exp(psi[o] * inv_eps + lnSp[o]);
+    if (lb > -INFINITY) {
+      acc[3] += exp(lb) * psi[o];
+      acc[4] += fabs(cmass - exp(lb));
+    } else {
+      acc[4] += cmass;
+    }
+  }
+  const int B = gridDim.y;
+  for (int q = 0; q < 5; ++q) {
+    const double s = block_sum(acc[q], red);
+    if (threadIdx.x == 0) part[((size_t)q * B + bz) * nblk + blockIdx.x] = s;
+  }
+}
+
+// Deterministic final sums of the read-out partials: out[q][bz] for q in 0..4.
+__global__ void k_sum_parts(const double* part, int nblk, double* out) {
+  __shared__ double red[4];
+  const int q = blockIdx.x, bz = blockIdx.y, B = gridDim.y;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += part[((size_t)q * B + bz) * nblk + i];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) out[(size_t)q * B + bz] = v;
+}
+
+// Trapezoid integration (step 1/sqrt(n)): phi[j][0] from Tx along j, then along k with Ty.
+// One block per row; rowpart[bz][j] = sum_k a_jk phi_jk for the a-weighted mean.
+__global__ __launch_bounds__(NTHREADS) void k_integrate(const double* Tx, const double* Ty, const double* lna,
+                                                        int n, int np, double* phi, double* rowpart) {
+  __shared__ double red[4];
+  __shared__ double tsum[NTHREADS];
+  const int j = blockIdx.x, bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  const double hh = 0.5 / sqrt((double)n);
+  // phi[j][0] = sum_{i<j} h/2 (Tx[i][0] + Tx[i+1][0])
+  double c = 0.0;
+  for (int i = threadIdx.x; i < j; i += blockDim.x)
+    c += hh * (Tx[bz * plane + (size_t)i * np] + Tx[bz * plane + (size_t)(i + 1) * np]);
+  const double base = block_sum(c, red);
+  // scan of increments d_k = h/2 (Ty[j][k-1] + Ty[j][k]) over contiguous chunks per thread
+  const double* ty = Ty + bz * plane + (size_t)j * np;
+  const int chunk = (n + NTHREADS - 1) / NTHREADS;
+  const int k0 = threadIdx.x * chunk, k1 = min(n, k0 + chunk);
+  double s = 0.0;
+  for (int k = max(k0, 1); k < k1; ++k) s += hh * (ty[k - 1] + ty[k]);
+  tsum[threadIdx.x] = s;
+  __syncthreads();
+  double prefix = 0.0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) prefix += tsum[t];
+  double run = base + prefix;
+  double wsum = 0.0;
+  double* ph = phi + bz * plane + (size_t)j * np;
+  const double* la = lna + (size_t)j * np;
+  for (int k = k0; k < k1; ++k) {
+    if (k >= 1) run += hh * (ty[k - 1] + ty[k]);
+    ph[k] = run;
+    if (la[k] > -INFINITY) wsum += exp(la[k]) * run;
+  }
+  wsum = block_sum(wsum, red);
+  if (threadIdx.x == 0) rowpart[(size_t)bz * n + j] = wsum;
+}
+
+// Remove the a-weighted mean and write the caller's dense [batch][n][n] layout.
+__global__ __launch_bounds__(NTHREADS) void k_center(const double* phi, const double* rowpart, int n, int np,
+                                                     double* out) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, bz = blockIdx.y;
+  double v = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) v += rowpart[(size_t)bz * n + r];
+  const double mean = block_sum(v, red);
+  const double* ph = phi + (size_t)bz * np * np + (size_t)j * np;
+  double* o = out + ((size_t)bz * n + j) * n;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) o[k] = ph[k] - mean;
+}
+
+}  // namespace fot

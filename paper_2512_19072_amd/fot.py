@@ -1,0 +1,230 @@
+"""ctypes binding of libfot.so (include/fot.h) with the same entry-point names.
+
+Only argument marshalling lives here: every step of the solve runs in the HIP kernels of
+libfot.so.  Device arrays are passed as raw pointers of CUDA (HIP) float64 tensors and work
+is issued on torch's current stream.  If the library is missing the import-time loader
+raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfot.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fot.h")
+
+FOT_OK, FOT_E_INVALID, FOT_E_NOMEM, FOT_E_HIP, FOT_E_NONFINITE, FOT_E_STATE, FOT_E_UNSUPPORTED = range(7)
+FOT_F64, FOT_F32, FOT_BF16, FOT_F16 = range(4)
+FOT_FLAG_PROFILE = 1
+PRECISIONS = {"f64": FOT_F64, "f32": FOT_F32, "bf16": FOT_BF16, "f16": FOT_F16}
+STATUS_NAMES = {0: "FOT_OK", 1: "FOT_E_INVALID", 2: "FOT_E_NOMEM", 3: "FOT_E_HIP", 4: "FOT_E_NONFINITE",
+                5: "FOT_E_STATE", 6: "FOT_E_UNSUPPORTED"}
+
+
+class fot_plan_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("batch", ctypes.c_int), ("precision", ctypes.c_int),
+                ("max_iters", ctypes.c_int), ("checkpoint_every", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class fot_report(ctypes.Structure):
+    _fields_ = [("err_a", _dp), ("err_b", _dp), ("dual", _dp), ("transport_cost", _dp),
+                ("err_a_history", _dp), ("err_b_history", _dp), ("iters_done", ctypes.c_int),
+                ("nonfinite", ctypes.c_int), ("ms_total", ctypes.c_double), ("ms_iterations", ctypes.c_double),
+                ("ms_contract", ctypes.c_double), ("n_contract", ctypes.c_int)]
+
+
+class FOTError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def header_functions(path: str = HEADER) -> list:
+    """Names of the functions declared in include/fot.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fot_[a-z_]+)\s*\(", text)))
+
+
+def load(path: str = LIB_PATH):
+    """Load libfot.so (once) and declare the signatures of fot.h."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfot.so not found at {path}; build it with `python -m paper_2512_19072_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.fot_plan.argtypes = [ctypes.POINTER(fot_plan_desc), vp, ctypes.POINTER(vp)]
+    lib.fot_plan.restype = ip
+    lib.fot_solve.argtypes = [vp, vp, vp, ctypes.POINTER(dp), ip, ip, ip, vp, ctypes.POINTER(fot_report)]
+    lib.fot_solve.restype = ip
+    lib.fot_potentials.argtypes = [vp, vp, vp, vp, vp]
+    lib.fot_potentials.restype = ip
+    lib.fot_backward.argtypes = [vp, ctypes.POINTER(dp), vp, vp]
+    lib.fot_backward.restype = ip
+    lib.fot_destroy.argtypes = [vp]
+    lib.fot_destroy.restype = ip
+    lib.fot_last_error.argtypes = []
+    lib.fot_last_error.restype = ctypes.c_char_p
+    lib.fot_version.argtypes = []
+    lib.fot_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != FOT_OK:
+        msg = load().fot_last_error().decode(errors="replace")
+        raise FOTError(status, f"{what}: {msg}")
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a contiguous CUDA float64 tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("device arrays must be CUDA (HIP) tensors")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("device arrays must be contiguous float64")
+    return t.data_ptr()
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+# ----------------------------------------------------------------------------- raw API
+def fot_version() -> str:
+    return load().fot_version().decode()
+
+
+def fot_last_error() -> str:
+    return load().fot_last_error().decode(errors="replace")
+
+
+def fot_plan(n: int, batch: int = 1, precision="f32", max_iters: int = 1000, checkpoint_every: int = 0,
+             flags: int = 0, stream=None) -> int:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d = fot_plan_desc(n, batch, prec, max_iters, checkpoint_every, flags)
+    h = ctypes.c_void_p()
+    _check(load().fot_plan(ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)), "fot_plan")
+    return h.value
+
+
+def fot_solve(plan: int, g, G, eps, iters: int, warm_start: bool = False, phase_out=None,
+              report: Optional[fot_report] = None, check: bool = True) -> int:
+    e = np.ascontiguousarray(np.atleast_1d(np.asarray(eps, dtype=np.float64)))
+    st = load().fot_solve(ctypes.c_void_p(plan), ctypes.c_void_p(_ptr(g)), ctypes.c_void_p(_ptr(G)),
+                          e.ctypes.data_as(_dp), int(e.size), int(iters), int(bool(warm_start)),
+                          ctypes.c_void_p(_ptr(phase_out)), ctypes.byref(report) if report is not None else None)
+    if check:
+        _check(st, "fot_solve")
+    return st
+
+
+def fot_potentials(plan: int, f_out=None, psi_out=None, f_in=None, psi_in=None):
+    _check(load().fot_potentials(ctypes.c_void_p(plan), ctypes.c_void_p(_ptr(f_out)),
+                                 ctypes.c_void_p(_ptr(psi_out)), ctypes.c_void_p(_ptr(f_in)),
+                                 ctypes.c_void_p(_ptr(psi_in))), "fot_potentials")
+
+
+def fot_backward(plan: int, dL_dDual: Optional[Sequence[float]], dL_dphase, dL_dG):
+    if dL_dDual is None:
+        dd = None
+    else:
+        arr = np.ascontiguousarray(np.asarray(dL_dDual, dtype=np.float64))
+        dd = arr.ctypes.data_as(_dp)
+    _check(load().fot_backward(ctypes.c_void_p(plan), dd, ctypes.c_void_p(_ptr(dL_dphase)),
+                               ctypes.c_void_p(_ptr(dL_dG))), "fot_backward")
+
+
+def fot_destroy(plan: int):
+    _check(load().fot_destroy(ctypes.c_void_p(plan)), "fot_destroy")
+
+
+# ----------------------------------------------------------------------------- convenience
+class Report:
+    """Host-side buffers for fot_report."""
+
+    def __init__(self, batch: int, iters: int):
+        self.err_a = np.zeros(batch)
+        self.err_b = np.zeros(batch)
+        self.dual = np.zeros(batch)
+        self.transport_cost = np.zeros(batch)
+        self.err_a_history = np.zeros((iters, batch))
+        self.err_b_history = np.zeros((iters, batch))
+        self.raw = fot_report()
+        r = self.raw
+        r.err_a = self.err_a.ctypes.data_as(_dp)
+        r.err_b = self.err_b.ctypes.data_as(_dp)
+        r.dual = self.dual.ctypes.data_as(_dp)
+        r.transport_cost = self.transport_cost.ctypes.data_as(_dp)
+        r.err_a_history = self.err_a_history.ctypes.data_as(_dp)
+        r.err_b_history = self.err_b_history.ctypes.data_as(_dp)
+
+    def __getattr__(self, name):
+        return getattr(self.__dict__["raw"], name)
+
+
+class Plan:
+    """Owning wrapper of a fot_plan_t bound to torch's current stream."""
+
+    def __init__(self, n: int, batch: int = 1, precision="f32", max_iters: int = 1000,
+                 checkpoint_every: int = 0, profile: bool = False):
+        self.n, self.batch, self.precision = n, batch, precision
+        self.max_iters = max_iters
+        self.checkpoint_every = checkpoint_every
+        self.handle = fot_plan(n, batch, precision, max_iters, checkpoint_every,
+                               FOT_FLAG_PROFILE if profile else 0)
+
+    def solve(self, g, G, eps, iters: int, warm_start: bool = False, phase: bool = True, check: bool = True):
+        """Run fot_solve; returns (phase tensor or None, Report, status)."""
+        import torch
+        phase_out = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=g.device) if phase else None
+        rep = Report(self.batch, iters)
+        st = fot_solve(self.handle, g, G, eps, iters, warm_start, phase_out, rep.raw, check=check)
+        return phase_out, rep, st
+
+    def potentials(self):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        f = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=dev)
+        psi = torch.empty_like(f)
+        fot_potentials(self.handle, f, psi, None, None)
+        return f, psi
+
+    def set_potentials(self, f=None, psi=None):
+        fot_potentials(self.handle, None, None, f, psi)
+
+    def backward(self, dL_dDual, dL_dphase):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=dev)
+        fot_backward(self.handle, dL_dDual, dL_dphase, out)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fot_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,73 @@
+"""Helpers shared by the GPU parity tests: run the library, run the oracle, compare.
+
+Comparison (the paper leaves potentials defined only up to (f + k, psi - k)): potentials are
+gauge-fixed by subtracting their a- (resp. b-) weighted mean and compared on finite entries,
+as max |x - ref| / (max ref - min ref); the phase likewise (it is defined up to a constant and
+both sides remove the a-weighted mean); scalars relative to their magnitude.
+"""
+import numpy as np
+
+import oracle as O
+
+
+def device():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def to_dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=device())
+
+
+def run_gpu(g, G, eps, iters, precision, checkpoint_every=0, max_iters=None, profile=False):
+    from paper_2512_19072_amd import fot as F
+    G = np.asarray(G)
+    if G.ndim == 2:
+        G = G[None]
+    n, B = g.shape[0], G.shape[0]
+    plan = F.Plan(n, B, precision, max_iters=max_iters or iters, checkpoint_every=checkpoint_every,
+                  profile=profile)
+    phase, rep, st = plan.solve(to_dev(g), to_dev(G), eps, iters)
+    f, psi = plan.potentials()
+    out = dict(phase=phase.cpu().numpy(), f=f.cpu().numpy(), psi=psi.cpu().numpy(), rep=rep, plan=plan)
+    return out
+
+
+def gauge_rel(x, ref, w):
+    m = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(x), m), "different sets of infinite potentials"
+    if not m.any():
+        return 0.0
+    xs = x[m] - np.sum(w[m] * x[m]) / np.sum(w[m])
+    rs = ref[m] - np.sum(w[m] * ref[m]) / np.sum(w[m])
+    rng = rs.max() - rs.min()
+    return float(np.max(np.abs(xs - rs)) / (rng if rng > 0 else 1.0))
+
+
+def range_rel(x, ref):
+    rng = ref.max() - ref.min()
+    return float(np.max(np.abs(x - ref)) / (rng if rng > 0 else 1.0))
+
+
+def compare(gpu, ref, g, G, b_index=0):
+    """Dict of relative errors of one target of a GPU solve against an oracle Result."""
+    a = O.normalise(g)
+    b = O.normalise(G)
+    rep = gpu["rep"]
+    e = {}
+    e["f"] = gauge_rel(gpu["f"][b_index], ref.f, a)
+    e["psi"] = gauge_rel(gpu["psi"][b_index], ref.psi, b)
+    e["phase"] = range_rel(gpu["phase"][b_index], ref.phase)
+    e["dual"] = abs(rep.dual[b_index] - ref.dual) / max(abs(ref.dual), 1e-300)
+    e["cost"] = abs(rep.transport_cost[b_index] - ref.cost) / max(abs(ref.cost), 1e-300)
+    e["err_a"] = abs(rep.err_a[b_index] - ref.err_a) / max(ref.err_a, 1e-300)
+    ha = rep.err_a_history[:, b_index]
+    hb = rep.err_b_history[:, b_index]
+    e["hist_a"] = float(np.max(np.abs(ha - ref.err_a_hist) / np.maximum(ref.err_a_hist, 1e-300)))
+    e["hist_b"] = float(np.max(np.abs(hb - ref.err_b_hist) / np.maximum(ref.err_b_hist, 1e-300)))
+    e["err_b_gpu"] = float(rep.err_b[b_index])
+    return e

@@ -1,0 +1,206 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (range-normalised, gauge-fixed; see tests/parity_util.py):
+  FP64 operands  1e-10: FP64 MFMA and FP64 BLAS differ only in summation order; after 200
+                 iterations of a contractive map the differences stay ~1e-13.
+  FP32 operands  1e-6 on potentials and phase (the stated target); scalars 1e-6.
+  BF16 operands  1e-3 on potentials (the stated target).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2512_19072_amd import workloads as W
+from tests.parity_util import compare, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rand_case(n, seed, zeros=True):
+    rng = np.random.default_rng(seed)
+    c = n // 2
+    g = W.gaussian(n, c + 3, c - 2, 0.2 * n) + 0.05 * rng.uniform(0, 1, (n, n))
+    G = np.sqrt(np.where(rng.uniform(0, 1, (n, n)) < 0.7, 1.0, 1e-6)) * W.gaussian(n, c, c, 0.35 * n)
+    if zeros:
+        G[:, 0] = 0.0
+        G[3, :] = 0.0
+        g[-1, :] = 0.0
+    return g, G
+
+
+def test_workload0_f64_matches_oracle():
+    """64 x 64 Gaussian -> hard disk (exact zeros), FP64, 200 iterations."""
+    wl = W.workload(0)
+    g, G = wl.images()
+    _say("case: gauss_to_disk n=64 f64 200 it")
+    gpu = run_gpu(g, G, 1e-2, 200, "f64")
+    ref = O.solve_sep(g, G[0], 1e-2, 200)
+    e = compare(gpu, ref, g, G[0])
+    _say(e)
+    for k in ("f", "psi", "phase", "dual", "cost"):
+        assert e[k] < 1e-10, (k, e[k])
+    assert e["err_a"] < 1e-6
+    assert e["hist_a"] < 1e-6 and e["hist_b"] < 1e-6
+    assert e["err_b_gpu"] < 1e-13
+    assert gpu["rep"].nonfinite == 0
+
+
+@pytest.mark.parametrize("n,prec", [(100, "f64"), (100, "f32"), (130, "f32"), (72, "bf16"), (72, "f16")])
+def test_ragged_sizes(n, prec):
+    """Sizes that are not multiples of the 64-pixel tile, with zero rows/columns."""
+    g, G = _rand_case(n, n)
+    eps, T = 2e-2, 60
+    _say(f"case: ragged n={n} {prec}")
+    gpu = run_gpu(g, G, eps, T, prec)
+    ref = O.solve_sep(g, G, eps, T)
+    e = compare(gpu, ref, g, G)
+    _say(e)
+    tol = {"f64": 1e-10, "f32": 1e-6, "bf16": 1e-3, "f16": 1e-3}[prec]
+    for k in ("f", "psi", "phase"):
+        assert e[k] < tol, (k, e[k])
+    assert e["dual"] < tol
+
+
+def test_batch_targets_are_independent():
+    n, B, eps, T = 96, 3, 1e-2, 40
+    rng = np.random.default_rng(3)
+    g = W.gaussian(n, n // 2, n // 2, 20.0)
+    Gs = np.stack([_rand_case(n, 10 + b)[1] for b in range(B)])
+    _say(f"case: batch n={n} B={B} f32")
+    gpu = run_gpu(g, Gs, eps, T, "f32")
+    for b in range(B):
+        ref = O.solve_sep(g, Gs[b], eps, T)
+        e = compare(gpu, ref, g, Gs[b], b_index=b)
+        assert e["f"] < 1e-6 and e["psi"] < 1e-6 and e["phase"] < 1e-6, (b, e)
+
+
+def test_deterministic_and_warm_start():
+    """Two solves are bit-identical; 30 + 30 warm-started iterations equal 60 iterations."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n = 128
+    g, G = _rand_case(n, 5)
+    gd, Gd = to_dev(g), to_dev(G[None])
+    plan = F.Plan(n, 1, "f32", max_iters=60)
+    p1, r1, _ = plan.solve(gd, Gd, 1e-2, 60)
+    f1, s1 = plan.potentials()
+    p2, r2, _ = plan.solve(gd, Gd, 1e-2, 60)
+    f2, s2 = plan.potentials()
+    assert bool((p1 == p2).all()) and bool((f1 == f2).all()) and bool((s1 == s2).all())
+    assert np.array_equal(r1.err_a_history, r2.err_a_history) and r1.dual[0] == r2.dual[0]
+    plan.solve(gd, Gd, 1e-2, 30)
+    p3, r3, _ = plan.solve(gd, Gd, 1e-2, 30, warm_start=True)
+    f3, s3 = plan.potentials()
+    assert bool((f3 == f1).all()) and bool((s3 == s1).all()) and bool((p3 == p1).all())
+
+
+def test_potentials_roundtrip():
+    import torch
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n = 80
+    g, G = _rand_case(n, 6)
+    plan = F.Plan(n, 1, "f64", max_iters=20)
+    plan.solve(to_dev(g), to_dev(G[None]), 1e-2, 20)
+    f, psi = plan.potentials()
+    f2 = f * 0 + 0.25
+    plan.set_potentials(f2, psi)
+    f3, psi3 = plan.potentials()
+    assert bool((f3 == f2).all()) and bool((psi3 == psi).all())
+    assert f3.shape == (1, n, n) and f3.dtype == torch.float64
+
+
+@pytest.mark.parametrize("bad", ["negative", "nan", "zero", "eps", "iters"])
+def test_invalid_inputs(bad):
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n = 64
+    g, G = _rand_case(n, 1, zeros=False)
+    eps, iters = 1e-2, 5
+    if bad == "negative":
+        G[2, 2] = -1.0
+    elif bad == "nan":
+        g[1, 1] = np.nan
+    elif bad == "zero":
+        G[:] = 0.0
+    elif bad == "eps":
+        eps = -1.0
+    elif bad == "iters":
+        iters = 6
+    plan = F.Plan(n, 1, "f32", max_iters=5)
+    with pytest.raises(F.FOTError) as ei:
+        plan.solve(to_dev(g), to_dev(G[None]), eps, iters)
+    assert ei.value.status == F.FOT_E_INVALID
+    # the plan stays usable
+    g2, G2 = _rand_case(n, 1, zeros=False)
+    plan.solve(to_dev(g2), to_dev(G2[None]), 1e-2, 5)
+
+
+def test_nonfinite_is_reported():
+    """Input and target supports are disjoint half-planes (columns < 32 and >= 32 of 64).
+    At eps = 5e-4 the Gibbs factor at distance 32 is exp(-250): zero in FP32, so after the
+    first V-update a whole column of the target has no contribution and its potential
+    overflows; FOT_E_NONFINITE is returned and the plan stays usable.  In FP64 the same
+    factor is representable and the potentials stay finite."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n = 64
+    g = np.zeros((n, n))
+    g[:, : n // 2] = 1.0
+    G = np.zeros((n, n))
+    G[:, n // 2:] = 1.0
+    plan = F.Plan(n, 1, "f32", max_iters=3)
+    _, rep, st = plan.solve(to_dev(g), to_dev(G[None]), 5e-4, 1, check=False)
+    assert st == F.FOT_E_NONFINITE and rep.nonfinite == 1
+    plan64 = F.Plan(n, 1, "f64", max_iters=3)
+    _, rep64, st64 = plan64.solve(to_dev(g), to_dev(G[None]), 5e-4, 1, check=False)
+    assert st64 == F.FOT_OK and rep64.nonfinite == 0
+    g2, G2 = _rand_case(n, 2, zeros=False)
+    plan.solve(to_dev(g2), to_dev(G2[None]), 1e-2, 3)
+
+
+def test_tiny_grids():
+    for n in (1, 2, 3):
+        g = np.arange(1, n * n + 1, dtype=np.float64).reshape(n, n)
+        G = np.arange(n * n, 0, -1, dtype=np.float64).reshape(n, n)
+        gpu = run_gpu(g, G, 0.1, 5, "f64")
+        ref = O.solve_sep(g, G, 0.1, 5)
+        e = compare(gpu, ref, g, G)
+        assert e["f"] < 1e-10 and e["psi"] < 1e-10 and e["dual"] < 1e-10, (n, e)
+
+
+def test_annealed_schedule_scaled_lattice():
+    """The 2048 lattice workload scaled to n=256: annealed eps 5e-2 -> 2e-3 over 400 its."""
+    n, T = 256, 400
+    g, G = W.speckle_to_lattice(n)
+    e = W.anneal_schedule(5e-2, 2e-3, T)
+    _say("case: lattice n=256 annealed f32")
+    gpu = run_gpu(g, G, e, T, "f32")
+    ref = O.solve_sep(g, G, e, T)
+    err = compare(gpu, ref, g, G)
+    _say(err)
+    assert err["f"] < 1e-6 and err["psi"] < 1e-6 and err["phase"] < 1e-5
+    assert err["dual"] < 1e-6
+
+
+def test_workload1_full_size_f32():
+    """1024 x 1024 two-Gaussian -> ellipses and rings, FP32 operands, eps 5e-3, 200 its."""
+    wl = W.workload(1)
+    g, G = wl.images()
+    _say("case: twogauss_to_shapes n=1024 f32 200 it")
+    gpu = run_gpu(g, G, 5e-3, 200, "f32")
+    _say("gpu done; oracle running")
+    ref = O.solve_sep(g, G[0], 5e-3, 200)
+    e = compare(gpu, ref, g, G[0])
+    _say(e)
+    assert e["f"] < 1e-6 and e["psi"] < 1e-6, e
+    assert e["phase"] < 1e-6, e
+    assert e["dual"] < 1e-6 and e["cost"] < 1e-6, e
