@@ -58,7 +58,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "normalise", "coords", "cost_1d", "gibbs_1d", "cost_dense", "eps_schedule",
+    "normalise", "log_intensity", "coords", "cost_1d", "gibbs_1d", "cost_dense", "eps_schedule",
     "solve_dense", "solve_sep", "sep_log_apply", "integrate", "integrate_adjoint",
     "grad_G", "lp_ot_cost", "entropy", "primal_entropic", "Result",
 ]
@@ -78,6 +78,19 @@ def normalise(amp: np.ndarray) -> np.ndarray:
     if not np.isfinite(total) or total <= 0.0:
         raise ValueError("amplitude must be finite with positive total intensity")
     return inten / total
+
+
+def log_intensity(amp: np.ndarray) -> np.ndarray:
+    """ln(amp^2 / sum amp^2) evaluated as 2 ln|amp| - ln sum amp^2.
+
+    A pixel has zero mass exactly when its amplitude is zero (reading R6); a nonzero
+    amplitude whose square underflows still has a finite log-intensity."""
+    amp = np.asarray(amp, dtype=np.float64)
+    total = float(np.sum(amp * amp))
+    if not np.isfinite(total) or total <= 0.0:
+        raise ValueError("amplitude must be finite with positive total intensity")
+    with np.errstate(divide="ignore"):
+        return 2.0 * np.log(np.abs(amp)) - math.log(total)
 
 
 def coords(n: int) -> np.ndarray:
@@ -214,7 +227,7 @@ def solve_dense(g: np.ndarray, G: np.ndarray, eps, iters: int) -> Result:
     e = eps_schedule(eps, iters)
     a = normalise(g).ravel()
     b = normalise(G).ravel()
-    la, lb = _log(a), _log(b)
+    la, lb = log_intensity(g).ravel(), log_intensity(G).ravel()
     C = cost_dense(n)
     f = np.full(n * n, e[0] * math.log(1.0 / (n * n)))       # u^0 = 1/n^2
     psi = np.full(n * n, e[0] * math.log(1.0 / (n * n)))     # V^0 = 1/n^2
@@ -229,13 +242,13 @@ def solve_dense(g: np.ndarray, G: np.ndarray, eps, iters: int) -> Result:
         err_a_hist[t] = np.abs(Gam.sum(axis=1) - a).sum()
         # Eq. 7: u = a / (K V)
         f = ep * la - ep * _lse((psi[None, :] - C) / ep, axis=1)
-        f[a == 0] = NEG_INF
+        f[la == NEG_INF] = NEG_INF
         Gam = np.exp((f[:, None] + psi[None, :] - C) / ep)
         err_b_hist[t] = np.abs(Gam.sum(axis=0) - b).sum()
         # Eq. 8: V = b / (K^T u)
         psi_prev = psi
         psi = ep * lb - ep * _lse((f[:, None] - C) / ep, axis=0)
-        psi[b == 0] = NEG_INF
+        psi[lb == NEG_INF] = NEG_INF
         Gam = np.exp((f[:, None] + psi[None, :] - C) / ep)
         dual_hist[t] = _masked_dot(a, f) + _masked_dot(b, psi) - ep * Gam.sum()
     ep = e[-1]
@@ -313,16 +326,15 @@ def sep_log_apply(X: np.ndarray, lam_left: np.ndarray, lam_right: np.ndarray,
     return lnS, ratios
 
 
-def _solve_sep_one(a, b, e, iters, keep_tape=False):
+def _solve_sep_one(a, b, la, lb, e, iters, keep_tape=False):
     n = a.shape[0]
-    la, lb = _log(a), _log(b)
     f = np.full((n, n), e[0] * math.log(1.0 / (n * n)))
     psi = np.full((n, n), e[0] * math.log(1.0 / (n * n)))
     err_a_hist = np.zeros(iters)
     err_b_hist = np.zeros(iters)
     dual_hist = np.zeros(iters)
     tape = [] if keep_tape else None
-    am, bm = a > 0, b > 0
+    am, bm = la > NEG_INF, lb > NEG_INF
     lam = None
     lam_eps = None
     psi_prev = psi
@@ -355,13 +367,13 @@ def _solve_sep_one(a, b, e, iters, keep_tape=False):
     return f, psi, psi_prev, lnS, lnSp, err_a_hist, err_b_hist, dual_hist, tape
 
 
-def _readout(a, b, f, psi, lnS_last, lnSp_last, ep):
+def _readout(a, b, la, lb, f, psi, lnS_last, lnSp_last, ep):
     """Final plan statistics and Eq. 9-10 for potentials (f, psi) = (f_T, psi_T)."""
     n = a.shape[0]
     lam = gibbs_1d(n, ep)
     lamH = lam * cost_1d(n)
     X = coords(n)
-    am = a > 0
+    am = la > NEG_INF
     ones = np.ones((n, n))
     # ln(Lambda.V_T.Lambda) and the ratios needed for Eq. 9-10 and for <Gamma, c>
     lnS_T, (rx, ry, rcx, rcy) = sep_log_apply(
@@ -376,7 +388,7 @@ def _readout(a, b, f, psi, lnS_last, lnSp_last, ep):
     Ty = ry * scale
     row_mass = np.where(am, a * scale, 0.0)            # u_T * S(V_T)
     err_a = float(np.sum(np.abs(row_mass - a)))
-    col_mass = np.where(b > 0, np.exp(psi / ep + lnSp_last), 0.0)
+    col_mass = np.exp(psi / ep + lnSp_last)        # 0 where psi = -inf
     err_b = float(np.sum(np.abs(col_mass - b)))
     mass = float(row_mass.sum())
     cost = float(np.sum(row_mass * (rcx + rcy)))
@@ -395,8 +407,9 @@ def solve_sep(g: np.ndarray, G: np.ndarray, eps, iters: int):
     e = eps_schedule(eps, iters)
     a = normalise(g)
     b = normalise(G)
-    f, psi, psi_prev, lnS, lnSp, ea, eb, dh, _ = _solve_sep_one(a, b, e, iters)
-    Tx, Ty, err_a, err_b, mass, cost, dual = _readout(a, b, f, psi, lnS, lnSp, e[-1])
+    la, lb = log_intensity(g), log_intensity(G)
+    f, psi, psi_prev, lnS, lnSp, ea, eb, dh, _ = _solve_sep_one(a, b, la, lb, e, iters)
+    Tx, Ty, err_a, err_b, mass, cost, dual = _readout(a, b, la, lb, f, psi, lnS, lnSp, e[-1])
     return Result(f=f, psi=psi, lnS_last=lnS, err_a_hist=ea, err_b_hist=eb, dual_hist=dh,
                   err_a=err_a, err_b=err_b, dual=dual, cost=cost, mass=mass,
                   Tx=Tx, Ty=Ty, phase=integrate(Tx, Ty, a), eps_last=float(e[-1]))
@@ -428,8 +441,9 @@ def grad_G(g: np.ndarray, G: np.ndarray, eps, iters: int, dD: float,
     Gd = np.asarray(G, dtype=np.float64)
     Z = float(np.sum(Gd * Gd))
     b = Gd * Gd / Z
-    am, bm = a > 0, b > 0
-    f, psi, psi_prev, lnS, lnSp, _, _, _, tape = _solve_sep_one(a, b, e, iters, keep_tape=True)
+    la, lb = log_intensity(g), log_intensity(Gd)
+    am, bm = la > NEG_INF, lb > NEG_INF
+    f, psi, psi_prev, lnS, lnSp, _, _, _, tape = _solve_sep_one(a, b, la, lb, e, iters, keep_tape=True)
     X = coords(n)
     ones = np.ones((n, n))
 

@@ -26,6 +26,12 @@ def _wrong_normalise(amp):
     return amp / amp.sum()                                      # amplitude, not intensity
 
 
+def _wrong_log_intensity(amp):
+    amp = np.asarray(amp, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return np.log(np.abs(amp)) - np.log(np.abs(amp).sum())  # amplitude, not intensity
+
+
 _real_sep = F.sep_log_apply
 
 
@@ -51,6 +57,7 @@ CASES = [
     ("cost_1d", _wrong_cost, [P.test_product_measures_factorise]),
     ("coords", _wrong_coords, [P.test_gaussian_to_gaussian_affine_map,
                                 P.test_phase_matches_continuum_closed_form]),
+    ("log_intensity", _wrong_log_intensity, [P.test_two_by_two_first_iteration]),
     ("normalise", _wrong_normalise, [P.test_two_by_two_first_iteration]),
     ("sep_log_apply", _transposed_sep, [lambda: P.test_dense_equals_separable(7, 1e-2)]),
     ("integrate", _wrong_step_integrate, [P.test_phase_matches_continuum_closed_form]),

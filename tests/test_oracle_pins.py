@@ -261,6 +261,11 @@ def test_two_by_two_first_iteration():
     # explicit: u_00 = 4 (1/30) / (1 + e^-1)^2
     assert math.exp(res.f[0, 0] / eps) == pytest.approx(4.0 / 30.0 / (1.0 + math.exp(-1.0)) ** 2,
                                                         rel=1e-14)
+    # the entering plan u = V = 1/4 has row sums (1/4)(1 + r)^2/4 at every pixel
+    assert res.err_a_hist[0] == pytest.approx(np.sum(np.abs((1.0 + r) ** 2 / 16.0 - a)), rel=1e-13)
+    # after the V-update the plan has column sums b, so D = <f,a> + <psi,b> - eps
+    d_hand = np.sum(a * eps * np.log(u)) + np.sum(b * eps * np.log(V)) - eps
+    assert res.dual_hist[0] == pytest.approx(d_hand, rel=1e-13)
 
 
 # ---------------------------------------------------------------- P11: phase closed form
