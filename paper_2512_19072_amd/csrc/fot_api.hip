@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -274,11 +275,13 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   if (!p) return fail(FOT_E_NOMEM, "fot_plan: host allocation failed");
   p->d = d;
   p->n = d.n;
-  p->np = ((d.n + TILE - 1) / TILE) * TILE;
+  p->esz = d.precision == FOT_F64 ? 8 : d.precision == FOT_F32 ? 4 : 2;
+  // padded side: whole 64-pixel tiles and whole ROWB-byte K stages
+  const int align = std::max(TILE, (int)(ROWB / p->esz));
+  p->np = ((d.n + align - 1) / align) * align;
   p->B = d.batch;
   p->prec = d.precision;
   p->tiles = (p->np / TILE) * (p->np / TILE);
-  p->esz = d.precision == FOT_F64 ? 8 : d.precision == FOT_F32 ? 4 : 2;
   p->zsz = d.precision == FOT_F64 ? 8 : 4;
   p->plane = (size_t)p->np * p->np;
   p->stream = (hipStream_t)stream;

@@ -23,13 +23,15 @@ namespace fot {
 
 constexpr int TILE = 64;          // output tile edge of one workgroup
 constexpr int NTHREADS = 256;     // 4 wave64s, each owning a 32 x 32 quarter of the tile
-constexpr int ROWB = 128;         // bytes of one operand row per K stage
-constexpr int LDS_RS = 144;       // LDS row stride in bytes (16 B of padding: conflict-free b128 reads)
+constexpr int ROWB = 256;         // bytes of one operand row per K stage
+constexpr int LDS_RS = ROWB + 16; // LDS row stride in bytes (16 B of padding: conflict-free b128 reads)
+constexpr int CHUNKS = ROWB / 16; // 16-byte chunks per operand row per stage
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // one 16-byte fragment
 
 // ------------------------------------------------------------------ element conversions
 template <typename T> __device__ __forceinline__ T from_float(float x);
@@ -76,10 +78,14 @@ __device__ __forceinline__ double key_to_shift(unsigned key) {
 // instruction assigns to K inside the fragment.
 template <typename T> struct Mma;
 
+// Output layout of the 16 x 16 accumulator: lane l holds column l % 16; register e holds
+// row row(l / 16, e).  FP32/BF16/FP16 blocks are 4 consecutive rows per lane group, FP64
+// rows are interleaved with stride 4 (checked by the GEMM parity tests).
 template <> struct Mma<float> {
   typedef f32x4 acc_t;
   typedef float out_t;
-  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * g + e; }
+  static __device__ __forceinline__ void run(const u32x4& a, const u32x4& b, acc_t& c) {
     const f32x4 av = __builtin_bit_cast(f32x4, a);
     const f32x4 bv = __builtin_bit_cast(f32x4, b);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], bv[0], c, 0, 0, 0);
@@ -92,7 +98,8 @@ template <> struct Mma<float> {
 template <> struct Mma<double> {
   typedef f64x4 acc_t;
   typedef double out_t;
-  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+  static __device__ __forceinline__ int row(int g, int e) { return g + 4 * e; }
+  static __device__ __forceinline__ void run(const u32x4& a, const u32x4& b, acc_t& c) {
     typedef double d2 __attribute__((ext_vector_type(2)));
     const d2 av = __builtin_bit_cast(d2, a);
     const d2 bv = __builtin_bit_cast(d2, b);
@@ -104,7 +111,8 @@ template <> struct Mma<double> {
 template <> struct Mma<__bf16> {
   typedef f32x4 acc_t;
   typedef float out_t;
-  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * g + e; }
+  static __device__ __forceinline__ void run(const u32x4& a, const u32x4& b, acc_t& c) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   }
@@ -113,7 +121,8 @@ template <> struct Mma<__bf16> {
 template <> struct Mma<_Float16> {
   typedef f32x4 acc_t;
   typedef float out_t;
-  static __device__ __forceinline__ void run(const uint4& a, const uint4& b, acc_t& c) {
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * g + e; }
+  static __device__ __forceinline__ void run(const u32x4& a, const u32x4& b, acc_t& c) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
                                                __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
   }
@@ -249,22 +258,15 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
   const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
   const unsigned char* Bb = (const unsigned char*)p.B + ((size_t)bz * p.sB) * sizeof(T) + (size_t)col0 * pitch;
 
-  // each thread moves two 16-byte chunks of A and two of B per K stage
-  const int ra0 = tid >> 3, qa = tid & 7, ra1 = ra0 + 32;
-  uint4 ga0, ga1, gb0, gb1;
-  auto gload = [&](int kt) {
-    const size_t ko = (size_t)kt * ROWB + (size_t)qa * 16;
-    ga0 = *(const uint4*)(Ab + (size_t)ra0 * pitch + ko);
-    ga1 = *(const uint4*)(Ab + (size_t)ra1 * pitch + ko);
-    gb0 = *(const uint4*)(Bb + (size_t)ra0 * pitch + ko);
-    gb1 = *(const uint4*)(Bb + (size_t)ra1 * pitch + ko);
-  };
-  auto sstore = [&](int s) {
-    *(uint4*)(&lds[s][0][ra0 * LDS_RS + qa * 16]) = ga0;
-    *(uint4*)(&lds[s][0][ra1 * LDS_RS + qa * 16]) = ga1;
-    *(uint4*)(&lds[s][1][ra0 * LDS_RS + qa * 16]) = gb0;
-    *(uint4*)(&lds[s][1][ra1 * LDS_RS + qa * 16]) = gb1;
-  };
+  // each thread moves LOADS 16-byte chunks of A and of B per K stage (kept in registers
+  // while the previous stage is consumed)
+  constexpr int LOADS = TILE * CHUNKS / NTHREADS;
+  constexpr int RSTEP = NTHREADS / CHUNKS;        // rows covered by one pass of the block
+  const int rl = tid / CHUNKS, ql = tid % CHUNKS;
+  const unsigned char* Ag = Ab + (size_t)rl * pitch + (size_t)ql * 16;
+  const unsigned char* Bg = Bb + (size_t)rl * pitch + (size_t)ql * 16;
+  const int sofs = rl * LDS_RS + ql * 16;
+  u32x4 ga[LOADS], gb[LOADS];
 
   acc_t acc[2][2];
 #pragma unroll
@@ -272,32 +274,54 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{};
 
-  gload(0);
-  sstore(0);
+#pragma unroll
+  for (int u = 0; u < LOADS; ++u) {
+    ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
+    gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch);
+  }
+#pragma unroll
+  for (int u = 0; u < LOADS; ++u) {
+    *(u32x4*)(&lds[0][0][sofs + u * RSTEP * LDS_RS]) = ga[u];
+    *(u32x4*)(&lds[0][1][sofs + u * RSTEP * LDS_RS]) = gb[u];
+  }
   __syncthreads();
   for (int kt = 0; kt < p.nk; ++kt) {
     const int s = kt & 1;
-    if (kt + 1 < p.nk) gload(kt + 1);
+    const bool more = kt + 1 < p.nk;
+    if (more) {
+      const size_t ko = (size_t)(kt + 1) * ROWB;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      uint4 af[2], bf[2];
+      for (int u = 0; u < LOADS; ++u) {
+        ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch + ko);
+        gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch + ko);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < CHUNKS / 4; ++h) {
+      u32x4 af[2], bf[2];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
-        af[rb] = *(const uint4*)(&lds[s][0][(wm * 32 + rb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+        af[rb] = *(const u32x4*)(&lds[s][0][(wm * 32 + rb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb)
-        bf[cb] = *(const uint4*)(&lds[s][1][(wn * 32 + cb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+        bf[cb] = *(const u32x4*)(&lds[s][1][(wn * 32 + cb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) Mma<T>::run(af[rb], bf[cb], acc[rb][cb]);
     }
-    if (kt + 1 < p.nk) sstore(s ^ 1);
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < LOADS; ++u) {
+        *(u32x4*)(&lds[s ^ 1][0][sofs + u * RSTEP * LDS_RS]) = ga[u];
+        *(u32x4*)(&lds[s ^ 1][1][sofs + u * RSTEP * LDS_RS]) = gb[u];
+      }
+    }
     __syncthreads();
   }
 
   // ---------------------------------------------------------------- epilogues
-  // acc[rb][cb][e] is C[row0 + wm*32 + rb*16 + g*4 + e][col0 + wn*32 + cb*16 + r16]
+  // acc[rb][cb][e] is C[row0 + wm*32 + rb*16 + Mma<T>::row(g, e)][col0 + wn*32 + cb*16 + r16]
   const int n = p.n, np = p.np;
   if constexpr (EPI == EPI_RAW) {
     zt* out = (zt*)p.out + (size_t)bz * p.sOut;
@@ -307,7 +331,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + g * 4 + e;
+          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
           const int j = col0 + wn * 32 + cb * 16 + r16;
           if (i < n && j < n) out[(size_t)i * np + j] = (zt)acc[rb][cb][e];
         }
@@ -321,7 +345,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + g * 4 + e;
+          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
           const int j = col0 + wn * 32 + cb * 16 + r16;
           if (i < n && j < n) {
             const zt z = log((zt)acc[rb][cb][e]);
@@ -349,28 +373,52 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
     const unsigned* ck = p.colkey + (size_t)bz * np;
     double err = 0.0;
     int bad = 0;
+    // all loads first: pot is written below and may not be reordered above the stores
+    double la_v[2][2][4], fo_v[2][2][4], shift[2];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       const int j = col0 + wn * 32 + cb * 16 + r16;
-      const double shift = (j < n) ? key_to_shift(ck[j]) : 0.0;
+      shift[cb] = (j < n) ? key_to_shift(ck[j]) : 0.0;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + g * 4 + e;
+          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
+          const bool ok = i < n && j < n;
+          const size_t o = (size_t)i * np + j;
+          la_v[cb][rb][e] = ok ? lnm[o] : 0.0;
+          fo_v[cb][rb][e] = ok ? pot[o] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int j = col0 + wn * 32 + cb * 16 + r16;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
           if (i < n && j < n) {
             const size_t o = (size_t)i * np + j;
-            const double lnS = shift + log((double)acc[rb][cb][e]);
-            const double la = lnm[o];
-            const double fold = pot[o];
+            // ln S in the accumulator's precision, shifted in FP64
+            const double lnS = shift[cb] + (double)log(acc[rb][cb][e]);
+            const double la = la_v[cb][rb][e];
+            const double fold = fo_v[cb][rb][e];
             double fnew;
             if (la == -INFINITY) {
               fnew = -INFINITY;
               // entering plan's mass on a zero-mass pixel: u_old * S
-              err += exp(fold * inv_eps + lnS);
+              if constexpr (sizeof(zt) == 8)
+                err += exp(fold * inv_eps + lnS);
+              else
+                err += (double)expf((float)(fold * inv_eps + lnS));
             } else {
               fnew = eps * (la - lnS);
-              err += fabs(exp(la + (fold - fnew) * inv_eps) - exp(la));
+              // a |u_old / u_new - 1| = a |exp((f_old - f_new)/eps) - 1|
+              if constexpr (sizeof(zt) == 8)
+                err += fabs(exp(la + (fold - fnew) * inv_eps) - exp(la));
+              else
+                err += (double)(expf((float)la) * fabsf(expm1f((float)((fold - fnew) * inv_eps))));
               bad |= !(fabs(fnew) < INFINITY);
             }
             pot[o] = fnew;
@@ -394,6 +442,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int np, double inv_eps,
                                                      double* mrow, T* out, T* out2, unsigned* colkey) {
+  constexpr int MAXV = 32;  // n <= 8192 = 32 * NTHREADS
   __shared__ double red[4];
   const int i = blockIdx.x, bz = blockIdx.y;
   const size_t plane = (size_t)np * np;
@@ -409,21 +458,31 @@ __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int
     return;
   }
   const double* row = P + bz * plane + (size_t)i * np;
+  const int cnt = (n + NTHREADS - 1) / NTHREADS;   // np <= cnt * NTHREADS as well
+  double v[MAXV];
   double m = -INFINITY;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmax(m, row[k] * inv_eps);
+#pragma unroll
+  for (int c = 0; c < MAXV; ++c) {
+    if (c < cnt) {
+      const int k = threadIdx.x + c * NTHREADS;
+      v[c] = (k < n) ? row[k] * inv_eps : -INFINITY;
+      m = fmax(m, v[c]);
+    }
+  }
   m = block_max(m, red);
   if (!(m > -INFINITY && m < INFINITY)) m = 0.0;
   if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = m;
   const double ysc = 1.0 / sqrt((double)n);
-  for (int k = threadIdx.x; k < np; k += blockDim.x) {
-    T v = (T)0, v2 = (T)0;
-    if (k < n) {
-      const double x = row[k] * inv_eps - m;
-      v = exp_op<T>(x);
-      if (o2) v2 = scaled_exp_op<T>(x, (double)(k - n / 2) * ysc);
+#pragma unroll
+  for (int c = 0; c < MAXV; ++c) {
+    if (c < cnt) {
+      const int k = threadIdx.x + c * NTHREADS;
+      if (k < np) {
+        const bool ok = k < n;
+        o[k] = ok ? exp_op<T>(v[c] - m) : (T)0;
+        if (o2) o2[k] = ok ? scaled_exp_op<T>(v[c] - m, (double)(k - n / 2) * ysc) : (T)0;
+      }
     }
-    o[k] = v;
-    if (o2) o2[k] = v2;
   }
 }
 
@@ -434,35 +493,43 @@ __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int
 template <typename T, typename ZT, int MODE>
 __global__ __launch_bounds__(NTHREADS) void k_colexpT(const ZT* Z, const double* mrow, const unsigned* colkey,
                                                       int n, int np, T* outT) {
-  __shared__ T tile[TILE][TILE + 2];
+  // each thread transposes a 4 x 4 block: rows L0..L0+3 of Z, columns k0..k0+3
+  typedef ZT zv4 __attribute__((ext_vector_type(4)));
+  typedef T tv4 __attribute__((ext_vector_type(4)));
   const int bz = blockIdx.z;
-  const int L0 = blockIdx.y * TILE, k0 = blockIdx.x * TILE;
+  const int L0 = blockIdx.y * TILE + 4 * (threadIdx.x >> 4);
+  const int k0 = blockIdx.x * TILE + 4 * (threadIdx.x & 15);
   const size_t plane = (size_t)np * np;
-  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int gk = k0 + c;
-  const double mk = (gk < n) ? key_to_shift(colkey[(size_t)bz * np + gk]) : 0.0;
   const double xsc = 1.0 / sqrt((double)n);
-#pragma unroll 4
-  for (int r = rg; r < TILE; r += 4) {
-    const int gL = L0 + r;
-    T v = (T)0;
-    if (gL < n && gk < n) {
-      const double z = (double)Z[bz * plane + (size_t)gL * np + gk];
-      const double ml = mrow[(size_t)bz * np + gL];
-      if (MODE == 2) {
-        v = (z == 0.0) ? (T)0 : signed_exp_op<T>(log(fabs(z)) + (ml - mk), z < 0.0);
-      } else {
-        if (MODE == 1)
-          v = scaled_exp_op<T>((ml - mk) + z, (double)(gL - n / 2) * xsc);
-        else
-          v = exp_op<T>((ml - mk) + z);
-      }
-    }
-    tile[c][r] = v;
+  double mk[4], ml[4];
+  zv4 z[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    mk[i] = (k0 + i < n) ? key_to_shift(colkey[(size_t)bz * np + k0 + i]) : 0.0;
+    ml[i] = (L0 + i < n) ? mrow[(size_t)bz * np + L0 + i] : 0.0;
+    z[i] = *(const zv4*)(Z + bz * plane + (size_t)(L0 + i) * np + k0);
   }
-  __syncthreads();
-#pragma unroll 4
-  for (int r = rg; r < TILE; r += 4) outT[bz * plane + (size_t)(k0 + r) * np + L0 + c] = tile[r][c];
+  tv4 out[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      T v = (T)0;
+      if (L0 + i < n && k0 + j < n) {
+        const double zz = (double)z[i][j];
+        if (MODE == 2) {
+          v = (zz == 0.0) ? (T)0 : signed_exp_op<T>(log(fabs(zz)) + (ml[i] - mk[j]), zz < 0.0);
+        } else if (MODE == 1) {
+          v = scaled_exp_op<T>((ml[i] - mk[j]) + zz, (double)(L0 + i - n / 2) * xsc);
+        } else {
+          v = exp_op<T>((ml[i] - mk[j]) + zz);
+        }
+      }
+      out[j][i] = v;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) *(tv4*)(outT + bz * plane + (size_t)(k0 + j) * np + L0) = out[j];
 }
 
 // Gibbs factor Lambda[i][k] = exp(-(i-k)^2 / (2 n^2 eps)) (Sec. 3, after Eq. 6), optionally

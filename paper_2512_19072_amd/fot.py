@@ -57,14 +57,38 @@ def header_functions(path: str = HEADER) -> list:
     return sorted(set(re.findall(r"\b(fot_[a-z_]+)\s*\(", text)))
 
 
+def _hip_runtimes_mapped() -> list:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return sorted(paths)
+
+
 def load(path: str = LIB_PATH):
-    """Load libfot.so (once) and declare the signatures of fot.h."""
+    """Load libfot.so (once) and declare the signatures of fot.h.
+
+    torch ships its own HIP runtime with the same SONAME as the system one.  torch is
+    imported first so that libfot.so binds to that runtime: torch's device memory and
+    streams are then valid handles for the library (one runtime per process)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libfot.so not found at {path}; build it with `python -m paper_2512_19072_amd.build`")
+    try:
+        import torch  # noqa: F401  (binds the process to torch's HIP runtime before libfot loads)
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
+    rts = _hip_runtimes_mapped()
+    if len(rts) > 1:
+        raise RuntimeError("two HIP runtimes are loaded in this process: " + ", ".join(rts))
     vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lib.fot_plan.argtypes = [ctypes.POINTER(fot_plan_desc), vp, ctypes.POINTER(vp)]
     lib.fot_plan.restype = ip

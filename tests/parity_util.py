@@ -53,21 +53,28 @@ def range_rel(x, ref):
     return float(np.max(np.abs(x - ref)) / (rng if rng > 0 else 1.0))
 
 
-def compare(gpu, ref, g, G, b_index=0):
+# Marginal errors shrink to the rounding floor of each precision, so they are compared as
+# |gpu - ref| <= rtol * ref + floor; the entries report the worst ratio (pass if <= 1).
+HIST_TOL = {"f64": (1e-6, 1e-12), "f32": (1e-3, 2e-6), "bf16": (0.1, 1e-3), "f16": (0.1, 1e-3)}
+
+
+def compare(gpu, ref, g, G, b_index=0, precision="f64"):
     """Dict of relative errors of one target of a GPU solve against an oracle Result."""
     a = O.normalise(g)
     b = O.normalise(G)
     rep = gpu["rep"]
+    rtol, floor = HIST_TOL[precision]
     e = {}
     e["f"] = gauge_rel(gpu["f"][b_index], ref.f, a)
     e["psi"] = gauge_rel(gpu["psi"][b_index], ref.psi, b)
     e["phase"] = range_rel(gpu["phase"][b_index], ref.phase)
     e["dual"] = abs(rep.dual[b_index] - ref.dual) / max(abs(ref.dual), 1e-300)
     e["cost"] = abs(rep.transport_cost[b_index] - ref.cost) / max(abs(ref.cost), 1e-300)
-    e["err_a"] = abs(rep.err_a[b_index] - ref.err_a) / max(ref.err_a, 1e-300)
+    e["err_a"] = abs(rep.err_a[b_index] - ref.err_a) / (rtol * ref.err_a + floor)
     ha = rep.err_a_history[:, b_index]
     hb = rep.err_b_history[:, b_index]
-    e["hist_a"] = float(np.max(np.abs(ha - ref.err_a_hist) / np.maximum(ref.err_a_hist, 1e-300)))
-    e["hist_b"] = float(np.max(np.abs(hb - ref.err_b_hist) / np.maximum(ref.err_b_hist, 1e-300)))
+    e["hist_a"] = float(np.max(np.abs(ha - ref.err_a_hist) / (rtol * ref.err_a_hist + floor)))
+    e["hist_b"] = float(np.max(np.abs(hb - ref.err_b_hist) / (rtol * ref.err_b_hist + floor)))
     e["err_b_gpu"] = float(rep.err_b[b_index])
+    e["err_a_values"] = (float(rep.err_a[b_index]), float(ref.err_a))
     return e

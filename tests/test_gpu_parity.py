@@ -43,12 +43,11 @@ def test_workload0_f64_matches_oracle():
     _say("case: gauss_to_disk n=64 f64 200 it")
     gpu = run_gpu(g, G, 1e-2, 200, "f64")
     ref = O.solve_sep(g, G[0], 1e-2, 200)
-    e = compare(gpu, ref, g, G[0])
+    e = compare(gpu, ref, g, G[0], precision="f64")
     _say(e)
     for k in ("f", "psi", "phase", "dual", "cost"):
         assert e[k] < 1e-10, (k, e[k])
-    assert e["err_a"] < 1e-6
-    assert e["hist_a"] < 1e-6 and e["hist_b"] < 1e-6
+    assert e["err_a"] <= 1 and e["hist_a"] <= 1 and e["hist_b"] <= 1, e
     assert e["err_b_gpu"] < 1e-13
     assert gpu["rep"].nonfinite == 0
 
@@ -61,12 +60,13 @@ def test_ragged_sizes(n, prec):
     _say(f"case: ragged n={n} {prec}")
     gpu = run_gpu(g, G, eps, T, prec)
     ref = O.solve_sep(g, G, eps, T)
-    e = compare(gpu, ref, g, G)
+    e = compare(gpu, ref, g, G, precision=prec)
     _say(e)
     tol = {"f64": 1e-10, "f32": 1e-6, "bf16": 1e-3, "f16": 1e-3}[prec]
     for k in ("f", "psi", "phase"):
         assert e[k] < tol, (k, e[k])
     assert e["dual"] < tol
+    assert e["hist_a"] <= 1 and e["hist_b"] <= 1, e
 
 
 def test_batch_targets_are_independent():
@@ -78,7 +78,7 @@ def test_batch_targets_are_independent():
     gpu = run_gpu(g, Gs, eps, T, "f32")
     for b in range(B):
         ref = O.solve_sep(g, Gs[b], eps, T)
-        e = compare(gpu, ref, g, Gs[b], b_index=b)
+        e = compare(gpu, ref, g, Gs[b], b_index=b, precision="f32")
         assert e["f"] < 1e-6 and e["psi"] < 1e-6 and e["phase"] < 1e-6, (b, e)
 
 
@@ -111,7 +111,7 @@ def test_potentials_roundtrip():
     plan = F.Plan(n, 1, "f64", max_iters=20)
     plan.solve(to_dev(g), to_dev(G[None]), 1e-2, 20)
     f, psi = plan.potentials()
-    f2 = f * 0 + 0.25
+    f2 = torch.full_like(f, 0.25)
     plan.set_potentials(f2, psi)
     f3, psi3 = plan.potentials()
     assert bool((f3 == f2).all()) and bool((psi3 == psi).all())
@@ -173,7 +173,7 @@ def test_tiny_grids():
         G = np.arange(n * n, 0, -1, dtype=np.float64).reshape(n, n)
         gpu = run_gpu(g, G, 0.1, 5, "f64")
         ref = O.solve_sep(g, G, 0.1, 5)
-        e = compare(gpu, ref, g, G)
+        e = compare(gpu, ref, g, G, precision="f64")
         assert e["f"] < 1e-10 and e["psi"] < 1e-10 and e["dual"] < 1e-10, (n, e)
 
 
@@ -185,7 +185,7 @@ def test_annealed_schedule_scaled_lattice():
     _say("case: lattice n=256 annealed f32")
     gpu = run_gpu(g, G, e, T, "f32")
     ref = O.solve_sep(g, G, e, T)
-    err = compare(gpu, ref, g, G)
+    err = compare(gpu, ref, g, G, precision="f32")
     _say(err)
     assert err["f"] < 1e-6 and err["psi"] < 1e-6 and err["phase"] < 1e-5
     assert err["dual"] < 1e-6
@@ -199,8 +199,9 @@ def test_workload1_full_size_f32():
     gpu = run_gpu(g, G, 5e-3, 200, "f32")
     _say("gpu done; oracle running")
     ref = O.solve_sep(g, G[0], 5e-3, 200)
-    e = compare(gpu, ref, g, G[0])
+    e = compare(gpu, ref, g, G[0], precision="f32")
     _say(e)
     assert e["f"] < 1e-6 and e["psi"] < 1e-6, e
+    assert e["hist_a"] <= 1 and e["err_a"] <= 1, e
     assert e["phase"] < 1e-6, e
     assert e["dual"] < 1e-6 and e["cost"] < 1e-6, e
