@@ -33,12 +33,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True):
+def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True, graph=True):
     n = g.shape[-1]
     dev = torch.device("cuda", 0)
     gd = torch.tensor(g, dtype=torch.float64, device=dev)
     Gd = torch.tensor(G, dtype=torch.float64, device=dev)
-    plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile)
+    plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph)
     for _ in range(warmup):
         plan.solve(gd, Gd, eps, iters)
     torch.cuda.synchronize()
@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=100, help="oracle iterations in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch the iteration loop kernel by kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the FOT solve is measured on one "
@@ -77,10 +78,17 @@ def main():
     n, iters, eps = wl.n, wl.iters, float(wl.eps[0])
     g, G = wl.images()
     log(f"bench: workload {wl.name} n={n} iters={iters} eps={eps} f32, steps={args.steps} warmup={args.warmup}")
-    elapsed, reps = run_variant(F, W, torch, "f32", g, G, eps, iters, args.steps, args.warmup)
+    graph = not args.no_graph
+    # timed region 1: the production launch path (graph replay of the iteration loop)
+    elapsed, reps = run_variant(F, W, torch, "f32", g, G, eps, iters, args.steps, args.warmup,
+                                profile=False, graph=graph)
     ms_per_step = 1e3 * elapsed / args.steps
     value = n * n * iters * args.steps / elapsed / 1e6
-    ms_gemm = sum(r.ms_contract for r in reps) / max(1, sum(r.n_contract for r in reps))
+    # timed region 2: the same steps launched kernel by kernel with HIP events around every
+    # contraction GEMM on the solve's stream (events cannot be timed inside a graph)
+    el_prof, reps_prof = run_variant(F, W, torch, "f32", g, G, eps, iters, args.steps, args.warmup,
+                                     profile=True, graph=False)
+    ms_gemm = sum(r.ms_contract for r in reps_prof) / max(1, sum(r.n_contract for r in reps_prof))
     flop = 2.0 * n ** 3
     achieved = flop / (ms_gemm * 1e-3) / 1e12
     err_a_f32 = reps[-1].err_a_history[:, 0].copy()
@@ -94,19 +102,25 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "twogauss_to_shapes", "n": n, "iters": iters, "eps": eps, "batch": 1,
-                   "precision": "f32", "seed": 0},
+                   "precision": "f32", "seed": 0, "graph": bool(reps[-1].graph)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32"], 4), "traffic": None,
                      "kernel": "fot::k_gemm<float,*> (contraction GEMM, 2 n^3 flop per launch)",
-                     "avg_launch_us": round(ms_gemm * 1e3, 3)},
+                     "avg_launch_us": round(ms_gemm * 1e3, 3),
+                     "timing": "HIP events around every GEMM launch over a second timed region of "
+                               f"{args.steps} steps launched kernel by kernel "
+                               f"({1e3 * el_prof / args.steps:.2f} ms/step)"},
     }
 
     if not args.no_variants:
         variants = {}
         for prec in ("bf16", "f16"):
-            el, rp = run_variant(F, W, torch, prec, g, G, eps, iters, args.steps, args.warmup)
+            el, rp = run_variant(F, W, torch, prec, g, G, eps, iters, args.steps, args.warmup,
+                                 profile=False, graph=graph)
             v = n * n * iters * args.steps / el / 1e6
-            msg = sum(r.ms_contract for r in rp) / max(1, sum(r.n_contract for r in rp))
+            _, rpp = run_variant(F, W, torch, prec, g, G, eps, iters, max(1, args.steps // 2), 1,
+                                 profile=True, graph=False)
+            msg = sum(r.ms_contract for r in rpp) / max(1, sum(r.n_contract for r in rpp))
             ach = flop / (msg * 1e-3) / 1e12
             hist = rp[-1].err_a_history[:, 0]
             ms_it = float(np.median([r.ms_iterations for r in rp])) / iters

@@ -49,7 +49,11 @@ typedef enum {
 typedef enum { FOT_F64 = 0, FOT_F32 = 1, FOT_BF16 = 2, FOT_F16 = 3 } fot_precision;
 
 enum {
-  FOT_FLAG_PROFILE = 1   /* time every contraction launch with HIP events (fot_report.ms_contract) */
+  FOT_FLAG_PROFILE = 1,  /* time every contraction launch with HIP events (fot_report.ms_contract);
+                            the iteration loop is then launched kernel by kernel (events
+                            recorded inside a graph cannot be timed) */
+  FOT_FLAG_NO_GRAPH = 2  /* launch the iteration loop kernel by kernel instead of replaying a
+                            HIP graph of it (the results are bit-identical either way) */
 };
 
 typedef struct {
@@ -76,6 +80,7 @@ typedef struct {
   double ms_iterations;   /* HIP-event time of the iteration loop only */
   double ms_contract;     /* FOT_FLAG_PROFILE: summed HIP-event time of contraction launches */
   int n_contract;         /* FOT_FLAG_PROFILE: number of contraction launches timed */
+  int graph;              /* 1 if the iteration loop was replayed as a HIP graph */
 } fot_report;
 
 /* Create a plan: validates desc, allocates O(n^2 * batch) device workspace once (no later

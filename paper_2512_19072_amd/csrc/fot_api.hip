@@ -2,6 +2,7 @@
 // (arXiv 2512.19072, Sec. 3), the phase read-out (Eq. 9-10) and the C ABI of fot.h.
 #include "fot.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -50,7 +51,7 @@ struct fot_plan_s {
   double *mrow = nullptr, *Tx = nullptr, *Ty = nullptr, *phi = nullptr;
   double *rowsum_g = nullptr, *rowsum_G = nullptr, *rowpart = nullptr, *partials = nullptr;
   double *hist_a = nullptr, *hist_b = nullptr, *rparts = nullptr, *rsums = nullptr;
-  unsigned *colkey = nullptr, *counters = nullptr;
+  unsigned* colkey = nullptr;
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
   void *lam = nullptr, *lamH = nullptr, *opA = nullptr, *opA2 = nullptr;
@@ -60,12 +61,22 @@ struct fot_plan_s {
   double* tape = nullptr;
   int n_ckpt = 0;
   double lam_eps = -1.0;
+  double* pending_hist = nullptr;   // marginal-error sum still to be finished by the next row-exp
   bool lamH_valid = false;
   bool has_state = false;
   bool tape_valid = false;
   int last_iters = 0;
   std::vector<double> last_eps;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // cached HIP graph of the iteration loop, keyed by (iters, eps schedule, tape)
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<double> graph_eps;
+  bool graph_tape = false;
+  int graph_prof = 0;          // profiler events captured inside the graph
+  bool graph_broken = false;   // capture/instantiate failed once: launch eagerly from then on
+  bool used_graph = false;
   std::vector<hipEvent_t> prof;
   int prof_used = 0;
   std::vector<void*> allocs;
@@ -91,7 +102,18 @@ fot_status dalloc_t(fot_plan_s* p, Ptr** out, size_t count) {
   return s;
 }
 
+void drop_graph(fot_plan_s* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->graph_eps.clear();
+}
+
 void release(fot_plan_s* p) {
+  drop_graph(p);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  p->cap = nullptr;
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
   for (auto& e : p->ev)
@@ -101,6 +123,17 @@ void release(fot_plan_s* p) {
 }
 
 // ------------------------------------------------------------------ launch helpers
+// The marginal-error partials of the last potential update, to be summed by the next row-exp.
+PendingSum take_pending(fot_plan_s* p) {
+  PendingSum ps{nullptr, p->tiles, nullptr};
+  if (p->pending_hist) {
+    ps.parts = p->partials;
+    ps.out = p->pending_hist;
+    p->pending_hist = nullptr;
+  }
+  return ps;
+}
+
 template <typename T>
 struct Ops {
   typedef typename Mma<T>::out_t zt;
@@ -108,17 +141,22 @@ struct Ops {
   static fot_status gemm_launch(fot_plan_s* p, int epi, const GemmArgs& a) {
     dim3 grid(p->np / TILE, p->np / TILE, p->B);
     const bool prof = (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
-    if (prof) HIP_TRY(hipEventRecord(p->prof[p->prof_used], p->stream));
+    // profiled launches carry start/stop events that bracket the kernel's own execution
+    hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
+    hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
     switch (epi) {
-      case EPI_LOGROW: hipLaunchKernelGGL((k_gemm<T, EPI_LOGROW>), grid, dim3(NTHREADS), 0, p->stream, a); break;
-      case EPI_UPDATE: hipLaunchKernelGGL((k_gemm<T, EPI_UPDATE>), grid, dim3(NTHREADS), 0, p->stream, a); break;
-      default: hipLaunchKernelGGL((k_gemm<T, EPI_RAW>), grid, dim3(NTHREADS), 0, p->stream, a); break;
+      case EPI_LOGROW:
+        hipExtLaunchKernelGGL((k_gemm<T, EPI_LOGROW>), grid, dim3(NTHREADS), 0, p->stream, e0, e1, 0, a);
+        break;
+      case EPI_UPDATE:
+        hipExtLaunchKernelGGL((k_gemm<T, EPI_UPDATE>), grid, dim3(NTHREADS), 0, p->stream, e0, e1, 0, a);
+        break;
+      default:
+        hipExtLaunchKernelGGL((k_gemm<T, EPI_RAW>), grid, dim3(NTHREADS), 0, p->stream, e0, e1, 0, a);
+        break;
     }
     LAUNCH_CHECK();
-    if (prof) {
-      HIP_TRY(hipEventRecord(p->prof[p->prof_used + 1], p->stream));
-      p->prof_used += 2;
-    }
+    if (prof) p->prof_used += 2;
     return FOT_OK;
   }
 
@@ -152,7 +190,7 @@ struct Ops {
                          double* hist, double* lnS_out, double eps) {
     const long long plane = (long long)p->plane;
     hipLaunchKernelGGL(k_rowexp<T>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, Pin, p->n, p->np, 1.0 / eps,
-                       p->mrow, (T*)p->opA, (T*)nullptr, p->colkey);
+                       p->mrow, (T*)p->opA, (T*)nullptr, p->colkey, take_pending(p));
     LAUNCH_CHECK();
     GemmArgs g1 = base_args(p, p->opA, plane, p->lam, 0);
     g1.out = p->Z;
@@ -174,10 +212,79 @@ struct Ops {
     g2.eps = eps;
     g2.inv_eps = 1.0 / eps;
     g2.partials = p->partials;
-    g2.counters = p->counters;
-    g2.hist = hist;
     g2.flag = p->flag;
-    return gemm_launch(p, EPI_UPDATE, g2);
+    fot_status st = gemm_launch(p, EPI_UPDATE, g2);
+    p->pending_hist = hist;
+    return st;
+  }
+
+  // The iteration loop of Algorithm 1 on p->stream: Lambda is regenerated whenever eps
+  // changes (and at the start), psi is checkpointed every k iterations if a tape exists.
+  static fot_status loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
+    const long long plane = (long long)p->plane;
+    const int B = p->B;
+    for (int t = 0; t < iters; ++t) {
+      const double ep = e[t];
+      fot_status s;
+      if (t == 0 || ep != e[t - 1])
+        if ((s = fill_lambda(p, ep, false)) != FOT_OK) return s;
+      if (p->tape && (t % p->d.checkpoint_every) == 0) {
+        const size_t cnt = (size_t)B * p->plane;
+        hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, p->stream, p->psi,
+                           p->tape + (size_t)(t / p->d.checkpoint_every) * cnt, cnt);
+        LAUNCH_CHECK();
+      }
+      const bool last = (t == iters - 1);
+      if ((s = half(p, p->psi, p->f, p->lna, 0, p->hist_a + (size_t)t * B, last ? p->lnS : nullptr, ep)) != FOT_OK)
+        return s;
+      if ((s = half(p, p->f, p->psi, p->lnb, plane, p->hist_b + (size_t)t * B, last ? p->lnSp : nullptr, ep)) !=
+          FOT_OK)
+        return s;
+    }
+    return FOT_OK;
+  }
+
+  // Run the loop as a cached HIP graph replayed on p->stream (captured on a private stream).
+  // If capture or instantiation fails, the loop is launched eagerly (results are identical).
+  static fot_status loop_graph(fot_plan_s* p, const std::vector<double>& e, int iters) {
+    const bool tape = p->tape != nullptr;
+    if (!(p->gexec && p->graph_eps == e && p->graph_tape == tape)) {
+      drop_graph(p);
+      hipStream_t user = p->stream;
+      const int prof0 = p->prof_used;
+      p->stream = p->cap;
+      p->pending_hist = nullptr;
+      hipError_t eb = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+      fot_status s = (eb == hipSuccess) ? loop(p, e, iters) : FOT_E_HIP;
+      hipGraph_t g = nullptr;
+      hipError_t ec = (eb == hipSuccess) ? hipStreamEndCapture(p->cap, &g) : eb;
+      p->stream = user;
+      hipError_t ei = hipErrorUnknown;
+      if (s == FOT_OK && ec == hipSuccess && g) ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        p->gexec = nullptr;
+        (void)hipGetLastError();
+        p->graph_broken = true;
+        p->prof_used = prof0;
+        p->pending_hist = nullptr;
+        g_err.clear();
+        return loop(p, e, iters);
+      }
+      p->graph = g;
+      p->graph_eps = e;
+      p->graph_tape = tape;
+      p->graph_prof = p->prof_used;
+    } else {
+      p->prof_used = p->graph_prof;
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
+    p->used_graph = true;
+    // state after the loop, as if it had been launched directly
+    p->pending_hist = p->hist_b + (size_t)(iters - 1) * p->B;
+    p->lam_eps = e[iters - 1];
+    p->lamH_valid = false;
+    return FOT_OK;
   }
 
   // Phase read-out (Eq. 9-10), final marginals, dual value and transport cost.
@@ -189,7 +296,7 @@ struct Ops {
       if (s != FOT_OK) return s;
     }
     hipLaunchKernelGGL(k_rowexp<T>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np, 1.0 / eps,
-                       p->mrow, (T*)p->opA, (T*)p->opA2, p->colkey);
+                       p->mrow, (T*)p->opA, (T*)p->opA2, p->colkey, take_pending(p));
     LAUNCH_CHECK();
     GemmArgs g1 = base_args(p, p->opA, plane, p->lam, 0);
     g1.out = p->Z;
@@ -318,7 +425,6 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   ALLOC(p->rparts, (size_t)5 * p->B * READOUT_BLOCKS);
   ALLOC(p->rsums, (size_t)5 * p->B);
   ALLOC(p->colkey, (size_t)p->B * p->np);
-  ALLOC(p->counters, (size_t)p->B);
   ALLOC(p->flag, (size_t)1);
   ALLOCV(p->lam, p->plane * p->esz);
   ALLOCV(p->lamH, p->plane * p->esz);
@@ -342,12 +448,13 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   }
 #undef ALLOC
 #undef ALLOCV
-  if (hipMemsetAsync(p->counters, 0, sizeof(unsigned) * p->B, p->stream) != hipSuccess ||
-      hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
+  if (hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
       hipMemsetAsync(p->flag, 0, sizeof(int), p->stream) != hipSuccess)
     return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
   for (auto& e : p->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: event create failed"));
+  if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(FOT_E_HIP, "fot_plan: stream create failed"));
   if (d.flags & FOT_FLAG_PROFILE) {
     const size_t ne = 2 * ((size_t)d.max_iters * 4 + 16);
     p->prof.resize(ne, nullptr);
@@ -421,6 +528,7 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   const int n = p->n, np = p->np, B = p->B;
   p->prof_used = 0;
   p->tape_valid = false;
+  p->pending_hist = nullptr;
 
   HIP_TRY(hipEventRecord(p->ev[0], p->stream));
   HIP_TRY(hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
@@ -447,23 +555,10 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   fot_status st = dispatch(p->prec, [&](auto tag) -> fot_status {
     typedef decltype(tag) T;
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
-    const long long plane = (long long)p->plane;
-    for (int t = 0; t < iters; ++t) {
-      const double ep = e[t];
-      fot_status s;
-      if (p->lam_eps != ep)
-        if ((s = Ops<T>::fill_lambda(p, ep, false)) != FOT_OK) return s;
-      if (p->tape && (t % p->d.checkpoint_every) == 0)
-        HIP_TRY(hipMemcpyAsync(p->tape + (size_t)(t / p->d.checkpoint_every) * B * p->plane, p->psi,
-                               sizeof(double) * B * p->plane, hipMemcpyDeviceToDevice, p->stream));
-      const bool last = (t == iters - 1);
-      if ((s = Ops<T>::half(p, p->psi, p->f, p->lna, 0, p->hist_a + (size_t)t * B, last ? p->lnS : nullptr, ep)) !=
-          FOT_OK)
-        return s;
-      if ((s = Ops<T>::half(p, p->f, p->psi, p->lnb, plane, p->hist_b + (size_t)t * B, last ? p->lnSp : nullptr,
-                            ep)) != FOT_OK)
-        return s;
-    }
+    const bool graph = !(p->d.flags & (FOT_FLAG_NO_GRAPH | FOT_FLAG_PROFILE)) && !p->graph_broken;
+    p->used_graph = false;
+    fot_status s0 = graph ? Ops<T>::loop_graph(p, e, iters) : Ops<T>::loop(p, e, iters);
+    if (s0 != FOT_OK) return s0;
     HIP_TRY(hipEventRecord(p->ev[2], p->stream));
     fot_status s = Ops<T>::readout(p, e[iters - 1], phase_out);
     if (s != FOT_OK) return s;
@@ -511,6 +606,7 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     }
     rep->ms_contract = tot;
     rep->n_contract = cnt;
+    rep->graph = p->used_graph ? 1 : 0;
   }
   if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_solve: a potential became non-finite");
   return FOT_OK;

@@ -164,34 +164,6 @@ __device__ __forceinline__ double block_max(double v, double* scratch) {
   return s;
 }
 
-__device__ __forceinline__ double load_acquire_relaxed(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Every workgroup writes its partial; the last one to arrive (per batch entry) sums all
-// partials in index order and stores the total.  The counter is reset for the next launch.
-__device__ void finish_partials(double part, double* partials, unsigned* counter, int nparts,
-                                int slot, double* out, double* scratch, int* s_last) {
-  if (threadIdx.x == 0) {
-    partials[slot] = part;
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    *s_last = (prev == (unsigned)(nparts - 1));
-  }
-  __syncthreads();
-  if (*s_last) {
-    __threadfence();
-    const double* base = partials + (slot - (slot % nparts));
-    double v = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += load_acquire_relaxed(base + i);
-    const double total = block_sum(v, scratch);
-    if (threadIdx.x == 0) {
-      *out = total;
-      *counter = 0u;
-    }
-  }
-}
-
 // ------------------------------------------------------------------ GEMM (C = A . B^T)
 enum Epilogue { EPI_LOGROW = 0, EPI_UPDATE = 1, EPI_RAW = 2 };
 
@@ -212,9 +184,7 @@ struct GemmArgs {
   double* pot;              // potential updated in place, [batch][np][np]
   double* lnS_out;          // optional copy of ln S
   double eps, inv_eps;
-  double* partials;         // [batch][tiles]
-  unsigned* counters;       // [batch]
-  double* hist;             // [batch] error of the entering plan
+  double* partials;         // [batch][tiles] per-workgroup marginal-error partials
   int* flag;                // bit 0: non-finite potential
 };
 
@@ -245,7 +215,6 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][TILE * LDS_RS];
   __shared__ double red[4];
   __shared__ float cmax[2][TILE];
-  __shared__ int s_last;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -273,6 +242,28 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{};
+
+  // EPI_UPDATE reads ln(marginal) and the old potential of its 16 outputs per thread; the
+  // loads are issued here so that their latency is hidden behind the K loop.
+  double la_v[2][2][4], fo_v[2][2][4];
+  if constexpr (EPI == EPI_UPDATE) {
+    const double* lnm = p.lnmarg + (size_t)bz * p.sMarg;
+    const double* pot = p.pot + (size_t)bz * (size_t)p.np * p.np;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int j = col0 + wn * 32 + cb * 16 + r16;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
+          const bool ok = i < p.n && j < p.n;
+          const size_t o = (size_t)i * p.np + j;
+          la_v[cb][rb][e] = ok ? lnm[o] : 0.0;
+          fo_v[cb][rb][e] = ok ? pot[o] : 0.0;
+        }
+    }
+  }
 
 #pragma unroll
   for (int u = 0; u < LOADS; ++u) {
@@ -367,28 +358,16 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
     }
   } else {  // EPI_UPDATE
     const double eps = p.eps, inv_eps = p.inv_eps;
-    const double* lnm = p.lnmarg + (size_t)bz * p.sMarg;
     double* pot = p.pot + (size_t)bz * (size_t)np * np;
     double* lns = p.lnS_out ? p.lnS_out + (size_t)bz * (size_t)np * np : nullptr;
     const unsigned* ck = p.colkey + (size_t)bz * np;
     double err = 0.0;
     int bad = 0;
-    // all loads first: pot is written below and may not be reordered above the stores
-    double la_v[2][2][4], fo_v[2][2][4], shift[2];
+    double shift[2];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       const int j = col0 + wn * 32 + cb * 16 + r16;
       shift[cb] = (j < n) ? key_to_shift(ck[j]) : 0.0;
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
-          const bool ok = i < n && j < n;
-          const size_t o = (size_t)i * np + j;
-          la_v[cb][rb][e] = ok ? lnm[o] : 0.0;
-          fo_v[cb][rb][e] = ok ? pot[o] : 0.0;
-        }
     }
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
@@ -427,10 +406,10 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
         }
     }
     if (bad) atomicOr(p.flag, 1);
+    // per-workgroup partial; the next kernel in stream order sums them in index order
     const double part = block_sum(err, red);
     const int tiles = gridDim.x * gridDim.y;
-    finish_partials(part, p.partials, p.counters + bz, tiles, bz * tiles + blockIdx.x + gridDim.x * blockIdx.y,
-                    p.hist + bz, red, &s_last);
+    if (tid == 0) p.partials[(size_t)bz * tiles + blockIdx.x + gridDim.x * blockIdx.y] = part;
   }
 }
 
@@ -439,12 +418,30 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
 //   m_i = max_k P_ik / eps (0 if the row has no finite entry), out_ik = exp(P_ik/eps - m_i).
 // Optionally out2_ik = out_ik * Y_k with Y_k = (k - floor(n/2)) / sqrt(n) (Eq. 10 moment).
 // Also clears the column-max keys that the following pass 1 fills.
+//
+// Block 0 of each batch entry also finishes the marginal-error reduction of the preceding
+// potential update: red_out[bz] = sum of red_parts[bz][0..red_tiles) in index order.
+struct PendingSum {
+  const double* parts;   // nullptr: nothing pending
+  int tiles;
+  double* out;           // [batch]
+};
+
+__device__ __forceinline__ void finish_pending(const PendingSum& ps, int bz, double* red) {
+  double v = 0.0;
+  for (int t = threadIdx.x; t < ps.tiles; t += blockDim.x) v += ps.parts[(size_t)bz * ps.tiles + t];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) ps.out[bz] = v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int np, double inv_eps,
-                                                     double* mrow, T* out, T* out2, unsigned* colkey) {
+                                                     double* mrow, T* out, T* out2, unsigned* colkey,
+                                                     const PendingSum pend) {
   constexpr int MAXV = 32;  // n <= 8192 = 32 * NTHREADS
   __shared__ double red[4];
   const int i = blockIdx.x, bz = blockIdx.y;
+  if (i == 0 && pend.parts) finish_pending(pend, bz, red);
   const size_t plane = (size_t)np * np;
   T* o = out + bz * plane + (size_t)i * np;
   T* o2 = out2 ? out2 + bz * plane + (size_t)i * np : nullptr;
@@ -587,6 +584,11 @@ __global__ void k_logmarg(const double* x, const double* rowsum, int n, int np, 
     }
     o[k] = v;
   }
+}
+
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 __global__ void k_fill_pot(double* pot, int n, int np, int batch, double value) {

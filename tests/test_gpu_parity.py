@@ -205,3 +205,37 @@ def test_workload1_full_size_f32():
     assert e["hist_a"] <= 1 and e["err_a"] <= 1, e
     assert e["phase"] < 1e-6, e
     assert e["dual"] < 1e-6 and e["cost"] < 1e-6, e
+
+
+@pytest.mark.parametrize("profile", [False, True])
+def test_graph_replays_match_eager(profile):
+    """The HIP-graph replay of the iteration loop equals the eager launches bit for bit, on
+    every replay, with unrelated eager GPU work and synchronisations between replays, and
+    after a re-capture for a new eps schedule."""
+    import torch
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n, T = 128, 40
+    g, G = _rand_case(n, 9)
+    gd, Gd = to_dev(g), to_dev(G[None])
+    sched = W.anneal_schedule(5e-2, 5e-3, T)
+    eager = F.Plan(n, 1, "f32", max_iters=T, graph=False)
+    ref = {}
+    for key, eps in (("const", 1e-2), ("anneal", sched)):
+        ph, rep, _ = eager.solve(gd, Gd, eps, T)
+        f, psi = eager.potentials()
+        assert rep.graph == 0
+        ref[key] = (ph.clone(), f.clone(), psi.clone(), rep.err_a_history.copy(), rep.dual.copy())
+    plan = F.Plan(n, 1, "f32", max_iters=T, graph=True, profile=profile)
+    for it, key in enumerate(("const", "const", "anneal", "const", "anneal")):
+        junk = torch.randn(4096, device=gd.device)
+        _ = (junk * junk).sum().item()
+        torch.cuda.synchronize()
+        ph, rep, _ = plan.solve(gd, Gd, 1e-2 if key == "const" else sched, T)
+        f, psi = plan.potentials()
+        assert rep.graph == (0 if profile else 1), "unexpected launch path"
+        r = ref[key]
+        assert bool((ph == r[0]).all()) and bool((f == r[1]).all()) and bool((psi == r[2]).all()), (it, key)
+        assert np.array_equal(rep.err_a_history, r[3]) and np.array_equal(rep.dual, r[4]), (it, key)
+        if profile:
+            assert rep.n_contract == 4 * T + 8 and rep.ms_contract > 0
