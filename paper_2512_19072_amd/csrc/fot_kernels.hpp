@@ -208,55 +208,72 @@ __device__ __forceinline__ void tile_of(int tiles_x, int tiles_y, int swz, int* 
   *tc = in / gsz;
 }
 
-template <typename T, int EPI>
-__global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
+// Tile configuration: a BM x BN output tile per workgroup of NW wave64s; every wave owns an
+// (RB*16) x (CB*16) block of 16 x 16 MFMA tiles.
+template <int BM_, int BN_, int NW_, int RB_, int CB_>
+struct Cfg {
+  static constexpr int BM = BM_, BN = BN_, NW = NW_, RB = RB_, CB = CB_;
+  static constexpr int WTM = 16 * RB, WTN = 16 * CB;          // wave tile
+  static constexpr int WGN = BN / WTN, WGM = BM / WTM;         // waves along N and M
+  static constexpr int THREADS = 64 * NW;
+  static_assert(WGN * WGM == NW, "waves must tile the workgroup tile");
+  static_assert((BM * CHUNKS) % THREADS == 0 && (BN * CHUNKS) % THREADS == 0, "loads must divide");
+};
+typedef Cfg<64, 64, 4, 2, 2> Cfg64x64w4;
+typedef Cfg<64, 64, 8, 2, 1> Cfg64x64w8;
+typedef Cfg<64, 32, 4, 2, 1> Cfg64x32w4;
+
+template <typename T, int EPI, typename C>
+__global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   typedef typename Mma<T>::acc_t acc_t;
   typedef typename Mma<T>::out_t zt;           // float, or double for FP64
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][TILE * LDS_RS];
-  __shared__ double red[4];
-  __shared__ float cmax[2][TILE];
+  constexpr int BM = C::BM, BN = C::BN, RB = C::RB, CB = C::CB;
+  __shared__ __attribute__((aligned(16))) unsigned char ldsA[2][BM * LDS_RS];
+  __shared__ __attribute__((aligned(16))) unsigned char ldsB[2][BN * LDS_RS];
+  __shared__ double red[C::NW];
+  __shared__ float cmax[C::WGM][BN];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / C::WGN, wn = wave % C::WGN;
   const int r16 = lane & 15, g = lane >> 4;
   const int bz = blockIdx.z;
   int tr, tc;
   tile_of(gridDim.x, gridDim.y, p.xcd_swizzle, &tr, &tc);
-  const int row0 = tr * TILE, col0 = tc * TILE;
+  const int row0 = tr * BM, col0 = tc * BN;
   const size_t pitch = (size_t)p.np * sizeof(T);
   const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
   const unsigned char* Bb = (const unsigned char*)p.B + ((size_t)bz * p.sB) * sizeof(T) + (size_t)col0 * pitch;
 
-  // each thread moves LOADS 16-byte chunks of A and of B per K stage (kept in registers
-  // while the previous stage is consumed)
-  constexpr int LOADS = TILE * CHUNKS / NTHREADS;
-  constexpr int RSTEP = NTHREADS / CHUNKS;        // rows covered by one pass of the block
+  // each thread moves LA (LB) 16-byte chunks of A (B) per K stage, kept in registers while
+  // the previous stage is consumed
+  constexpr int LA = BM * CHUNKS / C::THREADS, LB = BN * CHUNKS / C::THREADS;
+  constexpr int RSTEP = C::THREADS / CHUNKS;      // rows covered by one pass of the block
   const int rl = tid / CHUNKS, ql = tid % CHUNKS;
   const unsigned char* Ag = Ab + (size_t)rl * pitch + (size_t)ql * 16;
   const unsigned char* Bg = Bb + (size_t)rl * pitch + (size_t)ql * 16;
   const int sofs = rl * LDS_RS + ql * 16;
-  u32x4 ga[LOADS], gb[LOADS];
+  u32x4 ga[LA], gb[LB];
 
-  acc_t acc[2][2];
+  acc_t acc[RB][CB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{};
+    for (int j = 0; j < CB; ++j) acc[i][j] = acc_t{};
 
-  // EPI_UPDATE reads ln(marginal) and the old potential of its 16 outputs per thread; the
-  // loads are issued here so that their latency is hidden behind the K loop.
-  double la_v[2][2][4], fo_v[2][2][4];
+  // EPI_UPDATE reads ln(marginal) and the old potential of its outputs; the loads are
+  // issued here so that their latency is hidden behind the K loop.
+  double la_v[CB][RB][4], fo_v[CB][RB][4];
   if constexpr (EPI == EPI_UPDATE) {
     const double* lnm = p.lnmarg + (size_t)bz * p.sMarg;
     const double* pot = p.pot + (size_t)bz * (size_t)p.np * p.np;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int j = col0 + wn * 32 + cb * 16 + r16;
+    for (int cb = 0; cb < CB; ++cb) {
+      const int j = col0 + wn * C::WTN + cb * 16 + r16;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
+          const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const bool ok = i < p.n && j < p.n;
           const size_t o = (size_t)i * p.np + j;
           la_v[cb][rb][e] = ok ? lnm[o] : 0.0;
@@ -266,15 +283,13 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
   }
 
 #pragma unroll
-  for (int u = 0; u < LOADS; ++u) {
-    ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
-    gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch);
-  }
+  for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
 #pragma unroll
-  for (int u = 0; u < LOADS; ++u) {
-    *(u32x4*)(&lds[0][0][sofs + u * RSTEP * LDS_RS]) = ga[u];
-    *(u32x4*)(&lds[0][1][sofs + u * RSTEP * LDS_RS]) = gb[u];
-  }
+  for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch);
+#pragma unroll
+  for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[0][sofs + u * RSTEP * LDS_RS]) = ga[u];
+#pragma unroll
+  for (int u = 0; u < LB; ++u) *(u32x4*)(&ldsB[0][sofs + u * RSTEP * LDS_RS]) = gb[u];
   __syncthreads();
   for (int kt = 0; kt < p.nk; ++kt) {
     const int s = kt & 1;
@@ -282,62 +297,62 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
     if (more) {
       const size_t ko = (size_t)(kt + 1) * ROWB;
 #pragma unroll
-      for (int u = 0; u < LOADS; ++u) {
-        ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch + ko);
-        gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch + ko);
-      }
+      for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch + ko);
+#pragma unroll
+      for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch + ko);
     }
 #pragma unroll
     for (int h = 0; h < CHUNKS / 4; ++h) {
-      u32x4 af[2], bf[2];
+      u32x4 af[RB], bf[CB];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-        af[rb] = *(const u32x4*)(&lds[s][0][(wm * 32 + rb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+      for (int rb = 0; rb < RB; ++rb)
+        af[rb] = *(const u32x4*)(&ldsA[s][(wm * C::WTM + rb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-        bf[cb] = *(const u32x4*)(&lds[s][1][(wn * 32 + cb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+      for (int cb = 0; cb < CB; ++cb)
+        bf[cb] = *(const u32x4*)(&ldsB[s][(wn * C::WTN + cb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) Mma<T>::run(af[rb], bf[cb], acc[rb][cb]);
+        for (int cb = 0; cb < CB; ++cb) Mma<T>::run(af[rb], bf[cb], acc[rb][cb]);
     }
     if (more) {
 #pragma unroll
-      for (int u = 0; u < LOADS; ++u) {
-        *(u32x4*)(&lds[s ^ 1][0][sofs + u * RSTEP * LDS_RS]) = ga[u];
-        *(u32x4*)(&lds[s ^ 1][1][sofs + u * RSTEP * LDS_RS]) = gb[u];
-      }
+      for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[s ^ 1][sofs + u * RSTEP * LDS_RS]) = ga[u];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) *(u32x4*)(&ldsB[s ^ 1][sofs + u * RSTEP * LDS_RS]) = gb[u];
     }
     __syncthreads();
   }
 
   // ---------------------------------------------------------------- epilogues
-  // acc[rb][cb][e] is C[row0 + wm*32 + rb*16 + Mma<T>::row(g, e)][col0 + wn*32 + cb*16 + r16]
+  // acc[rb][cb][e] is C[row0 + wm*WTM + rb*16 + Mma<T>::row(g, e)][col0 + wn*WTN + cb*16 + r16]
   const int n = p.n, np = p.np;
   if constexpr (EPI == EPI_RAW) {
     zt* out = (zt*)p.out + (size_t)bz * p.sOut;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
-          const int j = col0 + wn * 32 + cb * 16 + r16;
+          const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
+          const int j = col0 + wn * C::WTN + cb * 16 + r16;
           if (i < n && j < n) out[(size_t)i * np + j] = (zt)acc[rb][cb][e];
         }
   } else if constexpr (EPI == EPI_LOGROW) {
     zt* out = (zt*)p.out + (size_t)bz * p.sOut;
     const double* mrow = p.mrow + (size_t)bz * np;
-    double cm[2] = {-INFINITY, -INFINITY};
+    double cm[CB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int cb = 0; cb < CB; ++cb) cm[cb] = -INFINITY;
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
-          const int j = col0 + wn * 32 + cb * 16 + r16;
+          const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
+          const int j = col0 + wn * C::WTN + cb * 16 + r16;
           if (i < n && j < n) {
             const zt z = log((zt)acc[rb][cb][e]);
             out[(size_t)i * np + j] = z;
@@ -345,14 +360,16 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
           }
         }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
       cm[cb] = fmax(cm[cb], __shfl_xor(cm[cb], 16, 64));
       cm[cb] = fmax(cm[cb], __shfl_xor(cm[cb], 32, 64));
-      if (g == 0) cmax[wm][wn * 32 + cb * 16 + r16] = (float)cm[cb];
+      if (g == 0) cmax[wm][wn * C::WTN + cb * 16 + r16] = (float)cm[cb];
     }
     __syncthreads();
-    if (tid < TILE) {
-      const float m = fmaxf(cmax[0][tid], cmax[1][tid]);
+    if (tid < BN) {
+      float m = cmax[0][tid];
+#pragma unroll
+      for (int w = 1; w < C::WGM; ++w) m = fmaxf(m, cmax[w][tid]);
       const int j = col0 + tid;
       if (j < n && m > -INFINITY) atomicMax(p.colkey + (size_t)bz * np + j, float_key(m));
     }
@@ -363,24 +380,19 @@ __global__ __launch_bounds__(NTHREADS) void k_gemm(const GemmArgs p) {
     const unsigned* ck = p.colkey + (size_t)bz * np;
     double err = 0.0;
     int bad = 0;
-    double shift[2];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int j = col0 + wn * 32 + cb * 16 + r16;
-      shift[cb] = (j < n) ? key_to_shift(ck[j]) : 0.0;
-    }
+    for (int cb = 0; cb < CB; ++cb) {
+      const int j = col0 + wn * C::WTN + cb * 16 + r16;
+      const double shift = (j < n) ? key_to_shift(ck[j]) : 0.0;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int j = col0 + wn * 32 + cb * 16 + r16;
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * 32 + rb * 16 + Mma<T>::row(g, e);
+          const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           if (i < n && j < n) {
             const size_t o = (size_t)i * np + j;
             // ln S in the accumulator's precision, shifted in FP64
-            const double lnS = shift[cb] + (double)log(acc[rb][cb][e]);
+            const double lnS = shift + (double)log(acc[rb][cb][e]);
             const double la = la_v[cb][rb][e];
             const double fold = fo_v[cb][rb][e];
             double fnew;
