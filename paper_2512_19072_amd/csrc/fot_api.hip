@@ -54,12 +54,24 @@ struct fot_plan_s {
   unsigned* colkey = nullptr;
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
-  void *lam = nullptr, *lamH = nullptr, *opA = nullptr, *opA2 = nullptr;
-  void *opB = nullptr, *opBx = nullptr, *opBy = nullptr, *opBc = nullptr;
-  void *Z = nullptr, *Zy = nullptr, *Zc = nullptr;
-  void *S = nullptr, *Sx = nullptr, *Sy = nullptr, *Scx = nullptr, *Scy = nullptr;
+  void *lam = nullptr, *opA = nullptr, *opB = nullptr, *Z = nullptr;
   double* tape = nullptr;
   int n_ckpt = 0;
+  // reverse mode (allocated when checkpoint_every > 0)
+  double *fbar = nullptr, *psibar = nullptr, *psibar2 = nullptr, *psiprev = nullptr, *lbbar = nullptr;
+  double *Tbx = nullptr, *Tby = nullptr, *wtmp = nullptr, *cbar = nullptr, *rsum_tmp = nullptr;
+  double *gsums = nullptr, *dd_dev = nullptr, *hist_scratch = nullptr;
+  double *seg_f = nullptr, *seg_psi = nullptr, *seg_lnS = nullptr, *seg_lnSp = nullptr;
+  // The phase read-out and the reverse-sweep contractions run with FP64 operands in every
+  // precision (once per solve; their signed sums cancel too strongly for FP32).  For FP64 plans
+  // these alias the loop's buffers, otherwise they are separate.
+  double *flam = nullptr, *flamH = nullptr, *fA = nullptr, *fA2 = nullptr, *fB = nullptr, *fBx = nullptr;
+  double *fBy = nullptr, *fBc = nullptr, *fZ = nullptr, *fZy = nullptr, *fZc = nullptr, *fS = nullptr;
+  double *fSx = nullptr, *fSy = nullptr, *fScx = nullptr, *fScy = nullptr;
+  double flam_eps_sep = -1.0;
+  bool flamH_valid_sep = false;
+  double* flam_eps = nullptr;   // -> lam_eps (FP64 plans) or flam_eps_sep
+  bool* flamH_valid = nullptr;  // -> lamH_valid or flamH_valid_sep
   double lam_eps = -1.0;
   double* pending_hist = nullptr;   // marginal-error sum still to be finished by the next row-exp
   bool lamH_valid = false;
@@ -134,6 +146,11 @@ PendingSum take_pending(fot_plan_s* p) {
   return ps;
 }
 
+fot_status rev_lambda(fot_plan_s* p, double eps);
+fot_status rev_contract(fot_plan_s* p, const double* v, const double* L);
+fot_status rev_axpy(fot_plan_s* p, const double* P, double eps, const double* lnm, long long sMarg, double scale,
+                    int row_coord, int col_coord, int acc, double* out);
+
 template <typename T>
 struct Ops {
   typedef typename Mma<T>::out_t zt;
@@ -178,14 +195,14 @@ struct Ops {
     return a;
   }
 
-  static fot_status fill_lambda(fot_plan_s* p, double eps, bool withH) {
+  static fot_status fill_lambda(fot_plan_s* p, double eps, bool /*unused*/) {
     const size_t total = p->plane;
     const int blocks = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(k_fill_lambda<T>, dim3(blocks), dim3(256), 0, p->stream, (T*)p->lam,
-                       withH ? (T*)p->lamH : (T*)nullptr, p->n, p->np, 1.0 / eps);
+    hipLaunchKernelGGL(k_fill_lambda<T>, dim3(blocks), dim3(256), 0, p->stream, (T*)p->lam, (T*)nullptr, p->n,
+                       p->np, 1.0 / eps);
     LAUNCH_CHECK();
     p->lam_eps = eps;
-    p->lamH_valid = withH;
+    p->lamH_valid = false;
     return FOT_OK;
   }
 
@@ -292,65 +309,222 @@ struct Ops {
     return FOT_OK;
   }
 
-  // Phase read-out (Eq. 9-10), final marginals, dual value and transport cost.
-  static fot_status readout(fot_plan_s* p, double eps, double* phase_out) {
+  // ---------------------------------------------------------------- reverse mode
+  static fot_status ensure_lambda(fot_plan_s* p, double eps) {
+    if (p->lam_eps != eps) return fill_lambda(p, eps, false);
+    return FOT_OK;
+  }
+
+  static fot_status backward(fot_plan_s* p, const double* dphi, double* dG) {
     const long long plane = (long long)p->plane;
+    const size_t BP = (size_t)p->B * p->plane;
+    const int T_ = p->last_iters, k = p->d.checkpoint_every, B = p->B, n = p->n, np = p->np;
+    const std::vector<double>& e = p->last_eps;
+    const int nseg = (T_ + k - 1) / k;
     fot_status s;
-    if (p->lam_eps != eps || !p->lamH_valid) {
-      s = fill_lambda(p, eps, true);
-      if (s != FOT_OK) return s;
-    }
-    hipLaunchKernelGGL(k_rowexp<T>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np, 1.0 / eps,
-                       p->mrow, (T*)p->opA, (T*)p->opA2, p->colkey, take_pending(p));
+    const dim3 eg(256, B);
+    auto contract = [&](const double* v, const double* L, double eps) -> fot_status {
+      fot_status r = rev_lambda(p, eps);
+      return r != FOT_OK ? r : rev_contract(p, v, L);
+    };
+    auto axpy = [&](const double* P, double eps, const double* lnm, long long sMarg, double scale, int rc, int cc,
+                    int acc, double* out) { return rev_axpy(p, P, eps, lnm, sMarg, scale, rc, cc, acc, out); };
+    // seeds: fbar = dD a (the final u-update's f enters D as <f,a>), psibar = dD b
+    hipLaunchKernelGGL(k_seed, dim3(256, B), dim3(256), 0, p->stream, p->dd_dev, p->lna, 0LL, n, np, p->fbar);
+    hipLaunchKernelGGL(k_seed, dim3(256, B), dim3(256), 0, p->stream, p->dd_dev, p->lnb, plane, n, np, p->psibar);
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, p->stream, p->lbbar, BP, 0.0);
     LAUNCH_CHECK();
-    GemmArgs g1 = base_args(p, p->opA, plane, p->lam, 0);
-    g1.out = p->Z;
-    g1.sOut = plane;
-    g1.mrow = p->mrow;
-    g1.colkey = p->colkey;
-    if ((s = gemm_launch(p, EPI_LOGROW, g1)) != FOT_OK) return s;
-    GemmArgs gy = base_args(p, p->opA2, plane, p->lam, 0);
-    gy.out = p->Zy;
-    gy.sOut = plane;
-    if ((s = gemm_launch(p, EPI_RAW, gy)) != FOT_OK) return s;
-    GemmArgs gc = base_args(p, p->opA, plane, p->lamH, 0);
-    gc.out = p->Zc;
-    gc.sOut = plane;
-    if ((s = gemm_launch(p, EPI_RAW, gc)) != FOT_OK) return s;
-    dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
-    hipLaunchKernelGGL((k_colexpT<T, zt, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Z, p->mrow,
-                       p->colkey, p->n, p->np, (T*)p->opB);
-    hipLaunchKernelGGL((k_colexpT<T, zt, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Z, p->mrow,
-                       p->colkey, p->n, p->np, (T*)p->opBx);
-    hipLaunchKernelGGL((k_colexpT<T, zt, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Zy, p->mrow,
-                       p->colkey, p->n, p->np, (T*)p->opBy);
-    hipLaunchKernelGGL((k_colexpT<T, zt, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Zc, p->mrow,
-                       p->colkey, p->n, p->np, (T*)p->opBc);
-    LAUNCH_CHECK();
-    struct Job { const void* A; const void* Bm; void* out; } jobs[5] = {
-        {p->lam, p->opB, p->S}, {p->lam, p->opBx, p->Sx}, {p->lam, p->opBy, p->Sy},
-        {p->lamH, p->opB, p->Scx}, {p->lam, p->opBc, p->Scy}};
-    for (auto& j : jobs) {
-      GemmArgs g = base_args(p, j.A, 0, j.Bm, plane);
-      g.out = j.out;
-      g.sOut = plane;
-      if ((s = gemm_launch(p, EPI_RAW, g)) != FOT_OK) return s;
+    if (dphi) {  // transpose of the integration: dL/dphi -> (dL/dTx, dL/dTy)
+      hipLaunchKernelGGL(k_rowsum_dense, dim3(n, B), dim3(NTHREADS), 0, p->stream, dphi, n, p->rsum_tmp);
+      hipLaunchKernelGGL(k_int_adj_rows, dim3(n, B), dim3(NTHREADS), 0, p->stream, dphi, p->rsum_tmp, p->lna, n,
+                         np, p->Tby, p->cbar, p->Tbx);
+      hipLaunchKernelGGL(k_int_adj_col, dim3(B), dim3(64), 0, p->stream, p->cbar, n, np, p->Tbx);
+      LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL((k_readout<zt>), dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream,
-                       (const zt*)p->S, (const zt*)p->Sx, (const zt*)p->Sy, (const zt*)p->Scx, (const zt*)p->Scy,
-                       p->colkey, p->lnS, p->lna, p->lnb, p->f, p->psi, p->lnSp, p->n, p->np, eps, p->Tx, p->Ty,
-                       p->rparts);
-    hipLaunchKernelGGL(k_sum_parts, dim3(5, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS,
-                       p->rsums);
-    hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->Tx, p->Ty, p->lna, p->n,
-                       p->np, p->phi, p->rowpart);
-    if (phase_out)
-      hipLaunchKernelGGL(k_center, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->phi, p->rowpart, p->n,
-                         p->np, phase_out);
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int t0 = sg * k, t1 = std::min(T_, t0 + k);
+      const double* tape_in = p->tape + (size_t)sg * BP;
+      // replay the segment from its checkpoint (bit-identical to the forward solve)
+      const double* pin = tape_in;
+      for (int i = t0; i < t1; ++i) {
+        const int q = i - t0;
+        if ((s = ensure_lambda(p, e[i])) != FOT_OK) return s;
+        if ((s = half(p, pin, p->seg_f + q * BP, p->lna, 0, p->hist_scratch, p->seg_lnS + q * BP, e[i])) != FOT_OK)
+          return s;
+        if ((s = half(p, p->seg_f + q * BP, p->seg_psi + q * BP, p->lnb, plane, p->hist_scratch + B,
+                      p->seg_lnSp + q * BP, e[i])) != FOT_OK)
+          return s;
+        pin = p->seg_psi + q * BP;
+      }
+      p->pending_hist = nullptr;
+      auto psi_in = [&](int i) -> const double* { return i > t0 ? p->seg_psi + (size_t)(i - 1 - t0) * BP : tape_in; };
+      bool have_prev = false;
+      if (sg == nseg - 1 && dphi) {
+        // phase: Tx = Sx(V_T)/S(V_{T-1}) and Ty likewise (Eq. 9-10)
+        const int i = T_ - 1, q = i - t0;
+        const double ep = e[i];
+        if ((s = ensure_lambda(p, ep)) != FOT_OK) return s;
+        const double* lnSl = p->seg_lnS + (size_t)q * BP;
+        const double* psiT = p->seg_psi + (size_t)q * BP;
+        // psibar_T += (V_T / eps) [X K(Tbx / S) + Y K(Tby / S)]
+        if ((s = contract(p->Tbx, lnSl, ep)) != FOT_OK) return s;
+        if ((s = axpy(psiT, ep, p->lnb, plane, 1.0 / ep, 1, 0, 1, p->psibar)) != FOT_OK) return s;
+        if ((s = contract(p->Tby, lnSl, ep)) != FOT_OK) return s;
+        if ((s = axpy(psiT, ep, p->lnb, plane, 1.0 / ep, 0, 1, 1, p->psibar)) != FOT_OK) return s;
+        // psibar_{T-1} += -(V_{T-1} / eps) K((Tbx Tx + Tby Ty) / S)
+        hipLaunchKernelGGL(k_moment_weight, eg, dim3(256), 0, p->stream, p->Tbx, p->Tx, p->Tby, p->Ty, n, np,
+                           p->wtmp);
+        LAUNCH_CHECK();
+        if ((s = contract(p->wtmp, lnSl, ep)) != FOT_OK) return s;
+        if ((s = axpy(psi_in(i), ep, p->lnb, plane, -1.0 / ep, 0, 0, 0, p->psiprev)) != FOT_OK) return s;
+        have_prev = true;
+      }
+      for (int i = t1 - 1; i >= t0; --i) {
+        const int q = i - t0;
+        const double ep = e[i];
+        if ((s = ensure_lambda(p, ep)) != FOT_OK) return s;
+        // V-update psi_i = eps (ln b - ln S'(f_i)):  lbbar += eps psibar;  fbar += -u_i K(psibar / S')
+        hipLaunchKernelGGL(k_axpy_masked, eg, dim3(256), 0, p->stream, p->psibar, p->lnb, n, np, ep, p->lbbar);
+        LAUNCH_CHECK();
+        if ((s = contract(p->psibar, p->seg_lnSp + (size_t)q * BP, ep)) != FOT_OK) return s;
+        if ((s = axpy(p->seg_f + (size_t)q * BP, ep, p->lna, 0, -1.0, 0, 0, i == T_ - 1 ? 1 : 0, p->fbar)) != FOT_OK)
+          return s;
+        // u-update f_i = eps (ln a - ln S(psi_{i-1})):  psibar_{i-1} = -V_{i-1} K(fbar / S)
+        if (i > 0) {
+          if ((s = contract(p->fbar, p->seg_lnS + (size_t)q * BP, ep)) != FOT_OK) return s;
+          double* dst = p->psibar2;
+          if (i == T_ - 1 && have_prev) {
+            if ((s = axpy(psi_in(i), ep, p->lnb, plane, -1.0, 0, 0, 1, p->psiprev)) != FOT_OK) return s;
+            dst = p->psiprev;
+            p->psiprev = p->psibar;
+            p->psibar = dst;
+          } else {
+            if ((s = axpy(psi_in(i), ep, p->lnb, plane, -1.0, 0, 0, 0, dst)) != FOT_OK) return s;
+            p->psibar2 = p->psibar;
+            p->psibar = dst;
+          }
+        }
+      }
+    }
+    // normalisation Jacobian: dL/dG from lbbar and the explicit dD <psi_T, b> term
+    hipLaunchKernelGGL(k_grad_sums, dim3(B), dim3(NTHREADS), 0, p->stream, p->lbbar, p->psi, p->lnb, p->dd_dev, n,
+                       np, p->gsums);
+    hipLaunchKernelGGL(k_grad_final, dim3(256, B), dim3(256), 0, p->stream, p->rowsum_G, p->lbbar, p->psi, p->lnb,
+                       p->dd_dev, p->gsums, n, np, dG);
     LAUNCH_CHECK();
     return FOT_OK;
   }
+
 };
+
+// ------------------------------------------------------------------ FP64 read-out and reverse sweep
+// Lambda (and Lambda o H) with FP64 elements for the read-out and the reverse sweep.
+fot_status fill64(fot_plan_s* p, double eps, bool withH) {
+  if (*p->flam_eps == eps && (!withH || *p->flamH_valid)) return FOT_OK;
+  hipLaunchKernelGGL(k_fill_lambda<double>, dim3((unsigned)((p->plane + 255) / 256)), dim3(256), 0, p->stream,
+                     p->flam, withH ? p->flamH : (double*)nullptr, p->n, p->np, 1.0 / eps);
+  LAUNCH_CHECK();
+  *p->flam_eps = eps;
+  *p->flamH_valid = withH;
+  return FOT_OK;
+}
+
+fot_status rev_lambda(fot_plan_s* p, double eps) { return fill64(p, eps, false); }
+
+// Signed contraction K(w), w = v e^{-L}, with FP64 operands and accumulation: the sums of the
+// reverse sweep cancel strongly.  Leaves the pass-2 output (divided by e^{m'_k}) in p->fS and
+// the column shifts in p->colkey.
+fot_status rev_contract(fot_plan_s* p, const double* v, const double* L) {
+  typedef Ops<double> R;
+  const long long plane = (long long)p->plane;
+  fot_status s;
+  hipLaunchKernelGGL(k_rowexp_signed<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, v, L, p->n, p->np,
+                     p->mrow, p->fA, p->fA2, p->colkey);
+  LAUNCH_CHECK();
+  GemmArgs gs = R::base_args(p, p->fA, plane, p->flam, 0);
+  gs.out = p->fZy;
+  gs.sOut = plane;
+  if ((s = R::gemm_launch(p, EPI_RAW, gs)) != FOT_OK) return s;
+  GemmArgs ga = R::base_args(p, p->fA2, plane, p->flam, 0);
+  ga.out = p->fZ;
+  ga.sOut = plane;
+  ga.mrow = p->mrow;
+  ga.colkey = p->colkey;
+  if ((s = R::gemm_launch(p, EPI_LOGROW, ga)) != FOT_OK) return s;
+  dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
+  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZy,
+                     p->mrow, p->colkey, p->n, p->np, p->fB);
+  LAUNCH_CHECK();
+  GemmArgs g2 = R::base_args(p, p->flam, 0, p->fB, plane);
+  g2.out = p->fS;
+  g2.sOut = plane;
+  return R::gemm_launch(p, EPI_RAW, g2);
+}
+
+// out (masked by lnm) = [acc ? out : 0] + scale * coords * e^{P/eps} * K(w), K(w) from rev_contract.
+fot_status rev_axpy(fot_plan_s* p, const double* P, double eps, const double* lnm, long long sMarg, double scale,
+                    int row_coord, int col_coord, int acc, double* out) {
+  hipLaunchKernelGGL((k_adj_axpy<double>), dim3(256, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->fS,
+                     p->colkey, P, 1.0 / eps, lnm, sMarg, p->n, p->np, scale, row_coord, col_coord, acc, out);
+  LAUNCH_CHECK();
+  return FOT_OK;
+}
+
+// Phase read-out (Eq. 9-10), final marginals, dual value and transport cost, with FP64 operands.
+fot_status readout64(fot_plan_s* p, double eps, double* phase_out) {
+  typedef Ops<double> R;
+  const long long plane = (long long)p->plane;
+  fot_status s;
+  if ((s = fill64(p, eps, true)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np,
+                     1.0 / eps, p->mrow, p->fA, p->fA2, p->colkey, take_pending(p));
+  LAUNCH_CHECK();
+  GemmArgs g1 = R::base_args(p, p->fA, plane, p->flam, 0);
+  g1.out = p->fZ;
+  g1.sOut = plane;
+  g1.mrow = p->mrow;
+  g1.colkey = p->colkey;
+  if ((s = R::gemm_launch(p, EPI_LOGROW, g1)) != FOT_OK) return s;
+  GemmArgs gy = R::base_args(p, p->fA2, plane, p->flam, 0);
+  gy.out = p->fZy;
+  gy.sOut = plane;
+  if ((s = R::gemm_launch(p, EPI_RAW, gy)) != FOT_OK) return s;
+  GemmArgs gc = R::base_args(p, p->fA, plane, p->flamH, 0);
+  gc.out = p->fZc;
+  gc.sOut = plane;
+  if ((s = R::gemm_launch(p, EPI_RAW, gc)) != FOT_OK) return s;
+  dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
+  hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
+                     p->mrow, p->colkey, p->n, p->np, p->fB);
+  hipLaunchKernelGGL((k_colexpT<double, double, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
+                     p->mrow, p->colkey, p->n, p->np, p->fBx);
+  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZy,
+                     p->mrow, p->colkey, p->n, p->np, p->fBy);
+  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZc,
+                     p->mrow, p->colkey, p->n, p->np, p->fBc);
+  LAUNCH_CHECK();
+  struct Job { const void* A; const void* Bm; void* out; } jobs[5] = {
+      {p->flam, p->fB, p->fS}, {p->flam, p->fBx, p->fSx}, {p->flam, p->fBy, p->fSy},
+      {p->flamH, p->fB, p->fScx}, {p->flam, p->fBc, p->fScy}};
+  for (auto& j : jobs) {
+    GemmArgs g = R::base_args(p, j.A, 0, j.Bm, plane);
+    g.out = j.out;
+    g.sOut = plane;
+    if ((s = R::gemm_launch(p, EPI_RAW, g)) != FOT_OK) return s;
+  }
+  hipLaunchKernelGGL((k_readout<double>), dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream,
+                     (const double*)p->fS, (const double*)p->fSx, (const double*)p->fSy, (const double*)p->fScx,
+                     (const double*)p->fScy, p->colkey, p->lnS, p->lna, p->lnb, p->f, p->psi, p->lnSp, p->n, p->np,
+                     eps, p->Tx, p->Ty, p->rparts);
+  hipLaunchKernelGGL(k_sum_parts, dim3(5, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS, p->rsums);
+  hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->Tx, p->Ty, p->lna, p->n, p->np,
+                     p->phi, p->rowpart);
+  if (phase_out)
+    hipLaunchKernelGGL(k_center, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->phi, p->rowpart, p->n, p->np,
+                       phase_out);
+  LAUNCH_CHECK();
+  return FOT_OK;
+}
 
 template <typename F>
 fot_status dispatch(int prec, F&& fn) {
@@ -432,24 +606,57 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   ALLOC(p->colkey, (size_t)p->B * p->np);
   ALLOC(p->flag, (size_t)1);
   ALLOCV(p->lam, p->plane * p->esz);
-  ALLOCV(p->lamH, p->plane * p->esz);
   ALLOCV(p->opA, BP * p->esz);
-  ALLOCV(p->opA2, BP * p->esz);
   ALLOCV(p->opB, BP * p->esz);
-  ALLOCV(p->opBx, BP * p->esz);
-  ALLOCV(p->opBy, BP * p->esz);
-  ALLOCV(p->opBc, BP * p->esz);
   ALLOCV(p->Z, BP * p->zsz);
-  ALLOCV(p->Zy, BP * p->zsz);
-  ALLOCV(p->Zc, BP * p->zsz);
-  ALLOCV(p->S, BP * p->zsz);
-  ALLOCV(p->Sx, BP * p->zsz);
-  ALLOCV(p->Sy, BP * p->zsz);
-  ALLOCV(p->Scx, BP * p->zsz);
-  ALLOCV(p->Scy, BP * p->zsz);
+  if (d.precision == FOT_F64) {
+    p->flam = (double*)p->lam;
+    p->fA = (double*)p->opA;
+    p->fB = (double*)p->opB;
+    p->fZ = (double*)p->Z;
+    p->flam_eps = &p->lam_eps;
+    p->flamH_valid = &p->lamH_valid;
+  } else {
+    ALLOC(p->flam, p->plane);
+    ALLOC(p->fA, BP);
+    ALLOC(p->fB, BP);
+    ALLOC(p->fZ, BP);
+    p->flam_eps = &p->flam_eps_sep;
+    p->flamH_valid = &p->flamH_valid_sep;
+  }
+  ALLOC(p->flamH, p->plane);
+  ALLOC(p->fA2, BP);
+  ALLOC(p->fBx, BP);
+  ALLOC(p->fBy, BP);
+  ALLOC(p->fBc, BP);
+  ALLOC(p->fZy, BP);
+  ALLOC(p->fZc, BP);
+  ALLOC(p->fS, BP);
+  ALLOC(p->fSx, BP);
+  ALLOC(p->fSy, BP);
+  ALLOC(p->fScx, BP);
+  ALLOC(p->fScy, BP);
   if (d.checkpoint_every > 0) {
     p->n_ckpt = (d.max_iters + d.checkpoint_every - 1) / d.checkpoint_every;
+    const size_t kseg = (size_t)std::min(d.checkpoint_every, d.max_iters);
     ALLOC(p->tape, (size_t)p->n_ckpt * BP);
+    ALLOC(p->fbar, BP);
+    ALLOC(p->psibar, BP);
+    ALLOC(p->psibar2, BP);
+    ALLOC(p->psiprev, BP);
+    ALLOC(p->lbbar, BP);
+    ALLOC(p->Tbx, BP);
+    ALLOC(p->Tby, BP);
+    ALLOC(p->wtmp, BP);
+    ALLOC(p->cbar, (size_t)p->B * p->n);
+    ALLOC(p->rsum_tmp, (size_t)p->B * p->n);
+    ALLOC(p->gsums, (size_t)2 * p->B);
+    ALLOC(p->dd_dev, (size_t)p->B);
+    ALLOC(p->hist_scratch, (size_t)2 * p->B);
+    ALLOC(p->seg_f, kseg * BP);
+    ALLOC(p->seg_psi, kseg * BP);
+    ALLOC(p->seg_lnS, kseg * BP);
+    ALLOC(p->seg_lnSp, kseg * BP);
   }
 #undef ALLOC
 #undef ALLOCV
@@ -565,7 +772,7 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     fot_status s0 = graph ? Ops<T>::loop_graph(p, e, iters) : Ops<T>::loop(p, e, iters);
     if (s0 != FOT_OK) return s0;
     HIP_TRY(hipEventRecord(p->ev[2], p->stream));
-    fot_status s = Ops<T>::readout(p, e[iters - 1], phase_out);
+    fot_status s = readout64(p, e[iters - 1], phase_out);
     if (s != FOT_OK) return s;
     HIP_TRY(hipEventRecord(p->ev[3], p->stream));
     return FOT_OK;
@@ -619,11 +826,28 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
 
 fot_status fot_backward(fot_plan_t p, const double* dL_dDual, const double* dL_dphase, double* dL_dG) {
   g_err.clear();
-  (void)dL_dDual;
-  (void)dL_dphase;
-  (void)dL_dG;
   if (!p) return fail(FOT_E_INVALID, "fot_backward: null plan");
-  return fail(FOT_E_UNSUPPORTED, "fot_backward: not available yet");
+  if (!dL_dG) return fail(FOT_E_INVALID, "fot_backward: null output");
+  if (!p->tape) return fail(FOT_E_STATE, "fot_backward: the plan has no tape (checkpoint_every = 0)");
+  if (!p->tape_valid) return fail(FOT_E_STATE, "fot_backward: no taped solve to differentiate");
+  std::vector<double> dd((size_t)p->B, 0.0);
+  if (dL_dDual)
+    for (int b = 0; b < p->B; ++b) {
+      if (!std::isfinite(dL_dDual[b])) return fail(FOT_E_INVALID, "fot_backward: dL/dD must be finite");
+      dd[b] = dL_dDual[b];
+    }
+  HIP_TRY(hipMemcpyAsync(p->dd_dev, dd.data(), sizeof(double) * p->B, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
+  fot_status st = dispatch(p->prec, [&](auto tag) -> fot_status {
+    typedef decltype(tag) T;
+    return Ops<T>::backward(p, dL_dphase, dL_dG);
+  });
+  if (st != FOT_OK) return st;
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_backward: a replayed potential became non-finite");
+  return FOT_OK;
 }
 
 }  // extern "C"

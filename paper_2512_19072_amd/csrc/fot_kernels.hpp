@@ -259,6 +259,14 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int j = 0; j < CB; ++j) acc[i][j] = acc_t{};
+  // FP32 accumulators are flushed into FP64 running sums after every K stage, so rounding
+  // grows with the 64-128 products of one stage rather than with the whole K extent.
+  constexpr bool FLUSH = sizeof(typename Mma<T>::out_t) == 4;
+  f64x4 accd[RB][CB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) accd[i][j] = f64x4{};
 
   // EPI_UPDATE reads ln(marginal) and the old potential of its outputs; the loads are
   // issued here so that their latency is hidden behind the K loop.
@@ -315,6 +323,16 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) Mma<T>::run(af[rb], bf[cb], acc[rb][cb]);
     }
+    if constexpr (FLUSH) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) accd[rb][cb][e] += (double)acc[rb][cb][e];
+          acc[rb][cb] = acc_t{};
+        }
+    }
     if (more) {
 #pragma unroll
       for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[s ^ 1][sofs + u * RSTEP * LDS_RS]) = ga[u];
@@ -325,7 +343,25 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   }
 
   // ---------------------------------------------------------------- epilogues
-  // acc[rb][cb][e] is C[row0 + wm*WTM + rb*16 + Mma<T>::row(g, e)][col0 + wn*WTN + cb*16 + r16]
+  // result(rb, cb, e) is C[row0 + wm*WTM + rb*16 + Mma<T>::row(g, e)][col0 + wn*WTN + cb*16 + r16]
+  auto result = [&](int rb, int cb, int e) -> double {
+    if constexpr (FLUSH)
+      return accd[rb][cb][e];
+    else
+      return (double)acc[rb][cb][e];
+  };
+  // ln of a result.  The pass-1 output is stored in FP32 anyway, so logf of the once-rounded
+  // sum suffices there; the potential update takes an FP64 log for FP32 and FP64 operands (the
+  // rounding of logf is correlated enough to be amplified through the iterations and their
+  // adjoint) and logf for 16-bit operands, whose own rounding is far larger.
+  auto log_result = [&](int rb, int cb, int e, bool fine) -> double {
+    if constexpr (FLUSH) {
+      if (fine && sizeof(T) == 4) return log(accd[rb][cb][e]);
+      return (double)logf((float)accd[rb][cb][e]);
+    } else {
+      return log((double)acc[rb][cb][e]);
+    }
+  };
   const int n = p.n, np = p.np;
   if constexpr (EPI == EPI_RAW) {
     zt* out = (zt*)p.out + (size_t)bz * p.sOut;
@@ -337,7 +373,7 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
         for (int e = 0; e < 4; ++e) {
           const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int j = col0 + wn * C::WTN + cb * 16 + r16;
-          if (i < n && j < n) out[(size_t)i * np + j] = (zt)acc[rb][cb][e];
+          if (i < n && j < n) out[(size_t)i * np + j] = (zt)result(rb, cb, e);
         }
   } else if constexpr (EPI == EPI_LOGROW) {
     zt* out = (zt*)p.out + (size_t)bz * p.sOut;
@@ -354,7 +390,7 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
           const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int j = col0 + wn * C::WTN + cb * 16 + r16;
           if (i < n && j < n) {
-            const zt z = log((zt)acc[rb][cb][e]);
+            const zt z = (zt)log_result(rb, cb, e, false);
             out[(size_t)i * np + j] = z;
             cm[cb] = fmax(cm[cb], mrow[i] + (double)z);
           }
@@ -391,8 +427,8 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
           const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           if (i < n && j < n) {
             const size_t o = (size_t)i * np + j;
-            // ln S in the accumulator's precision, shifted in FP64
-            const double lnS = shift + (double)log(acc[rb][cb][e]);
+            // ln S, shifted in FP64
+            const double lnS = shift + log_result(rb, cb, e, true);
             const double la = la_v[cb][rb][e];
             const double fold = fo_v[cb][rb][e];
             double fnew;
@@ -719,6 +755,269 @@ __global__ __launch_bounds__(NTHREADS) void k_center(const double* phi, const do
   const double* ph = phi + (size_t)bz * np * np + (size_t)j * np;
   double* o = out + ((size_t)bz * n + j) * n;
   for (int k = threadIdx.x; k < n; k += blockDim.x) o[k] = ph[k] - mean;
+}
+
+// ------------------------------------------------------------------ reverse mode
+// Every reverse half-step is one signed separable contraction
+//   out_x = c_x * e^{P_x/eps} * sum_y K_xy v_y e^{-L_y}
+// (K = Lambda (x) Lambda).  With h_y = ln|v_y| - L_y and the row shift m_r = max_row h, the
+// pass-1 operands are sign(v) e^{h - m_r} (signed) and e^{h - m_r} (magnitude); the magnitude
+// product supplies the column shifts for pass 2, so every intermediate is bounded by 1 times
+// the row/column scale and the signed sums cannot overflow.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_rowexp_signed(const double* v, const double* L, int n, int np,
+                                                            double* mrow, T* out_signed, T* out_abs,
+                                                            unsigned* colkey) {
+  constexpr int MAXV = 32;
+  __shared__ double red[4];
+  const int i = blockIdx.x, bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  T* os = out_signed + bz * plane + (size_t)i * np;
+  T* oa = out_abs + bz * plane + (size_t)i * np;
+  if (threadIdx.x == 0) colkey[(size_t)bz * np + i] = 0u;
+  if (i >= n) {
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      os[k] = (T)0;
+      oa[k] = (T)0;
+    }
+    if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = 0.0;
+    return;
+  }
+  const double* vr = v + bz * plane + (size_t)i * np;
+  const double* lr = L + bz * plane + (size_t)i * np;
+  const int cnt = (n + NTHREADS - 1) / NTHREADS;
+  double h[MAXV];
+  bool neg[MAXV];
+  double m = -INFINITY;
+#pragma unroll
+  for (int c = 0; c < MAXV; ++c) {
+    if (c < cnt) {
+      const int k = threadIdx.x + c * NTHREADS;
+      double hv = -INFINITY;
+      bool ng = false;
+      if (k < n) {
+        const double vv = vr[k];
+        ng = vv < 0.0;
+        if (vv != 0.0) hv = log(fabs(vv)) - lr[k];
+      }
+      h[c] = hv;
+      neg[c] = ng;
+      m = fmax(m, hv);
+    }
+  }
+  m = block_max(m, red);
+  if (!(m > -INFINITY && m < INFINITY)) m = 0.0;
+  if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = m;
+#pragma unroll
+  for (int c = 0; c < MAXV; ++c) {
+    if (c < cnt) {
+      const int k = threadIdx.x + c * NTHREADS;
+      if (k < np) {
+        const bool ok = k < n;
+        oa[k] = ok ? exp_op<T>(h[c] - m) : (T)0;
+        os[k] = ok ? signed_exp_op<T>(h[c] - m, neg[c]) : (T)0;
+      }
+    }
+  }
+}
+
+// out = (mask ? (acc ? out : 0) + scale * wr_x * wc_x * sign(S) e^{P/eps + m'_k + ln|S|} : 0)
+// where S is the pass-2 output of a signed contraction (divided by e^{m'_k}), the mask is
+// ln(marginal) > -inf, and wr / wc are optional row / column coordinates (Eq. 9-10 moments).
+template <typename ZT>
+__global__ __launch_bounds__(NTHREADS) void k_adj_axpy(const ZT* S, const unsigned* colkey, const double* P,
+                                                       double inv_eps, const double* lnm, long long sMarg,
+                                                       int n, int np, double scale, int row_coord, int col_coord,
+                                                       int accumulate, double* out) {
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  const double csc = 1.0 / sqrt((double)n);
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / n), k = (int)(idx % n);
+    const size_t o = bz * plane + (size_t)j * np + k;
+    double val = 0.0;
+    if (lnm[bz * sMarg + (size_t)j * np + k] > -INFINITY) {
+      const double s = (double)S[o];
+      double w = scale;
+      if (row_coord) w *= (double)(j - n / 2) * csc;
+      if (col_coord) w *= (double)(k - n / 2) * csc;
+      if (s != 0.0 && w != 0.0) {
+        const double mag = exp(P[o] * inv_eps + key_to_shift(colkey[(size_t)bz * np + k]) + log(fabs(s)));
+        val = ((s < 0.0) != (w < 0.0) ? -mag : mag) * fabs(w);
+      }
+      if (accumulate) val += out[o];
+    }
+    out[o] = val;
+  }
+}
+
+// acc += eps * v where the mask ln(marginal) > -inf holds (reverse of psi = eps ln b - ...).
+__global__ void k_axpy_masked(const double* v, const double* lnm, int n, int np, double eps, double* acc) {
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t o = bz * plane + (size_t)(idx / n) * np + (idx % n);
+    if (lnm[o] > -INFINITY) acc[o] += eps * v[o];
+  }
+}
+
+// out = dD[bz] * marginal (masked), in the padded layout; marginal = exp(lnm).
+__global__ void k_seed(const double* dD, const double* lnm, long long sMarg, int n, int np, double* out) {
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / np), k = (int)(idx % np);
+    double v = 0.0;
+    if (j < n && k < n) {
+      const double l = lnm[bz * sMarg + idx];
+      if (l > -INFINITY) v = dD[bz] * exp(l);
+    }
+    out[bz * plane + idx] = v;
+  }
+}
+
+// Transpose of the trapezoid integration with the a-weighted mean removed.
+// Step 1 (one block per row): row sums of dphi (caller layout) and of a * total later.
+__global__ __launch_bounds__(NTHREADS) void k_rowsum_dense(const double* x, int n, double* rowsum) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, bz = blockIdx.y;
+  const double* r = x + ((size_t)bz * n + j) * n;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) s += r[k];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) rowsum[(size_t)bz * n + j] = s;
+}
+
+// Step 2 (one block per row j): pb = dphi - a * total; Tby[j][m] = h/2 (R[m] + R[m-1]) with
+// R[i] = sum_{k>i} pb[j][k]; cbar[j] = sum_k pb[j][k].
+__global__ __launch_bounds__(NTHREADS) void k_int_adj_rows(const double* dphi, const double* rowsum,
+                                                           const double* lna, int n, int np, double* Tby,
+                                                           double* cbar, double* Tbx) {
+  __shared__ double red[4];
+  __shared__ double tsum[NTHREADS];
+  const int j = blockIdx.x, bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  double t = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) t += rowsum[(size_t)bz * n + r];
+  const double total = block_sum(t, red);
+  const double* dp = dphi + ((size_t)bz * n + j) * n;
+  const double* la = lna + (size_t)j * np;
+  const double hh = 0.5 / sqrt((double)n);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) Tbx[bz * plane + (size_t)j * np + k] = 0.0;
+  // contiguous chunk per thread, scanned from the right
+  const int chunk = (n + NTHREADS - 1) / NTHREADS;
+  const int k0 = threadIdx.x * chunk, k1 = min(n, k0 + chunk);
+  double s = 0.0;
+  for (int k = k0; k < k1; ++k) s += dp[k] - (la[k] > -INFINITY ? exp(la[k]) : 0.0) * total;
+  tsum[threadIdx.x] = s;
+  __syncthreads();
+  double suffix = 0.0;  // sum of pb over chunks to the right
+  for (int q = threadIdx.x + 1; q < NTHREADS; ++q) suffix += tsum[q];
+  double* ty = Tby + bz * plane + (size_t)j * np;
+  // R[i] = suffix_after(i); walk i from k1-1 down to k0
+  double run = suffix;  // sum_{k >= k1} pb
+  for (int i = k1 - 1; i >= k0; --i) {
+    const double Ri = run;  // sum_{k > i} pb
+    const double Rim1 = run + (dp[i] - (la[i] > -INFINITY ? exp(la[i]) : 0.0) * total);  // R[i-1]
+    double v = 0.0;
+    if (i <= n - 2) v += hh * Ri;
+    if (i >= 1) v += hh * Rim1;
+    ty[i] = v;
+    run = Rim1;
+  }
+  double rs = 0.0;
+  for (int q = 0; q < NTHREADS; ++q) rs += tsum[q];
+  if (threadIdx.x == 0) cbar[(size_t)bz * n + j] = rs;
+}
+
+// Step 3 (one block per target): Tbx[m][0] = h/2 (Rc[m] + Rc[m-1]) with Rc[i] = sum_{j>i} cbar[j];
+// the other columns of Tbx were zeroed by step 2.
+__global__ __launch_bounds__(NTHREADS) void k_int_adj_col(const double* cbar, int n, int np, double* Tbx) {
+  const int bz = blockIdx.x;
+  const size_t plane = (size_t)np * np;
+  double* tx = Tbx + bz * plane;
+  if (threadIdx.x == 0) {
+    const double hh = 0.5 / sqrt((double)n);
+    const double* cb = cbar + (size_t)bz * n;
+    double run = 0.0;  // sum_{j > i} cbar
+    for (int i = n - 1; i >= 0; --i) {
+      const double Ri = run, Rim1 = run + cb[i];
+      double v = 0.0;
+      if (i <= n - 2) v += hh * Ri;
+      if (i >= 1) v += hh * Rim1;
+      tx[(size_t)i * np] = v;
+      run = Rim1;
+    }
+  }
+}
+
+// w = Tbx * Tx + Tby * Ty (padded layout, valid pixels only).
+__global__ void k_moment_weight(const double* Tbx, const double* Tx, const double* Tby, const double* Ty, int n,
+                                int np, double* w) {
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t o = bz * plane + (size_t)(idx / n) * np + (idx % n);
+    w[o] = Tbx[o] * Tx[o] + Tby[o] * Ty[o];
+  }
+}
+
+// Per-target sums for the normalisation Jacobian: out[0][bz] = sum lbbar, out[1][bz] = dD <psi, b>.
+__global__ __launch_bounds__(NTHREADS) void k_grad_sums(const double* lbbar, const double* psi, const double* lnb,
+                                                        const double* dD, int n, int np, double* out) {
+  __shared__ double red[4];
+  const int bz = blockIdx.x, B = gridDim.x;
+  const size_t plane = (size_t)np * np;
+  double s0 = 0.0, s1 = 0.0;
+  for (size_t idx = threadIdx.x; idx < (size_t)n * n; idx += blockDim.x) {
+    const size_t o = bz * plane + (size_t)(idx / n) * np + (idx % n);
+    if (lnb[o] > -INFINITY) {
+      s0 += lbbar[o];
+      s1 += exp(lnb[o]) * psi[o];
+    }
+  }
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    out[bz] = s0;
+    out[B + bz] = dD[bz] * s1;
+  }
+}
+
+// dL/dG = (2G/Z)(bbar - <bbar, b>), bbar = lbbar / b + dD psi (b = G^2/Z), written as
+// 2 lbbar / G + (2G/Z)(dD psi - sum lbbar - dD <psi,b>); zero where G = 0.  G is rebuilt from
+// the stored ln b and Z = sum G^2 of the solve: G = exp((ln b + ln Z)/2).
+__global__ void k_grad_final(const double* rowsum_G, const double* lbbar, const double* psi, const double* lnb,
+                             const double* dD, const double* sums, int n, int np, double* dG) {
+  __shared__ double Zs;
+  const int bz = blockIdx.y, B = gridDim.y;
+  const size_t plane = (size_t)np * np;
+  if (threadIdx.x == 0) {
+    double z = 0.0;
+    for (int r = 0; r < n; ++r) z += rowsum_G[(size_t)bz * n + r];
+    Zs = z;
+  }
+  __syncthreads();
+  const double Z = Zs, lz = log(Zs);
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t o = bz * plane + (size_t)(idx / n) * np + (idx % n);
+    double v = 0.0;
+    if (lnb[o] > -INFINITY) {
+      const double g = exp(0.5 * (lnb[o] + lz));
+      v = 2.0 * lbbar[o] / g + (2.0 * g / Z) * (dD[bz] * psi[o] - sums[bz] - sums[B + bz]);
+    }
+    dG[(size_t)bz * n * n + idx] = v;
+  }
+}
+
+__global__ void k_fill(double* x, size_t count, double value) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = value;
 }
 
 }  // namespace fot

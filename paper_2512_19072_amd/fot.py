@@ -253,3 +253,41 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------- autograd
+def _autograd_function():
+    import torch
+
+    class FOTFunction(torch.autograd.Function):
+        """(dual [B], phase [B][n][n]) = FOT(G) for a fixed input amplitude g.
+
+        The forward pass runs fot_solve on ``plan`` (which must have checkpoint_every > 0);
+        the backward pass runs fot_backward, replaying the iterations from the checkpoints."""
+
+        @staticmethod
+        def forward(ctx, G, g, plan, eps, iters):
+            phase, rep, _ = plan.solve(g, G.detach().contiguous(), eps, iters)
+            ctx.plan = plan
+            dual = torch.tensor(rep.dual, dtype=torch.float64, device=G.device)
+            return dual, phase
+
+        @staticmethod
+        def backward(ctx, grad_dual, grad_phase):
+            dd = None if grad_dual is None else grad_dual.detach().double().cpu().numpy()
+            gp = None if grad_phase is None else grad_phase.detach().double().contiguous()
+            dG = ctx.plan.backward(dd, gp)
+            return dG, None, None, None, None
+
+    return FOTFunction
+
+
+_FOT_FUNCTION = None
+
+
+def fot_apply(G, g, plan: "Plan", eps, iters: int):
+    """Differentiable solve: returns (dual [B], phase [B][n][n]) as torch tensors."""
+    global _FOT_FUNCTION
+    if _FOT_FUNCTION is None:
+        _FOT_FUNCTION = _autograd_function()
+    return _FOT_FUNCTION.apply(G, g, plan, eps, iters)

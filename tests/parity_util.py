@@ -53,6 +53,15 @@ def range_rel(x, ref):
     return float(np.max(np.abs(x - ref)) / (rng if rng > 0 else 1.0))
 
 
+def _hist_ratio(h, ref, rtol, floor):
+    """max |h - ref| / (rtol ref + floor) over the finite entries; infinite entries must match."""
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(h), fin), "different sets of infinite marginal errors"
+    if not fin.any():
+        return 0.0
+    return float(np.max(np.abs(h[fin] - ref[fin]) / (rtol * ref[fin] + floor)))
+
+
 # Marginal errors shrink to the rounding floor of each precision, so they are compared as
 # |gpu - ref| <= rtol * ref + floor; the entries report the worst ratio (pass if <= 1).
 HIST_TOL = {"f64": (1e-6, 1e-12), "f32": (1e-3, 2e-6), "bf16": (0.1, 1e-3), "f16": (0.1, 1e-3)}
@@ -73,8 +82,8 @@ def compare(gpu, ref, g, G, b_index=0, precision="f64"):
     e["err_a"] = abs(rep.err_a[b_index] - ref.err_a) / (rtol * ref.err_a + floor)
     ha = rep.err_a_history[:, b_index]
     hb = rep.err_b_history[:, b_index]
-    e["hist_a"] = float(np.max(np.abs(ha - ref.err_a_hist) / (rtol * ref.err_a_hist + floor)))
-    e["hist_b"] = float(np.max(np.abs(hb - ref.err_b_hist) / (rtol * ref.err_b_hist + floor)))
+    e["hist_a"] = _hist_ratio(ha, ref.err_a_hist, rtol, floor)
+    e["hist_b"] = _hist_ratio(hb, ref.err_b_hist, rtol, floor)
     e["err_b_gpu"] = float(rep.err_b[b_index])
     e["err_a_values"] = (float(rep.err_a[b_index]), float(ref.err_a))
     return e
