@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "fot_kernels.hpp"
+#include "fot_fused.hpp"
 
 using namespace fot;
 
@@ -52,6 +52,8 @@ struct fot_plan_s {
   double *rowsum_g = nullptr, *rowsum_G = nullptr, *rowpart = nullptr, *partials = nullptr;
   double *hist_a = nullptr, *hist_b = nullptr, *rparts = nullptr, *rsums = nullptr;
   unsigned* colkey = nullptr;
+  int *kexpA = nullptr, *kexpT = nullptr;   // exponent tables of the block-normalised loop operands
+  int nb = 0;
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
   void *lam = nullptr, *opA = nullptr, *opB = nullptr, *Z = nullptr;
@@ -206,38 +208,83 @@ struct Ops {
     return FOT_OK;
   }
 
-  // One half-step: Pout = eps (lnm - ln(Lambda . exp(Pin/eps) . Lambda)) with the fused
-  // marginal error of the entering plan written to hist[batch].
+  static fot_status fused_launch(fot_plan_s* p, int pass, const FusedArgs& a) {
+    dim3 grid(p->np / GC::BN, p->np / GC::BM, p->B);
+    const dim3 block(GC::THREADS);
+    const bool prof = (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
+    hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
+    hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
+    if (pass == 1)
+      hipExtLaunchKernelGGL((k_fused<T, 1, GC>), grid, block, 0, p->stream, e0, e1, 0, a);
+    else
+      hipExtLaunchKernelGGL((k_fused<T, 2, GC>), grid, block, 0, p->stream, e0, e1, 0, a);
+    LAUNCH_CHECK();
+    if (prof) p->prof_used += 2;
+    return FOT_OK;
+  }
+
+  // Block-normalised pass-1 operand of a potential (start of a solve or of a replayed segment).
+  static fot_status prep(fot_plan_s* p, const double* P, double eps) {
+    hipLaunchKernelGGL(k_prep_blocks<T>, dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np, 1.0 / eps,
+                       (T*)p->opA, p->kexpA);
+    LAUNCH_CHECK();
+    return FOT_OK;
+  }
+
+  // One half-step: Pout = eps (lnm - ln(Lambda . exp(Pin/eps) . Lambda)) (Eq. 7 or Eq. 8), the
+  // marginal error of the entering plan to hist[batch] (finished by the next pass 1), and, if
+  // next_eps > 0, the block-normalised operand of Pout for the next half-step.  The operand of
+  // Pin must be in p->opA / p->kexpA.
   static fot_status half(fot_plan_s* p, const double* Pin, double* Pout, const double* lnm, long long sMarg,
-                         double* hist, double* lnS_out, double eps) {
+                         double* hist, double* lnS_out, double eps, double next_eps) {
+    (void)Pin;
     const long long plane = (long long)p->plane;
-    hipLaunchKernelGGL(k_rowexp<T>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, Pin, p->n, p->np, 1.0 / eps,
-                       p->mrow, (T*)p->opA, (T*)nullptr, p->colkey, take_pending(p));
-    LAUNCH_CHECK();
-    GemmArgs g1 = base_args(p, p->opA, plane, p->lam, 0);
-    g1.out = p->Z;
-    g1.sOut = plane;
-    g1.mrow = p->mrow;
-    g1.colkey = p->colkey;
-    fot_status s = gemm_launch(p, EPI_LOGROW, g1);
+    FusedArgs a{};
+    a.n = p->n;
+    a.np = p->np;
+    a.nk = (int)((size_t)p->np * sizeof(T) / ROWB);
+    a.nb = p->nb;
+    a.xcd_swizzle = 1;
+    // pass 1: W = At . Lambda
+    a.A = p->opA;
+    a.sA = plane;
+    a.B = p->lam;
+    a.sB = 0;
+    a.kexp = p->kexpA;
+    a.outT = p->opB;
+    a.kexpT = p->kexpT;
+    PendingSum ps = take_pending(p);
+    a.pend_parts = ps.parts;
+    a.pend_tiles = ps.tiles;
+    a.pend_out = ps.out;
+    fot_status s = fused_launch(p, 1, a);
     if (s != FOT_OK) return s;
-    dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
-    hipLaunchKernelGGL((k_colexpT<T, zt, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const zt*)p->Z, p->mrow,
-                       p->colkey, p->n, p->np, (T*)p->opB);
-    LAUNCH_CHECK();
-    GemmArgs g2 = base_args(p, p->lam, 0, p->opB, plane);
-    g2.colkey = p->colkey;
-    g2.lnmarg = lnm;
-    g2.sMarg = sMarg;
-    g2.pot = Pout;
-    g2.lnS_out = lnS_out;
-    g2.eps = eps;
-    g2.inv_eps = 1.0 / eps;
-    g2.partials = p->partials;
-    g2.flag = p->flag;
-    fot_status st = gemm_launch(p, EPI_UPDATE, g2);
+    // pass 2: S = Lambda . Bt, potential update, next operand
+    FusedArgs b{};
+    b.n = p->n;
+    b.np = p->np;
+    b.nk = a.nk;
+    b.nb = p->nb;
+    b.xcd_swizzle = 1;
+    b.A = p->lam;
+    b.sA = 0;
+    b.B = p->opB;
+    b.sB = plane;
+    b.kexp = p->kexpT;
+    b.lnmarg = lnm;
+    b.sMarg = sMarg;
+    b.pot = Pout;
+    b.lnS_out = lnS_out;
+    b.eps = eps;
+    b.inv_eps = 1.0 / eps;
+    b.next_inv_eps = next_eps > 0.0 ? 1.0 / next_eps : 0.0;
+    b.nextA = p->opA;
+    b.kexpN = p->kexpA;
+    b.partials = p->partials;
+    b.flag = p->flag;
+    s = fused_launch(p, 2, b);
     p->pending_hist = hist;
-    return st;
+    return s;
   }
 
   // The iteration loop of Algorithm 1 on p->stream: Lambda is regenerated whenever eps
@@ -245,9 +292,10 @@ struct Ops {
   static fot_status loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
     const long long plane = (long long)p->plane;
     const int B = p->B;
+    fot_status s = prep(p, p->psi, e[0]);
+    if (s != FOT_OK) return s;
     for (int t = 0; t < iters; ++t) {
       const double ep = e[t];
-      fot_status s;
       if (t == 0 || ep != e[t - 1])
         if ((s = fill_lambda(p, ep, false)) != FOT_OK) return s;
       if (p->tape && (t % p->d.checkpoint_every) == 0) {
@@ -257,10 +305,11 @@ struct Ops {
         LAUNCH_CHECK();
       }
       const bool last = (t == iters - 1);
-      if ((s = half(p, p->psi, p->f, p->lna, 0, p->hist_a + (size_t)t * B, last ? p->lnS : nullptr, ep)) != FOT_OK)
-        return s;
-      if ((s = half(p, p->f, p->psi, p->lnb, plane, p->hist_b + (size_t)t * B, last ? p->lnSp : nullptr, ep)) !=
+      if ((s = half(p, p->psi, p->f, p->lna, 0, p->hist_a + (size_t)t * B, last ? p->lnS : nullptr, ep, ep)) !=
           FOT_OK)
+        return s;
+      if ((s = half(p, p->f, p->psi, p->lnb, plane, p->hist_b + (size_t)t * B, last ? p->lnSp : nullptr, ep,
+                    last ? 0.0 : e[t + 1])) != FOT_OK)
         return s;
     }
     return FOT_OK;
@@ -346,13 +395,15 @@ struct Ops {
       const double* tape_in = p->tape + (size_t)sg * BP;
       // replay the segment from its checkpoint (bit-identical to the forward solve)
       const double* pin = tape_in;
+      if ((s = prep(p, tape_in, e[t0])) != FOT_OK) return s;
       for (int i = t0; i < t1; ++i) {
         const int q = i - t0;
         if ((s = ensure_lambda(p, e[i])) != FOT_OK) return s;
-        if ((s = half(p, pin, p->seg_f + q * BP, p->lna, 0, p->hist_scratch, p->seg_lnS + q * BP, e[i])) != FOT_OK)
+        if ((s = half(p, pin, p->seg_f + q * BP, p->lna, 0, p->hist_scratch, p->seg_lnS + q * BP, e[i], e[i])) !=
+            FOT_OK)
           return s;
         if ((s = half(p, p->seg_f + q * BP, p->seg_psi + q * BP, p->lnb, plane, p->hist_scratch + B,
-                      p->seg_lnSp + q * BP, e[i])) != FOT_OK)
+                      p->seg_lnSp + q * BP, e[i], i + 1 < t1 ? e[i + 1] : 0.0)) != FOT_OK)
           return s;
         pin = p->seg_psi + q * BP;
       }
@@ -604,6 +655,9 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   ALLOC(p->rparts, (size_t)5 * p->B * READOUT_BLOCKS);
   ALLOC(p->rsums, (size_t)5 * p->B);
   ALLOC(p->colkey, (size_t)p->B * p->np);
+  p->nb = p->np / XBLK;
+  ALLOC(p->kexpA, (size_t)p->B * p->np * p->nb);
+  ALLOC(p->kexpT, (size_t)p->B * p->np * p->nb);
   ALLOC(p->flag, (size_t)1);
   ALLOCV(p->lam, p->plane * p->esz);
   ALLOCV(p->opA, BP * p->esz);
@@ -660,7 +714,12 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   }
 #undef ALLOC
 #undef ALLOCV
-  if (hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
+  // the fused loop kernels never write the padded borders of their operands: zero them once
+  if (hipMemsetAsync(p->opA, 0, BP * p->esz, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->opB, 0, BP * p->esz, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->kexpA, 0, sizeof(int) * p->B * p->np * p->nb, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->kexpT, 0, sizeof(int) * p->B * p->np * p->nb, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
       hipMemsetAsync(p->flag, 0, sizeof(int), p->stream) != hipSuccess)
     return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
   for (auto& e : p->ev)
