@@ -53,7 +53,7 @@ struct fot_plan_s {
   double *hist_a = nullptr, *hist_b = nullptr, *rparts = nullptr, *rsums = nullptr;
   unsigned* colkey = nullptr;
   int *kexpA = nullptr, *kexpT = nullptr;   // exponent tables of the block-normalised loop operands
-  int nb = 0;
+  int nbA = 0, nbT = 0;
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
   void *lam = nullptr, *opA = nullptr, *opB = nullptr, *Z = nullptr;
@@ -215,9 +215,11 @@ struct Ops {
     hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
     hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
     if (pass == 1)
-      hipExtLaunchKernelGGL((k_fused<T, 1, GC>), grid, block, 0, p->stream, e0, e1, 0, a);
+      hipExtLaunchKernelGGL((k_fused<T, 1, GC>), grid, block, (uint32_t)fused_dyn_lds<1, GC>(p->np), p->stream, e0,
+                            e1, 0, a);
     else
-      hipExtLaunchKernelGGL((k_fused<T, 2, GC>), grid, block, 0, p->stream, e0, e1, 0, a);
+      hipExtLaunchKernelGGL((k_fused<T, 2, GC>), grid, block, (uint32_t)fused_dyn_lds<2, GC>(p->np), p->stream, e0,
+                            e1, 0, a);
     LAUNCH_CHECK();
     if (prof) p->prof_used += 2;
     return FOT_OK;
@@ -225,8 +227,8 @@ struct Ops {
 
   // Block-normalised pass-1 operand of a potential (start of a solve or of a replayed segment).
   static fot_status prep(fot_plan_s* p, const double* P, double eps) {
-    hipLaunchKernelGGL(k_prep_blocks<T>, dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np, 1.0 / eps,
-                       (T*)p->opA, p->kexpA);
+    hipLaunchKernelGGL((k_prep_blocks<T, GC::BN>), dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np,
+                       1.0 / eps, (T*)p->opA, p->kexpA);
     LAUNCH_CHECK();
     return FOT_OK;
   }
@@ -243,7 +245,8 @@ struct Ops {
     a.n = p->n;
     a.np = p->np;
     a.nk = (int)((size_t)p->np * sizeof(T) / ROWB);
-    a.nb = p->nb;
+    a.nbA = p->nbA;
+    a.nbT = p->nbT;
     a.xcd_swizzle = 1;
     // pass 1: W = At . Lambda
     a.A = p->opA;
@@ -264,7 +267,8 @@ struct Ops {
     b.n = p->n;
     b.np = p->np;
     b.nk = a.nk;
-    b.nb = p->nb;
+    b.nbA = p->nbA;
+    b.nbT = p->nbT;
     b.xcd_swizzle = 1;
     b.A = p->lam;
     b.sA = 0;
@@ -618,7 +622,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   p->np = ((d.n + align - 1) / align) * align;
   p->B = d.batch;
   p->prec = d.precision;
-  p->tiles = (p->np / TILE) * (p->np / TILE);
+  // one marginal-error partial per output tile of the fused pass-2 kernel
+  p->tiles = (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN);
   p->zsz = d.precision == FOT_F64 ? 8 : 4;
   p->plane = (size_t)p->np * p->np;
   p->stream = (hipStream_t)stream;
@@ -655,9 +660,10 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   ALLOC(p->rparts, (size_t)5 * p->B * READOUT_BLOCKS);
   ALLOC(p->rsums, (size_t)5 * p->B);
   ALLOC(p->colkey, (size_t)p->B * p->np);
-  p->nb = p->np / XBLK;
-  ALLOC(p->kexpA, (size_t)p->B * p->np * p->nb);
-  ALLOC(p->kexpT, (size_t)p->B * p->np * p->nb);
+  p->nbA = p->np / Ops<float>::GC::BN;
+  p->nbT = p->np / Ops<float>::GC::BM;
+  ALLOC(p->kexpA, (size_t)p->B * p->np * p->nbA);
+  ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
   ALLOC(p->flag, (size_t)1);
   ALLOCV(p->lam, p->plane * p->esz);
   ALLOCV(p->opA, BP * p->esz);
@@ -717,8 +723,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   // the fused loop kernels never write the padded borders of their operands: zero them once
   if (hipMemsetAsync(p->opA, 0, BP * p->esz, p->stream) != hipSuccess ||
       hipMemsetAsync(p->opB, 0, BP * p->esz, p->stream) != hipSuccess ||
-      hipMemsetAsync(p->kexpA, 0, sizeof(int) * p->B * p->np * p->nb, p->stream) != hipSuccess ||
-      hipMemsetAsync(p->kexpT, 0, sizeof(int) * p->B * p->np * p->nb, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->kexpA, 0, sizeof(int) * p->B * p->np * p->nbA, p->stream) != hipSuccess ||
+      hipMemsetAsync(p->kexpT, 0, sizeof(int) * p->B * p->np * p->nbT, p->stream) != hipSuccess ||
       hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
       hipMemsetAsync(p->flag, 0, sizeof(int), p->stream) != hipSuccess)
     return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));

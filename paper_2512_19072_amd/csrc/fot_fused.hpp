@@ -24,16 +24,21 @@
 
 namespace fot {
 
-constexpr int XBLK = 64;                  // K extent of one exponent block
-constexpr int KSENT = -(1 << 20);          // exponent of an all-zero block
+constexpr int KSENT = -(1 << 30);          // exponent of an all-zero block
+constexpr double KMIN = -1.0e9;            // lowest exponent of a block holding a finite value
 constexpr double LN2 = 0.69314718055994530942;
 constexpr double INV_LN2 = 1.44269504088896340736;
+// ln 2 split so that e * LN2_HI is exact for |e| < 2^21 (head has 32 significant bits)
+constexpr double LN2_HI = 6.93147180369123816490e-01;
+constexpr double LN2_LO = 1.90821492927058770002e-10;
 
 struct FusedArgs {
   const void* A;            // [batch][np][np] pass-1: At;  pass-2: Lambda (shared, sA = 0)
   const void* B;            // [batch][np][np] pass-1: Lambda (shared); pass-2: Bt
   long long sA, sB;
-  int n, np, nk, nb;        // nb = np / XBLK exponent blocks per row
+  int n, np, nk;
+  int nbA;                  // exponent blocks per row of the pass-1 operand (np / BN)
+  int nbT;                  // exponent blocks per row of the pass-2 operand (np / BM)
   int xcd_swizzle;
   const int* kexp;          // [batch][np][nb] exponents of the block-normalised operand (pass 1: A, pass 2: B)
   // pass 1 outputs
@@ -58,79 +63,152 @@ struct FusedArgs {
 // exp(x - K ln 2) rounded to the operand type, with the K of a block's maximum.  The prep
 // kernel and the pass-2 epilogue both use these two functions, so the operand built after a
 // replay from a checkpoint is bit-identical to the one built inside the iteration.
+// block_exponent is monotone in x, so the exponent of a block's maximum equals the maximum of
+// its elements' exponents: the pass-2 epilogue reduces integers, the prep kernel doubles.
 __device__ __forceinline__ int block_exponent(double xmax) {
-  return (xmax > -INFINITY) ? (int)ceil(xmax * INV_LN2) : KSENT;
+  return (xmax > -INFINITY) ? (int)ceil(fmax(xmax * INV_LN2, KMIN)) : KSENT;
 }
 template <typename T>
 __device__ __forceinline__ T block_operand(double x, int K) {
   return (K == KSENT) ? (T)0 : exp_op<T>(x - (double)K * LN2);
 }
 
-// Block-normalised pass-1 operand of a potential P (FP64 [batch][np][np]): one wave per row.
-template <typename T>
+// max over the 16 lanes of each row of a wave (DPP: quad swaps, then half-row and row mirrors)
+__device__ __forceinline__ int row16_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+  return v;
+}
+
+// Natural logarithm in FP64 (within a few ulp) for the log-domain update: v = m 2^e with m in
+// [1/sqrt 2, sqrt 2), ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| < 0.172, summed by its odd
+// power series to s^19 (truncation below 2^-55 relative), plus e ln 2 in two parts.  Zero,
+// infinity and NaN take the library path.
+__device__ __forceinline__ double log_fp64(double v) {
+  if (!(v > 0.0 && v < INFINITY)) return log(v);
+  int e;
+  double m = frexp(v, &e);
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    --e;
+  }
+  const double num = m - 1.0, den = m + 1.0;  // num is exact
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  double q = num * r;
+  q = fma(fma(-q, den, num), r, q);
+  const double s2 = q * q;
+  double t = 1.0 / 19.0;
+  t = fma(t, s2, 1.0 / 17.0);
+  t = fma(t, s2, 1.0 / 15.0);
+  t = fma(t, s2, 1.0 / 13.0);
+  t = fma(t, s2, 1.0 / 11.0);
+  t = fma(t, s2, 1.0 / 9.0);
+  t = fma(t, s2, 1.0 / 7.0);
+  t = fma(t, s2, 1.0 / 5.0);
+  t = fma(t, s2, 1.0 / 3.0);
+  const double q2 = 2.0 * q;
+  const double lnm = fma(q2 * s2, t, q2);
+  const double de = (double)e;
+  return fma(de, LN2_HI, fma(de, LN2_LO, lnm));
+}
+
+// 64-bit DPP move (two 32-bit halves), CTRL a DPP16 row control
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)h2 << 32) | (unsigned)l2);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order: rows of 16 by DPP, then the four row sums
+// in row order.  Every lane returns the same value.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int l = __builtin_amdgcn_readlane(lo, 16 * r), h = __builtin_amdgcn_readlane(hi, 16 * r);
+    s += __longlong_as_double(((long long)h << 32) | (unsigned)l);
+  }
+  return s;
+}
+
+// max over groups of XB consecutive lanes (XB = 32 or 64)
+template <int XB>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int off = XB / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block-normalised pass-1 operand of a potential P (FP64 [batch][np][np]), blocks of XB
+// columns: one wave per row.
+template <typename T, int XB>
 __global__ __launch_bounds__(64) void k_prep_blocks(const double* P, int n, int np, double inv_eps, T* out,
                                                     int* kexp) {
   const int j = blockIdx.x, bz = blockIdx.y, lane = threadIdx.x;
-  const int nb = np / XBLK;
+  const int nb = np / XB;
   const size_t plane = (size_t)np * np;
   T* o = out + bz * plane + (size_t)j * np;
   int* ko = kexp + ((size_t)bz * np + j) * nb;
-  for (int blk = 0; blk < nb; ++blk) {
-    const int k = blk * XBLK + lane;
+  for (int c0 = 0; c0 < np; c0 += 64) {
+    const int k = c0 + lane;
     const bool ok = j < n && k < n;
     const double x = ok ? P[bz * plane + (size_t)j * np + k] * inv_eps : -INFINITY;
-    const int K = block_exponent(wave_max(x));
+    const int K = block_exponent(group_max<XB>(x));
     o[k] = ok ? block_operand<T>(x, K) : (T)0;
-    if (lane == 0) ko[blk] = K;
+    if (lane % XB == 0) ko[k / XB] = K;
   }
+}
+
+// Launch with dynamic LDS of fused_dyn_lds<PASS, C>(np) bytes (the exponent-difference table).
+template <int PASS, typename C>
+constexpr int fused_scaled_rows() { return PASS == 1 ? C::BM : C::BN; }
+template <int PASS, typename C>
+inline size_t fused_dyn_lds(int np) {
+  const int xb = PASS == 1 ? C::BN : C::BM;
+  return (size_t)(np / xb) * fused_scaled_rows<PASS, C>() * sizeof(short);
 }
 
 template <typename T, int PASS, typename C>
 __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
-  static_assert(C::BM == XBLK && C::BN == XBLK, "exponent blocks are the 64-wide output tiles");
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int BM = C::BM, BN = C::BN, RB = C::RB, CB = C::CB;
+  constexpr int XB = PASS == 1 ? BN : BM;         // K extent of one exponent block of this pass
+  constexpr int SR = fused_scaled_rows<PASS, C>(); // rows whose exponents scale the sums
   constexpr int HPS = CHUNKS / 4;                 // fragment steps per K stage
   constexpr int EPH = 64 / (int)sizeof(T);        // K elements per fragment step (4 lane groups)
-  constexpr int HB = XBLK / EPH;                  // fragment steps per exponent block
-  constexpr int MAXNB = 128;                      // np <= 8192
+  constexpr int HB = XB / EPH;                    // fragment steps per exponent block
+  static_assert(HB >= 1 && XB % EPH == 0, "exponent blocks must hold whole fragment steps");
   __shared__ __attribute__((aligned(16))) unsigned char ldsA[2][BM * LDS_RS];
   __shared__ __attribute__((aligned(16))) unsigned char ldsB[2][BN * LDS_RS];
-  __shared__ short dtab[MAXNB][XBLK];             // exponent - row reference, per block
-  __shared__ int rref[XBLK];                      // reference exponent of each scaled row
+  extern __shared__ short dtab[];                 // [np / XB][SR]: exponent - row reference
+  __shared__ int rref[SR];                        // reference exponent of each scaled row
   __shared__ double red[C::NW];
-  __shared__ double xred[C::WGN][BM];             // pass 2: row maxima of the next operand
+  __shared__ int kred[C::WGN][BM];                // pass 2: row exponents of the next operand
   __shared__ int ered[C::WGM][BN];                // pass 1: column exponent maxima
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / C::WGN, wn = wave % C::WGN;
   const int r16 = lane & 15, g = lane >> 4;
   const int bz = blockIdx.z;
-  const int n = p.n, np = p.np, nb = p.nb;
+  const int n = p.n, np = p.np;
+  const int nbk = PASS == 1 ? p.nbA : p.nbT;     // exponent blocks along this pass's K
   int tr, tc;
   tile_of(gridDim.x, gridDim.y, p.xcd_swizzle, &tr, &tc);
   const int row0 = tr * BM, col0 = tc * BN;
   const size_t plane = (size_t)np * np;
-
-  // ---- exponent table of the block-normalised operand for this tile's 64 scaled rows
-  // (pass 1: A rows = output rows; pass 2: B rows = output columns)
-  {
-    const int srow0 = (PASS == 1) ? row0 : col0;
-    const int* kx = p.kexp + ((size_t)bz * np + srow0) * nb;
-    for (int r = tid / 8; r < XBLK; r += C::THREADS / 8) {
-      const int sub = tid % 8;
-      int m = KSENT;
-      for (int b = sub; b < nb; b += 8) m = max(m, kx[(size_t)r * nb + b]);
-      m = max(m, __shfl_xor(m, 1, 64));
-      m = max(m, __shfl_xor(m, 2, 64));
-      m = max(m, __shfl_xor(m, 4, 64));
-      if (sub == 0) rref[r] = m;
-      for (int b = sub; b < nb; b += 8) {
-        const int d = kx[(size_t)r * nb + b] - m;
-        dtab[b][r] = (short)max(d, -1100);     // 2^-1100 underflows to 0 in FP64
-      }
-    }
-  }
 
   const size_t pitch = (size_t)np * sizeof(T);
   const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
@@ -143,15 +221,12 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   const int sofs = rl * LDS_RS + ql * 16;
   u32x4 ga[LA], gb[LB];
 
-  acc_t acc[RB][CB];
-  f64x4 accd[RB][CB];
+  // ---- prologue: every global read the tile needs before its first flush is issued here,
+  // the first K stage first, so that their latencies overlap
 #pragma unroll
-  for (int i = 0; i < RB; ++i)
+  for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
 #pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      acc[i][j] = acc_t{};
-      accd[i][j] = f64x4{};
-    }
+  for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch);
 
   // pass-2 epilogue inputs, prefetched so that their latency hides behind the K loop
   double la_v[CB][RB][4], fo_v[CB][RB][4];
@@ -174,25 +249,63 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     }
   }
 
-  // marginal-error sum of the preceding update, finished in index order by one workgroup
-  if constexpr (PASS == 1) {
-    if (p.pend_parts && blockIdx.x == 0 && blockIdx.y == 0) {
-      double v = 0.0;
-      for (int t = tid; t < p.pend_tiles; t += C::THREADS) v += p.pend_parts[(size_t)bz * p.pend_tiles + t];
-      v = block_sum(v, red);
-      if (tid == 0) p.pend_out[bz] = v;
+  // marginal-error partials of the preceding update, summed in index order by workgroup 0;
+  // the first PEND_REG per thread are read now, the sum is formed in the epilogue
+  constexpr int PEND_REG = 2;
+  const bool pend_wg = PASS == 1 && p.pend_parts && blockIdx.x == 0 && blockIdx.y == 0;
+  double pend_v[PEND_REG];
+#pragma unroll
+  for (int q = 0; q < PEND_REG; ++q) {
+    const int t = tid + q * C::THREADS;
+    pend_v[q] = (pend_wg && t < p.pend_tiles) ? p.pend_parts[(size_t)bz * p.pend_tiles + t] : 0.0;
+  }
+
+  // exponent table of the block-normalised operand for this tile's scaled rows
+  // (pass 1: A rows = output rows; pass 2: B rows = output columns)
+  {
+    const int srow0 = (PASS == 1) ? row0 : col0;
+    const int* kx = p.kexp + ((size_t)bz * np + srow0) * nbk;
+    for (int r = tid / 8; r < SR; r += C::THREADS / 8) {
+      const int sub = tid % 8;
+      int m = KSENT;
+      for (int b = sub; b < nbk; b += 8) m = max(m, kx[(size_t)r * nbk + b]);
+      m = max(m, __shfl_xor(m, 1, 64));
+      m = max(m, __shfl_xor(m, 2, 64));
+      m = max(m, __shfl_xor(m, 4, 64));
+      if (sub == 0) rref[r] = m;
+      for (int b = sub; b < nbk; b += 8) {
+        const int d = kx[(size_t)r * nbk + b] - m;
+        dtab[b * SR + r] = (short)max(d, -1100);   // 2^-1100 underflows to 0 in FP64
+      }
     }
   }
 
+  acc_t acc[RB][CB];
+  f64x4 accd[RB][CB];
 #pragma unroll
-  for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-  for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch);
+    for (int j = 0; j < CB; ++j) {
+      acc[i][j] = acc_t{};
+      accd[i][j] = f64x4{};
+    }
+
+  // Main loop over K stages, LDS double-buffered.  Within a stage the fragments of step h+1 are
+  // read while the MFMAs of step h run; at the end of a stage the next stage's tiles are stored,
+  // the workgroup synchronises, the next stage's first fragments are requested, and only then
+  // is the exponent block flushed, so that the FP64 flush overlaps the LDS latency.
 #pragma unroll
   for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[0][sofs + u * RSTEP * LDS_RS]) = ga[u];
 #pragma unroll
   for (int u = 0; u < LB; ++u) *(u32x4*)(&ldsB[0][sofs + u * RSTEP * LDS_RS]) = gb[u];
   __syncthreads();
+  const int aofs = (wm * C::WTM + r16) * LDS_RS + g * 16;
+  const int bofs = (wn * C::WTN + r16) * LDS_RS + g * 16;
+  u32x4 af[RB], bf[CB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) af[rb] = *(const u32x4*)(&ldsA[0][aofs + rb * 16 * LDS_RS]);
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) bf[cb] = *(const u32x4*)(&ldsB[0][bofs + cb * 16 * LDS_RS]);
   for (int kt = 0; kt < p.nk; ++kt) {
     const int s = kt & 1;
     const bool more = kt + 1 < p.nk;
@@ -205,17 +318,36 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     }
 #pragma unroll
     for (int h = 0; h < HPS; ++h) {
-      u32x4 af[RB], bf[CB];
+      const bool last = h + 1 == HPS;
+      u32x4 an[RB] = {}, bn[CB] = {};
+      if (!last) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-        af[rb] = *(const u32x4*)(&ldsA[s][(wm * C::WTM + rb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+        for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&ldsA[s][aofs + rb * 16 * LDS_RS + (h + 1) * 64]);
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
-        bf[cb] = *(const u32x4*)(&ldsB[s][(wn * C::WTN + cb * 16 + r16) * LDS_RS + (h * 4 + g) * 16]);
+        for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&ldsB[s][bofs + cb * 16 * LDS_RS + (h + 1) * 64]);
+      }
+      // sub-products outermost: consecutive MFMAs go to different accumulators
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int q = 0; q < Mma<T>::NSUB; ++q)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) Mma<T>::run(af[rb], bf[cb], acc[rb][cb]);
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) Mma<T>::sub(af[rb], bf[cb], acc[rb][cb], q);
+      if (last) {
+        if (more) {
+#pragma unroll
+          for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[s ^ 1][sofs + u * RSTEP * LDS_RS]) = ga[u];
+#pragma unroll
+          for (int u = 0; u < LB; ++u) *(u32x4*)(&ldsB[s ^ 1][sofs + u * RSTEP * LDS_RS]) = gb[u];
+        }
+        __syncthreads();
+        if (more) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&ldsA[s ^ 1][aofs + rb * 16 * LDS_RS]);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&ldsB[s ^ 1][bofs + cb * 16 * LDS_RS]);
+        }
+      }
       const int hh = kt * HPS + h;
       if ((hh + 1) % HB == 0) {
         // end of an exponent block: add its partial sums, scaled exactly by 2^(K - Kref)
@@ -227,24 +359,22 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const int sr = (PASS == 1) ? wm * C::WTM + rb * 16 + Mma<T>::row(g, e) : wn * C::WTN + cb * 16 + r16;
-              accd[rb][cb][e] += ldexp((double)acc[rb][cb][e], (int)dtab[blk][sr]);
+              accd[rb][cb][e] += ldexp((double)acc[rb][cb][e], (int)dtab[blk * SR + sr]);
             }
             acc[rb][cb] = acc_t{};
           }
       }
-    }
-    if (more) {
 #pragma unroll
-      for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[s ^ 1][sofs + u * RSTEP * LDS_RS]) = ga[u];
+      for (int rb = 0; rb < RB; ++rb) af[rb] = an[rb];
 #pragma unroll
-      for (int u = 0; u < LB; ++u) *(u32x4*)(&ldsB[s ^ 1][sofs + u * RSTEP * LDS_RS]) = gb[u];
+      for (int cb = 0; cb < CB; ++cb) bf[cb] = bn[cb];
     }
-    __syncthreads();
   }
 
   // ---------------------------------------------------------------- epilogues
   // accd[rb][cb][e] belongs to output row row0 + wm*WTM + rb*16 + Mma<T>::row(g, e) and column
-  // col0 + wn*WTN + cb*16 + r16; its true value is accd * 2^(reference exponent).
+  // col0 + wn*WTN + cb*16 + r16; its true value is accd * 2^(reference exponent).  The element
+  // work is written without branches (selects), so the compiler interleaves the elements.
   if constexpr (PASS == 1) {
     // W[L][k] = accd 2^{R_L}.  Column block exponent K'[k] = max over this tile's rows of the
     // binary exponent of W; Bt[k][L] = W 2^{-K'} in (0, 1).
@@ -260,11 +390,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int i = row0 + lr, j = col0 + wn * C::WTN + cb * 16 + r16;
           const double v = accd[rb][cb][e];
-          if (i < n && j < n && v > 0.0) {
-            int ex;
-            (void)frexp(v, &ex);
-            ecol[cb] = max(ecol[cb], rref[lr] + ex);
-          }
+          int ex;
+          (void)frexp(v, &ex);
+          ecol[cb] = max(ecol[cb], (i < n && j < n && v > 0.0) ? rref[lr] + ex : KSENT);
         }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -272,7 +400,23 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       ecol[cb] = max(ecol[cb], __shfl_xor(ecol[cb], 32, 64));
       if (g == 0) ered[wm][wn * C::WTN + cb * 16 + r16] = ecol[cb];
     }
+    // pending marginal-error sum: entries beyond the prefetched ones, then per-wave sums
+    double pend = 0.0;
+    if (pend_wg) {
+#pragma unroll
+      for (int q = 0; q < PEND_REG; ++q) pend += pend_v[q];
+      for (int t = tid + PEND_REG * C::THREADS; t < p.pend_tiles; t += C::THREADS)
+        pend += p.pend_parts[(size_t)bz * p.pend_tiles + t];
+      pend = wave_sum_dpp(pend);
+      if (lane == 0) red[wave] = pend;
+    }
     __syncthreads();
+    if (pend_wg && tid == 0) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < C::NW; ++w) v += red[w];
+      p.pend_out[bz] = v;
+    }
     T* outT = (T*)p.outT + (size_t)bz * plane;
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -281,18 +425,33 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       int K = ered[0][lc];
 #pragma unroll
       for (int w = 1; w < C::WGM; ++w) K = max(K, ered[w][lc]);
-      if (wm == 0 && g == 0 && j < n) p.kexpT[((size_t)bz * np + j) * nb + tr] = K;
+      if (wm == 0 && g == 0 && j < n) p.kexpT[((size_t)bz * np + j) * p.nbT + tr] = K;
+      if (j >= n) continue;  // padded rows of Bt stay zero
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RB; ++rb) {
+        if constexpr (sizeof(T) == 8) {
+          // FP64 rows g + 4e are not contiguous: element stores
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
-          const int i = row0 + lr;
-          if (i < n && j < n) {
+          for (int e = 0; e < 4; ++e) {
+            const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
+            const int i = row0 + lr;
             const double v = (K == KSENT) ? 0.0 : ldexp(accd[rb][cb][e], rref[lr] - K);
-            outT[(size_t)j * np + i] = (T)v;
+            if (i < n) outT[(size_t)j * np + i] = v;
           }
+        } else {
+          // rows 4g .. 4g+3 are contiguous in Bt row j: one 16-byte (FP32) or 8-byte store
+          typedef T tv4 __attribute__((ext_vector_type(4)));
+          const int lr0 = wm * C::WTM + rb * 16 + 4 * g;
+          tv4 w;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int lr = lr0 + e;
+            const double v = (K == KSENT || row0 + lr >= n) ? 0.0 : ldexp(accd[rb][cb][e], rref[lr] - K);
+            w[e] = (T)v;
+          }
+          *(tv4*)(outT + (size_t)j * np + row0 + lr0) = w;
         }
+      }
     }
   } else {
     // S = accd 2^{R'_k};  f_new = eps (ln m - ln S) in FP64, the marginal-error partial of the
@@ -301,7 +460,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     double* pot = p.pot + (size_t)bz * plane;
     double* lns = p.lnS_out ? p.lnS_out + (size_t)bz * plane : nullptr;
     double err = 0.0;
-    int bad = 0;
+    bool bad = false;
     double fnew_v[CB][RB][4];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -313,23 +472,22 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
-          double fnew = -INFINITY;
-          if (i < n && j < n) {
-            const size_t o = (size_t)i * np + j;
-            const double v = accd[rb][cb][e];
-            // ln S: FP64 log for FP32/FP64 operands, logf for 16-bit operands
-            const double lnS = shift + ((sizeof(T) == 2) ? (double)logf((float)v) : log(v));
-            const double la = la_v[cb][rb][e];
-            const double fold = fo_v[cb][rb][e];
-            if (la == -INFINITY) {
-              // entering plan's mass on a zero-mass pixel: u_old * S
-              err += (double)expf((float)(fold * inv_eps + lnS));
-            } else {
-              fnew = eps * (la - lnS);
-              // a |u_old / u_new - 1| = a |exp((f_old - f_new)/eps) - 1|
-              err += (double)(expf((float)la) * fabsf(expm1f((float)((fold - fnew) * inv_eps))));
-              bad |= !(fabs(fnew) < INFINITY);
-            }
+          const bool ok = i < n && j < n;
+          const double v = accd[rb][cb][e];
+          // ln S: FP64 log for FP32/FP64 operands, logf for 16-bit operands
+          const double lnS = shift + ((sizeof(T) == 2) ? (double)logf((float)v) : log_fp64(v));
+          const double la = la_v[cb][rb][e];
+          const double fold = fo_v[cb][rb][e];
+          const bool zm = la == -INFINITY;
+          const double fnew = (ok && !zm) ? eps * (la - lnS) : -INFINITY;
+          // marginal-error term of the entering plan at this pixel: on a zero-mass pixel its
+          // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp((f_old - f_new)/eps) - 1|
+          const float tz = expf((float)(fold * inv_eps + lnS));
+          const float ta = expf((float)la) * fabsf(expm1f((float)((fold - fnew) * inv_eps)));
+          err += ok ? (double)(zm ? tz : ta) : 0.0;
+          bad = bad || (ok && !zm && !(fabs(fnew) < INFINITY));
+          const size_t o = (size_t)i * np + j;
+          if (ok) {
             pot[o] = fnew;
             if (lns) lns[o] = lnS;
           }
@@ -337,29 +495,32 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         }
     }
     if (bad) atomicOr(p.flag, 1);
-    const double part = block_sum(err, red);
-    const int tiles = gridDim.x * gridDim.y;
-    if (tid == 0) p.partials[(size_t)bz * tiles + blockIdx.x + gridDim.x * blockIdx.y] = part;
+    err = wave_sum_dpp(err);
+    if (lane == 0) red[wave] = err;
 
     if (p.next_inv_eps > 0.0) {
-      // next pass-1 operand: per output row, exponent of the max over this tile's 64 columns
+      // next pass-1 operand: per output row, the exponent of the max over this tile's columns
       const double ninv = p.next_inv_eps;
-      double xm[RB][4];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          double m = -INFINITY;
+          int k = KSENT;
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) m = fmax(m, fnew_v[cb][rb][e] * ninv);
-          m = fmax(m, __shfl_xor(m, 1, 64));
-          m = fmax(m, __shfl_xor(m, 2, 64));
-          m = fmax(m, __shfl_xor(m, 4, 64));
-          m = fmax(m, __shfl_xor(m, 8, 64));
-          xm[rb][e] = m;
-          if (r16 == 0) xred[wn][wm * C::WTM + rb * 16 + Mma<T>::row(g, e)] = m;
+          for (int cb = 0; cb < CB; ++cb) k = max(k, block_exponent(fnew_v[cb][rb][e] * ninv));
+          k = row16_max(k);   // over the 16 columns of this lane's block row
+          if (r16 == 0) kred[wn][wm * C::WTM + rb * 16 + Mma<T>::row(g, e)] = k;
         }
-      __syncthreads();
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < C::NW; ++w) v += red[w];
+      p.partials[(size_t)bz * gridDim.x * gridDim.y + blockIdx.x + gridDim.x * blockIdx.y] = v;
+    }
+    if (p.next_inv_eps > 0.0) {
+      const double ninv = p.next_inv_eps;
       T* nA = (T*)p.nextA + (size_t)bz * plane;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -367,18 +528,17 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         for (int e = 0; e < 4; ++e) {
           const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int i = row0 + lr;
-          double m = xred[0][lr];
+          int K = kred[0][lr];
 #pragma unroll
-          for (int w = 1; w < C::WGN; ++w) m = fmax(m, xred[w][lr]);
-          const int K = block_exponent(m);
-          if (wn == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * nb + tc] = K;
+          for (int w = 1; w < C::WGN; ++w) K = max(K, kred[w][lr]);
+          if (wn == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc] = K;
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
             const int j = col0 + wn * C::WTN + cb * 16 + r16;
-            if (i < n && j < n) nA[(size_t)i * np + j] = block_operand<T>(fnew_v[cb][rb][e] * ninv, K);
+            const T x = block_operand<T>(fnew_v[cb][rb][e] * ninv, K);
+            if (i < n && j < n) nA[(size_t)i * np + j] = x;
           }
         }
-      (void)xm;
     }
   }
 }

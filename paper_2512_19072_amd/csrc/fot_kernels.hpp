@@ -93,6 +93,13 @@ template <> struct Mma<float> {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], bv[2], c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], bv[3], c, 0, 0, 0);
   }
+  // the q-th of run's NSUB products (callers interleave accumulators between them)
+  static constexpr int NSUB = 4;
+  static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int q) {
+    const f32x4 av = __builtin_bit_cast(f32x4, a);
+    const f32x4 bv = __builtin_bit_cast(f32x4, b);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], c, 0, 0, 0);
+  }
 };
 
 template <> struct Mma<double> {
@@ -106,6 +113,11 @@ template <> struct Mma<double> {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], c, 0, 0, 0);
   }
+  static constexpr int NSUB = 2;
+  static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int q) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(__builtin_bit_cast(d2, a)[q], __builtin_bit_cast(d2, b)[q], c, 0, 0, 0);
+  }
 };
 
 template <> struct Mma<__bf16> {
@@ -116,6 +128,8 @@ template <> struct Mma<__bf16> {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   }
+  static constexpr int NSUB = 1;
+  static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int) { run(a, b, c); }
 };
 
 template <> struct Mma<_Float16> {
@@ -126,6 +140,8 @@ template <> struct Mma<_Float16> {
     c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
                                                __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
   }
+  static constexpr int NSUB = 1;
+  static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int) { run(a, b, c); }
 };
 
 // ------------------------------------------------------------------ reductions
