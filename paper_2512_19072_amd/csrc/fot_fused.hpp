@@ -172,6 +172,29 @@ __global__ __launch_bounds__(64) void k_prep_blocks(const double* P, int n, int 
   }
 }
 
+// Wait until at most N vector-memory loads of this wave are outstanding (direct LDS loads
+// included: they complete in issue order with the others).
+template <int N>
+__device__ __forceinline__ void vm_wait() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14));
+}
+
+// 16-byte global -> LDS load of this lane's source; the wave's 64 lanes fill the 1 KB at
+// lds_dst (wave-uniform) in lane order.  Written in assembly so that the compiler does not
+// track it: completion is awaited explicitly (vm_wait) before the workgroup barrier that
+// publishes the stage, which lets two stages be in flight while a third is read.
+__device__ __forceinline__ void dma16(const void* src, const unsigned char* lds_dst) {
+  const unsigned lds_addr =
+      __builtin_amdgcn_readfirstlane((unsigned)(size_t)(const __attribute__((address_space(3))) unsigned char*)lds_dst);
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(lds_addr)
+               : "memory", "m0");
+}
+
+constexpr int FUSED_NBUF = 2;   // K stages resident in LDS (one in flight while one is consumed)
+
 // Launch with dynamic LDS of fused_dyn_lds<PASS, C>(np) bytes (the exponent-difference table).
 template <int PASS, typename C>
 constexpr int fused_scaled_rows() { return PASS == 1 ? C::BM : C::BN; }
@@ -181,8 +204,9 @@ inline size_t fused_dyn_lds(int np) {
   return (size_t)(np / xb) * fused_scaled_rows<PASS, C>() * sizeof(short);
 }
 
-template <typename T, int PASS, typename C>
+template <typename T, int PASS, typename C, int NBUF = FUSED_NBUF>
 __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
+  static_assert(NBUF >= 2, "at least double buffering");
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int BM = C::BM, BN = C::BN, RB = C::RB, CB = C::CB;
   constexpr int XB = PASS == 1 ? BN : BM;         // K extent of one exponent block of this pass
@@ -191,8 +215,13 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   constexpr int EPH = 64 / (int)sizeof(T);        // K elements per fragment step (4 lane groups)
   constexpr int HB = XB / EPH;                    // fragment steps per exponent block
   static_assert(HB >= 1 && XB % EPH == 0, "exponent blocks must hold whole fragment steps");
-  __shared__ __attribute__((aligned(16))) unsigned char ldsA[2][BM * LDS_RS];
-  __shared__ __attribute__((aligned(16))) unsigned char ldsB[2][BN * LDS_RS];
+  // K-stage buffers as distinct objects, so that the compiler can tell a direct load into one
+  // buffer from reads of another (it would otherwise wait for every load in flight)
+  __shared__ __attribute__((aligned(1024))) unsigned char lds0[(BM + BN) * ROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds1[(BM + BN) * ROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds2[(NBUF > 2 ? BM + BN : 1) * ROWB];
+  static_assert(NBUF <= 3, "three stage buffers at most");
+  auto bufp = [](int j) -> unsigned char* { return j == 0 ? lds0 : j == 1 ? lds1 : lds2; };
   extern __shared__ short dtab[];                 // [np / XB][SR]: exponent - row reference
   __shared__ int rref[SR];                        // reference exponent of each scaled row
   __shared__ double red[C::NW];
@@ -210,23 +239,58 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   const int row0 = tr * BM, col0 = tc * BN;
   const size_t plane = (size_t)np * np;
 
+  // ---- operand staging: each K stage of the tile (BM rows of A, then BN rows of B, 256 bytes
+  // per row) is copied global -> LDS by 16-byte direct loads (no register round trip).  A wave
+  // instruction fills 1 KB of LDS, lane l at byte 16 l: four rows of 256 bytes.  LDS rows are
+  // unpadded; the 16-byte chunk c of row r sits in slot c ^ (r mod 16), so the fragment reads
+  // (16 rows, one chunk) hit 16 distinct slots, i.e. all banks once.
   const size_t pitch = (size_t)np * sizeof(T);
   const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
   const unsigned char* Bb = (const unsigned char*)p.B + ((size_t)bz * p.sB) * sizeof(T) + (size_t)col0 * pitch;
-  constexpr int LA = BM * CHUNKS / C::THREADS, LB = BN * CHUNKS / C::THREADS;
-  constexpr int RSTEP = C::THREADS / CHUNKS;
-  const int rl = tid / CHUNKS, ql = tid % CHUNKS;
-  const unsigned char* Ag = Ab + (size_t)rl * pitch + (size_t)ql * 16;
-  const unsigned char* Bg = Bb + (size_t)rl * pitch + (size_t)ql * 16;
-  const int sofs = rl * LDS_RS + ql * 16;
-  u32x4 ga[LA], gb[LB];
+  constexpr int UNITS = (BM + BN) / 4;            // 1 KB load units per stage
+  constexpr int UPW = UNITS / C::NW;              // units per wave
+  static_assert(UNITS % C::NW == 0 && ROWB == 256, "stage staging assumes 256-byte rows in whole units per wave");
+  const unsigned char* dsrc[UPW];
+#pragma unroll
+  for (int i = 0; i < UPW; ++i) {
+    const int u = wave + C::NW * i;
+    const int r = 4 * u + (lane >> 4);
+    const int c = (lane & 15) ^ (r & 15);
+    dsrc[i] = (r < BM ? Ab + (size_t)r * pitch : Bb + (size_t)(r - BM) * pitch) + c * 16;
+  }
+  auto stage_load = [&](int kk, unsigned char* dst) {
+#pragma unroll
+    for (int i = 0; i < UPW; ++i) dma16(dsrc[i] + (size_t)kk * ROWB, dst + (wave + C::NW * i) * 1024);
+  };
 
-  // ---- prologue: every global read the tile needs before its first flush is issued here,
-  // the first K stage first, so that their latencies overlap
+  // ---- prologue: stage 0 and the exponent table first (the table build waits for its loads,
+  // and with them for stage 0), then the later stages and the epilogue inputs
+  stage_load(0, bufp(0));
+
+  // exponent table of the block-normalised operand for this tile's scaled rows
+  // (pass 1: A rows = output rows; pass 2: B rows = output columns)
+  {
+    const int srow0 = (PASS == 1) ? row0 : col0;
+    const int* kx = p.kexp + ((size_t)bz * np + srow0) * nbk;
+    for (int r = tid / 8; r < SR; r += C::THREADS / 8) {
+      const int sub = tid % 8;
+      int m = KSENT;
+      for (int b = sub; b < nbk; b += 8) m = max(m, kx[(size_t)r * nbk + b]);
+      m = max(m, __shfl_xor(m, 1, 64));
+      m = max(m, __shfl_xor(m, 2, 64));
+      m = max(m, __shfl_xor(m, 4, 64));
+      if (sub == 0) rref[r] = m;
+      for (int b = sub; b < nbk; b += 8) {
+        const int d = kx[(size_t)r * nbk + b] - m;
+        dtab[b * SR + r] = (short)max(d, -1100);   // 2^-1100 underflows to 0 in FP64
+      }
+    }
+  }
+  vm_wait<0>();
+  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
-#pragma unroll
-  for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch);
+  for (int kk = 1; kk < NBUF - 1; ++kk)
+    if (kk < p.nk) stage_load(kk, bufp(kk));
 
   // pass-2 epilogue inputs, prefetched so that their latency hides behind the K loop
   double la_v[CB][RB][4], fo_v[CB][RB][4];
@@ -260,26 +324,6 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     pend_v[q] = (pend_wg && t < p.pend_tiles) ? p.pend_parts[(size_t)bz * p.pend_tiles + t] : 0.0;
   }
 
-  // exponent table of the block-normalised operand for this tile's scaled rows
-  // (pass 1: A rows = output rows; pass 2: B rows = output columns)
-  {
-    const int srow0 = (PASS == 1) ? row0 : col0;
-    const int* kx = p.kexp + ((size_t)bz * np + srow0) * nbk;
-    for (int r = tid / 8; r < SR; r += C::THREADS / 8) {
-      const int sub = tid % 8;
-      int m = KSENT;
-      for (int b = sub; b < nbk; b += 8) m = max(m, kx[(size_t)r * nbk + b]);
-      m = max(m, __shfl_xor(m, 1, 64));
-      m = max(m, __shfl_xor(m, 2, 64));
-      m = max(m, __shfl_xor(m, 4, 64));
-      if (sub == 0) rref[r] = m;
-      for (int b = sub; b < nbk; b += 8) {
-        const int d = kx[(size_t)r * nbk + b] - m;
-        dtab[b * SR + r] = (short)max(d, -1100);   // 2^-1100 underflows to 0 in FP64
-      }
-    }
-  }
-
   acc_t acc[RB][CB];
   f64x4 accd[RB][CB];
 #pragma unroll
@@ -290,41 +334,37 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       accd[i][j] = f64x4{};
     }
 
-  // Main loop over K stages, LDS double-buffered.  Within a stage the fragments of step h+1 are
-  // read while the MFMAs of step h run; at the end of a stage the next stage's tiles are stored,
-  // the workgroup synchronises, the next stage's first fragments are requested, and only then
-  // is the exponent block flushed, so that the FP64 flush overlaps the LDS latency.
-#pragma unroll
-  for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[0][sofs + u * RSTEP * LDS_RS]) = ga[u];
-#pragma unroll
-  for (int u = 0; u < LB; ++u) *(u32x4*)(&ldsB[0][sofs + u * RSTEP * LDS_RS]) = gb[u];
-  __syncthreads();
-  const int aofs = (wm * C::WTM + r16) * LDS_RS + g * 16;
-  const int bofs = (wn * C::WTN + r16) * LDS_RS + g * 16;
+  // Main loop over K stages, NBUF LDS buffers (stage kt + NBUF - 1 is requested when stage kt
+  // starts).  Within a stage the fragments of step h+1 are read while the MFMAs of step h run;
+  // at the end of a stage the workgroup waits for the next stage, synchronises, requests the
+  // next stage's first fragments, and only then flushes the exponent block, so that the FP64
+  // flush overlaps the LDS latency.
+  const int arow = (wm * C::WTM + r16) * ROWB, brow = (BM + wn * C::WTN + r16) * ROWB;
+  const int sw = (g ^ r16) << 4;                  // slot of chunk 4h+g in this lane's rows, h = 0
   u32x4 af[RB], bf[CB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) af[rb] = *(const u32x4*)(&ldsA[0][aofs + rb * 16 * LDS_RS]);
+  for (int rb = 0; rb < RB; ++rb) af[rb] = *(const u32x4*)(&lds0[arow + rb * 16 * ROWB + sw]);
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) bf[cb] = *(const u32x4*)(&ldsB[0][bofs + cb * 16 * LDS_RS]);
-  for (int kt = 0; kt < p.nk; ++kt) {
-    const int s = kt & 1;
+  for (int cb = 0; cb < CB; ++cb) bf[cb] = *(const u32x4*)(&lds0[brow + cb * 16 * ROWB + sw]);
+  for (int kt0 = 0; kt0 < p.nk; kt0 += NBUF)
+#pragma unroll
+  for (int jb = 0; jb < NBUF; ++jb) {                // stage kt uses buffer jb = kt mod NBUF
+    const int kt = kt0 + jb;
+    if (kt >= p.nk) break;
+    const unsigned char* cur = bufp(jb);
     const bool more = kt + 1 < p.nk;
-    if (more) {
-      const size_t ko = (size_t)(kt + 1) * ROWB;
-#pragma unroll
-      for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch + ko);
-#pragma unroll
-      for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch + ko);
-    }
+    const bool ahead = kt + NBUF - 1 < p.nk;       // a stage is requested NBUF - 1 ahead
+    if (ahead) stage_load(kt + NBUF - 1, bufp((jb + NBUF - 1) % NBUF));
 #pragma unroll
     for (int h = 0; h < HPS; ++h) {
       const bool last = h + 1 == HPS;
       u32x4 an[RB] = {}, bn[CB] = {};
       if (!last) {
+        const int so = sw ^ ((h + 1) << 6);        // chunk 4(h+1)+g
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&ldsA[s][aofs + rb * 16 * LDS_RS + (h + 1) * 64]);
+        for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&cur[arow + rb * 16 * ROWB + so]);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&ldsB[s][bofs + cb * 16 * LDS_RS + (h + 1) * 64]);
+        for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&cur[brow + cb * 16 * ROWB + so]);
       }
       // sub-products outermost: consecutive MFMAs go to different accumulators
 #pragma unroll
@@ -334,18 +374,21 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) Mma<T>::sub(af[rb], bf[cb], acc[rb][cb], q);
       if (last) {
+        if (ahead && NBUF > 2)
+          vm_wait<(NBUF > 2 ? UPW : 0)>();         // stage kt+1 landed; kt+NBUF-1 may be in flight
+        else
+          vm_wait<0>();
+        // workgroup barrier without a memory fence (a fence would wait for the stage still in
+        // flight); the compiler-only fences keep LDS accesses on their side of it
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (more) {
+          const unsigned char* nxt = bufp((jb + 1) % NBUF);
 #pragma unroll
-          for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[s ^ 1][sofs + u * RSTEP * LDS_RS]) = ga[u];
+          for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&nxt[arow + rb * 16 * ROWB + sw]);
 #pragma unroll
-          for (int u = 0; u < LB; ++u) *(u32x4*)(&ldsB[s ^ 1][sofs + u * RSTEP * LDS_RS]) = gb[u];
-        }
-        __syncthreads();
-        if (more) {
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&ldsA[s ^ 1][aofs + rb * 16 * LDS_RS]);
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&ldsB[s ^ 1][bofs + cb * 16 * LDS_RS]);
+          for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&nxt[brow + cb * 16 * ROWB + sw]);
         }
       }
       const int hh = kt * HPS + h;
