@@ -49,7 +49,8 @@ typedef enum {
 typedef enum { FOT_F64 = 0, FOT_F32 = 1, FOT_BF16 = 2, FOT_F16 = 3 } fot_precision;
 
 enum {
-  FOT_FLAG_PROFILE = 1,  /* time every contraction launch with HIP events (fot_report.ms_contract);
+  FOT_FLAG_PROFILE = 1,  /* time every launch of the iteration kernels (the fused per-axis
+                            contractions of Eq. 7-8) with HIP events (fot_report.ms_contract);
                             the iteration loop is then launched kernel by kernel (events
                             recorded inside a graph cannot be timed) */
   FOT_FLAG_NO_GRAPH = 2  /* launch the iteration loop kernel by kernel instead of replaying a
@@ -78,8 +79,8 @@ typedef struct {
   int nonfinite;          /* 1 if a non-finite potential appeared (status FOT_E_NONFINITE) */
   double ms_total;        /* HIP-event time of the whole solve on the plan's stream */
   double ms_iterations;   /* HIP-event time of the iteration loop only */
-  double ms_contract;     /* FOT_FLAG_PROFILE: summed HIP-event time of contraction launches */
-  int n_contract;         /* FOT_FLAG_PROFILE: number of contraction launches timed */
+  double ms_contract;     /* FOT_FLAG_PROFILE: summed HIP-event time of the iteration kernels */
+  int n_contract;         /* FOT_FLAG_PROFILE: number of iteration-kernel launches timed */
   int graph;              /* 1 if the iteration loop was replayed as a HIP graph */
 } fot_report;
 

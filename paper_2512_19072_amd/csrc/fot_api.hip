@@ -164,23 +164,11 @@ struct Ops {
   static fot_status gemm_launch(fot_plan_s* p, int epi, const GemmArgs& a) {
     dim3 grid(p->np / GC::BN, p->np / GC::BM, p->B);
     const dim3 block(GC::THREADS);
-    const bool prof = (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
-    // profiled launches carry start/stop events that bracket the kernel's own execution
-    hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
-    hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
-    switch (epi) {
-      case EPI_LOGROW:
-        hipExtLaunchKernelGGL((k_gemm<T, EPI_LOGROW, GC>), grid, block, 0, p->stream, e0, e1, 0, a);
-        break;
-      case EPI_UPDATE:
-        hipExtLaunchKernelGGL((k_gemm<T, EPI_UPDATE, GC>), grid, block, 0, p->stream, e0, e1, 0, a);
-        break;
-      default:
-        hipExtLaunchKernelGGL((k_gemm<T, EPI_RAW, GC>), grid, block, 0, p->stream, e0, e1, 0, a);
-        break;
-    }
+    if (epi == EPI_LOGROW)
+      hipLaunchKernelGGL((k_gemm<T, EPI_LOGROW, GC>), grid, block, 0, p->stream, a);
+    else
+      hipLaunchKernelGGL((k_gemm<T, EPI_RAW, GC>), grid, block, 0, p->stream, a);
     LAUNCH_CHECK();
-    if (prof) p->prof_used += 2;
     return FOT_OK;
   }
 

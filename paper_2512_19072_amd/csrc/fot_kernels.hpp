@@ -181,7 +181,7 @@ __device__ __forceinline__ double block_max(double v, double* scratch) {
 }
 
 // ------------------------------------------------------------------ GEMM (C = A . B^T)
-enum Epilogue { EPI_LOGROW = 0, EPI_UPDATE = 1, EPI_RAW = 2 };
+enum Epilogue { EPI_LOGROW = 0, EPI_RAW = 2 };
 
 struct GemmArgs {
   const void* A;            // [batch][np][np] (row i, K contiguous); sA = 0 shares it
@@ -194,14 +194,6 @@ struct GemmArgs {
   long long sOut;
   const double* mrow;       // [batch][np] row shifts of the pass-1 operand
   unsigned* colkey;         // [batch][np] column-max keys (pass 1 writes, pass 2 reads)
-  // EPI_UPDATE
-  const double* lnmarg;     // ln a or ln b, [np][np] with batch stride sMarg
-  long long sMarg;
-  double* pot;              // potential updated in place, [batch][np][np]
-  double* lnS_out;          // optional copy of ln S
-  double eps, inv_eps;
-  double* partials;         // [batch][tiles] per-workgroup marginal-error partials
-  int* flag;                // bit 0: non-finite potential
 };
 
 // Map the linear workgroup id to a tile so that the workgroups that land on one XCD
@@ -246,7 +238,6 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   constexpr int BM = C::BM, BN = C::BN, RB = C::RB, CB = C::CB;
   __shared__ __attribute__((aligned(16))) unsigned char ldsA[2][BM * LDS_RS];
   __shared__ __attribute__((aligned(16))) unsigned char ldsB[2][BN * LDS_RS];
-  __shared__ double red[C::NW];
   __shared__ float cmax[C::WGM][BN];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -283,28 +274,6 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int j = 0; j < CB; ++j) accd[i][j] = f64x4{};
-
-  // EPI_UPDATE reads ln(marginal) and the old potential of its outputs; the loads are
-  // issued here so that their latency is hidden behind the K loop.
-  double la_v[CB][RB][4], fo_v[CB][RB][4];
-  if constexpr (EPI == EPI_UPDATE) {
-    const double* lnm = p.lnmarg + (size_t)bz * p.sMarg;
-    const double* pot = p.pot + (size_t)bz * (size_t)p.np * p.np;
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int j = col0 + wn * C::WTN + cb * 16 + r16;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
-          const bool ok = i < p.n && j < p.n;
-          const size_t o = (size_t)i * p.np + j;
-          la_v[cb][rb][e] = ok ? lnm[o] : 0.0;
-          fo_v[cb][rb][e] = ok ? pot[o] : 0.0;
-        }
-    }
-  }
 
 #pragma unroll
   for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
@@ -366,17 +335,12 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
     else
       return (double)acc[rb][cb][e];
   };
-  // ln of a result.  The pass-1 output is stored in FP32 anyway, so logf of the once-rounded
-  // sum suffices there; the potential update takes an FP64 log for FP32 and FP64 operands (the
-  // rounding of logf is correlated enough to be amplified through the iterations and their
-  // adjoint) and logf for 16-bit operands, whose own rounding is far larger.
-  auto log_result = [&](int rb, int cb, int e, bool fine) -> double {
-    if constexpr (FLUSH) {
-      if (fine && sizeof(T) == 4) return log(accd[rb][cb][e]);
+  // ln of a result (the FP32 output of FP32/16-bit operands is stored rounded anyway)
+  auto log_result = [&](int rb, int cb, int e) -> double {
+    if constexpr (FLUSH)
       return (double)logf((float)accd[rb][cb][e]);
-    } else {
+    else
       return log((double)acc[rb][cb][e]);
-    }
   };
   const int n = p.n, np = p.np;
   if constexpr (EPI == EPI_RAW) {
@@ -406,7 +370,7 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
           const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int j = col0 + wn * C::WTN + cb * 16 + r16;
           if (i < n && j < n) {
-            const zt z = (zt)log_result(rb, cb, e, false);
+            const zt z = (zt)log_result(rb, cb, e);
             out[(size_t)i * np + j] = z;
             cm[cb] = fmax(cm[cb], mrow[i] + (double)z);
           }
@@ -425,55 +389,6 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
       const int j = col0 + tid;
       if (j < n && m > -INFINITY) atomicMax(p.colkey + (size_t)bz * np + j, float_key(m));
     }
-  } else {  // EPI_UPDATE
-    const double eps = p.eps, inv_eps = p.inv_eps;
-    double* pot = p.pot + (size_t)bz * (size_t)np * np;
-    double* lns = p.lnS_out ? p.lnS_out + (size_t)bz * (size_t)np * np : nullptr;
-    const unsigned* ck = p.colkey + (size_t)bz * np;
-    double err = 0.0;
-    int bad = 0;
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int j = col0 + wn * C::WTN + cb * 16 + r16;
-      const double shift = (j < n) ? key_to_shift(ck[j]) : 0.0;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
-          if (i < n && j < n) {
-            const size_t o = (size_t)i * np + j;
-            // ln S, shifted in FP64
-            const double lnS = shift + log_result(rb, cb, e, true);
-            const double la = la_v[cb][rb][e];
-            const double fold = fo_v[cb][rb][e];
-            double fnew;
-            if (la == -INFINITY) {
-              fnew = -INFINITY;
-              // entering plan's mass on a zero-mass pixel: u_old * S
-              if constexpr (sizeof(zt) == 8)
-                err += exp(fold * inv_eps + lnS);
-              else
-                err += (double)expf((float)(fold * inv_eps + lnS));
-            } else {
-              fnew = eps * (la - lnS);
-              // a |u_old / u_new - 1| = a |exp((f_old - f_new)/eps) - 1|
-              if constexpr (sizeof(zt) == 8)
-                err += fabs(exp(la + (fold - fnew) * inv_eps) - exp(la));
-              else
-                err += (double)(expf((float)la) * fabsf(expm1f((float)((fold - fnew) * inv_eps))));
-              bad |= !(fabs(fnew) < INFINITY);
-            }
-            pot[o] = fnew;
-            if (lns) lns[o] = lnS;
-          }
-        }
-    }
-    if (bad) atomicOr(p.flag, 1);
-    // per-workgroup partial; the next kernel in stream order sums them in index order
-    const double part = block_sum(err, red);
-    const int tiles = gridDim.x * gridDim.y;
-    if (tid == 0) p.partials[(size_t)bz * tiles + blockIdx.x + gridDim.x * blockIdx.y] = part;
   }
 }
 

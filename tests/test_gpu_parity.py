@@ -238,4 +238,4 @@ def test_graph_replays_match_eager(profile):
         assert bool((ph == r[0]).all()) and bool((f == r[1]).all()) and bool((psi == r[2]).all()), (it, key)
         assert np.array_equal(rep.err_a_history, r[3]) and np.array_equal(rep.dual, r[4]), (it, key)
         if profile:
-            assert rep.n_contract == 4 * T + 8 and rep.ms_contract > 0
+            assert rep.n_contract == 4 * T and rep.ms_contract > 0   # the iteration kernels only
