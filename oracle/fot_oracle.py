@@ -326,10 +326,22 @@ def sep_log_apply(X: np.ndarray, lam_left: np.ndarray, lam_right: np.ndarray,
     return lnS, ratios
 
 
-def _solve_sep_one(a, b, la, lb, e, iters, keep_tape=False):
+def _mass_minus_marginal(m, lnm, d):
+    """sum |m exp(d) - m| over pixels of positive marginal m (ln m given): the entering plan's
+    pixel mass m e^d is at most the plan's total mass, but e^d alone overflows for tiny m, so
+    large d use exp(ln m + d) - m (the same quantity)."""
+    small = d < 10.0
+    return float(np.sum(m[small] * np.abs(np.expm1(d[small])))
+                 + np.sum(np.abs(np.exp(lnm[~small] + d[~small]) - m[~small])))
+
+
+def _solve_sep_one(a, b, la, lb, e, iters, keep_tape=False, start=None):
     n = a.shape[0]
-    f = np.full((n, n), e[0] * math.log(1.0 / (n * n)))
-    psi = np.full((n, n), e[0] * math.log(1.0 / (n * n)))
+    if start is None:
+        f = np.full((n, n), e[0] * math.log(1.0 / (n * n)))
+        psi = np.full((n, n), e[0] * math.log(1.0 / (n * n)))
+    else:                                       # continue from given potentials (f, psi)
+        f, psi = (np.array(x, dtype=np.float64) for x in start)
     err_a_hist = np.zeros(iters)
     err_b_hist = np.zeros(iters)
     dual_hist = np.zeros(iters)
@@ -350,14 +362,14 @@ def _solve_sep_one(a, b, la, lb, e, iters, keep_tape=False):
         # marginal identity: row sums of the entering plan are u_old S = a exp((f_old - f_new)/eps)
         # where a > 0, and exp(f_old/eps + ln S) where a = 0 (nonzero only while f_old is finite)
         with np.errstate(invalid="ignore", over="ignore"):
-            err_a_hist[t] = (np.sum(a[am] * np.abs(np.exp((f[am] - f_new[am]) / ep) - 1.0))
+            err_a_hist[t] = (_mass_minus_marginal(a[am], la[am], (f[am] - f_new[am]) / ep)
                              + np.sum(np.exp(f[~am] / ep + lnS[~am])))
         f = f_new
         # Eq. 8 in log form
         lnSp, _ = sep_log_apply(f / ep, lam, lam)
         psi_new = np.where(bm, ep * (lb - lnSp), NEG_INF)
         with np.errstate(invalid="ignore", over="ignore"):
-            err_b_hist[t] = (np.sum(b[bm] * np.abs(np.exp((psi[bm] - psi_new[bm]) / ep) - 1.0))
+            err_b_hist[t] = (_mass_minus_marginal(b[bm], lb[bm], (psi[bm] - psi_new[bm]) / ep)
                              + np.sum(np.exp(psi[~bm] / ep + lnSp[~bm])))
         psi_prev, psi = psi, psi_new
         # after a V-update sum(Gamma) = sum(b) = 1
@@ -396,19 +408,21 @@ def _readout(a, b, la, lb, f, psi, lnS_last, lnSp_last, ep):
     return Tx, Ty, err_a, err_b, mass, cost, dual
 
 
-def solve_sep(g: np.ndarray, G: np.ndarray, eps, iters: int):
+def solve_sep(g: np.ndarray, G: np.ndarray, eps, iters: int, start=None):
     """O2: separable FOT (Algorithm 1) in FP64.  ``G`` may be [n][n] or [B][n][n].
 
-    Returns a :class:`Result` for a single target, or a list of them for a batch.
+    ``start = (f, psi)`` continues from given potentials instead of u = V = 1/n^2 (single
+    target only).  Returns a :class:`Result` for a single target, or a list of them for a batch.
     """
     G = np.asarray(G, dtype=np.float64)
     if G.ndim == 3:
+        assert start is None, "start potentials are per target"
         return [solve_sep(g, Gb, eps, iters) for Gb in G]
     e = eps_schedule(eps, iters)
     a = normalise(g)
     b = normalise(G)
     la, lb = log_intensity(g), log_intensity(G)
-    f, psi, psi_prev, lnS, lnSp, ea, eb, dh, _ = _solve_sep_one(a, b, la, lb, e, iters)
+    f, psi, psi_prev, lnS, lnSp, ea, eb, dh, _ = _solve_sep_one(a, b, la, lb, e, iters, start=start)
     Tx, Ty, err_a, err_b, mass, cost, dual = _readout(a, b, la, lb, f, psi, lnS, lnSp, e[-1])
     return Result(f=f, psi=psi, lnS_last=lnS, err_a_hist=ea, err_b_hist=eb, dual_hist=dh,
                   err_a=err_a, err_b=err_b, dual=dual, cost=cost, mass=mass,

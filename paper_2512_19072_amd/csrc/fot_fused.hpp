@@ -524,9 +524,13 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const bool zm = la == -INFINITY;
           const double fnew = (ok && !zm) ? eps * (la - lnS) : -INFINITY;
           // marginal-error term of the entering plan at this pixel: on a zero-mass pixel its
-          // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp((f_old - f_new)/eps) - 1|
+          // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp(d) - 1| with
+          // d = (f_old - f_new)/eps, evaluated as exp(ln a + d) - a once d is large (a e^d is the
+          // pixel's entering mass, at most 1, while e^d alone can overflow FP32 for tiny a)
           const float tz = expf((float)(fold * inv_eps + lnS));
-          const float ta = expf((float)la) * fabsf(expm1f((float)((fold - fnew) * inv_eps)));
+          const double d = (fold - fnew) * inv_eps;
+          const float ta = (d < 10.0) ? expf((float)la) * fabsf(expm1f((float)d))
+                                      : expf((float)(la + d)) - expf((float)la);
           err += ok ? (double)(zm ? tz : ta) : 0.0;
           bad = bad || (ok && !zm && !(fabs(fnew) < INFINITY));
           const size_t o = (size_t)i * np + j;

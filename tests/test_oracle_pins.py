@@ -391,3 +391,38 @@ def test_grad_envelope_limit():
     b = G * G / Z
     env = (2 * G / Z) * (r.psi - np.sum(r.psi * b))
     np.testing.assert_allclose(grad, env, atol=1e-9)
+
+
+def test_continuing_from_potentials_equals_one_run():
+    """O2 continued from the potentials of 30 iterations equals 60 iterations (bit for bit in
+    the potentials; the phase and scalars come from the same final state)."""
+    rng = np.random.default_rng(11)
+    n = 16
+    g = rng.uniform(0.2, 1.0, (n, n))
+    G = rng.uniform(0.0, 1.0, (n, n))
+    G[3] = 0.0
+    e = O.eps_schedule(np.geomspace(5e-2, 5e-3, 60), 60)
+    full = O.solve_sep(g, G, e, 60)
+    half = O.solve_sep(g, G, e[:30], 30)
+    rest = O.solve_sep(g, G, e[30:], 30, start=(half.f, half.psi))
+    assert np.array_equal(rest.f, full.f) and np.array_equal(rest.psi, full.psi)
+    assert np.array_equal(rest.phase, full.phase) and rest.dual == full.dual
+    assert np.array_equal(rest.err_a_hist, full.err_a_hist[30:])
+
+
+def test_history_with_tiny_marginals_matches_dense():
+    """Marginal-error history (Sec. 3 convergence criterion) with marginals near the FP64
+    underflow limit: the separable form's fused identity must stay finite and equal the dense
+    definition (row and column sums of the entering plan), where exp((f_old - f_new)/eps)
+    alone would overflow."""
+    rng = np.random.default_rng(5)
+    n = 8
+    g = rng.uniform(0.5, 1.0, (n, n))
+    G = rng.uniform(0.5, 1.0, (n, n))
+    G[2, 3] = 1e-160          # b ~ 1e-320
+    g[5, 1] = 1e-158          # a ~ 1e-316
+    dense = O.solve_dense(g, G, 2e-2, 12)
+    sep = O.solve_sep(g, G, 2e-2, 12)
+    assert np.all(np.isfinite(sep.err_a_hist)) and np.all(np.isfinite(sep.err_b_hist))
+    np.testing.assert_allclose(sep.err_a_hist, dense.err_a_hist, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(sep.err_b_hist, dense.err_b_hist, rtol=1e-9, atol=1e-15)
