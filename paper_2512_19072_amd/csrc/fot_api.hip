@@ -232,7 +232,7 @@ struct Ops {
     FusedArgs a{};
     a.n = p->n;
     a.np = p->np;
-    a.nk = (int)((size_t)p->np * sizeof(T) / ROWB);
+    a.nk = (int)((size_t)p->np * sizeof(T) / FROWB);
     a.nbA = p->nbA;
     a.nbT = p->nbT;
     a.xcd_swizzle = 1;
@@ -605,8 +605,10 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   p->d = d;
   p->n = d.n;
   p->esz = d.precision == FOT_F64 ? 8 : d.precision == FOT_F32 ? 4 : 2;
-  // padded side: whole 64-pixel tiles and whole ROWB-byte K stages
-  const int align = std::max(TILE, (int)(ROWB / p->esz));
+  // padded side: whole 64-pixel tiles and whole K stages of the fused kernels (FROWB bytes,
+  // a multiple of the read-out GEMM's ROWB)
+  static_assert(FROWB % ROWB == 0, "fused stages must also be whole read-out stages");
+  const int align = std::max(TILE, (int)(FROWB / p->esz));
   p->np = ((d.n + align - 1) / align) * align;
   p->B = d.batch;
   p->prec = d.precision;

@@ -193,6 +193,8 @@ __device__ __forceinline__ void dma16(const void* src, const unsigned char* lds_
                : "memory", "m0");
 }
 
+constexpr int FRAG_AHEAD = 2;  // LDS fragment reads issued this many MMA steps ahead
+constexpr int FROWB = 512;      // bytes of one operand row per K stage of the fused kernels
 constexpr int FUSED_NBUF = 2;   // K stages resident in LDS (one in flight while one is consumed)
 
 // Launch with dynamic LDS of fused_dyn_lds<PASS, C>(np) bytes (the exponent-difference table).
@@ -211,15 +213,15 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   constexpr int BM = C::BM, BN = C::BN, RB = C::RB, CB = C::CB;
   constexpr int XB = PASS == 1 ? BN : BM;         // K extent of one exponent block of this pass
   constexpr int SR = fused_scaled_rows<PASS, C>(); // rows whose exponents scale the sums
-  constexpr int HPS = CHUNKS / 4;                 // fragment steps per K stage
+  constexpr int HPS = FROWB / 64;                 // fragment steps per K stage
   constexpr int EPH = 64 / (int)sizeof(T);        // K elements per fragment step (4 lane groups)
   constexpr int HB = XB / EPH;                    // fragment steps per exponent block
   static_assert(HB >= 1 && XB % EPH == 0, "exponent blocks must hold whole fragment steps");
   // K-stage buffers as distinct objects, so that the compiler can tell a direct load into one
   // buffer from reads of another (it would otherwise wait for every load in flight)
-  __shared__ __attribute__((aligned(1024))) unsigned char lds0[(BM + BN) * ROWB];
-  __shared__ __attribute__((aligned(1024))) unsigned char lds1[(BM + BN) * ROWB];
-  __shared__ __attribute__((aligned(1024))) unsigned char lds2[(NBUF > 2 ? BM + BN : 1) * ROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds0[(BM + BN) * FROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds1[(BM + BN) * FROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds2[(NBUF > 2 ? BM + BN : 1) * FROWB];
   static_assert(NBUF <= 3, "three stage buffers at most");
   auto bufp = [](int j) -> unsigned char* { return j == 0 ? lds0 : j == 1 ? lds1 : lds2; };
   extern __shared__ short dtab[];                 // [np / XB][SR]: exponent - row reference
@@ -247,20 +249,22 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   const size_t pitch = (size_t)np * sizeof(T);
   const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
   const unsigned char* Bb = (const unsigned char*)p.B + ((size_t)bz * p.sB) * sizeof(T) + (size_t)col0 * pitch;
-  constexpr int UNITS = (BM + BN) / 4;            // 1 KB load units per stage
+  constexpr int RPU = 1024 / FROWB;                // rows per 1 KB load unit
+  constexpr int CPR = FROWB / 16;                 // 16-byte chunks per row
+  constexpr int UNITS = (BM + BN) / RPU;          // 1 KB load units per stage
   constexpr int UPW = UNITS / C::NW;              // units per wave
-  static_assert(UNITS % C::NW == 0 && ROWB == 256, "stage staging assumes 256-byte rows in whole units per wave");
+  static_assert(UNITS % C::NW == 0 && BM % RPU == 0, "stage staging: whole units per wave, A/B split on a unit");
   const unsigned char* dsrc[UPW];
 #pragma unroll
   for (int i = 0; i < UPW; ++i) {
     const int u = wave + C::NW * i;
-    const int r = 4 * u + (lane >> 4);
-    const int c = (lane & 15) ^ (r & 15);
+    const int r = RPU * u + lane / CPR;
+    const int c = (lane % CPR) ^ (r & 15);
     dsrc[i] = (r < BM ? Ab + (size_t)r * pitch : Bb + (size_t)(r - BM) * pitch) + c * 16;
   }
   auto stage_load = [&](int kk, unsigned char* dst) {
 #pragma unroll
-    for (int i = 0; i < UPW; ++i) dma16(dsrc[i] + (size_t)kk * ROWB, dst + (wave + C::NW * i) * 1024);
+    for (int i = 0; i < UPW; ++i) dma16(dsrc[i] + (size_t)kk * FROWB, dst + (wave + C::NW * i) * 1024);
   };
 
   // ---- prologue: stage 0 and the exponent table first (the table build waits for its loads,
@@ -324,28 +328,46 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     pend_v[q] = (pend_wg && t < p.pend_tiles) ? p.pend_parts[(size_t)bz * p.pend_tiles + t] : 0.0;
   }
 
-  acc_t acc[RB][CB];
+  // Two sets of block accumulators, alternating by exponent block, so that a finished block is
+  // flushed (FP64 rescale and add) one step later, while the next block's MFMAs run into the
+  // other set; the block's exponent differences are read from LDS when the block starts.
+  constexpr int ND = (PASS == 1) ? RB * 4 : CB;   // distinct scaled rows per lane
+  acc_t acc[2][RB][CB];
   f64x4 accd[RB][CB];
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
-      acc[i][j] = acc_t{};
+      acc[0][i][j] = acc_t{};
+      acc[1][i][j] = acc_t{};
       accd[i][j] = f64x4{};
     }
+  int dcur[ND], dprev[ND];
+#pragma unroll
+  for (int q = 0; q < ND; ++q) dcur[q] = dprev[q] = 0;
+  // scaled row of exponent-difference entry q of this lane
+  auto srow = [&](int q) -> int {
+    return (PASS == 1) ? wm * C::WTM + (q / 4) * 16 + Mma<T>::row(g, q % 4) : wn * C::WTN + q * 16 + r16;
+  };
 
   // Main loop over K stages, NBUF LDS buffers (stage kt + NBUF - 1 is requested when stage kt
   // starts).  Within a stage the fragments of step h+1 are read while the MFMAs of step h run;
-  // at the end of a stage the workgroup waits for the next stage, synchronises, requests the
-  // next stage's first fragments, and only then flushes the exponent block, so that the FP64
-  // flush overlaps the LDS latency.
-  const int arow = (wm * C::WTM + r16) * ROWB, brow = (BM + wn * C::WTN + r16) * ROWB;
+  // at the end of a stage the workgroup waits for the next stage, synchronises and requests the
+  // next stage's first fragments.
+  static_assert((NBUF * HPS) % (2 * HB) == 0, "block parity must repeat with the unrolled stages");
+  const int arow = (wm * C::WTM + r16) * FROWB, brow = (BM + wn * C::WTN + r16) * FROWB;
   const int sw = (g ^ r16) << 4;                  // slot of chunk 4h+g in this lane's rows, h = 0
-  u32x4 af[RB], bf[CB];
+  // fragments of PD consecutive steps are in flight: slot h % PD holds step h of the stage
+  constexpr int PD = FRAG_AHEAD + 1;
+  static_assert(HPS >= PD, "a stage holds at least the fragments in flight");
+  u32x4 fa[PD][RB], fb[PD][CB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) af[rb] = *(const u32x4*)(&lds0[arow + rb * 16 * ROWB + sw]);
+  for (int hs = 0; hs < PD - 1; ++hs) {
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) bf[cb] = *(const u32x4*)(&lds0[brow + cb * 16 * ROWB + sw]);
+    for (int rb = 0; rb < RB; ++rb) fa[hs][rb] = *(const u32x4*)(&lds0[arow + rb * 16 * FROWB + (sw ^ (hs << 6))]);
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) fb[hs][cb] = *(const u32x4*)(&lds0[brow + cb * 16 * FROWB + (sw ^ (hs << 6))]);
+  }
   for (int kt0 = 0; kt0 < p.nk; kt0 += NBUF)
 #pragma unroll
   for (int jb = 0; jb < NBUF; ++jb) {                // stage kt uses buffer jb = kt mod NBUF
@@ -357,14 +379,22 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     if (ahead) stage_load(kt + NBUF - 1, bufp((jb + NBUF - 1) % NBUF));
 #pragma unroll
     for (int h = 0; h < HPS; ++h) {
+      const int hl = jb * HPS + h;                 // step within the unrolled stages
+      const int par = (hl / HB) & 1;               // accumulator set of this step's block
+      const bool first = hl % HB == 0, lastb = (hl + 1) % HB == 0;
       const bool last = h + 1 == HPS;
-      u32x4 an[RB] = {}, bn[CB] = {};
-      if (!last) {
-        const int so = sw ^ ((h + 1) << 6);        // chunk 4(h+1)+g
+      if (first) {
+        const int blk = (kt * HPS + h) / HB;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&cur[arow + rb * 16 * ROWB + so]);
+        for (int q = 0; q < ND; ++q) dcur[q] = dtab[blk * SR + srow(q)];
+      }
+      if (h + PD - 1 < HPS) {
+        const int ha = h + PD - 1;                 // step whose fragments are requested now
+        const int so = sw ^ (ha << 6);             // chunk 4 ha + g
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&cur[brow + cb * 16 * ROWB + so]);
+        for (int rb = 0; rb < RB; ++rb) fa[ha % PD][rb] = *(const u32x4*)(&cur[arow + rb * 16 * FROWB + so]);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) fb[ha % PD][cb] = *(const u32x4*)(&cur[brow + cb * 16 * FROWB + so]);
       }
       // sub-products outermost: consecutive MFMAs go to different accumulators
 #pragma unroll
@@ -372,7 +402,23 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) Mma<T>::sub(af[rb], bf[cb], acc[rb][cb], q);
+          for (int cb = 0; cb < CB; ++cb) Mma<T>::sub(fa[h % PD][rb], fb[h % PD][cb], acc[par][rb][cb], q);
+      if (first && !(kt == 0 && h == 0)) {
+        // flush the previous block (other set) with its exact power-of-two scales
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              accd[rb][cb][e] += ldexp((double)acc[par ^ 1][rb][cb][e], dprev[PASS == 1 ? rb * 4 + e : cb]);
+            acc[par ^ 1][rb][cb] = acc_t{};
+          }
+      }
+      if (lastb) {
+#pragma unroll
+        for (int q = 0; q < ND; ++q) dprev[q] = dcur[q];
+      }
       if (last) {
         if (ahead && NBUF > 2)
           vm_wait<(NBUF > 2 ? UPW : 0)>();         // stage kt+1 landed; kt+NBUF-1 may be in flight
@@ -386,32 +432,30 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         if (more) {
           const unsigned char* nxt = bufp((jb + 1) % NBUF);
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb) an[rb] = *(const u32x4*)(&nxt[arow + rb * 16 * ROWB + sw]);
+          for (int hs = 0; hs < PD - 1; ++hs) {
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) bn[cb] = *(const u32x4*)(&nxt[brow + cb * 16 * ROWB + sw]);
+            for (int rb = 0; rb < RB; ++rb)
+              fa[hs][rb] = *(const u32x4*)(&nxt[arow + rb * 16 * FROWB + (sw ^ (hs << 6))]);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+              fb[hs][cb] = *(const u32x4*)(&nxt[brow + cb * 16 * FROWB + (sw ^ (hs << 6))]);
+          }
         }
       }
-      const int hh = kt * HPS + h;
-      if ((hh + 1) % HB == 0) {
-        // end of an exponent block: add its partial sums, scaled exactly by 2^(K - Kref)
-        const int blk = hh / HB;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int sr = (PASS == 1) ? wm * C::WTM + rb * 16 + Mma<T>::row(g, e) : wn * C::WTN + cb * 16 + r16;
-              accd[rb][cb][e] += ldexp((double)acc[rb][cb][e], (int)dtab[blk * SR + sr]);
-            }
-            acc[rb][cb] = acc_t{};
-          }
-      }
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) af[rb] = an[rb];
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) bf[cb] = bn[cb];
     }
+  }
+  {
+    // flush the last block: it used set ((K steps - 1) / HB) & 1
+    const int lastpar = (((p.nk * HPS) - 1) / HB) & 1;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double v = lastpar ? (double)acc[1][rb][cb][e] : (double)acc[0][rb][cb][e];
+          accd[rb][cb][e] += ldexp((double)v, dprev[PASS == 1 ? rb * 4 + e : cb]);
+        }
   }
 
   // ---------------------------------------------------------------- epilogues
