@@ -217,10 +217,15 @@ class Plan:
         flags = (FOT_FLAG_PROFILE if profile else 0) | (0 if graph else FOT_FLAG_NO_GRAPH)
         self.handle = fot_plan(n, batch, precision, max_iters, checkpoint_every, flags)
 
-    def solve(self, g, G, eps, iters: int, warm_start: bool = False, phase: bool = True, check: bool = True):
-        """Run fot_solve; returns (phase tensor or None, Report, status)."""
+    def solve(self, g, G, eps, iters: int, warm_start: bool = False, phase: bool = True, check: bool = True,
+              out=None):
+        """Run fot_solve; returns (phase tensor or None, Report, status).  ``out`` is an optional
+        preallocated [batch][n][n] float64 device tensor for the phase."""
         import torch
-        phase_out = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=g.device) if phase else None
+        if out is not None:
+            phase_out = out
+        else:
+            phase_out = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=g.device) if phase else None
         rep = Report(self.batch, iters)
         st = fot_solve(self.handle, g, G, eps, iters, warm_start, phase_out, rep.raw, check=check)
         return phase_out, rep, st
