@@ -65,12 +65,12 @@ def measured_traffic(prec):
     return round(float(blob[prec]["bytes_per_launch"]))
 
 
-def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True, graph=True):
+def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True, graph=True, history=True):
     n = g.shape[-1]
     dev = torch.device("cuda", 0)
     gd = torch.tensor(g, dtype=torch.float64, device=dev)
     Gd = torch.tensor(G, dtype=torch.float64, device=dev)
-    plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph)
+    plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph, history=history)
     phase = torch.empty((G.shape[0], n, n), dtype=torch.float64, device=dev)
     for _ in range(warmup):
         plan.solve(gd, Gd, eps, iters, out=phase)
@@ -227,6 +227,19 @@ def main():
                 f"per-iteration speedup {base['ms_it'] / d['ms_it']:.2f}, equal-L1 speedup {sp} "
                 f"(E = {level:.2e}: f32 {t_reach.get('f32')} its, {prec} {t_reach.get(prec)} its)")
         out["variants"] = variants
+        # Algorithm 1 as the paper times it: a fixed number of iterations without evaluating a
+        # loss per iteration (FOT_FLAG_NO_HISTORY); final errors still come from the read-out.
+        nh = {}
+        for prec in ("f32", "bf16"):
+            el, rp = run_variant(F, W, torch, prec, g, G, eps, iters, args.steps, args.warmup,
+                                 profile=False, graph=graph, history=False)
+            nh[prec] = {"value": round(n * n * iters * args.steps / el / 1e6, 3),
+                        "ms_per_step": round(1e3 * el / args.steps, 4),
+                        "us_per_iteration": round(1e3 * float(np.median([r.ms_iterations for r in rp])) / iters, 2),
+                        "final_err_a": float(rp[-1].err_a[0])}
+            log(f"bench: {prec} without per-iteration errors {nh[prec]['value']:.1f} Mpx.it/s, "
+                f"{nh[prec]['us_per_iteration']:.1f} us/it")
+        out["no_history"] = nh
         out["equal_l1_protocol"] = ("err(T) = FP64 read-out row-marginal L1 after fresh solves of T = 5..iters "
                                     "step 5; E = 1.1 x the lowest error all precisions reach; speedup = "
                                     "T_f32(E) t_it,f32 / (T(E) t_it)")

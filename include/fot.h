@@ -53,8 +53,12 @@ enum {
                             contractions of Eq. 7-8) with HIP events (fot_report.ms_contract);
                             the iteration loop is then launched kernel by kernel (events
                             recorded inside a graph cannot be timed) */
-  FOT_FLAG_NO_GRAPH = 2  /* launch the iteration loop kernel by kernel instead of replaying a
+  FOT_FLAG_NO_GRAPH = 2, /* launch the iteration loop kernel by kernel instead of replaying a
                             HIP graph of it (the results are bit-identical either way) */
+  FOT_FLAG_NO_HISTORY = 4 /* do not evaluate the per-iteration marginal errors (the paper's
+                            practice of running a fixed number of iterations without a loss,
+                            Sec. 3 after Algorithm 1): err_*_history is filled with NaN; the
+                            potentials, phase and final report values are bit-identical */
 };
 
 typedef struct {
@@ -73,7 +77,8 @@ typedef struct {
   double* err_b;          /* [batch] sum_q |sum_p Gamma_pq - b_q| of the final plan */
   double* dual;           /* [batch] <f,a> + <psi,b> - eps sum Gamma, a = g^2/sum g^2, b = G^2/sum G^2 */
   double* transport_cost; /* [batch] sum Gamma_pq c_pq (Sec. 2, Eq. 2-3) */
-  double* err_a_history;  /* [iters][batch] row-marginal L1 of the plan entering each u-update */
+  double* err_a_history;  /* [iters][batch] row-marginal L1 of the plan entering each u-update
+                             (NaN with FOT_FLAG_NO_HISTORY) */
   double* err_b_history;  /* [iters][batch] column-marginal L1 of the plan entering each V-update */
   int iters_done;         /* iterations run */
   int nonfinite;          /* 1 if a non-finite potential appeared (status FOT_E_NONFINITE) */

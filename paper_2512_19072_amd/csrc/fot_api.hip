@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <algorithm>
+#include <limits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -62,7 +63,7 @@ struct fot_plan_s {
   // reverse mode (allocated when checkpoint_every > 0)
   double *fbar = nullptr, *psibar = nullptr, *psibar2 = nullptr, *psiprev = nullptr, *lbbar = nullptr;
   double *Tbx = nullptr, *Tby = nullptr, *wtmp = nullptr, *cbar = nullptr, *rsum_tmp = nullptr;
-  double *gsums = nullptr, *dd_dev = nullptr, *hist_scratch = nullptr;
+  double *gsums = nullptr, *dd_dev = nullptr;
   double *seg_f = nullptr, *seg_psi = nullptr, *seg_lnS = nullptr, *seg_lnSp = nullptr;
   // The phase read-out and the reverse-sweep contractions run with FP64 operands in every
   // precision (once per solve; their signed sums cancel too strongly for FP32).  For FP64 plans
@@ -274,8 +275,9 @@ struct Ops {
     b.kexpN = p->kexpA;
     b.partials = p->partials;
     b.flag = p->flag;
+    b.err_on = hist != nullptr;
     s = fused_launch(p, 2, b);
-    p->pending_hist = hist;
+    p->pending_hist = hist;   // nullptr: no marginal-error sum to finish
     return s;
   }
 
@@ -297,11 +299,12 @@ struct Ops {
         LAUNCH_CHECK();
       }
       const bool last = (t == iters - 1);
-      if ((s = half(p, p->psi, p->f, p->lna, 0, p->hist_a + (size_t)t * B, last ? p->lnS : nullptr, ep, ep)) !=
-          FOT_OK)
+      const bool hist = !(p->d.flags & FOT_FLAG_NO_HISTORY);
+      if ((s = half(p, p->psi, p->f, p->lna, 0, hist ? p->hist_a + (size_t)t * B : nullptr, last ? p->lnS : nullptr,
+                    ep, ep)) != FOT_OK)
         return s;
-      if ((s = half(p, p->f, p->psi, p->lnb, plane, p->hist_b + (size_t)t * B, last ? p->lnSp : nullptr, ep,
-                    last ? 0.0 : e[t + 1])) != FOT_OK)
+      if ((s = half(p, p->f, p->psi, p->lnb, plane, hist ? p->hist_b + (size_t)t * B : nullptr,
+                    last ? p->lnSp : nullptr, ep, last ? 0.0 : e[t + 1])) != FOT_OK)
         return s;
     }
     return FOT_OK;
@@ -344,7 +347,7 @@ struct Ops {
     HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
     p->used_graph = true;
     // state after the loop, as if it had been launched directly
-    p->pending_hist = p->hist_b + (size_t)(iters - 1) * p->B;
+    p->pending_hist = (p->d.flags & FOT_FLAG_NO_HISTORY) ? nullptr : p->hist_b + (size_t)(iters - 1) * p->B;
     p->lam_eps = e[iters - 1];
     p->lamH_valid = false;
     return FOT_OK;
@@ -391,11 +394,11 @@ struct Ops {
       for (int i = t0; i < t1; ++i) {
         const int q = i - t0;
         if ((s = ensure_lambda(p, e[i])) != FOT_OK) return s;
-        if ((s = half(p, pin, p->seg_f + q * BP, p->lna, 0, p->hist_scratch, p->seg_lnS + q * BP, e[i], e[i])) !=
-            FOT_OK)
+        // (the replay needs no marginal-error partials; the potentials do not depend on them)
+        if ((s = half(p, pin, p->seg_f + q * BP, p->lna, 0, nullptr, p->seg_lnS + q * BP, e[i], e[i])) != FOT_OK)
           return s;
-        if ((s = half(p, p->seg_f + q * BP, p->seg_psi + q * BP, p->lnb, plane, p->hist_scratch + B,
-                      p->seg_lnSp + q * BP, e[i], i + 1 < t1 ? e[i + 1] : 0.0)) != FOT_OK)
+        if ((s = half(p, p->seg_f + q * BP, p->seg_psi + q * BP, p->lnb, plane, nullptr, p->seg_lnSp + q * BP, e[i],
+                      i + 1 < t1 ? e[i + 1] : 0.0)) != FOT_OK)
           return s;
         pin = p->seg_psi + q * BP;
       }
@@ -600,6 +603,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   if (d.precision < FOT_F64 || d.precision > FOT_F16) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
+  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY))
+    return fail(FOT_E_INVALID, "fot_plan: unknown flag bits");
   fot_plan_s* p = new (std::nothrow) fot_plan_s();
   if (!p) return fail(FOT_E_NOMEM, "fot_plan: host allocation failed");
   p->d = d;
@@ -702,7 +707,6 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
     ALLOC(p->rsum_tmp, (size_t)p->B * p->n);
     ALLOC(p->gsums, (size_t)2 * p->B);
     ALLOC(p->dd_dev, (size_t)p->B);
-    ALLOC(p->hist_scratch, (size_t)2 * p->B);
     ALLOC(p->seg_f, kseg * BP);
     ALLOC(p->seg_psi, kseg * BP);
     ALLOC(p->seg_lnS, kseg * BP);
@@ -854,6 +858,10 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
       if (rep->err_b) rep->err_b[b] = err_b;
       if (rep->dual) rep->dual[b] = dots - epT * mass;
       if (rep->transport_cost) rep->transport_cost[b] = cost;
+    }
+    if (p->d.flags & FOT_FLAG_NO_HISTORY) {
+      std::fill(ha.begin(), ha.end(), std::numeric_limits<double>::quiet_NaN());
+      std::fill(hb.begin(), hb.end(), std::numeric_limits<double>::quiet_NaN());
     }
     if (rep->err_a_history) std::memcpy(rep->err_a_history, ha.data(), ha.size() * 8);
     if (rep->err_b_history) std::memcpy(rep->err_b_history, hb.data(), hb.size() * 8);

@@ -58,6 +58,7 @@ struct FusedArgs {
   int* kexpN;               // [batch][np][nb]
   double* partials;         // [batch][tiles]
   int* flag;
+  int err_on;               // pass 2: evaluate the marginal-error partial (reads the old potential)
 };
 
 // exp(x - K ln 2) rounded to the operand type, with the K of a block's maximum.  The prep
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const bool ok = i < n && j < n;
           const size_t o = (size_t)i * np + j;
           la_v[cb][rb][e] = ok ? lnm[o] : 0.0;
-          fo_v[cb][rb][e] = ok ? pot[o] : 0.0;
+          fo_v[cb][rb][e] = (ok && p.err_on) ? pot[o] : 0.0;
         }
     }
   }
@@ -567,15 +568,17 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const double fold = fo_v[cb][rb][e];
           const bool zm = la == -INFINITY;
           const double fnew = (ok && !zm) ? eps * (la - lnS) : -INFINITY;
-          // marginal-error term of the entering plan at this pixel: on a zero-mass pixel its
-          // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp(d) - 1| with
-          // d = (f_old - f_new)/eps, evaluated as exp(ln a + d) - a once d is large (a e^d is the
-          // pixel's entering mass, at most 1, while e^d alone can overflow FP32 for tiny a)
-          const float tz = expf((float)(fold * inv_eps + lnS));
-          const double d = (fold - fnew) * inv_eps;
-          const float ta = (d < 10.0) ? expf((float)la) * fabsf(expm1f((float)d))
-                                      : expf((float)(la + d)) - expf((float)la);
-          err += ok ? (double)(zm ? tz : ta) : 0.0;
+          if (p.err_on) {
+            // marginal-error term of the entering plan at this pixel: on a zero-mass pixel its
+            // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp(d) - 1| with
+            // d = (f_old - f_new)/eps, evaluated as exp(ln a + d) - a once d is large (a e^d is
+            // the pixel's entering mass, at most 1, while e^d alone can overflow FP32 for tiny a)
+            const float tz = expf((float)(fold * inv_eps + lnS));
+            const double d = (fold - fnew) * inv_eps;
+            const float ta = (d < 10.0) ? expf((float)la) * fabsf(expm1f((float)d))
+                                        : expf((float)(la + d)) - expf((float)la);
+            err += ok ? (double)(zm ? tz : ta) : 0.0;
+          }
           bad = bad || (ok && !zm && !(fabs(fnew) < INFINITY));
           const size_t o = (size_t)i * np + j;
           if (ok) {
@@ -586,8 +589,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         }
     }
     if (bad) atomicOr(p.flag, 1);
-    err = wave_sum_dpp(err);
-    if (lane == 0) red[wave] = err;
+    if (p.err_on) {
+      err = wave_sum_dpp(err);
+      if (lane == 0) red[wave] = err;
+    }
 
     if (p.next_inv_eps > 0.0) {
       // next pass-1 operand: per output row, the exponent of the max over this tile's columns
@@ -604,7 +609,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         }
     }
     __syncthreads();
-    if (tid == 0) {
+    if (p.err_on && tid == 0) {
       double v = 0.0;
 #pragma unroll
       for (int w = 0; w < C::NW; ++w) v += red[w];

@@ -239,3 +239,27 @@ def test_graph_replays_match_eager(profile):
         assert np.array_equal(rep.err_a_history, r[3]) and np.array_equal(rep.dual, r[4]), (it, key)
         if profile:
             assert rep.n_contract == 4 * T and rep.ms_contract > 0   # the iteration kernels only
+
+
+def test_no_history_flag_changes_nothing_else():
+    """FOT_FLAG_NO_HISTORY skips the per-iteration marginal errors: the history is NaN and the
+    potentials, phase and final report values are bit-identical to a run with the history."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n, T = 130, 25
+    g, G = _rand_case(n, 21)
+    gd, Gd = to_dev(g), to_dev(G[None])
+    for prec in ("f32", "bf16"):
+        runs = []
+        for hist in (True, False):
+            plan = F.Plan(n, 1, prec, max_iters=T, history=hist)
+            ph, rep, _ = plan.solve(gd, Gd, 1e-2, T)
+            f, psi = plan.potentials()
+            plan.close()
+            runs.append((ph, f, psi, rep))
+        (p1, f1, s1, r1), (p2, f2, s2, r2) = runs
+        _say(f"case: no-history {prec}: final err_a {r1.err_a[0]:.3e} / {r2.err_a[0]:.3e}")
+        assert bool((p1 == p2).all()) and bool((f1 == f2).all()) and bool((s1 == s2).all())
+        assert r1.err_a[0] == r2.err_a[0] and r1.err_b[0] == r2.err_b[0] and r1.dual[0] == r2.dual[0]
+        assert np.all(np.isfinite(r1.err_a_history)) and np.all(np.isnan(r2.err_a_history))
+        assert np.all(np.isnan(r2.err_b_history))
