@@ -69,9 +69,28 @@ struct FusedArgs {
 __device__ __forceinline__ int block_exponent(double xmax) {
   return (xmax > -INFINITY) ? (int)ceil(fmax(xmax * INV_LN2, KMIN)) : KSENT;
 }
+// 2^y by the hardware exponential (V_EXP_F32, about 1 ulp) of y rounded to FP32.
+__device__ __forceinline__ float exp2_hw(double y) { return __builtin_amdgcn_exp2f((float)y); }
+
+// exp(x - K ln 2) = 2^(x / ln 2 - K): the exponent is formed in FP64 (x reaches 1e4 in
+// magnitude) and lies in (-1, 0] for a block's largest element, so its FP32 rounding costs less
+// than one ulp of the result there; elements far below the block maximum, whose exponent is
+// rounded more coarsely or underflows, are negligible in every sum they enter.
 template <typename T>
 __device__ __forceinline__ T block_operand(double x, int K) {
-  return (K == KSENT) ? (T)0 : exp_op<T>(x - (double)K * LN2);
+  if constexpr (sizeof(T) == 8)
+    return (K == KSENT) ? 0.0 : exp(x - (double)K * LN2);
+  else
+    return (K == KSENT) ? (T)0 : from_float<T>(exp2_hw(fma(x, INV_LN2, -(double)K)));
+}
+
+// exp(x) and exp(d) - 1 (d < 10) in FP32 for the marginal-error terms, which need a few
+// significant digits: a short series below |d| = 0.03, the hardware exponential otherwise.
+__device__ __forceinline__ float exp_err(double x) { return exp2_hw(x * INV_LN2); }
+__device__ __forceinline__ float expm1_err(double d) {
+  const float df = (float)d;
+  const float series = df * (1.0f + df * (0.5f + df * (1.0f / 6.0f + df * (1.0f / 24.0f))));
+  return fabsf(df) < 0.03f ? series : exp2_hw(d * INV_LN2) - 1.0f;
 }
 
 // max over the 16 lanes of each row of a wave (DPP: quad swaps, then half-row and row mirrors)
@@ -573,10 +592,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
             // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp(d) - 1| with
             // d = (f_old - f_new)/eps, evaluated as exp(ln a + d) - a once d is large (a e^d is
             // the pixel's entering mass, at most 1, while e^d alone can overflow FP32 for tiny a)
-            const float tz = expf((float)(fold * inv_eps + lnS));
+            const float tz = exp_err(fold * inv_eps + lnS);
             const double d = (fold - fnew) * inv_eps;
-            const float ta = (d < 10.0) ? expf((float)la) * fabsf(expm1f((float)d))
-                                        : expf((float)(la + d)) - expf((float)la);
+            const float av = exp_err(la);
+            const float ta = (d < 10.0) ? av * fabsf(expm1_err(d)) : exp_err(la + d) - av;
             err += ok ? (double)(zm ? tz : ta) : 0.0;
           }
           bad = bad || (ok && !zm && !(fabs(fnew) < INFINITY));
