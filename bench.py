@@ -244,6 +244,45 @@ def main():
                                     "step 5; E = 1.1 x the lowest error all precisions reach; speedup = "
                                     "T_f32(E) t_it,f32 / (T(E) t_it)")
 
+    if not args.no_variants:
+        # A10: the reverse mode on its own workload (512^2, 8 targets, FP32 operands, 100
+        # iterations, checkpoints every 10): forward solve with tape, then fot_backward of
+        # L = D + 1/2 sum_p a_p phi_p^2, each timed over the same steps.
+        wl4 = W.workload(4)
+        g4, G4 = wl4.images()
+        dev = torch.device("cuda", 0)
+        g4d = torch.tensor(g4, dtype=torch.float64, device=dev)
+        G4d = torch.tensor(G4, dtype=torch.float64, device=dev)
+        a4 = torch.tensor(g4 ** 2 / np.sum(g4 ** 2), dtype=torch.float64, device=dev)
+        B4, n4, T4 = G4.shape[0], wl4.n, wl4.iters
+        plan = F.Plan(n4, B4, "f32", max_iters=T4, checkpoint_every=wl4.checkpoint_every)
+        ph4 = torch.empty((B4, n4, n4), dtype=torch.float64, device=dev)
+        dD = np.ones(B4)
+        for _ in range(args.warmup):
+            plan.solve(g4d, G4d, float(wl4.eps[0]), T4, out=ph4)
+            plan.backward(dD, (a4[None] * ph4).contiguous())
+        torch.cuda.synchronize()
+        tf = tb = 0.0
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            plan.solve(g4d, G4d, float(wl4.eps[0]), T4, out=ph4)
+            dphi = (a4[None] * ph4).contiguous()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan.backward(dD, dphi)
+            torch.cuda.synchronize()
+            tf += t1 - t0
+            tb += time.perf_counter() - t1
+        plan.close()
+        out["adjoint"] = {"workload": f"{wl4.name} {n4}x{n4}, {B4} targets, eps {float(wl4.eps[0])}, {T4} iterations, "
+                                      f"checkpoints every {wl4.checkpoint_every}, FP32 operands (FP64 reverse sweep)",
+                          "ms_forward": round(1e3 * tf / args.steps, 3), "ms_backward": round(1e3 * tb / args.steps, 3),
+                          "backward_over_forward": round(tb / tf, 3),
+                          "value_forward": round(B4 * n4 * n4 * T4 * args.steps / tf / 1e6, 3),
+                          "unit": "Mpixel·iter/s (targets x pixels x iterations)"}
+        log(f"bench: adjoint {out['adjoint']['ms_forward']:.2f} ms forward + {out['adjoint']['ms_backward']:.2f} ms "
+            f"backward per step ({B4} x {n4}^2, {T4} its)")
+
     if not args.no_cpu_baseline:
         import oracle
         try:

@@ -202,8 +202,9 @@ __device__ __forceinline__ void vm_wait() {
 
 // 16-byte global -> LDS load of this lane's source; the wave's 64 lanes fill the 1 KB at
 // lds_dst (wave-uniform) in lane order.  Written in assembly so that the compiler does not
-// track it: completion is awaited explicitly (vm_wait) before the workgroup barrier that
-// publishes the stage, which lets two stages be in flight while a third is read.
+// track it (it would wait for every such load before any LDS read): completion is awaited
+// explicitly (vm_wait) before the workgroup barrier that publishes the stage, so the next stage
+// stays in flight while the current one is read.
 __device__ __forceinline__ void dma16(const void* src, const unsigned char* lds_dst) {
   const unsigned lds_addr =
       __builtin_amdgcn_readfirstlane((unsigned)(size_t)(const __attribute__((address_space(3))) unsigned char*)lds_dst);
@@ -261,9 +262,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   const int row0 = tr * BM, col0 = tc * BN;
   const size_t plane = (size_t)np * np;
 
-  // ---- operand staging: each K stage of the tile (BM rows of A, then BN rows of B, 256 bytes
+  // ---- operand staging: each K stage of the tile (BM rows of A, then BN rows of B, FROWB bytes
   // per row) is copied global -> LDS by 16-byte direct loads (no register round trip).  A wave
-  // instruction fills 1 KB of LDS, lane l at byte 16 l: four rows of 256 bytes.  LDS rows are
+  // instruction fills 1 KB of LDS, lane l at byte 16 l: 1024 / FROWB whole rows.  LDS rows are
   // unpadded; the 16-byte chunk c of row r sits in slot c ^ (r mod 16), so the fragment reads
   // (16 rows, one chunk) hit 16 distinct slots, i.e. all banks once.
   const size_t pitch = (size_t)np * sizeof(T);
@@ -371,9 +372,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   };
 
   // Main loop over K stages, NBUF LDS buffers (stage kt + NBUF - 1 is requested when stage kt
-  // starts).  Within a stage the fragments of step h+1 are read while the MFMAs of step h run;
-  // at the end of a stage the workgroup waits for the next stage, synchronises and requests the
-  // next stage's first fragments.
+  // starts).  Within a stage the fragments of step h + FRAG_AHEAD are read while the MFMAs of
+  // step h run; at the end of a stage the workgroup waits for the next stage, synchronises and
+  // requests the next stage's first fragments.
   static_assert((NBUF * HPS) % (2 * HB) == 0, "block parity must repeat with the unrolled stages");
   const int arow = (wm * C::WTM + r16) * FROWB, brow = (BM + wn * C::WTN + r16) * FROWB;
   const int sw = (g ^ r16) << 4;                  // slot of chunk 4h+g in this lane's rows, h = 0
