@@ -40,7 +40,12 @@ typedef enum {
   FOT_E_HIP = 3,         /* a HIP runtime call failed */
   FOT_E_NONFINITE = 4,   /* a potential of a positive-mass pixel became non-finite */
   FOT_E_STATE = 5,       /* call order violated (e.g. backward without a taped solve) */
-  FOT_E_UNSUPPORTED = 6  /* option not available in this build */
+  FOT_E_UNSUPPORTED = 6, /* option not available in this build */
+  FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the final plan's column
+                            marginal error (fot_report.err_b, evaluated in FP64) exceeds what the
+                            operand type allows (FP64 1e-8, FP32 1e-5, BF16/FP16 2e-2): at this
+                            eps the Gibbs products underflowed in the operand type; use FOT_F64
+                            or a larger eps */
 } fot_status;
 
 /* Element type of the contraction operands (the Gibbs factor and the shifted exponentials
@@ -74,7 +79,9 @@ typedef struct {
 /* Results of fot_solve.  All pointers are HOST arrays owned by the caller; any may be NULL. */
 typedef struct {
   double* err_a;          /* [batch] sum_p |sum_q Gamma_pq - a_p| of the final plan (Sec. 3, conv. criterion) */
-  double* err_b;          /* [batch] sum_q |sum_p Gamma_pq - b_q| of the final plan */
+  double* err_b;          /* [batch] sum_q |sum_p Gamma_pq - b_q| of the final plan, in FP64: after
+                             the final V-update it measures the operand type's error in that
+                             update's products (FP32 ~1e-7, BF16 ~5e-4 on well-posed inputs) */
   double* dual;           /* [batch] <f,a> + <psi,b> - eps sum Gamma, a = g^2/sum g^2, b = G^2/sum G^2 */
   double* transport_cost; /* [batch] sum Gamma_pq c_pq (Sec. 2, Eq. 2-3) */
   double* err_a_history;  /* [iters][batch] row-marginal L1 of the plan entering each u-update
@@ -108,7 +115,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out);
  *   rep       host report, or NULL
  * Returns FOT_E_INVALID for bad arguments or amplitudes (nothing is run),
  * FOT_E_NONFINITE if a positive-mass potential overflowed (outputs undefined, the plan
- * stays usable), FOT_E_HIP on a runtime error. */
+ * stays usable), FOT_E_RANGE if the operand type could not represent the products at this
+ * eps (outputs written but inaccurate; see FOT_E_RANGE), FOT_E_HIP on a runtime error. */
 fot_status fot_solve(fot_plan_t plan, const double* g, const double* G,
                      const double* eps, int n_eps, int iters, int warm_start,
                      double* phase_out, fot_report* rep);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <algorithm>
 #include <limits>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -522,8 +523,33 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out) {
   const long long plane = (long long)p->plane;
   fot_status s;
   if ((s = fill64(p, eps, true)) != FOT_OK) return s;
+  dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
+  // ln S'(f_T) = ln(Lambda . u_T . Lambda) in FP64, replacing the loop's value (computed with the
+  // operand type), so that the column marginal below is the true one of the returned plan: its
+  // L1 error then measures how well the operand type represented the last V-update's products.
+  {
+    hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->f, p->n, p->np,
+                       1.0 / eps, p->mrow, p->fA, (double*)nullptr, p->colkey, take_pending(p));
+    LAUNCH_CHECK();
+    GemmArgs gf = R::base_args(p, p->fA, plane, p->flam, 0);
+    gf.out = p->fZ;
+    gf.sOut = plane;
+    gf.mrow = p->mrow;
+    gf.colkey = p->colkey;
+    if ((s = R::gemm_launch(p, EPI_LOGROW, gf)) != FOT_OK) return s;
+    hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
+                       p->mrow, p->colkey, p->n, p->np, p->fB);
+    LAUNCH_CHECK();
+    GemmArgs gs = R::base_args(p, p->flam, 0, p->fB, plane);
+    gs.out = p->fS;
+    gs.sOut = plane;
+    if ((s = R::gemm_launch(p, EPI_RAW, gs)) != FOT_OK) return s;
+    hipLaunchKernelGGL(k_lnS_raw, dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->fS,
+                       p->colkey, p->n, p->np, p->lnSp);
+    LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np,
-                     1.0 / eps, p->mrow, p->fA, p->fA2, p->colkey, take_pending(p));
+                     1.0 / eps, p->mrow, p->fA, p->fA2, p->colkey, PendingSum{nullptr, 0, nullptr});
   LAUNCH_CHECK();
   GemmArgs g1 = R::base_args(p, p->fA, plane, p->flam, 0);
   g1.out = p->fZ;
@@ -539,7 +565,6 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out) {
   gc.out = p->fZc;
   gc.sOut = plane;
   if ((s = R::gemm_launch(p, EPI_RAW, gc)) != FOT_OK) return s;
-  dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
   hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
                      p->mrow, p->colkey, p->n, p->np, p->fB);
   hipLaunchKernelGGL((k_colexpT<double, double, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
@@ -884,6 +909,21 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     rep->graph = p->used_graph ? 1 : 0;
   }
   if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_solve: a potential became non-finite");
+  {
+    // the final column marginal is exact up to the operand type's error in the last V-update
+    const double bound = p->prec == FOT_F64 ? 1e-8 : p->prec == FOT_F32 ? 1e-5 : 2e-2;
+    for (int b = 0; b < B; ++b) {
+      const double err_b = rs[4 * B + b];
+      if (!(err_b <= bound)) {
+        char msg[256];
+        std::snprintf(msg, sizeof msg,
+                      "fot_solve: target %d: final column-marginal L1 %.3g exceeds %.0e: the Gibbs products "
+                      "underflowed in the operand type at eps %.3g (use FOT_F64 or a larger eps)",
+                      b, err_b, bound, e[iters - 1]);
+        return fail(FOT_E_RANGE, msg);
+      }
+    }
+  }
   return FOT_OK;
 }
 

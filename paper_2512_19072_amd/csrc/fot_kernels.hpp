@@ -579,6 +579,20 @@ __global__ void k_fill_pot(double* pot, int n, int np, int batch, double value) 
   pot[idx] = (i < n && k < n) ? value : -INFINITY;
 }
 
+// ln S from a raw pass-2 output: ln S = m'_k + ln S~ (-inf where S~ = 0), valid pixels only.
+__global__ __launch_bounds__(NTHREADS) void k_lnS_raw(const double* S, const unsigned* colkey, int n, int np,
+                                                       double* lnS) {
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / n), k = (int)(idx % n);
+    const size_t o = bz * plane + (size_t)j * np + k;
+    const double v = S[o];
+    lnS[o] = (v > 0.0) ? key_to_shift(colkey[(size_t)bz * np + k]) + log(v) : -INFINITY;
+  }
+}
+
 // ------------------------------------------------------------------ read-out (Eq. 9-10)
 // Inputs per pixel p = (j,k): S, Sx, Sy, Scx, Scy are the pass-2 outputs for V_T divided by
 // exp(m'_k); lnS_prev = ln(Lambda V_{T-1} Lambda) from the final u-update.  u/a = 1/S_prev.

@@ -263,3 +263,28 @@ def test_no_history_flag_changes_nothing_else():
         assert r1.err_a[0] == r2.err_a[0] and r1.err_b[0] == r2.err_b[0] and r1.dual[0] == r2.dual[0]
         assert np.all(np.isfinite(r1.err_a_history)) and np.all(np.isnan(r2.err_a_history))
         assert np.all(np.isnan(r2.err_b_history))
+
+
+def test_range_loss_is_reported():
+    """Below the eps an operand type can represent (1024^2, eps 5e-4, FP32: the Gibbs products of
+    the per-block operands underflow), fot_solve still writes its outputs but returns FOT_E_RANGE,
+    with err_b (the final plan's column-marginal L1 evaluated in FP64) far above FP32's level; the
+    same case in FP64 operands is accurate and returns FOT_OK."""
+    from paper_2512_19072_amd import fot as F
+    n, T, eps = 1024, 50, 5e-4
+    g, G = W.twogauss_to_shapes(n)
+    _say("case: twogauss n=1024 eps=5e-4 f32 vs f64, 50 it")
+    plan = F.Plan(n, 1, "f32", max_iters=T)
+    from tests.parity_util import to_dev
+    gd, Gd = to_dev(g), to_dev(G[None] if G.ndim == 2 else G)
+    _, rep, st = plan.solve(gd, Gd, eps, T, check=False)
+    msg = F.fot_last_error()          # (the next call on this thread clears it)
+    plan.close()
+    assert st == F.FOT_E_RANGE, st
+    assert "use FOT_F64" in msg, msg
+    assert rep.err_b[0] > 1e-5
+    plan = F.Plan(n, 1, "f64", max_iters=T)
+    _, rep64, st64 = plan.solve(gd, Gd, eps, T, check=False)
+    plan.close()
+    _say(f"err_b f32 {rep.err_b[0]:.3e}, f64 {rep64.err_b[0]:.3e}")
+    assert st64 == F.FOT_OK and rep64.err_b[0] < 1e-12
