@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-iters", type=int, default=100, help="oracle iterations in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=200, help="oracle iterations in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch the iteration loop kernel by kernel")
@@ -294,10 +294,30 @@ def main():
         t0 = time.perf_counter()
         oracle.solve_sep(g, G[0], eps, k)
         t_cpu = time.perf_counter() - t0
+        cpu_model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
+        affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         out["cpu_baseline"] = {"value": round(n * n * k / t_cpu / 1e6, 3), "unit": "Mpixel·iter/s",
                                "cores": cores, "kind": "oracle",
                                "sample": f"{wl.name} {n}x{n}, eps {eps}: first {k} of {iters} iterations plus "
-                                         f"read-out, FP64 separable oracle (numpy/OpenBLAS), {t_cpu:.1f} s"}
+                                         f"read-out, FP64 separable oracle (numpy/OpenBLAS), {t_cpu:.1f} s; "
+                                         f"{cpu_model}, {affinity} CPUs in this process's affinity"}
+        # the same oracle restricted to one thread, on a shorter sample
+        try:
+            from threadpoolctl import threadpool_limits
+            k1 = max(2, k // 10)
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                oracle.solve_sep(g, G[0], eps, k1)
+                t1 = time.perf_counter() - t0
+            out["cpu_baseline"]["single_thread"] = {"value": round(n * n * k1 / t1 / 1e6, 3),
+                                                    "sample": f"first {k1} iterations plus read-out, {t1:.1f} s"}
+        except ImportError:
+            pass
         log(f"bench: cpu oracle {out['cpu_baseline']['value']} Mpx.it/s on {cores} threads ({t_cpu:.1f} s)")
     print(json.dumps(out), flush=True)
 
