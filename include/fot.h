@@ -43,15 +43,20 @@ typedef enum {
   FOT_E_UNSUPPORTED = 6, /* option not available in this build */
   FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the final plan's column
                             marginal error (fot_report.err_b, evaluated in FP64) exceeds what the
-                            operand type allows (FP64 1e-8, FP32 1e-5, BF16/FP16 2e-2): at this
+                            operand type allows (FP64 1e-8, FP32 1e-5, BF16x3 1e-4,
+                            BF16/FP16 2e-2): at this
                             eps the Gibbs products underflowed in the operand type; use FOT_F64
                             or a larger eps */
 } fot_status;
 
 /* Element type of the contraction operands (the Gibbs factor and the shifted exponentials
  * that the per-axis matrix products consume).  Accumulation is FP32 (FP64 for FOT_F64);
- * potentials, logarithms of the marginals, and all reductions are FP64 in every mode. */
-typedef enum { FOT_F64 = 0, FOT_F32 = 1, FOT_BF16 = 2, FOT_F16 = 3 } fot_precision;
+ * potentials, logarithms of the marginals, and all reductions are FP64 in every mode.
+ * FOT_BF16X3 splits each operand value v into hi = bf16(v) and lo = bf16(v - hi) and forms
+ * every product as hi.hi + hi.lo + lo.hi with three BF16 matrix-core operations: about 16
+ * significant bits per operand (between BF16's 8 and FP32's 24) at BF16 matrix-core rates,
+ * with FP32's exponent range and FP32's memory footprint (4 bytes per operand value). */
+typedef enum { FOT_F64 = 0, FOT_F32 = 1, FOT_BF16 = 2, FOT_F16 = 3, FOT_BF16X3 = 4 } fot_precision;
 
 enum {
   FOT_FLAG_PROFILE = 1,  /* time every launch of the iteration kernels (the fused per-axis

@@ -604,6 +604,7 @@ fot_status dispatch(int prec, F&& fn) {
     case FOT_F32: return fn((float)0);
     case FOT_BF16: return fn((__bf16)0);
     case FOT_F16: return fn((_Float16)0);
+    case FOT_BF16X3: return fn(bf16x3{});
     default: return fail(FOT_E_UNSUPPORTED, "unknown precision");
   }
 }
@@ -625,7 +626,7 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   const fot_plan_desc d = *desc;
   if (d.n < 1 || d.n > 8192) return fail(FOT_E_INVALID, "fot_plan: n must be in [1, 8192]");
   if (d.batch < 1 || d.batch > 65535) return fail(FOT_E_INVALID, "fot_plan: batch must be in [1, 65535]");
-  if (d.precision < FOT_F64 || d.precision > FOT_F16) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
+  if (d.precision < FOT_F64 || d.precision > FOT_BF16X3) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
   if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY))
@@ -634,7 +635,7 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   if (!p) return fail(FOT_E_NOMEM, "fot_plan: host allocation failed");
   p->d = d;
   p->n = d.n;
-  p->esz = d.precision == FOT_F64 ? 8 : d.precision == FOT_F32 ? 4 : 2;
+  p->esz = d.precision == FOT_F64 ? 8 : (d.precision == FOT_F32 || d.precision == FOT_BF16X3) ? 4 : 2;
   // padded side: whole 64-pixel tiles and whole K stages of the fused kernels (FROWB bytes,
   // a multiple of the read-out GEMM's ROWB)
   static_assert(FROWB % ROWB == 0, "fused stages must also be whole read-out stages");
@@ -911,7 +912,10 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_solve: a potential became non-finite");
   {
     // the final column marginal is exact up to the operand type's error in the last V-update
-    const double bound = p->prec == FOT_F64 ? 1e-8 : p->prec == FOT_F32 ? 1e-5 : 2e-2;
+    const double bound = p->prec == FOT_F64    ? 1e-8
+                         : p->prec == FOT_F32    ? 1e-5
+                         : p->prec == FOT_BF16X3 ? 1e-4
+                                                 : 2e-2;
     for (int b = 0; b < B; ++b) {
       const double err_b = rs[4 * B + b];
       if (!(err_b <= bound)) {

@@ -81,7 +81,7 @@ __device__ __forceinline__ T block_operand(double x, int K) {
   if constexpr (sizeof(T) == 8)
     return (K == KSENT) ? 0.0 : exp(x - (double)K * LN2);
   else
-    return (K == KSENT) ? (T)0 : from_float<T>(exp2_hw(fma(x, INV_LN2, -(double)K)));
+    return (K == KSENT) ? T{} : from_float<T>(exp2_hw(fma(x, INV_LN2, -(double)K)));
 }
 
 // exp(x) and exp(d) - 1 (d < 10) in FP32 for the marginal-error terms, which need a few
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(64) void k_prep_blocks(const double* P, int n, int 
     const bool ok = j < n && k < n;
     const double x = ok ? P[bz * plane + (size_t)j * np + k] * inv_eps : -INFINITY;
     const int K = block_exponent(group_max<XB>(x));
-    o[k] = ok ? block_operand<T>(x, K) : (T)0;
+    store_op<T>(o, k, ok ? block_operand<T>(x, K) : T{});
     if (lane % XB == 0) ko[k / XB] = K;
   }
 }
@@ -235,9 +235,12 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   constexpr int XB = PASS == 1 ? BN : BM;         // K extent of one exponent block of this pass
   constexpr int SR = fused_scaled_rows<PASS, C>(); // rows whose exponents scale the sums
   constexpr int HPS = FROWB / 64;                 // fragment steps per K stage
-  constexpr int EPH = 64 / (int)sizeof(T);        // K elements per fragment step (4 lane groups)
+  constexpr int EPH = 64 / (int)sizeof(T);        // K elements per fragment step (4 lane groups;
+                                                  // BF16x3: 32 values over a hi and a lo step)
   constexpr int HB = XB / EPH;                    // fragment steps per exponent block
+  constexpr bool PAIRED = Mma<T>::PAIRED;
   static_assert(HB >= 1 && XB % EPH == 0, "exponent blocks must hold whole fragment steps");
+  static_assert(!PAIRED || (HB % 2 == 0 && HPS % 2 == 0), "hi/lo step pairs within a block and a stage");
   // K-stage buffers as distinct objects, so that the compiler can tell a direct load into one
   // buffer from reads of another (it would otherwise wait for every load in flight)
   __shared__ __attribute__((aligned(1024))) unsigned char lds0[(BM + BN) * FROWB];
@@ -378,12 +381,14 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   static_assert((NBUF * HPS) % (2 * HB) == 0, "block parity must repeat with the unrolled stages");
   const int arow = (wm * C::WTM + r16) * FROWB, brow = (BM + wn * C::WTN + r16) * FROWB;
   const int sw = (g ^ r16) << 4;                  // slot of chunk 4h+g in this lane's rows, h = 0
-  // fragments of PD consecutive steps are in flight: slot h % PD holds step h of the stage
-  constexpr int PD = FRAG_AHEAD + 1;
+  // fragments of PD consecutive steps are live: slot h % PD holds step h of the stage (the
+  // fragments of step h + FA are requested at step h; a BF16x3 pair step also reads step h - 1)
+  constexpr int FA = FRAG_AHEAD;
+  constexpr int PD = FA + 1 + (PAIRED ? 1 : 0);
   static_assert(HPS >= PD, "a stage holds at least the fragments in flight");
   u32x4 fa[PD][RB], fb[PD][CB];
 #pragma unroll
-  for (int hs = 0; hs < PD - 1; ++hs) {
+  for (int hs = 0; hs < FA; ++hs) {
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) fa[hs][rb] = *(const u32x4*)(&lds0[arow + rb * 16 * FROWB + (sw ^ (hs << 6))]);
 #pragma unroll
@@ -409,21 +414,42 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
         for (int q = 0; q < ND; ++q) dcur[q] = dtab[blk * SR + srow(q)];
       }
-      if (h + PD - 1 < HPS) {
-        const int ha = h + PD - 1;                 // step whose fragments are requested now
+      if (h + FA < HPS) {
+        const int ha = h + FA;                     // step whose fragments are requested now
         const int so = sw ^ (ha << 6);             // chunk 4 ha + g
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) fa[ha % PD][rb] = *(const u32x4*)(&cur[arow + rb * 16 * FROWB + so]);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) fb[ha % PD][cb] = *(const u32x4*)(&cur[brow + cb * 16 * FROWB + so]);
       }
-      // sub-products outermost: consecutive MFMAs go to different accumulators
+      if constexpr (PAIRED) {
+        // hi.hi on the hi step; hi.lo and lo.hi on the lo step (consecutive MFMAs go to
+        // different accumulators)
+        const int hc = h % PD, hp = (h + PD - 1) % PD;
+        if (h % 2 == 0) {
 #pragma unroll
-      for (int q = 0; q < Mma<T>::NSUB; ++q)
+          for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int cb = 0; cb < CB; ++cb) Mma<T>::run(fa[hc][rb], fb[hc][cb], acc[par][rb][cb]);
+        } else {
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) Mma<T>::sub(fa[h % PD][rb], fb[h % PD][cb], acc[par][rb][cb], q);
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) Mma<T>::run(fa[hp][rb], fb[hc][cb], acc[par][rb][cb]);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) Mma<T>::run(fa[hc][rb], fb[hp][cb], acc[par][rb][cb]);
+        }
+      } else {
+        // sub-products outermost: consecutive MFMAs go to different accumulators
+#pragma unroll
+        for (int q = 0; q < Mma<T>::NSUB; ++q)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) Mma<T>::sub(fa[h % PD][rb], fb[h % PD][cb], acc[par][rb][cb], q);
+      }
       if (first && !(kt == 0 && h == 0)) {
         // flush the previous block (other set) with its exact power-of-two scales
 #pragma unroll
@@ -453,7 +479,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         if (more) {
           const unsigned char* nxt = bufp((jb + 1) % NBUF);
 #pragma unroll
-          for (int hs = 0; hs < PD - 1; ++hs) {
+          for (int hs = 0; hs < FA; ++hs) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
               fa[hs][rb] = *(const u32x4*)(&nxt[arow + rb * 16 * FROWB + (sw ^ (hs << 6))]);
@@ -546,6 +572,23 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
             const double v = (K == KSENT) ? 0.0 : ldexp(accd[rb][cb][e], rref[lr] - K);
             if (i < n) outT[(size_t)j * np + i] = v;
           }
+        } else if constexpr (PAIRED) {
+          // rows 4g .. 4g+3: one 8-byte store of their hi halves and one of their lo halves
+          typedef __bf16 hv4 __attribute__((ext_vector_type(4)));
+          const int lr0 = wm * C::WTM + rb * 16 + 4 * g;
+          const int k0 = row0 + lr0;
+          hv4 wh, wl;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int lr = lr0 + e;
+            const double v = (K == KSENT || row0 + lr >= n) ? 0.0 : ldexp(accd[rb][cb][e], rref[lr] - K);
+            const T x = cvt_op<T>(v);
+            wh[e] = x.hi;
+            wl[e] = x.lo;
+          }
+          __bf16* r = (__bf16*)(outT + (size_t)j * np) + 2 * (k0 & ~31) + (k0 & 31);
+          *(hv4*)r = wh;
+          *(hv4*)(r + 32) = wl;
         } else {
           // rows 4g .. 4g+3 are contiguous in Bt row j: one 16-byte (FP32) or 8-byte store
           typedef T tv4 __attribute__((ext_vector_type(4)));
@@ -652,7 +695,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           for (int cb = 0; cb < CB; ++cb) {
             const int j = col0 + wn * C::WTN + cb * 16 + r16;
             const T x = block_operand<T>(fnew_v[cb][rb][e] * ninv, K);
-            if (i < n && j < n) nA[(size_t)i * np + j] = x;
+            if (i < n && j < n) store_op<T>(nA + (size_t)i * np, j, x);
           }
         }
     }

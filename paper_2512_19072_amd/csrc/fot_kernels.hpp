@@ -39,6 +39,38 @@ template <> __device__ __forceinline__ float from_float<float>(float x) { return
 template <> __device__ __forceinline__ __bf16 from_float<__bf16>(float x) { return (__bf16)x; }
 template <> __device__ __forceinline__ _Float16 from_float<_Float16>(float x) { return (_Float16)x; }
 
+// BF16x3 operands: a value v is held as hi = bf16(v) and lo = bf16(v - hi), both rounded to
+// nearest even, so hi + lo carries about 16 significant bits with BF16's (= FP32's) exponent
+// range.  A product of two such operands is formed as hi.hi + hi.lo + lo.hi by three BF16
+// MFMAs into one FP32 accumulator; the dropped lo.lo term is below 2^-16 of the product.
+// In memory an operand row of np values takes 2 np BF16 (4 bytes per value, like FP32):
+// each group of 32 consecutive values is stored as its 32 hi halves, then its 32 lo halves,
+// so one 64-byte fragment step of the GEMM reads either the hi or the lo halves of 32 values
+// and the MFMA loop needs no repacking.  The struct is the element type of the API (its size
+// sets the row pitch); it is not the memory layout.
+struct bf16x3 {
+  __bf16 hi, lo;
+};
+template <> __device__ __forceinline__ bf16x3 from_float<bf16x3>(float x) {
+  const __bf16 h = (__bf16)x;
+  return bf16x3{h, (__bf16)(x - (float)h)};   // x - hi is exact in FP32
+}
+
+// a double rounded to the operand type (BF16x3: split from the double itself)
+template <typename T> __device__ __forceinline__ T cvt_op(double v) { return (T)v; }
+template <> __device__ __forceinline__ bf16x3 cvt_op<bf16x3>(double v) {
+  const __bf16 h = (__bf16)v;
+  return bf16x3{h, (__bf16)(v - (double)h)};
+}
+
+// element k of an operand row that starts at `row` (np elements of T)
+template <typename T> __device__ __forceinline__ void store_op(T* row, int k, T v) { row[k] = v; }
+template <> __device__ __forceinline__ void store_op<bf16x3>(bf16x3* row, int k, bf16x3 v) {
+  __bf16* r = (__bf16*)row + 2 * (k & ~31) + (k & 31);
+  r[0] = v.hi;
+  r[32] = v.lo;
+}
+
 // exp of a non-positive log-weight, rounded to the operand type.  FP64 operands use the
 // FP64 exponential; the others evaluate expf on the FP32-rounded argument (the argument is
 // <= 0 and near 0 for the entries that matter, so its rounding is harmless).
@@ -95,6 +127,7 @@ template <> struct Mma<float> {
   }
   // the q-th of run's NSUB products (callers interleave accumulators between them)
   static constexpr int NSUB = 4;
+  static constexpr bool PAIRED = false;
   static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int q) {
     const f32x4 av = __builtin_bit_cast(f32x4, a);
     const f32x4 bv = __builtin_bit_cast(f32x4, b);
@@ -114,6 +147,7 @@ template <> struct Mma<double> {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], c, 0, 0, 0);
   }
   static constexpr int NSUB = 2;
+  static constexpr bool PAIRED = false;
   static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int q) {
     typedef double d2 __attribute__((ext_vector_type(2)));
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(__builtin_bit_cast(d2, a)[q], __builtin_bit_cast(d2, b)[q], c, 0, 0, 0);
@@ -129,7 +163,14 @@ template <> struct Mma<__bf16> {
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   }
   static constexpr int NSUB = 1;
+  static constexpr bool PAIRED = false;
   static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int) { run(a, b, c); }
+};
+
+// BF16x3: fragment steps come in pairs, the hi halves of 32 K values and then their lo halves
+// (the fused GEMM issues hi.hi on the first step of a pair and hi.lo, lo.hi on the second)
+template <> struct Mma<bf16x3> : Mma<__bf16> {
+  static constexpr bool PAIRED = true;
 };
 
 template <> struct Mma<_Float16> {
@@ -141,6 +182,7 @@ template <> struct Mma<_Float16> {
                                                __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
   }
   static constexpr int NSUB = 1;
+  static constexpr bool PAIRED = false;
   static __device__ __forceinline__ void sub(const u32x4& a, const u32x4& b, acc_t& c, int) { run(a, b, c); }
 };
 
@@ -519,8 +561,8 @@ __global__ void k_fill_lambda(T* lam, T* lamH, int n, int np, double inv_eps) {
   const double d = (double)(i - k);
   const double h = d * d / (2.0 * (double)n * (double)n);
   const double v = exp(-h * inv_eps);
-  lam[idx] = (T)v;
-  if (lamH) lamH[idx] = (T)(v * h);
+  store_op<T>(lam + (size_t)i * np, k, cvt_op<T>(v));
+  if (lamH) store_op<T>(lamH + (size_t)i * np, k, cvt_op<T>(v * h));
 }
 
 // ------------------------------------------------------------------ marginals (Eq. 2)

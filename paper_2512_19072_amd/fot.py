@@ -19,11 +19,11 @@ LIB_PATH = os.path.join(HERE, "libfot.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "fot.h")
 
 FOT_OK, FOT_E_INVALID, FOT_E_NOMEM, FOT_E_HIP, FOT_E_NONFINITE, FOT_E_STATE, FOT_E_UNSUPPORTED, FOT_E_RANGE = range(8)
-FOT_F64, FOT_F32, FOT_BF16, FOT_F16 = range(4)
+FOT_F64, FOT_F32, FOT_BF16, FOT_F16, FOT_BF16X3 = range(5)
 FOT_FLAG_PROFILE = 1
 FOT_FLAG_NO_GRAPH = 2
 FOT_FLAG_NO_HISTORY = 4
-PRECISIONS = {"f64": FOT_F64, "f32": FOT_F32, "bf16": FOT_BF16, "f16": FOT_F16}
+PRECISIONS = {"f64": FOT_F64, "f32": FOT_F32, "bf16": FOT_BF16, "f16": FOT_F16, "bf16x3": FOT_BF16X3}
 STATUS_NAMES = {0: "FOT_OK", 1: "FOT_E_INVALID", 2: "FOT_E_NOMEM", 3: "FOT_E_HIP", 4: "FOT_E_NONFINITE",
                 5: "FOT_E_STATE", 6: "FOT_E_UNSUPPORTED", 7: "FOT_E_RANGE"}
 

@@ -61,3 +61,15 @@ def test_header_structs_match_binding():
         assert field in text
     for field, _ in F.fot_report._fields_:
         assert field in text
+
+
+def test_header_enum_values_match_binding():
+    """Every FOT_* constant that fot.h defines with an explicit value has the same value in the
+    Python binding (statuses, precisions, flags)."""
+    import re
+    text = open(F.HEADER).read()
+    pairs = re.findall(r"\b(FOT_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)
+    assert len(pairs) >= 15
+    for name, val in pairs:
+        assert getattr(F, name) == int(val), name
+    assert F.PRECISIONS["bf16x3"] == F.FOT_BF16X3
