@@ -298,6 +298,64 @@ def main():
         log(f"bench: adjoint {out['adjoint']['ms_forward']:.2f} ms forward + {out['adjoint']['ms_backward']:.2f} ms "
             f"backward per step ({B4} x {n4}^2, {T4} its)")
 
+        # output beam and L1 intensity loss of the FP32 phase of the headline workload, and
+        # Gerchberg-Saxton rounds from it (FP64 transforms on the matrix cores)
+        dev = torch.device("cuda", 0)
+        gd = torch.tensor(g, dtype=torch.float64, device=dev)
+        Gd = torch.tensor(G, dtype=torch.float64, device=dev)
+        plan = F.Plan(n, G.shape[0], "f32", max_iters=iters)
+        ph, _, _ = plan.solve(gd, Gd, eps, iters)
+        _, l_fot = plan.output_beam(gd, ph, Gd, intensity=False)
+        torch.cuda.synchronize()
+        reps_b = max(1, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps_b):
+            plan.output_beam(gd, ph, Gd, intensity=False)
+        t_beam = (time.perf_counter() - t0) / reps_b
+        gs_rounds = 10
+        ph_gs = ph.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.polish_gs(gd, Gd, ph_gs, gs_rounds)
+        t_gs = (time.perf_counter() - t0) / gs_rounds
+        _, l_gs = plan.output_beam(gd, ph_gs, Gd, intensity=False)
+        _, l_flat = plan.output_beam(gd, torch.zeros_like(ph), Gd, intensity=False)
+        plan.close()
+        tflop = 16.0 * n ** 3 / t_beam / 1e12
+        out["output_beam"] = {"workload": f"{wl.name} {n}x{n}: FP32 FOT phase after {iters} iterations",
+                              "ms_output_beam": round(1e3 * t_beam, 3), "ms_per_gs_round": round(1e3 * t_gs, 3),
+                              "transform_tflops_fp64": round(tflop, 2),
+                              "l1_flat_phase": float(l_flat[0]), "l1_fot": float(l_fot[0]),
+                              f"l1_fot_plus_{gs_rounds}_gs": float(l_gs[0])}
+        log(f"bench: output beam {1e3 * t_beam:.2f} ms ({tflop:.1f} TFLOP/s FP64), GS round {1e3 * t_gs:.2f} ms; "
+            f"L1 flat {l_flat[0]:.4f}, FOT {l_fot[0]:.4f}, FOT + {gs_rounds} GS {l_gs[0]:.4f}")
+
+        # small-grid latency (the paper's 128^2, 200 iterations): one whole solve per call,
+        # inputs resident, timed wall-clock around the call
+        ns = 128
+        gs_, Gs_ = W.twogauss_to_shapes(ns)
+        Gs_ = Gs_ if Gs_.ndim == 3 else Gs_[None]
+        gsd = torch.tensor(gs_, dtype=torch.float64, device=dev)
+        Gsd = torch.tensor(Gs_, dtype=torch.float64, device=dev)
+        small = {}
+        for prec in ("f32", "bf16"):
+            plan = F.Plan(ns, 1, prec, max_iters=200)
+            phs = torch.empty((1, ns, ns), dtype=torch.float64, device=dev)
+            for _ in range(2):
+                plan.solve(gsd, Gsd, 5e-3, 200, out=phs)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                plan.solve(gsd, Gsd, 5e-3, 200, out=phs)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            plan.close()
+            small[prec] = round(1e3 * float(np.median(ts)), 3)
+        out["small_grid"] = {"workload": f"twogauss_to_shapes {ns}x{ns}, eps 5e-3, 200 iterations + read-out",
+                             "ms_per_solve": small}
+        log(f"bench: {ns}^2 x 200 iterations: {small} ms per solve")
+
     if not args.no_cpu_baseline:
         import oracle
         try:

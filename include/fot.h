@@ -15,7 +15,8 @@
  *     batches are [batch][n][n].  X_L = (L - floor(n/2)) / sqrt(n) (Sec. 2).
  *   - Every array argument except the fot_report fields is a DEVICE pointer owned by the
  *     caller (for example a torch tensor's data pointer); the library never frees it.
- *     The plan owns all its workspace, allocated once in fot_plan.
+ *     The plan owns all its workspace, allocated once in fot_plan (the output-beam
+ *     workspace of fot_output_beam / fot_polish_gs at the first such call).
  *   - Potentials are FP64: f = eps ln u and psi = eps ln V (Eq. 6), -inf at zero-mass pixels.
  *   - Work is issued on the plan's stream in stream order.  fot_solve synchronises once at
  *     its end to fill the report; fot_backward synchronises once at its end to report errors.
@@ -139,6 +140,30 @@ fot_status fot_potentials(fot_plan_t plan, double* f_out, double* psi_out,
  * bit-identical to the forward solve.  Zero-amplitude target pixels get gradient 0. */
 fot_status fot_backward(fot_plan_t plan, const double* dL_dDual, const double* dL_dphase,
                         double* dL_dG);
+
+/* Output beam of a phase and its L1 intensity loss (Sec. 4; Eq. 1 for the beam).
+ *   g          [n][n]        input amplitude (>= 0, not all zero), shared by the batch
+ *   phase      [batch][n][n] phase in cycles (for example fot_solve's phase_out)
+ *   G          [batch][n][n] target amplitude, or NULL when no loss is wanted
+ *   intensity  [batch][n][n] output, or NULL: the unit-power far-field intensity
+ *              I_LM = |F[g e^{2 pi i phase}]_LM|^2 / (n^2 sum g^2), with the centred transform
+ *              F[f]_LM = sum_jk f_jk exp(-2 pi i ((j-c)(L-c) + (k-c)(M-c)) / n), c = floor(n/2)
+ *              (x_j X_L of Sec. 2; this sign sends light to where the phase gradient points)
+ *   l1         HOST double[batch], or NULL: sum_LM |I_LM - G_LM^2 / sum G^2| (needs G)
+ * The transform runs as FP64 matrix-core products (about 16 n^3 flop per target).  Returns
+ * FOT_E_INVALID for null g or phase, l1 without G, or amplitudes that are negative,
+ * non-finite or all zero.  Synchronises the plan's stream before returning. */
+fot_status fot_output_beam(fot_plan_t plan, const double* g, const double* phase, const double* G,
+                           double* intensity, double* l1);
+
+/* Gerchberg-Saxton polishing of a phase (the textbook step that Sec. 4 names as the usual
+ * follow-up to an OT phase), in place: iters rounds of
+ *   F = F[g e^{2 pi i phase}];  F <- G F / |F|  (G where F = 0);
+ *   f = conj-transform of F;    phase <- arg(f) / (2 pi) in (-1/2, 1/2]  (0 where f = 0)
+ * with the transform of fot_output_beam.  g [n][n], G and phase [batch][n][n] as there.
+ * iters = 0 leaves the phase unchanged.  Returns FOT_E_INVALID for null arguments, iters < 0
+ * or invalid amplitudes (the phase is then unchanged).  Synchronises before returning. */
+fot_status fot_polish_gs(fot_plan_t plan, const double* g, const double* G, double* phase, int iters);
 
 /* Release the plan and all its device memory (after finishing its stream's work). */
 fot_status fot_destroy(fot_plan_t plan);

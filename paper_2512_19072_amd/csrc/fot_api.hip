@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "fot_fused.hpp"
+#include "fot_beam.hpp"
 
 using namespace fot;
 
@@ -95,6 +96,12 @@ struct fot_plan_s {
   bool used_graph = false;
   std::vector<hipEvent_t> prof;
   int prof_used = 0;
+  // output beam and Gerchberg-Saxton workspace (allocated at the first such call): the four
+  // DFT operands [np][2np], the field, the half-transformed field and the transform
+  // ([batch][np][2np] each), and per-target scalars
+  double *bWa = nullptr, *bWb = nullptr, *bWca = nullptr, *bWcb = nullptr;
+  double *bfc = nullptr, *bHt = nullptr, *bF = nullptr;
+  double *bpow = nullptr, *bsumG = nullptr, *brow = nullptr, *bl1 = nullptr;
   std::vector<void*> allocs;
 };
 
@@ -597,6 +604,98 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out) {
   return FOT_OK;
 }
 
+// ------------------------------------------------------------------ output beam (Sec. 4)
+__global__ void k_flag_nonpositive(const double* v, int cnt, int* flag) {
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+    if (!(v[i] > 0.0 && v[i] < INFINITY)) atomicOr(flag, 4);
+}
+
+fot_status beam_ready(fot_plan_s* p) {
+  if (p->bWa) return FOT_OK;
+  const size_t wsz = (size_t)p->np * 2 * p->np, fsz = (size_t)p->B * wsz;
+  fot_status s;
+  double** w[4] = {&p->bWa, &p->bWb, &p->bWca, &p->bWcb};
+  for (double** x : w)
+    if ((s = dalloc_t(p, x, wsz)) != FOT_OK) return s;
+  double** f[3] = {&p->bfc, &p->bHt, &p->bF};
+  for (double** x : f) {
+    if ((s = dalloc_t(p, x, fsz)) != FOT_OK) return s;
+    HIP_TRY(hipMemsetAsync(*x, 0, fsz * sizeof(double), p->stream));   // padding stays zero
+  }
+  if ((s = dalloc_t(p, &p->bpow, (size_t)p->B)) != FOT_OK) return s;
+  if ((s = dalloc_t(p, &p->bsumG, (size_t)p->B)) != FOT_OK) return s;
+  if ((s = dalloc_t(p, &p->brow, (size_t)p->B * p->n)) != FOT_OK) return s;
+  if ((s = dalloc_t(p, &p->bl1, (size_t)p->B)) != FOT_OK) return s;
+  const size_t cells = (size_t)p->np * p->np;
+  hipLaunchKernelGGL(k_dft_operands, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, p->stream, p->n, p->np,
+                     p->bWa, p->bWb, p->bWca, p->bWcb);
+  LAUNCH_CHECK();
+  return FOT_OK;
+}
+
+// dst = F[src] (forward) or conj-F[src] (inverse, without the 1/n^2), both in the [Re | Im]
+// row layout: four FP64 MFMA GEMMs with K = 2 np.
+fot_status beam_dft(fot_plan_s* p, const double* src, double* dst, bool inverse) {
+  const int np = p->np;
+  const long long wsz = (long long)np * 2 * np;
+  GemmArgs a{};
+  a.n = p->n;
+  a.np = np;
+  a.kp = 2 * np;
+  a.nk = (int)((size_t)2 * np * sizeof(double) / ROWB);
+  a.ldo = 2 * np;
+  a.xcd_swizzle = 1;
+  a.sA = 0;
+  a.sB = wsz;
+  a.sOut = wsz;
+  const double* Wr = inverse ? p->bWca : p->bWa;
+  const double* Wi = inverse ? p->bWcb : p->bWb;
+  typedef Ops<double> R;
+  fot_status s;
+  // step A: Ht[M][j] = sum_k W[M][k] f[j][k]
+  a.B = src;
+  a.A = Wr;
+  a.out = p->bHt;
+  if ((s = R::gemm_launch(p, EPI_RAW, a)) != FOT_OK) return s;
+  a.A = Wi;
+  a.out = p->bHt + np;
+  if ((s = R::gemm_launch(p, EPI_RAW, a)) != FOT_OK) return s;
+  // step B: F[L][M] = sum_j W[L][j] Ht[M][j]
+  a.B = p->bHt;
+  a.A = Wr;
+  a.out = dst;
+  if ((s = R::gemm_launch(p, EPI_RAW, a)) != FOT_OK) return s;
+  a.A = Wi;
+  a.out = dst + np;
+  return R::gemm_launch(p, EPI_RAW, a);
+}
+
+// Row sums of g^2 (and of G^2 if given) with input validation, 1 / (n^2 sum g^2) per target,
+// sum G^2 per target; flag bits 2 (negative or non-finite amplitude) and 4 (zero total).
+fot_status beam_inputs(fot_plan_s* p, const double* g, const double* G) {
+  const int n = p->n, B = p->B;
+  HIP_TRY(hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
+  hipLaunchKernelGGL(k_rowsumsq, dim3(n, 1), dim3(NTHREADS), 0, p->stream, g, n, p->rowsum_g, p->flag);
+  hipLaunchKernelGGL(k_inv_power, dim3(1), dim3(NTHREADS), 0, p->stream, p->rowsum_g, n, B, p->bpow);
+  hipLaunchKernelGGL(k_flag_nonpositive, dim3(1), dim3(NTHREADS), 0, p->stream, p->bpow, B, p->flag);
+  if (G) {
+    hipLaunchKernelGGL(k_rowsumsq, dim3(n, B), dim3(NTHREADS), 0, p->stream, G, n, p->rowsum_G, p->flag);
+    hipLaunchKernelGGL(k_sum_rows, dim3(B), dim3(NTHREADS), 0, p->stream, p->rowsum_G, n, p->bsumG);
+    hipLaunchKernelGGL(k_flag_nonpositive, dim3(1), dim3(NTHREADS), 0, p->stream, p->bsumG, B, p->flag);
+  }
+  LAUNCH_CHECK();
+  return FOT_OK;
+}
+
+fot_status beam_flag(fot_plan_s* p, const char* who) {
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (hflag & 2) return fail(FOT_E_INVALID, std::string(who) + ": amplitudes must be finite and >= 0");
+  if (hflag & 4) return fail(FOT_E_INVALID, std::string(who) + ": an image has zero (or non-finite) total intensity");
+  return FOT_OK;
+}
+
 template <typename F>
 fot_status dispatch(int prec, F&& fn) {
   switch (prec) {
@@ -954,6 +1053,53 @@ fot_status fot_backward(fot_plan_t p, const double* dL_dDual, const double* dL_d
   HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_backward: a replayed potential became non-finite");
+  return FOT_OK;
+}
+
+fot_status fot_output_beam(fot_plan_t p, const double* g, const double* phase, const double* G, double* intensity,
+                           double* l1) {
+  g_err.clear();
+  if (!p || !g || !phase) return fail(FOT_E_INVALID, "fot_output_beam: null argument");
+  if (l1 && !G) return fail(FOT_E_INVALID, "fot_output_beam: the L1 loss needs the target G");
+  const int n = p->n, np = p->np, B = p->B;
+  fot_status s;
+  if ((s = beam_ready(p)) != FOT_OK) return s;
+  if ((s = beam_inputs(p, g, G)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_beam_field, dim3(n, B), dim3(NTHREADS), 0, p->stream, g, phase, n, np, p->bfc);
+  LAUNCH_CHECK();
+  if ((s = beam_dft(p, p->bfc, p->bF, false)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_beam_intensity, dim3(n, B), dim3(NTHREADS), 0, p->stream, p->bF, n, np, p->bpow, G,
+                     p->bsumG, intensity, p->brow);
+  if (G) hipLaunchKernelGGL(k_sum_rows, dim3(B), dim3(NTHREADS), 0, p->stream, p->brow, n, p->bl1);
+  LAUNCH_CHECK();
+  if ((s = beam_flag(p, "fot_output_beam")) != FOT_OK) return s;
+  if (l1) {
+    HIP_TRY(hipMemcpyAsync(l1, p->bl1, sizeof(double) * B, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  return FOT_OK;
+}
+
+fot_status fot_polish_gs(fot_plan_t p, const double* g, const double* G, double* phase, int iters) {
+  g_err.clear();
+  if (!p || !g || !G || !phase) return fail(FOT_E_INVALID, "fot_polish_gs: null argument");
+  if (iters < 0) return fail(FOT_E_INVALID, "fot_polish_gs: iters must be >= 0");
+  const int n = p->n, np = p->np, B = p->B;
+  fot_status s;
+  if ((s = beam_ready(p)) != FOT_OK) return s;
+  if ((s = beam_inputs(p, g, G)) != FOT_OK) return s;
+  if ((s = beam_flag(p, "fot_polish_gs")) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_beam_field, dim3(n, B), dim3(NTHREADS), 0, p->stream, g, phase, n, np, p->bfc);
+  LAUNCH_CHECK();
+  for (int it = 0; it < iters; ++it) {
+    if ((s = beam_dft(p, p->bfc, p->bF, false)) != FOT_OK) return s;
+    hipLaunchKernelGGL(k_gs_project, dim3(n, B), dim3(NTHREADS), 0, p->stream, p->bF, G, n, np, p->bfc);
+    LAUNCH_CHECK();
+    if ((s = beam_dft(p, p->bfc, p->bF, true)) != FOT_OK) return s;
+    hipLaunchKernelGGL(k_gs_phase, dim3(n, B), dim3(NTHREADS), 0, p->stream, p->bF, g, n, np, phase, p->bfc);
+    LAUNCH_CHECK();
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
   return FOT_OK;
 }
 

@@ -231,7 +231,9 @@ struct GemmArgs {
   long long sA, sB;         // batch strides in elements
   int n, np, nk;            // valid size, padded size, number of K stages
   int xcd_swizzle;          // remap workgroups so each XCD works on a compact block of tiles
-  // EPI_LOGROW / EPI_RAW output (Z type, [batch][np][np])
+  int kp;                   // row pitch of A and B in elements (0: np); the K extent is nk stages
+  int ldo;                  // EPI_RAW: row pitch of the output in elements (0: np)
+  // EPI_LOGROW / EPI_RAW output (Z type, [batch][np][ldo])
   void* out;
   long long sOut;
   const double* mrow;       // [batch][np] row shifts of the pass-1 operand
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   int tr, tc;
   tile_of(gridDim.x, gridDim.y, p.xcd_swizzle, &tr, &tc);
   const int row0 = tr * BM, col0 = tc * BN;
-  const size_t pitch = (size_t)p.np * sizeof(T);
+  const size_t pitch = (size_t)(p.kp ? p.kp : p.np) * sizeof(T);
   const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
   const unsigned char* Bb = (const unsigned char*)p.B + ((size_t)bz * p.sB) * sizeof(T) + (size_t)col0 * pitch;
 
@@ -387,6 +389,7 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   const int n = p.n, np = p.np;
   if constexpr (EPI == EPI_RAW) {
     zt* out = (zt*)p.out + (size_t)bz * p.sOut;
+    const size_t ldo = p.ldo ? (size_t)p.ldo : (size_t)np;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
         for (int e = 0; e < 4; ++e) {
           const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int j = col0 + wn * C::WTN + cb * 16 + r16;
-          if (i < n && j < n) out[(size_t)i * np + j] = (zt)result(rb, cb, e);
+          if (i < n && j < n) out[(size_t)i * ldo + j] = (zt)result(rb, cb, e);
         }
   } else if constexpr (EPI == EPI_LOGROW) {
     zt* out = (zt*)p.out + (size_t)bz * p.sOut;

@@ -100,6 +100,10 @@ def load(path: str = LIB_PATH):
     lib.fot_potentials.restype = ip
     lib.fot_backward.argtypes = [vp, ctypes.POINTER(dp), vp, vp]
     lib.fot_backward.restype = ip
+    lib.fot_output_beam.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dp)]
+    lib.fot_output_beam.restype = ip
+    lib.fot_polish_gs.argtypes = [vp, vp, vp, vp, ip]
+    lib.fot_polish_gs.restype = ip
     lib.fot_destroy.argtypes = [vp]
     lib.fot_destroy.restype = ip
     lib.fot_last_error.argtypes = []
@@ -179,6 +183,19 @@ def fot_backward(plan: int, dL_dDual: Optional[Sequence[float]], dL_dphase, dL_d
                                ctypes.c_void_p(_ptr(dL_dG))), "fot_backward")
 
 
+def fot_output_beam(plan: int, g, phase, G=None, intensity=None, l1: Optional[np.ndarray] = None):
+    """fot_output_beam; ``l1`` is a host float64 array of length batch (or None)."""
+    lp = None if l1 is None else l1.ctypes.data_as(_dp)
+    _check(load().fot_output_beam(ctypes.c_void_p(plan), ctypes.c_void_p(_ptr(g)), ctypes.c_void_p(_ptr(phase)),
+                                  ctypes.c_void_p(_ptr(G)), ctypes.c_void_p(_ptr(intensity)), lp),
+           "fot_output_beam")
+
+
+def fot_polish_gs(plan: int, g, G, phase, iters: int):
+    _check(load().fot_polish_gs(ctypes.c_void_p(plan), ctypes.c_void_p(_ptr(g)), ctypes.c_void_p(_ptr(G)),
+                                ctypes.c_void_p(_ptr(phase)), int(iters)), "fot_polish_gs")
+
+
 def fot_destroy(plan: int):
     _check(load().fot_destroy(ctypes.c_void_p(plan)), "fot_destroy")
 
@@ -249,6 +266,19 @@ class Plan:
         out = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=dev)
         fot_backward(self.handle, dL_dDual, dL_dphase, out)
         return out
+
+    def output_beam(self, g, phase, G=None, intensity: bool = True):
+        """(unit-power output intensity [batch][n][n] or None, L1 loss per target or None)."""
+        import torch
+        I = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=g.device) if intensity else None
+        l1 = np.zeros(self.batch) if G is not None else None
+        fot_output_beam(self.handle, g, phase, G, I, l1)
+        return I, l1
+
+    def polish_gs(self, g, G, phase, iters: int):
+        """Gerchberg-Saxton rounds on ``phase`` (in place); returns it."""
+        fot_polish_gs(self.handle, g, G, phase, iters)
+        return phase
 
     def close(self):
         if getattr(self, "handle", None):

@@ -51,6 +51,8 @@ def test_null_arguments_are_rejected():
     assert lib.fot_solve(None, None, None, None, 1, 1, 0, None, None) == F.FOT_E_INVALID
     assert lib.fot_potentials(None, None, None, None, None) == F.FOT_E_INVALID
     assert lib.fot_backward(None, None, None, None) == F.FOT_E_INVALID
+    assert lib.fot_output_beam(None, None, None, None, None, None) == F.FOT_E_INVALID
+    assert lib.fot_polish_gs(None, None, None, None, 1) == F.FOT_E_INVALID
     assert lib.fot_destroy(None) == F.FOT_E_INVALID
 
 
