@@ -85,12 +85,24 @@ __device__ __forceinline__ T block_operand(double x, int K) {
 }
 
 // exp(x) and exp(d) - 1 (d < 10) in FP32 for the marginal-error terms, which need a few
-// significant digits: a short series below |d| = 0.03, the hardware exponential otherwise.
-__device__ __forceinline__ float exp_err(double x) { return exp2_hw(x * INV_LN2); }
-__device__ __forceinline__ float expm1_err(double d) {
-  const float df = (float)d;
-  const float series = df * (1.0f + df * (0.5f + df * (1.0f / 6.0f + df * (1.0f / 24.0f))));
-  return fabsf(df) < 0.03f ? series : exp2_hw(d * INV_LN2) - 1.0f;
+// significant digits: the argument is rounded to FP32 first (|x| stays below a few hundred where
+// the result is not negligible, so that costs under 1e-5 relative), then a short series below
+// |d| = 0.03 and the hardware exponential otherwise.
+constexpr float INV_LN2F = 1.44269504088896340736f;
+__device__ __forceinline__ float exp_err(float x) { return __builtin_amdgcn_exp2f(x * INV_LN2F); }
+__device__ __forceinline__ float expm1_err(float d) {
+  const float series = d * (1.0f + d * (0.5f + d * (1.0f / 6.0f + d * (1.0f / 24.0f))));
+  return fabsf(d) < 0.03f ? series : exp_err(d) - 1.0f;
+}
+
+// ln v of an FP32-accumulated contraction: v = m 2^e exactly (frexp, m in [1/2, 1)), then
+// log2 m by the hardware logarithm (V_LOG_F32) of m rounded to FP32.  The absolute error is about
+// 1e-7, the size of the relative rounding error that FP32 operands leave in v itself.  Zero,
+// infinity and NaN map to -inf, +inf and NaN.
+__device__ __forceinline__ double log_op32(double v) {
+  int e;
+  const double m = frexp(v, &e);
+  return ((double)e + (double)__builtin_amdgcn_logf((float)m)) * LN2;
 }
 
 // max over the 16 lanes of each row of a wave (DPP: quad swaps, then half-row and row mirrors)
@@ -625,8 +637,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const bool ok = i < n && j < n;
           const double v = accd[rb][cb][e];
-          // ln S: FP64 log for FP32/FP64 operands, logf for 16-bit operands
-          const double lnS = shift + ((sizeof(T) == 2) ? (double)logf((float)v) : log_fp64(v));
+          // ln S: FP64 logarithm for FP64 operands; for the FP32-accumulated types a logarithm
+          // as accurate as the sum itself
+          const double lnS = shift + ((sizeof(T) == 8) ? log_fp64(v) : log_op32(v));
           const double la = la_v[cb][rb][e];
           const double fold = fo_v[cb][rb][e];
           const bool zm = la == -INFINITY;
@@ -636,10 +649,11 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
             // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp(d) - 1| with
             // d = (f_old - f_new)/eps, evaluated as exp(ln a + d) - a once d is large (a e^d is
             // the pixel's entering mass, at most 1, while e^d alone can overflow FP32 for tiny a)
-            const float tz = exp_err(fold * inv_eps + lnS);
+            const float tz = exp_err((float)fma(fold, inv_eps, lnS));
             const double d = (fold - fnew) * inv_eps;
-            const float av = exp_err(la);
-            const float ta = (d < 10.0) ? av * fabsf(expm1_err(d)) : exp_err(la + d) - av;
+            const float df = (float)d, laf = (float)la;
+            const float av = exp_err(laf);
+            const float ta = (df < 10.0f) ? av * fabsf(expm1_err(df)) : exp_err(laf + df) - av;
             err += ok ? (double)(zm ? tz : ta) : 0.0;
           }
           bad = bad || (ok && !zm && !(fabs(fnew) < INFINITY));
