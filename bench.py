@@ -67,12 +67,14 @@ def measured_traffic(prec):
     return round(float(blob[prec]["bytes_per_launch"]))
 
 
-def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True, graph=True, history=True):
+def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True, graph=True, history=True,
+                cfot=False):
     n = g.shape[-1]
     dev = torch.device("cuda", 0)
     gd = torch.tensor(g, dtype=torch.float64, device=dev)
     Gd = torch.tensor(G, dtype=torch.float64, device=dev)
-    plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph, history=history)
+    plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph, history=history,
+                  cfot=cfot)
     phase = torch.empty((G.shape[0], n, n), dtype=torch.float64, device=dev)
     for _ in range(warmup):
         plan.solve(gd, Gd, eps, iters, out=phase)
@@ -329,6 +331,36 @@ def main():
                               f"l1_fot_plus_{gs_rounds}_gs": float(l_gs[0])}
         log(f"bench: output beam {1e3 * t_beam:.2f} ms ({tflop:.1f} TFLOP/s FP64), GS round {1e3 * t_gs:.2f} ms; "
             f"L1 flat {l_flat[0]:.4f}, FOT {l_fot[0]:.4f}, FOT + {gs_rounds} GS {l_gs[0]:.4f}")
+
+        # cFOT (Eq. 11): the same solve with FP64 FFT convolutions instead of the matrix products,
+        # against the FP64 and FP32 matrix-product paths (speed, and accuracy against FP64)
+        conv = {}
+        for name, prec, cf in (("cfot_f64_fft", "f64", True), ("gemm_f64", "f64", False)):
+            el, rp = run_variant(F, W, torch, prec, g, G, eps, iters, max(2, args.steps // 2), 1,
+                                 profile=False, graph=graph, cfot=cf)
+            _, rpp = run_variant(F, W, torch, prec, g, G, eps, iters, 1, 1, profile=True, graph=False, cfot=cf)
+            steps_c = max(2, args.steps // 2)
+            conv[name] = {"value": round(n * n * iters * steps_c / el / 1e6, 3),
+                          "us_per_iteration": round(1e3 * float(np.median([r.ms_iterations for r in rp])) / iters, 2),
+                          "pass_avg_us": round(1e3 * sum(r.ms_contract for r in rpp)
+                                               / max(1, sum(r.n_contract for r in rpp)), 3),
+                          "final_err_a": float(rp[-1].err_a[0])}
+        conv["gemm_" + prec0] = {"value": round(value, 3), "us_per_iteration": round(1e3 * ms_iter0, 2),
+                                 "pass_avg_us": round(1e3 * ms_gemm, 3), "final_err_a": float(reps[-1].err_a[0])}
+        pots = {}
+        for name, prec, cf in (("cfot_f64_fft", "f64", True), ("gemm_f64", "f64", False)):
+            plan = F.Plan(n, G.shape[0], prec, max_iters=iters, cfot=cf)
+            plan.solve(gd, Gd, eps, iters, phase=False)
+            pots[name] = plan.potentials()[0].cpu().numpy()[0]
+            plan.close()
+        fin = np.isfinite(pots["gemm_f64"])
+        dv = pots["cfot_f64_fft"][fin] - pots["gemm_f64"][fin]
+        conv["cfot_f_err_vs_f64_gemm"] = float(np.max(np.abs(dv - dv.mean())) / np.ptp(pots["gemm_f64"][fin]))
+        out["contraction_by_fft"] = conv
+        log(f"bench: cFOT (FP64 FFT) {conv['cfot_f64_fft']['value']:.1f} Mpx.it/s "
+            f"({conv['cfot_f64_fft']['us_per_iteration']:.1f} us/it, pass {conv['cfot_f64_fft']['pass_avg_us']:.1f} us), "
+            f"FP64 GEMM {conv['gemm_f64']['value']:.1f}, {prec0} GEMM {conv['gemm_' + prec0]['value']:.1f}; "
+            f"cFOT f error vs FP64 GEMM {conv['cfot_f_err_vs_f64_gemm']:.1e}")
 
         # small-grid latency (the paper's 128^2, 200 iterations): one whole solve per call,
         # inputs resident, timed wall-clock around the call

@@ -66,10 +66,22 @@ enum {
                             recorded inside a graph cannot be timed) */
   FOT_FLAG_NO_GRAPH = 2, /* launch the iteration loop kernel by kernel instead of replaying a
                             HIP graph of it (the results are bit-identical either way) */
-  FOT_FLAG_NO_HISTORY = 4 /* do not evaluate the per-iteration marginal errors (the paper's
+  FOT_FLAG_NO_HISTORY = 4, /* do not evaluate the per-iteration marginal errors (the paper's
                             practice of running a fixed number of iterations without a loss,
                             Sec. 3 after Algorithm 1): err_*_history is filled with NaN; the
                             potentials, phase and final report values are bit-identical */
+  FOT_FLAG_CFOT = 8      /* cFOT (Sec. 3, convolutional speedup, Eq. 11): apply Lambda . X .
+                            Lambda in the iterations as two 1-D linear convolutions with
+                            lambda_j = exp(-j^2 / (2 n^2 eps)) by FP64 FFTs of length N =
+                            2^ceil(log2(2n - 1)), O(n^2 log n) per half-step instead of the
+                            O(n^3) matrix products.  Requires FOT_F64, n <= 2048 and
+                            checkpoint_every = 0 (no reverse mode); otherwise fot_plan returns
+                            FOT_E_UNSUPPORTED.  The read-out (Eq. 9-10, the report) is the same
+                            FP64 computation as without the flag.  An FFT's rounding is relative
+                            to each whole row, so convolution values far below their row's
+                            largest lose accuracy: at small eps fot_solve may return
+                            FOT_E_NONFINITE, or FOT_E_RANGE when the final column-marginal L1
+                            exceeds 1e-6 */
 };
 
 typedef struct {

@@ -15,6 +15,7 @@
 
 #include "fot_fused.hpp"
 #include "fot_beam.hpp"
+#include "fot_cfot.hpp"
 
 using namespace fot;
 
@@ -102,6 +103,14 @@ struct fot_plan_s {
   double *bWa = nullptr, *bWb = nullptr, *bWca = nullptr, *bWcb = nullptr;
   double *bfc = nullptr, *bHt = nullptr, *bF = nullptr;
   double *bpow = nullptr, *bsumG = nullptr, *brow = nullptr, *bl1 = nullptr;
+  // cFOT (FOT_FLAG_CFOT): FFT length, twiddles, lambda's transform (for clam_eps), the transposed
+  // intermediate of a half-step, f^T and ln a^T (the u-update's orientation), ln S^T of the last
+  // u-update, and one marginal-error partial per workgroup
+  bool cfot = false;
+  int cN = 0;
+  cplx* ctw = nullptr;
+  double *clamhat = nullptr, *cY = nullptr, *cfT = nullptr, *clnaT = nullptr, *cS = nullptr, *cparts = nullptr;
+  double clam_eps = -1.0;
   std::vector<void*> allocs;
 };
 
@@ -161,6 +170,49 @@ fot_status rev_lambda(fot_plan_s* p, double eps);
 fot_status rev_contract(fot_plan_s* p, const double* v, const double* L);
 fot_status rev_axpy(fot_plan_s* p, const double* P, double eps, const double* lnm, long long sMarg, double scale,
                     int row_coord, int col_coord, int acc, double* out);
+
+// Run `loop` as a cached HIP graph replayed on p->stream (captured on a private stream), keyed by
+// the eps schedule and the tape setting.  If capture or instantiation fails, the loop is
+// launched eagerly (results are identical) and graphs are not tried again for this plan.
+// p->used_graph tells whether the graph ran (the caller then restores the state the loop would
+// have left).
+template <typename LoopFn>
+fot_status run_graph(fot_plan_s* p, const std::vector<double>& e, int iters, LoopFn loop) {
+  const bool tape = p->tape != nullptr;
+  if (!(p->gexec && p->graph_eps == e && p->graph_tape == tape)) {
+    drop_graph(p);
+    hipStream_t user = p->stream;
+    const int prof0 = p->prof_used;
+    p->stream = p->cap;
+    p->pending_hist = nullptr;
+    hipError_t eb = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    fot_status s = (eb == hipSuccess) ? loop(p, e, iters) : FOT_E_HIP;
+    hipGraph_t g = nullptr;
+    hipError_t ec = (eb == hipSuccess) ? hipStreamEndCapture(p->cap, &g) : eb;
+    p->stream = user;
+    hipError_t ei = hipErrorUnknown;
+    if (s == FOT_OK && ec == hipSuccess && g) ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      p->gexec = nullptr;
+      (void)hipGetLastError();
+      p->graph_broken = true;
+      p->prof_used = prof0;
+      p->pending_hist = nullptr;
+      g_err.clear();
+      return loop(p, e, iters);
+    }
+    p->graph = g;
+    p->graph_eps = e;
+    p->graph_tape = tape;
+    p->graph_prof = p->prof_used;
+  } else {
+    p->prof_used = p->graph_prof;
+  }
+  HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
+  p->used_graph = true;
+  return FOT_OK;
+}
 
 template <typename T>
 struct Ops {
@@ -318,47 +370,18 @@ struct Ops {
     return FOT_OK;
   }
 
-  // Run the loop as a cached HIP graph replayed on p->stream (captured on a private stream).
-  // If capture or instantiation fails, the loop is launched eagerly (results are identical).
+  // Run the loop as a cached HIP graph replayed on p->stream (see run_graph).
   static fot_status loop_graph(fot_plan_s* p, const std::vector<double>& e, int iters) {
-    const bool tape = p->tape != nullptr;
-    if (!(p->gexec && p->graph_eps == e && p->graph_tape == tape)) {
-      drop_graph(p);
-      hipStream_t user = p->stream;
-      const int prof0 = p->prof_used;
-      p->stream = p->cap;
-      p->pending_hist = nullptr;
-      hipError_t eb = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
-      fot_status s = (eb == hipSuccess) ? loop(p, e, iters) : FOT_E_HIP;
-      hipGraph_t g = nullptr;
-      hipError_t ec = (eb == hipSuccess) ? hipStreamEndCapture(p->cap, &g) : eb;
-      p->stream = user;
-      hipError_t ei = hipErrorUnknown;
-      if (s == FOT_OK && ec == hipSuccess && g) ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-      if (ei != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        p->gexec = nullptr;
-        (void)hipGetLastError();
-        p->graph_broken = true;
-        p->prof_used = prof0;
-        p->pending_hist = nullptr;
-        g_err.clear();
-        return loop(p, e, iters);
-      }
-      p->graph = g;
-      p->graph_eps = e;
-      p->graph_tape = tape;
-      p->graph_prof = p->prof_used;
-    } else {
-      p->prof_used = p->graph_prof;
+    fot_status s = run_graph(p, e, iters, [](fot_plan_s* q, const std::vector<double>& ee, int it) {
+      return loop(q, ee, it);
+    });
+    if (s == FOT_OK && p->used_graph) {
+      // state after the loop, as if it had been launched directly
+      p->pending_hist = (p->d.flags & FOT_FLAG_NO_HISTORY) ? nullptr : p->hist_b + (size_t)(iters - 1) * p->B;
+      p->lam_eps = e[iters - 1];
+      p->lamH_valid = false;
     }
-    HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
-    p->used_graph = true;
-    // state after the loop, as if it had been launched directly
-    p->pending_hist = (p->d.flags & FOT_FLAG_NO_HISTORY) ? nullptr : p->hist_b + (size_t)(iters - 1) * p->B;
-    p->lam_eps = e[iters - 1];
-    p->lamH_valid = false;
-    return FOT_OK;
+    return s;
   }
 
   // ---------------------------------------------------------------- reverse mode
@@ -696,6 +719,90 @@ fot_status beam_flag(fot_plan_s* p, const char* who) {
   return FOT_OK;
 }
 
+// ------------------------------------------------------------------ cFOT (Eq. 11)
+// One cFOT pass, with HIP-event timing under FOT_FLAG_PROFILE (counted like the fused passes).
+template <typename K, typename... Args>
+fot_status cfot_launch(fot_plan_s* p, K kernel, Args... args) {
+  const dim3 grid((unsigned)((p->n + 1) / 2), (unsigned)p->B);
+  const bool prof = (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
+  hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
+  hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, dim3(CFOT_THREADS), (uint32_t)cfot_lds_bytes(p->cN), p->stream, e0, e1, 0,
+                        args...);
+  LAUNCH_CHECK();
+  if (prof) p->prof_used += 2;
+  return FOT_OK;
+}
+
+// One half-step by convolutions: Pin (one orientation) -> Pout (the other), Eq. 7 or 8.
+fot_status cfot_half(fot_plan_s* p, const double* Pin, double* Pout, const double* lnm, long long sMarg,
+                     double* hist, double* lnS_out, double eps) {
+  const long long plane = (long long)p->plane;
+  fot_status s = cfot_launch(p, k_cfot_pass1, Pin, plane, 1.0 / eps, p->n, p->np, p->cN, (const cplx*)p->ctw,
+                             (const double*)p->clamhat, p->cY, plane);
+  if (s != FOT_OK) return s;
+  s = cfot_launch(p, k_cfot_pass2, (const double*)p->cY, plane, p->n, p->np, p->cN, (const cplx*)p->ctw,
+                  (const double*)p->clamhat, lnm, sMarg, Pout, plane, lnS_out, eps, p->cparts, p->flag,
+                  hist != nullptr ? 1 : 0);
+  if (s != FOT_OK) return s;
+  if (hist) {
+    hipLaunchKernelGGL(k_cfot_sum, dim3(p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->cparts,
+                       (p->n + 1) / 2, hist);
+    LAUNCH_CHECK();
+  }
+  return FOT_OK;
+}
+
+fot_status cfot_transpose(fot_plan_s* p, const double* in, long long sIn, double* out, long long sOut, int batch) {
+  const unsigned t = (unsigned)((p->n + 31) / 32);
+  hipLaunchKernelGGL(k_transpose64, dim3(t, t, batch), dim3(256), 0, p->stream, in, sIn, out, sOut, p->n, p->np);
+  LAUNCH_CHECK();
+  return FOT_OK;
+}
+
+// The iteration loop of Algorithm 1 with convolutions: f is carried transposed (with ln a
+// transposed to match) and restored to the natural layout at the end, with ln S of the last
+// u-update, so the read-out and the potentials API see the same state as after the GEMM loop.
+fot_status cfot_loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
+  const long long plane = (long long)p->plane;
+  const int B = p->B;
+  fot_status s;
+  if ((s = cfot_transpose(p, p->lna, 0, p->clnaT, 0, 1)) != FOT_OK) return s;
+  if ((s = cfot_transpose(p, p->f, plane, p->cfT, plane, B)) != FOT_OK) return s;
+  const bool hist = !(p->d.flags & FOT_FLAG_NO_HISTORY);
+  for (int t = 0; t < iters; ++t) {
+    const double ep = e[t];
+    if (t == 0 || ep != e[t - 1]) {
+      hipLaunchKernelGGL(k_cfot_lamhat, dim3(1), dim3(CFOT_THREADS), (uint32_t)cfot_lds_bytes(p->cN), p->stream,
+                         p->n, p->cN, 1.0 / ep, (const cplx*)p->ctw, p->clamhat);
+      LAUNCH_CHECK();
+    }
+    const bool last = t == iters - 1;
+    if ((s = cfot_half(p, p->psi, p->cfT, p->clnaT, 0, hist ? p->hist_a + (size_t)t * B : nullptr,
+                       last ? p->cS : nullptr, ep)) != FOT_OK)
+      return s;
+    if ((s = cfot_half(p, p->cfT, p->psi, p->lnb, plane, hist ? p->hist_b + (size_t)t * B : nullptr,
+                       last ? p->lnSp : nullptr, ep)) != FOT_OK)
+      return s;
+  }
+  if ((s = cfot_transpose(p, p->cfT, plane, p->f, plane, B)) != FOT_OK) return s;
+  if ((s = cfot_transpose(p, p->cS, plane, p->lnS, plane, B)) != FOT_OK) return s;
+  p->clam_eps = e[iters - 1];
+  p->pending_hist = nullptr;
+  return FOT_OK;
+}
+
+fot_status cfot_loop_graph(fot_plan_s* p, const std::vector<double>& e, int iters) {
+  fot_status s = run_graph(p, e, iters, [](fot_plan_s* q, const std::vector<double>& ee, int it) {
+    return cfot_loop(q, ee, it);
+  });
+  if (s == FOT_OK && p->used_graph) {
+    p->clam_eps = e[iters - 1];
+    p->pending_hist = nullptr;
+  }
+  return s;
+}
+
 template <typename F>
 fot_status dispatch(int prec, F&& fn) {
   switch (prec) {
@@ -728,8 +835,17 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   if (d.precision < FOT_F64 || d.precision > FOT_BF16X3) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
-  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY))
+  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT))
     return fail(FOT_E_INVALID, "fot_plan: unknown flag bits");
+  int cN = 0;
+  if (d.flags & FOT_FLAG_CFOT) {
+    if (d.precision != FOT_F64) return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT needs FOT_F64 (FP64 FFTs)");
+    if (d.checkpoint_every > 0)
+      return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT has no reverse mode (checkpoint_every must be 0)");
+    cN = 2;
+    while (cN < 2 * d.n - 1) cN <<= 1;
+    if (cN > CFOT_MAX_N) return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT supports n <= 2048");
+  }
   fot_plan_s* p = new (std::nothrow) fot_plan_s();
   if (!p) return fail(FOT_E_NOMEM, "fot_plan: host allocation failed");
   p->d = d;
@@ -816,6 +932,29 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   ALLOC(p->fSy, BP);
   ALLOC(p->fScx, BP);
   ALLOC(p->fScy, BP);
+  if (cN > 0) {
+    p->cfot = true;
+    p->cN = cN;
+    void* tw = nullptr;
+    if ((s = dalloc(p, &tw, sizeof(cplx) * (size_t)(cN / 2))) != FOT_OK) return bail(s);
+    p->ctw = (cplx*)tw;
+    ALLOC(p->clamhat, (size_t)cN);
+    ALLOC(p->cY, BP);
+    ALLOC(p->cfT, BP);
+    ALLOC(p->clnaT, p->plane);
+    ALLOC(p->cS, BP);
+    ALLOC(p->cparts, (size_t)p->B * ((p->n + 1) / 2));
+    const int lds = (int)cfot_lds_bytes(cN);
+    if (hipFuncSetAttribute((const void*)k_cfot_pass1, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)k_cfot_pass2, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)k_cfot_lamhat, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+            hipSuccess)
+      return bail(fail(FOT_E_HIP, "fot_plan: cannot reserve LDS for the FFT kernels"));
+    hipLaunchKernelGGL(k_cfot_twiddles, dim3((unsigned)((cN / 2 + 255) / 256)), dim3(256), 0, p->stream, cN, p->ctw);
+    if (hipGetLastError() != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: twiddle kernel launch failed"));
+  }
   if (d.checkpoint_every > 0) {
     p->n_ckpt = (d.max_iters + d.checkpoint_every - 1) / d.checkpoint_every;
     const size_t kseg = (size_t)std::min(d.checkpoint_every, d.max_iters);
@@ -953,7 +1092,11 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     HIP_TRY(hipEventRecord(p->ev[1], p->stream));
     const bool graph = !(p->d.flags & (FOT_FLAG_NO_GRAPH | FOT_FLAG_PROFILE)) && !p->graph_broken;
     p->used_graph = false;
-    fot_status s0 = graph ? Ops<T>::loop_graph(p, e, iters) : Ops<T>::loop(p, e, iters);
+    fot_status s0;
+    if (p->cfot)
+      s0 = graph ? cfot_loop_graph(p, e, iters) : cfot_loop(p, e, iters);
+    else
+      s0 = graph ? Ops<T>::loop_graph(p, e, iters) : Ops<T>::loop(p, e, iters);
     if (s0 != FOT_OK) return s0;
     HIP_TRY(hipEventRecord(p->ev[2], p->stream));
     fot_status s = readout64(p, e[iters - 1], phase_out);
@@ -1011,7 +1154,8 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_solve: a potential became non-finite");
   {
     // the final column marginal is exact up to the operand type's error in the last V-update
-    const double bound = p->prec == FOT_F64    ? 1e-8
+    const double bound = p->cfot                 ? 1e-6
+                         : p->prec == FOT_F64    ? 1e-8
                          : p->prec == FOT_F32    ? 1e-5
                          : p->prec == FOT_BF16X3 ? 1e-4
                                                  : 2e-2;
@@ -1020,8 +1164,11 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
       if (!(err_b <= bound)) {
         char msg[256];
         std::snprintf(msg, sizeof msg,
-                      "fot_solve: target %d: final column-marginal L1 %.3g exceeds %.0e: the Gibbs products "
-                      "underflowed in the operand type at eps %.3g (use FOT_F64 or a larger eps)",
+                      p->cfot ? "fot_solve: target %d: final column-marginal L1 %.3g exceeds %.0e: the FFT "
+                                "convolutions lost the small values at eps %.3g (use the matrix-product "
+                                "contraction or a larger eps)"
+                              : "fot_solve: target %d: final column-marginal L1 %.3g exceeds %.0e: the Gibbs "
+                                "products underflowed in the operand type at eps %.3g (use FOT_F64 or a larger eps)",
                       b, err_b, bound, e[iters - 1]);
         return fail(FOT_E_RANGE, msg);
       }

@@ -75,3 +75,18 @@ def test_header_enum_values_match_binding():
     for name, val in pairs:
         assert getattr(F, name) == int(val), name
     assert F.PRECISIONS["bf16x3"] == F.FOT_BF16X3
+
+
+@pytest.mark.parametrize("desc, msg", [
+    ((64, 1, 1, 10, 0, 8), "FOT_F64"),             # cFOT with FP32 operands
+    ((64, 1, 0, 10, 5, 8), "reverse mode"),        # cFOT with a tape
+    ((3000, 1, 0, 10, 0, 8), "n <= 2048"),         # FFT length beyond 4096
+])
+def test_cfot_plan_limits(desc, msg):
+    lib = F.load()
+    d = F.fot_plan_desc(*desc)
+    h = ctypes.c_void_p()
+    st = lib.fot_plan(ctypes.byref(d), None, ctypes.byref(h))
+    assert st == F.FOT_E_UNSUPPORTED
+    assert msg in F.fot_last_error()
+    assert h.value is None
