@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fot_fused.hpp"
@@ -734,16 +735,32 @@ fot_status cfot_launch(fot_plan_s* p, K kernel, Args... args) {
   return FOT_OK;
 }
 
+// fn(std::integral_constant<int, N>) for the plan's FFT length
+template <typename F>
+fot_status cfot_dispatch(int N, F&& fn) {
+  switch (N) {
+    case 256: return fn(std::integral_constant<int, 256>{});
+    case 512: return fn(std::integral_constant<int, 512>{});
+    case 1024: return fn(std::integral_constant<int, 1024>{});
+    case 2048: return fn(std::integral_constant<int, 2048>{});
+    case 4096: return fn(std::integral_constant<int, 4096>{});
+    default: return fail(FOT_E_UNSUPPORTED, "cFOT: unsupported FFT length");
+  }
+}
+
 // One half-step by convolutions: Pin (one orientation) -> Pout (the other), Eq. 7 or 8.
 fot_status cfot_half(fot_plan_s* p, const double* Pin, double* Pout, const double* lnm, long long sMarg,
                      double* hist, double* lnS_out, double eps) {
   const long long plane = (long long)p->plane;
-  fot_status s = cfot_launch(p, k_cfot_pass1, Pin, plane, 1.0 / eps, p->n, p->np, p->cN, (const cplx*)p->ctw,
-                             (const double*)p->clamhat, p->cY, plane);
-  if (s != FOT_OK) return s;
-  s = cfot_launch(p, k_cfot_pass2, (const double*)p->cY, plane, p->n, p->np, p->cN, (const cplx*)p->ctw,
-                  (const double*)p->clamhat, lnm, sMarg, Pout, plane, lnS_out, eps, p->cparts, p->flag,
-                  hist != nullptr ? 1 : 0);
+  fot_status s = cfot_dispatch(p->cN, [&](auto nc) -> fot_status {
+    constexpr int N = decltype(nc)::value;
+    fot_status r = cfot_launch(p, k_cfot_pass1<N>, Pin, plane, 1.0 / eps, p->n, p->np, (const cplx*)p->ctw,
+                               (const double*)p->clamhat, p->cY, plane);
+    if (r != FOT_OK) return r;
+    return cfot_launch(p, k_cfot_pass2<N>, (const double*)p->cY, plane, p->n, p->np, (const cplx*)p->ctw,
+                       (const double*)p->clamhat, lnm, sMarg, Pout, plane, lnS_out, eps, p->cparts, p->flag,
+                       hist != nullptr ? 1 : 0);
+  });
   if (s != FOT_OK) return s;
   if (hist) {
     hipLaunchKernelGGL(k_cfot_sum, dim3(p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->cparts,
@@ -773,9 +790,14 @@ fot_status cfot_loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
   for (int t = 0; t < iters; ++t) {
     const double ep = e[t];
     if (t == 0 || ep != e[t - 1]) {
-      hipLaunchKernelGGL(k_cfot_lamhat, dim3(1), dim3(CFOT_THREADS), (uint32_t)cfot_lds_bytes(p->cN), p->stream,
-                         p->n, p->cN, 1.0 / ep, (const cplx*)p->ctw, p->clamhat);
-      LAUNCH_CHECK();
+      s = cfot_dispatch(p->cN, [&](auto nc) -> fot_status {
+        constexpr int N = decltype(nc)::value;
+        hipLaunchKernelGGL(k_cfot_lamhat<N>, dim3(1), dim3(CFOT_THREADS), (uint32_t)cfot_lds_bytes(N), p->stream,
+                           p->n, 1.0 / ep, (const cplx*)p->ctw, p->clamhat);
+        LAUNCH_CHECK();
+        return FOT_OK;
+      });
+      if (s != FOT_OK) return s;
     }
     const bool last = t == iters - 1;
     if ((s = cfot_half(p, p->psi, p->cfT, p->clnaT, 0, hist ? p->hist_a + (size_t)t * B : nullptr,
@@ -842,7 +864,7 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
     if (d.precision != FOT_F64) return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT needs FOT_F64 (FP64 FFTs)");
     if (d.checkpoint_every > 0)
       return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT has no reverse mode (checkpoint_every must be 0)");
-    cN = 2;
+    cN = CFOT_MIN_N;
     while (cN < 2 * d.n - 1) cN <<= 1;
     if (cN > CFOT_MAX_N) return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT supports n <= 2048");
   }
@@ -945,13 +967,18 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
     ALLOC(p->cS, BP);
     ALLOC(p->cparts, (size_t)p->B * ((p->n + 1) / 2));
     const int lds = (int)cfot_lds_bytes(cN);
-    if (hipFuncSetAttribute((const void*)k_cfot_pass1, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-            hipSuccess ||
-        hipFuncSetAttribute((const void*)k_cfot_pass2, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-            hipSuccess ||
-        hipFuncSetAttribute((const void*)k_cfot_lamhat, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-            hipSuccess)
-      return bail(fail(FOT_E_HIP, "fot_plan: cannot reserve LDS for the FFT kernels"));
+    s = cfot_dispatch(cN, [&](auto nc) -> fot_status {
+      constexpr int N = decltype(nc)::value;
+      if (hipFuncSetAttribute((const void*)k_cfot_pass1<N>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+              hipSuccess ||
+          hipFuncSetAttribute((const void*)k_cfot_pass2<N>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+              hipSuccess ||
+          hipFuncSetAttribute((const void*)k_cfot_lamhat<N>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+              hipSuccess)
+        return fail(FOT_E_HIP, "fot_plan: cannot reserve LDS for the FFT kernels");
+      return FOT_OK;
+    });
+    if (s != FOT_OK) return bail(s);
     hipLaunchKernelGGL(k_cfot_twiddles, dim3((unsigned)((cN / 2 + 255) / 256)), dim3(256), 0, p->stream, cN, p->ctw);
     if (hipGetLastError() != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: twiddle kernel launch failed"));
   }

@@ -17,9 +17,11 @@
 //
 // Each workgroup transforms two rows at once as the real and imaginary parts of one complex
 // sequence (lambda's transform is real and even, so the two results stay separate), entirely in
-// LDS: a radix-2 decimation-in-frequency forward FFT (natural order in, bit-reversed out), the
-// product with lambda's transform held in the same bit-reversed order, and a radix-2
-// decimation-in-time inverse (bit-reversed in, natural out), so no permutation pass is needed.
+// LDS, by a mixed-radix Stockham FFT (natural order in and out): each stage reads R values per
+// work item with stride N/R, applies the stage twiddles, runs a radix-R DFT in registers
+// (R = 8, with one radix-4 or radix-2 stage last) and writes the R results with stride Ns, the
+// product of the radices done so far.  N = 2^k is a compile-time parameter (256 .. 4096), so
+// every index is a shift or a mask and the register arrays are fixed.
 //
 // Accuracy: an FFT's rounding is relative to the whole row, so a convolution value far below its
 // row's largest carries an absolute error of about 1e-16 of that row's sum.  This is the source of
@@ -37,7 +39,8 @@ struct cplx {
 };
 
 constexpr int CFOT_THREADS = 256;
-constexpr int CFOT_MAX_N = 4096;   // FFT length limit (n <= 2048)
+constexpr int CFOT_MIN_N = 256;    // FFT lengths: powers of two in [256, 4096] (n <= 2048)
+constexpr int CFOT_MAX_N = 4096;
 
 // Dynamic LDS of a cFOT pass: the sequence (N complex) and the twiddles (N/2 complex).
 inline size_t cfot_lds_bytes(int N) { return (size_t)N * sizeof(cplx) + (size_t)(N / 2) * sizeof(cplx); }
@@ -51,39 +54,97 @@ __global__ void k_cfot_twiddles(int N, cplx* tw) {
   tw[k] = cplx{c, -s};
 }
 
-// Forward FFT in place, natural order in, bit-reversed order out (radix-2, decimation in frequency).
-__device__ __forceinline__ void fft_dif(cplx* z, const cplx* tw, int N) {
-  for (int m = N; m >= 2; m >>= 1) {
-    const int half = m >> 1, ts = N / m;
-    const int lh = __builtin_ctz(half);
-    for (int q = threadIdx.x; q < N / 2; q += blockDim.x) {
-      const int g = q >> lh, j = q & (half - 1);
-      const int i0 = g * m + j, i1 = i0 + half;
-      const cplx a = z[i0], b = z[i1], w = tw[j * ts];
-      z[i0] = cplx{a.re + b.re, a.im + b.im};
-      const double dr = a.re - b.re, di = a.im - b.im;
-      z[i1] = cplx{dr * w.re - di * w.im, dr * w.im + di * w.re};
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * (DIR i)
+template <int DIR>
+__device__ __forceinline__ cplx cmul_i(cplx a) {
+  return DIR > 0 ? cplx{-a.im, a.re} : cplx{a.im, -a.re};
+}
+
+// In-register DFT of R = 2, 4 or 8 values, X_q = sum_r v_r exp(DIR 2 pi i r q / R), natural order.
+template <int R, int DIR>
+__device__ __forceinline__ void dft_small(cplx* v) {
+  if constexpr (R == 2) {
+    const cplx a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    const cplx s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const cplx s13 = cadd(v[1], v[3]), d13 = cmul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  } else {
+    static_assert(R == 8, "radix 2, 4 or 8");
+    cplx e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft_small<4, DIR>(e);
+    dft_small<4, DIR>(o);
+    constexpr double h = 0.70710678118654752440;   // exp(DIR 2 pi i q / 8), q = 1, 3
+    const cplx w1 = cplx{h, DIR * h}, w3 = cplx{-h, DIR * h};
+    const cplx t[4] = {o[0], cmul(o[1], w1), cmul_i<DIR>(o[2]), cmul(o[3], w3)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = cadd(e[q], t[q]);
+      v[q + 4] = csub(e[q], t[q]);
     }
-    __syncthreads();
   }
 }
 
-// Inverse FFT in place without the 1/N, bit-reversed order in, natural order out (radix-2,
-// decimation in time, conjugate twiddles).
-__device__ __forceinline__ void fft_dit_inv(cplx* z, const cplx* tw, int N) {
-  for (int m = 2; m <= N; m <<= 1) {
-    const int half = m >> 1, ts = N / m;
-    const int lh = __builtin_ctz(half);
-    for (int q = threadIdx.x; q < N / 2; q += blockDim.x) {
-      const int g = q >> lh, j = q & (half - 1);
-      const int i0 = g * m + j, i1 = i0 + half;
-      const cplx a = z[i0], c = z[i1], w = tw[j * ts];
-      // b = c * conj(w)
-      const double br = c.re * w.re + c.im * w.im, bi = c.im * w.re - c.re * w.im;
-      z[i0] = cplx{a.re + br, a.im + bi};
-      z[i1] = cplx{a.re - br, a.im - bi};
+// exp(DIR 2 pi i a / N) from the half table tw[k] = exp(-2 pi i k / N), k < N/2.
+template <int N, int DIR>
+__device__ __forceinline__ cplx twiddle(const cplx* tw, int a) {
+  const cplx w = tw[a & (N / 2 - 1)];
+  const cplx s = (a & (N / 2)) ? cplx{-w.re, -w.im} : w;
+  return DIR > 0 ? cplx{s.re, -s.im} : s;
+}
+
+// One Stockham stage of radix R after sub-transforms of size NS: work item j reads
+// z[j + r N/R], multiplies by exp(DIR 2 pi i (j mod NS) r / (NS R)), transforms, and writes
+// z[(j / NS) NS R + (j mod NS) + r NS].  All reads finish before the writes (in place).
+template <int N, int R, int NS, int DIR>
+__device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tw) {
+  constexpr int T = N / R;                           // work items
+  constexpr int IPT = (T + CFOT_THREADS - 1) / CFOT_THREADS;
+  cplx v[IPT][R];
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int j = threadIdx.x + it * CFOT_THREADS;
+    if (T % CFOT_THREADS == 0 || j < T) {
+      const int k = j & (NS - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const cplx x = z[j + r * T];
+        v[it][r] = (NS == 1 || r == 0) ? x : cmul(x, twiddle<N, DIR>(tw, k * r * (N / (NS * R))));
+      }
+      dft_small<R, DIR>(v[it]);
     }
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int j = threadIdx.x + it * CFOT_THREADS;
+    if (T % CFOT_THREADS == 0 || j < T) {
+      const int k = j & (NS - 1);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) z[base + r * NS] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+// FFT of length N in LDS, natural order in and out (DIR = -1 forward; +1 inverse without 1/N).
+template <int N, int DIR, int NS = 1>
+__device__ __forceinline__ void fft_lds(cplx* z, const cplx* tw) {
+  if constexpr (NS < N) {
+    constexpr int R = (N / NS) >= 8 ? 8 : N / NS;
+    stockham_stage<N, R, NS, DIR>(z, tw);
+    fft_lds<N, DIR, NS * R>(z, tw);
   }
 }
 
@@ -92,10 +153,10 @@ __device__ __forceinline__ void cfot_load_twiddles(cplx* tw_s, const cplx* tw, i
 }
 
 // The transform of lambda's circular extension, lambda_c[i] = lambda(i) for i < n and
-// lambda_c[N - i] = lambda(i) for 0 < i < n (zero between), in the bit-reversed order of
-// fft_dif.  It is real (lambda_c is real and even); the rounding residue of its imaginary part
-// is dropped.  One workgroup.
-__global__ __launch_bounds__(CFOT_THREADS) void k_cfot_lamhat(int n, int N, double inv_eps, const cplx* tw,
+// lambda_c[N - i] = lambda(i) for 0 < i < n (zero between).  It is real (lambda_c is real and
+// even); the rounding residue of its imaginary part is dropped.  One workgroup.
+template <int N>
+__global__ __launch_bounds__(CFOT_THREADS) void k_cfot_lamhat(int n, double inv_eps, const cplx* tw,
                                                               double* lamhat) {
   extern __shared__ cplx cf_lds[];
   cplx* z = cf_lds;
@@ -107,7 +168,7 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_lamhat(int n, int N, doub
     z[i] = cplx{d >= 0 ? exp(-(double)d * (double)d * s) : 0.0, 0.0};
   }
   __syncthreads();
-  fft_dif(z, tw_s, N);
+  fft_lds<N, -1>(z, tw_s);
   for (int i = threadIdx.x; i < N; i += blockDim.x) lamhat[i] = z[i].re;
 }
 
@@ -135,9 +196,10 @@ __device__ __forceinline__ void block_max2(double& a, double& b, double* scratch
 // Shared body of both passes: rows r0 = 2 blockIdx.x and r0 + 1 of X (log values times
 // `scale`, row pitch np, batch stride sX), convolved with lambda; on return z[k] holds the
 // convolution of row r0 (.re) and row r0 + 1 (.im) times N, and ma, mb the row shifts.
-__device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale, int n, int np, int N,
-                                                   const cplx* tw, const double* lamhat, cplx* z, cplx* tw_s,
-                                                   double* scratch, double& ma, double& mb) {
+template <int N>
+__device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale, int n, int np, const cplx* tw,
+                                                   const double* lamhat, cplx* z, cplx* tw_s, double* scratch,
+                                                   double& ma, double& mb) {
   const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
   const bool has1 = r1 < n;
   const double* xa = X + (size_t)r0 * np;
@@ -158,21 +220,22 @@ __device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale
     z[i] = cplx{va, vb};
   }
   __syncthreads();
-  fft_dif(z, tw_s, N);
+  fft_lds<N, -1>(z, tw_s);
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const double l = lamhat[i];
     z[i] = cplx{z[i].re * l, z[i].im * l};
   }
   __syncthreads();
-  fft_dit_inv(z, tw_s, N);
+  fft_lds<N, 1>(z, tw_s);
 }
 
 __device__ __forceinline__ double cfot_log(double y, double m) { return y > 0.0 ? m + log(y) : -INFINITY; }
 
 // Pass 1: outT[k][r] = ln of the row-r convolution at k (rows r of P scaled by 1/eps).
 // Grid (ceil(n/2), batch), CFOT_THREADS threads, cfot_lds_bytes(N) dynamic LDS.
+template <int N>
 __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, long long sP, double inv_eps, int n,
-                                                             int np, int N, const cplx* tw, const double* lamhat,
+                                                             int np, const cplx* tw, const double* lamhat,
                                                              double* outT, long long sO) {
   extern __shared__ cplx cf_lds[];
   __shared__ double scratch[8];
@@ -180,7 +243,7 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, lo
   cplx* tw_s = cf_lds + N;
   const int bz = blockIdx.y;
   double ma, mb;
-  cfot_convolve_pair(P + (size_t)bz * sP, inv_eps, n, np, N, tw, lamhat, z, tw_s, scratch, ma, mb);
+  cfot_convolve_pair<N>(P + (size_t)bz * sP, inv_eps, n, np, tw, lamhat, z, tw_s, scratch, ma, mb);
   const int r0 = 2 * blockIdx.x;
   const bool has1 = r0 + 1 < n;
   const double invN = 1.0 / (double)N;
@@ -196,7 +259,8 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, lo
 // Pout[r][j] = eps (lnm[r][j] - ln S) (Eq. 7 or 8 in the log domain), the marginal-error
 // partial of the entering plan (same identity as the GEMM path's), the non-finite flag and,
 // if requested, ln S itself.  Arrays in the orientation of Pout; one partial per workgroup.
-__global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass2(const double* Yt, long long sY, int n, int np, int N,
+template <int N>
+__global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass2(const double* Yt, long long sY, int n, int np,
                                                              const cplx* tw, const double* lamhat,
                                                              const double* lnm, long long sMarg, double* pot,
                                                              long long sP, double* lnS_out, double eps,
@@ -207,7 +271,7 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass2(const double* Yt, l
   cplx* tw_s = cf_lds + N;
   const int bz = blockIdx.y;
   double ma, mb;
-  cfot_convolve_pair(Yt + (size_t)bz * sY, 1.0, n, np, N, tw, lamhat, z, tw_s, scratch, ma, mb);
+  cfot_convolve_pair<N>(Yt + (size_t)bz * sY, 1.0, n, np, tw, lamhat, z, tw_s, scratch, ma, mb);
   const int r0 = 2 * blockIdx.x;
   const double invN = 1.0 / (double)N, inv_eps = 1.0 / eps;
   double err = 0.0;
