@@ -958,7 +958,7 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
     p->cfot = true;
     p->cN = cN;
     void* tw = nullptr;
-    if ((s = dalloc(p, &tw, sizeof(cplx) * (size_t)(cN / 2))) != FOT_OK) return bail(s);
+    if ((s = dalloc(p, &tw, sizeof(cplx) * (size_t)cfot_tw_count(cN))) != FOT_OK) return bail(s);
     p->ctw = (cplx*)tw;
     ALLOC(p->clamhat, (size_t)cN);
     ALLOC(p->cY, BP);
@@ -979,7 +979,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
       return FOT_OK;
     });
     if (s != FOT_OK) return bail(s);
-    hipLaunchKernelGGL(k_cfot_twiddles, dim3((unsigned)((cN / 2 + 255) / 256)), dim3(256), 0, p->stream, cN, p->ctw);
+    hipLaunchKernelGGL(k_cfot_twiddles, dim3((unsigned)((cfot_tw_count(cN) + 255) / 256)), dim3(256), 0, p->stream,
+                       cN, p->ctw);
     if (hipGetLastError() != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: twiddle kernel launch failed"));
   }
   if (d.checkpoint_every > 0) {

@@ -42,16 +42,36 @@ constexpr int CFOT_THREADS = 256;
 constexpr int CFOT_MIN_N = 256;    // FFT lengths: powers of two in [256, 4096] (n <= 2048)
 constexpr int CFOT_MAX_N = 4096;
 
-// Dynamic LDS of a cFOT pass: the sequence (N complex) and the twiddles (N/2 complex).
-inline size_t cfot_lds_bytes(int N) { return (size_t)N * sizeof(cplx) + (size_t)(N / 2) * sizeof(cplx); }
+// The Stockham stages of a length-N transform have sub-transform sizes NS = 1, 8, 64, ... (< N)
+// and radix R = min(8, N / NS).  Stage NS > 1 multiplies its work item j by the powers of
+// w = exp(-2 pi i (j mod NS) / (NS R)); the base twiddles of all stages sit in one table,
+// stage NS at offset cfot_tw_offset(NS), indexed by j mod NS (contiguous across a wave).
+constexpr int cfot_tw_offset(int NS) {
+  int off = 0;
+  for (int ns = 8; ns < NS; ns *= 8) off += ns;
+  return off;
+}
+constexpr int cfot_tw_count(int N) { return cfot_tw_offset(N); }
+// LDS index of sequence entry i: one pad entry per 16, which makes the strided stage writes
+// (stride 8 and 64 entries) free of bank conflicts
+__device__ __forceinline__ int zp(int i) { return i + (i >> 4); }
 
-// tw[k] = exp(-2 pi i k / N), k < N/2
+// Dynamic LDS of a cFOT pass: the padded sequence and the stage twiddles.
+inline size_t cfot_lds_bytes(int N) {
+  return (size_t)(N + N / 16) * sizeof(cplx) + (size_t)cfot_tw_count(N) * sizeof(cplx);
+}
+
+// The stage twiddle table of a length-N transform (cfot_tw_count(N) entries).
 __global__ void k_cfot_twiddles(int N, cplx* tw) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N / 2) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cfot_tw_count(N)) return;
+  int NS = 8;
+  while (i >= cfot_tw_offset(NS * 8) && NS * 8 < N) NS *= 8;
+  const int k = i - cfot_tw_offset(NS);
+  const int R = N / NS >= 8 ? 8 : N / NS;
   double s, c;
-  sincospi(2.0 * (double)k / (double)N, &s, &c);
-  tw[k] = cplx{c, -s};
+  sincospi(2.0 * (double)k / (double)(NS * R), &s, &c);
+  tw[i] = cplx{c, -s};
 }
 
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
@@ -95,19 +115,11 @@ __device__ __forceinline__ void dft_small(cplx* v) {
   }
 }
 
-// exp(DIR 2 pi i a / N) from the half table tw[k] = exp(-2 pi i k / N), k < N/2.
-template <int N, int DIR>
-__device__ __forceinline__ cplx twiddle(const cplx* tw, int a) {
-  const cplx w = tw[a & (N / 2 - 1)];
-  const cplx s = (a & (N / 2)) ? cplx{-w.re, -w.im} : w;
-  return DIR > 0 ? cplx{s.re, -s.im} : s;
-}
-
 // One Stockham stage of radix R after sub-transforms of size NS: work item j reads
-// z[j + r N/R], multiplies by exp(DIR 2 pi i (j mod NS) r / (NS R)), transforms, and writes
-// z[(j / NS) NS R + (j mod NS) + r NS].  All reads finish before the writes (in place).
+// z[j + r N/R], multiplies entry r by w^r with w = exp(DIR 2 pi i (j mod NS) / (NS R)), transforms,
+// and writes z[(j / NS) NS R + (j mod NS) + r NS].  All reads finish before the writes (in place).
 template <int N, int R, int NS, int DIR>
-__device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tw) {
+__device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tws) {
   constexpr int T = N / R;                           // work items
   constexpr int IPT = (T + CFOT_THREADS - 1) / CFOT_THREADS;
   cplx v[IPT][R];
@@ -116,10 +128,21 @@ __device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tw) {
     const int j = threadIdx.x + it * CFOT_THREADS;
     if (T % CFOT_THREADS == 0 || j < T) {
       const int k = j & (NS - 1);
+      cplx w = cplx{1.0, 0.0};
+      if constexpr (NS > 1) {
+        w = tws[cfot_tw_offset(NS) + k];
+        if (DIR > 0) w.im = -w.im;
+      }
+      cplx wr = w;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const cplx x = z[j + r * T];
-        v[it][r] = (NS == 1 || r == 0) ? x : cmul(x, twiddle<N, DIR>(tw, k * r * (N / (NS * R))));
+        const cplx x = z[zp(j + r * T)];
+        if (NS == 1 || r == 0) {
+          v[it][r] = x;
+        } else {
+          v[it][r] = cmul(x, wr);
+          if (r + 1 < R) wr = cmul(wr, w);
+        }
       }
       dft_small<R, DIR>(v[it]);
     }
@@ -132,7 +155,7 @@ __device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tw) {
       const int k = j & (NS - 1);
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[base + r * NS] = v[it][r];
+      for (int r = 0; r < R; ++r) z[zp(base + r * NS)] = v[it][r];
     }
   }
   __syncthreads();
@@ -149,7 +172,7 @@ __device__ __forceinline__ void fft_lds(cplx* z, const cplx* tw) {
 }
 
 __device__ __forceinline__ void cfot_load_twiddles(cplx* tw_s, const cplx* tw, int N) {
-  for (int k = threadIdx.x; k < N / 2; k += blockDim.x) tw_s[k] = tw[k];
+  for (int k = threadIdx.x; k < cfot_tw_count(N); k += blockDim.x) tw_s[k] = tw[k];
 }
 
 // The transform of lambda's circular extension, lambda_c[i] = lambda(i) for i < n and
@@ -160,16 +183,16 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_lamhat(int n, double inv_
                                                               double* lamhat) {
   extern __shared__ cplx cf_lds[];
   cplx* z = cf_lds;
-  cplx* tw_s = cf_lds + N;
+  cplx* tw_s = cf_lds + N + N / 16;
   cfot_load_twiddles(tw_s, tw, N);
   const double s = inv_eps / (2.0 * (double)n * (double)n);
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const int d = i < n ? i : (i > N - n ? N - i : -1);
-    z[i] = cplx{d >= 0 ? exp(-(double)d * (double)d * s) : 0.0, 0.0};
+    z[zp(i)] = cplx{d >= 0 ? exp(-(double)d * (double)d * s) : 0.0, 0.0};
   }
   __syncthreads();
   fft_lds<N, -1>(z, tw_s);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) lamhat[i] = z[i].re;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) lamhat[i] = z[zp(i)].re;
 }
 
 // Row maxima of two rows at once (a in .re, b in .im) over the first n entries.
@@ -193,37 +216,62 @@ __device__ __forceinline__ void block_max2(double& a, double& b, double* scratch
   }
 }
 
-// Shared body of both passes: rows r0 = 2 blockIdx.x and r0 + 1 of X (log values times
-// `scale`, row pitch np, batch stride sX), convolved with lambda; on return z[k] holds the
+// Row pair of this workgroup.  Workgroups are dealt to the 8 XCDs round-robin; giving each XCD a
+// contiguous range of pairs makes the transposed 16-byte stores of neighbouring pairs (which fill
+// the same 128-byte lines) meet in one L2.
+__device__ __forceinline__ int cfot_pair() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  if (nb % 8) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
+// Shared body of both passes: rows r0 = 2 cfot_pair() and r0 + 1 of X (log values times
+// `scale`, row pitch np, batch stride sX), convolved with lambda; on return z[zp(k)] holds the
 // convolution of row r0 (.re) and row r0 + 1 (.im) times N, and ma, mb the row shifts.
 template <int N>
 __device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale, int n, int np, const cplx* tw,
                                                    const double* lamhat, cplx* z, cplx* tw_s, double* scratch,
                                                    double& ma, double& mb) {
-  const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
+  static_assert(N % CFOT_THREADS == 0, "whole sequence entries per thread");
+  constexpr int PT = N / 2 / CFOT_THREADS > 0 ? N / 2 / CFOT_THREADS : 1;   // row values per thread (n <= N/2)
+  constexpr int LT = N / CFOT_THREADS;                                      // sequence entries per thread
+  const int tid = threadIdx.x;
+  const int r0 = 2 * cfot_pair(), r1 = r0 + 1;
   const bool has1 = r1 < n;
   const double* xa = X + (size_t)r0 * np;
   const double* xb = X + (size_t)r1 * np;
+  // every global read first (the rows once, into registers; lambda's transform; the twiddles)
+  double ra[PT], rb[PT], lh[LT];
+#pragma unroll
+  for (int q = 0; q < PT; ++q) {
+    const int i = tid + q * CFOT_THREADS;
+    ra[q] = i < n ? xa[i] * scale : -INFINITY;
+    rb[q] = (i < n && has1) ? xb[i] * scale : -INFINITY;
+  }
+#pragma unroll
+  for (int q = 0; q < LT; ++q) lh[q] = lamhat[tid + q * CFOT_THREADS];
   cfot_load_twiddles(tw_s, tw, N);
   double a = -INFINITY, b = -INFINITY;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    a = fmax(a, xa[i] * scale);
-    if (has1) b = fmax(b, xb[i] * scale);
+#pragma unroll
+  for (int q = 0; q < PT; ++q) {
+    a = fmax(a, ra[q]);
+    b = fmax(b, rb[q]);
   }
   block_max2(a, b, scratch);
   ma = (a > -INFINITY) ? a : 0.0;   // an all-zero row stays zero
   mb = (b > -INFINITY) ? b : 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const bool ok = i < n;
-    const double va = ok ? exp(xa[i] * scale - ma) : 0.0;
-    const double vb = (ok && has1) ? exp(xb[i] * scale - mb) : 0.0;
-    z[i] = cplx{va, vb};
+#pragma unroll
+  for (int q = 0; q < LT; ++q) {
+    const double va = q < PT ? exp(ra[q] - ma) : 0.0;   // entries from N/2 on are padding
+    const double vb = q < PT ? exp(rb[q] - mb) : 0.0;
+    z[zp(tid + q * CFOT_THREADS)] = cplx{va, vb};
   }
   __syncthreads();
   fft_lds<N, -1>(z, tw_s);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const double l = lamhat[i];
-    z[i] = cplx{z[i].re * l, z[i].im * l};
+#pragma unroll
+  for (int q = 0; q < LT; ++q) {
+    const int i = zp(tid + q * CFOT_THREADS);
+    z[i] = cplx{z[i].re * lh[q], z[i].im * lh[q]};
   }
   __syncthreads();
   fft_lds<N, 1>(z, tw_s);
@@ -240,16 +288,16 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, lo
   extern __shared__ cplx cf_lds[];
   __shared__ double scratch[8];
   cplx* z = cf_lds;
-  cplx* tw_s = cf_lds + N;
+  cplx* tw_s = cf_lds + N + N / 16;
   const int bz = blockIdx.y;
   double ma, mb;
   cfot_convolve_pair<N>(P + (size_t)bz * sP, inv_eps, n, np, tw, lamhat, z, tw_s, scratch, ma, mb);
-  const int r0 = 2 * blockIdx.x;
+  const int r0 = 2 * cfot_pair();
   const bool has1 = r0 + 1 < n;
   const double invN = 1.0 / (double)N;
   double* o = outT + (size_t)bz * sO + r0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const cplx y = z[k];
+    const cplx y = z[zp(k)];
     o[(size_t)k * np] = cfot_log(y.re * invN, ma);
     if (has1) o[(size_t)k * np + 1] = cfot_log(y.im * invN, mb);
   }
@@ -268,29 +316,44 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass2(const double* Yt, l
   extern __shared__ cplx cf_lds[];
   __shared__ double scratch[8];
   cplx* z = cf_lds;
-  cplx* tw_s = cf_lds + N;
+  cplx* tw_s = cf_lds + N + N / 16;
   const int bz = blockIdx.y;
+  const int r0 = 2 * cfot_pair();
+  constexpr int PT = N / 2 / CFOT_THREADS > 0 ? N / 2 / CFOT_THREADS : 1;
+  // the epilogue's inputs, read before the transforms so that their latency is hidden
+  double la_v[2][PT], fo_v[2][PT];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int r = r0 + q, j = threadIdx.x + t * CFOT_THREADS;
+      const bool ok = r < n && j < n;
+      la_v[q][t] = ok ? lnm[(size_t)bz * sMarg + (size_t)r * np + j] : 0.0;
+      fo_v[q][t] = (ok && err_on) ? pot[(size_t)bz * sP + (size_t)r * np + j] : 0.0;
+    }
   double ma, mb;
   cfot_convolve_pair<N>(Yt + (size_t)bz * sY, 1.0, n, np, tw, lamhat, z, tw_s, scratch, ma, mb);
-  const int r0 = 2 * blockIdx.x;
   const double invN = 1.0 / (double)N, inv_eps = 1.0 / eps;
   double err = 0.0;
   bool bad = false;
+#pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int r = r0 + q;
     if (r >= n) break;
     const double m = q == 0 ? ma : mb;
-    const double* lm = lnm + (size_t)bz * sMarg + (size_t)r * np;
     double* po = pot + (size_t)bz * sP + (size_t)r * np;
     double* ls = lnS_out ? lnS_out + (size_t)bz * sP + (size_t)r * np : nullptr;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const double y = (q == 0 ? z[j].re : z[j].im) * invN;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int j = threadIdx.x + t * CFOT_THREADS;
+      if (j >= n) break;
+      const double y = (q == 0 ? z[zp(j)].re : z[zp(j)].im) * invN;
       const double lnS = cfot_log(y, m);
-      const double la = lm[j];
+      const double la = la_v[q][t];
       const bool zm = la == -INFINITY;
       const double fnew = zm ? -INFINITY : eps * (la - lnS);
       if (err_on) {
-        const double fold = po[j];
+        const double fold = fo_v[q][t];
         const float tz = exp_err((float)fma(fold, inv_eps, lnS));
         const double d = (fold - fnew) * inv_eps;
         const float df = (float)d, laf = (float)la;
