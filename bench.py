@@ -76,21 +76,27 @@ def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile
     plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph, history=history,
                   cfot=cfot)
     phase = torch.empty((G.shape[0], n, n), dtype=torch.float64, device=dev)
-    for _ in range(warmup):
-        plan.solve(gd, Gd, eps, iters, out=phase)
+    try:
+        for _ in range(warmup):
+            plan.solve(gd, Gd, eps, iters, out=phase)
+    except Exception:
+        plan.close()
+        raise
     torch.cuda.synchronize()
     # no allocations and no garbage collection inside the timed region
     gc.collect()
     gc.disable()
-    t0 = time.perf_counter()
-    reps = []
-    for _ in range(steps):
-        _, rep, _ = plan.solve(gd, Gd, eps, iters, out=phase)
-        reps.append(rep)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    gc.enable()
-    plan.close()
+    try:
+        t0 = time.perf_counter()
+        reps = []
+        for _ in range(steps):
+            _, rep, _ = plan.solve(gd, Gd, eps, iters, out=phase)
+            reps.append(rep)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    finally:
+        gc.enable()
+        plan.close()
     return elapsed, reps
 
 
@@ -356,11 +362,23 @@ def main():
         fin = np.isfinite(pots["gemm_f64"])
         dv = pots["cfot_f64_fft"][fin] - pots["gemm_f64"][fin]
         conv["cfot_f_err_vs_f64_gemm"] = float(np.max(np.abs(dv - dv.mean())) / np.ptp(pots["gemm_f64"][fin]))
+        # per-iteration cost at 2048^2 (the lattice workload's size), constant eps 5e-3, 20 iterations
+        n2 = 2048
+        g2_, G2_ = W.speckle_to_lattice(n2)
+        G2_ = G2_ if G2_.ndim == 3 else G2_[None]
+        big = {}
+        for name, prec, cf in (("cfot_f64_fft", "f64", True), ("gemm_f32", "f32", False), ("gemm_bf16", "bf16", False)):
+            try:
+                el, rp = run_variant(F, W, torch, prec, g2_, G2_, 5e-3, 20, 3, 1, profile=False, graph=graph, cfot=cf)
+                big[name] = round(1e3 * float(np.median([r.ms_iterations for r in rp])) / 20, 2)
+            except F.FOTError as exc:   # (cFOT can lose the small values on this target)
+                big[name] = f"failed: {exc}"[:160]
+        conv["us_per_iteration_2048"] = big
         out["contraction_by_fft"] = conv
         log(f"bench: cFOT (FP64 FFT) {conv['cfot_f64_fft']['value']:.1f} Mpx.it/s "
             f"({conv['cfot_f64_fft']['us_per_iteration']:.1f} us/it, pass {conv['cfot_f64_fft']['pass_avg_us']:.1f} us), "
             f"FP64 GEMM {conv['gemm_f64']['value']:.1f}, {prec0} GEMM {conv['gemm_' + prec0]['value']:.1f}; "
-            f"cFOT f error vs FP64 GEMM {conv['cfot_f_err_vs_f64_gemm']:.1e}")
+            f"cFOT f error vs FP64 GEMM {conv['cfot_f_err_vs_f64_gemm']:.1e}; at 2048^2 (us/it): {big}")
 
         # small-grid latency (the paper's 128^2, 200 iterations): one whole solve per call,
         # inputs resident, timed wall-clock around the call
