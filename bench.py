@@ -39,16 +39,20 @@ def log(*a):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_fused_twogauss_1024.md")
 
 
+# the sources the fused half-step kernels are compiled from (their launch code in fot_api.hip
+# passes only sizes and pointers)
+FUSED_SOURCES = ("fot_fused.hpp", "fot_kernels.hpp")
+
+
 def kernel_source_hash():
-    """sha256 over the HIP sources (file name and bytes, sorted by name)."""
+    """sha256 over the fused kernels' sources (file name and bytes)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2512_19072_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in FUSED_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -111,6 +115,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch the iteration loop kernel by kernel")
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16", "f16", "bf16x3"],
                     help="operand precision of the headline run (profiling aid; the headline is f32)")
+    ap.add_argument("--cfot-run", action="store_true",
+                    help="profiling aid: only the headline workload's solves with cFOT (FP64 FFT convolutions), "
+                         "graph-replayed and then kernel by kernel, and one JSON line of their rates")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware-counter passes: two solves launched kernel by kernel "
                          "and one 256 MiB device-to-device copy whose bytes calibrate the counters")
@@ -138,6 +145,16 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"pmc_run": True, "precision": args.precision, "solves": 2, "iters": iters,
                           "copy_bytes": nbytes}), flush=True)
+        return
+    if args.cfot_run:
+        el, rp = run_variant(F, W, torch, "f64", g, G, eps, iters, args.steps, args.warmup, profile=False,
+                             graph=not args.no_graph, cfot=True)
+        _, rpp = run_variant(F, W, torch, "f64", g, G, eps, iters, args.steps, args.warmup, profile=True,
+                             graph=False, cfot=True)
+        pass_us = 1e3 * sum(r.ms_contract for r in rpp) / max(1, sum(r.n_contract for r in rpp))
+        print(json.dumps({"cfot_run": True, "value": round(n * n * iters * args.steps / el / 1e6, 3),
+                          "unit": "Mpixel·iter/s", "steps": args.steps, "pass_avg_us": round(pass_us, 3)}),
+              flush=True)
         return
     prec0 = args.precision
     log(f"bench: workload {wl.name} n={n} iters={iters} eps={eps} {prec0}, steps={args.steps} warmup={args.warmup}")

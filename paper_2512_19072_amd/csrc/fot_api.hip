@@ -748,25 +748,36 @@ fot_status cfot_dispatch(int N, F&& fn) {
   }
 }
 
-// One half-step by convolutions: Pin (one orientation) -> Pout (the other), Eq. 7 or 8.
+// One half-step by convolutions: Pin (one orientation) -> Pout (the other), Eq. 7 or 8.  The
+// marginal-error partials of this half-step are summed into hist by the next half-step's first
+// pass (p->pending_hist), or by cfot_finish_pending at the end of the loop.
 fot_status cfot_half(fot_plan_s* p, const double* Pin, double* Pout, const double* lnm, long long sMarg,
                      double* hist, double* lnS_out, double eps) {
   const long long plane = (long long)p->plane;
+  double* pend_out = p->pending_hist;
+  p->pending_hist = nullptr;
+  const int cnt = (p->n + 1) / 2;
   fot_status s = cfot_dispatch(p->cN, [&](auto nc) -> fot_status {
     constexpr int N = decltype(nc)::value;
     fot_status r = cfot_launch(p, k_cfot_pass1<N>, Pin, plane, 1.0 / eps, p->n, p->np, (const cplx*)p->ctw,
-                               (const double*)p->clamhat, p->cY, plane);
+                               (const double*)p->clamhat, p->cY, plane,
+                               pend_out ? (const double*)p->cparts : (const double*)nullptr, cnt, pend_out);
     if (r != FOT_OK) return r;
     return cfot_launch(p, k_cfot_pass2<N>, (const double*)p->cY, plane, p->n, p->np, (const cplx*)p->ctw,
                        (const double*)p->clamhat, lnm, sMarg, Pout, plane, lnS_out, eps, p->cparts, p->flag,
                        hist != nullptr ? 1 : 0);
   });
   if (s != FOT_OK) return s;
-  if (hist) {
-    hipLaunchKernelGGL(k_cfot_sum, dim3(p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->cparts,
-                       (p->n + 1) / 2, hist);
-    LAUNCH_CHECK();
-  }
+  p->pending_hist = hist;
+  return FOT_OK;
+}
+
+fot_status cfot_finish_pending(fot_plan_s* p) {
+  if (!p->pending_hist) return FOT_OK;
+  hipLaunchKernelGGL(k_cfot_sum, dim3(p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->cparts,
+                     (p->n + 1) / 2, p->pending_hist);
+  LAUNCH_CHECK();
+  p->pending_hist = nullptr;
   return FOT_OK;
 }
 
@@ -784,6 +795,7 @@ fot_status cfot_loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
   const long long plane = (long long)p->plane;
   const int B = p->B;
   fot_status s;
+  p->pending_hist = nullptr;
   if ((s = cfot_transpose(p, p->lna, 0, p->clnaT, 0, 1)) != FOT_OK) return s;
   if ((s = cfot_transpose(p, p->f, plane, p->cfT, plane, B)) != FOT_OK) return s;
   const bool hist = !(p->d.flags & FOT_FLAG_NO_HISTORY);
@@ -807,10 +819,10 @@ fot_status cfot_loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
                        last ? p->lnSp : nullptr, ep)) != FOT_OK)
       return s;
   }
+  if ((s = cfot_finish_pending(p)) != FOT_OK) return s;
   if ((s = cfot_transpose(p, p->cfT, plane, p->f, plane, B)) != FOT_OK) return s;
   if ((s = cfot_transpose(p, p->cS, plane, p->lnS, plane, B)) != FOT_OK) return s;
   p->clam_eps = e[iters - 1];
-  p->pending_hist = nullptr;
   return FOT_OK;
 }
 

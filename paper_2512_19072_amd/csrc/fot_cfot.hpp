@@ -279,17 +279,25 @@ __device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale
 
 __device__ __forceinline__ double cfot_log(double y, double m) { return y > 0.0 ? m + log(y) : -INFINITY; }
 
-// Pass 1: outT[k][r] = ln of the row-r convolution at k (rows r of P scaled by 1/eps).
+// Pass 1: outT[k][r] = ln of the row-r convolution at k (rows r of P scaled by 1/eps).  If
+// pend_parts is set, workgroup 0 of each target also sums the previous pass 2's marginal-error
+// partials (pend_cnt per target, fixed order) into pend_out[target].
 // Grid (ceil(n/2), batch), CFOT_THREADS threads, cfot_lds_bytes(N) dynamic LDS.
 template <int N>
 __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, long long sP, double inv_eps, int n,
                                                              int np, const cplx* tw, const double* lamhat,
-                                                             double* outT, long long sO) {
+                                                             double* outT, long long sO, const double* pend_parts,
+                                                             int pend_cnt, double* pend_out) {
   extern __shared__ cplx cf_lds[];
   __shared__ double scratch[8];
   cplx* z = cf_lds;
   cplx* tw_s = cf_lds + N + N / 16;
   const int bz = blockIdx.y;
+  // pending partials, read now so that their latency hides behind the transforms
+  const bool pend = pend_parts != nullptr && blockIdx.x == 0;
+  double pv = 0.0;
+  if (pend)
+    for (int i = threadIdx.x; i < pend_cnt; i += CFOT_THREADS) pv += pend_parts[(size_t)bz * pend_cnt + i];
   double ma, mb;
   cfot_convolve_pair<N>(P + (size_t)bz * sP, inv_eps, n, np, tw, lamhat, z, tw_s, scratch, ma, mb);
   const int r0 = 2 * cfot_pair();
@@ -300,6 +308,10 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, lo
     const cplx y = z[zp(k)];
     o[(size_t)k * np] = cfot_log(y.re * invN, ma);
     if (has1) o[(size_t)k * np + 1] = cfot_log(y.im * invN, mb);
+  }
+  if (pend) {
+    pv = block_sum(pv, scratch);
+    if (threadIdx.x == 0) pend_out[bz] = pv;
   }
 }
 
