@@ -147,3 +147,21 @@ def test_workload1_full_size_cfot():
          f"(GEMM {ref['rep'].err_a[0]:.3e}), err_b {gpu['rep'].err_b[0]:.3e}")
     assert gpu["st"] == F.FOT_OK, gpu["msg"]
     assert ef < 1e-8 and ep < 1e-8 and eph < 1e-8
+
+
+def test_cfot_annealed_schedule_and_profiling():
+    """An eps schedule (lambda's transform recomputed whenever eps changes, inside the captured
+    graph) against the oracle; profiling counts the four convolution passes per iteration."""
+    from paper_2512_19072_amd import fot as F
+    n, T = 96, 40
+    g, G = _rand_case(n, 31)
+    e = W.anneal_schedule(5e-2, 1e-2, T)
+    gpu = _run_cfot(g, G, e, T)
+    assert gpu["st"] == F.FOT_OK, gpu["msg"]
+    ref = O.solve_sep(g, G, e, T)
+    err = compare(gpu, ref, g, G, precision="f64")
+    _say(f"case: cfot annealed n={n}: f {err['f']:.2e}, phase {err['phase']:.2e}")
+    assert err["f"] < 1e-11 and err["psi"] < 1e-11 and err["phase"] < 1e-11 and err["dual"] < 1e-11
+    prof = _run_cfot(g, G, e, T, profile=True)
+    assert prof["rep"].n_contract == 4 * T and prof["rep"].ms_contract > 0
+    assert np.array_equal(prof["f"], gpu["f"]) and np.array_equal(prof["phase"], gpu["phase"])

@@ -24,9 +24,9 @@ from tests.parity_util import gauge_rel, range_rel, to_dev
 pytestmark = pytest.mark.gpu
 
 # (potentials and phase, relative scalars) for one iteration from identical potentials
-TOL = {"f32": (1e-6, 1e-6), "bf16": (2e-3, 2e-3)}
+TOL = {"f32": (1e-6, 1e-6), "bf16": (2e-3, 2e-3), "bf16x3": (1e-5, 1e-5)}
 # column-marginal L1 of the final plan (exact up to the operand rounding of the last update)
-ERR_B = {"f32": 1e-5, "bf16": 5e-2}
+ERR_B = {"f32": 1e-5, "bf16": 5e-2, "bf16x3": 1e-4}
 
 
 def _say(*a):
@@ -34,7 +34,7 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "bf16", "bf16x3"])
 def test_workload3_full_size(prec):
     import torch
     from paper_2512_19072_amd import fot as F
