@@ -227,7 +227,8 @@ __device__ __forceinline__ int cfot_pair() {
 
 // Shared body of both passes: rows r0 = 2 cfot_pair() and r0 + 1 of X (log values times
 // `scale`, row pitch np, batch stride sX), convolved with lambda; on return z[zp(k)] holds the
-// convolution of row r0 (.re) and row r0 + 1 (.im) times N, and ma, mb the row shifts.
+// convolution of row r0 (.re) and row r0 + 1 (.im) times N, and ma, mb the row shifts (-inf for
+// a row without mass).
 template <int N>
 __device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale, int n, int np, const cplx* tw,
                                                    const double* lamhat, cplx* z, cplx* tw_s, double* scratch,
@@ -258,12 +259,16 @@ __device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale
     b = fmax(b, rb[q]);
   }
   block_max2(a, b, scratch);
-  ma = (a > -INFINITY) ? a : 0.0;   // an all-zero row stays zero
-  mb = (b > -INFINITY) ? b : 0.0;
+  // The shifts returned are the row maxima themselves, -inf for a row without mass: the two rows
+  // share one complex transform, whose rounding leaks about 1e-16 of one row into the other, so
+  // an empty row's output is not exactly zero; its -inf shift keeps every output of it at -inf.
+  ma = a;
+  mb = b;
+  const double sa = (a > -INFINITY) ? a : 0.0, sb = (b > -INFINITY) ? b : 0.0;
 #pragma unroll
   for (int q = 0; q < LT; ++q) {
-    const double va = q < PT ? exp(ra[q] - ma) : 0.0;   // entries from N/2 on are padding
-    const double vb = q < PT ? exp(rb[q] - mb) : 0.0;
+    const double va = q < PT ? exp(ra[q] - sa) : 0.0;   // entries from N/2 on are padding
+    const double vb = q < PT ? exp(rb[q] - sb) : 0.0;
     z[zp(tid + q * CFOT_THREADS)] = cplx{va, vb};
   }
   __syncthreads();
@@ -277,6 +282,7 @@ __device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale
   fft_lds<N, 1>(z, tw_s);
 }
 
+// m + ln y, -inf for y <= 0 (lost to rounding) or m = -inf (a row without mass)
 __device__ __forceinline__ double cfot_log(double y, double m) { return y > 0.0 ? m + log(y) : -INFINITY; }
 
 // Pass 1: outT[k][r] = ln of the row-r convolution at k (rows r of P scaled by 1/eps).  If
