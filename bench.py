@@ -397,6 +397,29 @@ def main():
             f"FP64 GEMM {conv['gemm_f64']['value']:.1f}, {prec0} GEMM {conv['gemm_' + prec0]['value']:.1f}; "
             f"cFOT f error vs FP64 GEMM {conv['cfot_f_err_vs_f64_gemm']:.1e}; at 2048^2 (us/it): {big}")
 
+        # synthetic re-run of the eps sweep of Fig. 3: the L1 intensity loss of the output beam of
+        # 200 iterations at 512^2, for matrix products (FP64 operands, valid down to the paper's
+        # 2e-4) and for cFOT (FP64 FFT convolutions), on the two-Gaussian -> shapes stand-in
+        n5 = 512
+        g5, G5 = W.twogauss_to_shapes(n5)
+        G5 = G5 if G5.ndim == 3 else G5[None]
+        g5d = torch.tensor(g5, dtype=torch.float64, device=dev)
+        G5d = torch.tensor(G5, dtype=torch.float64, device=dev)
+        sweep = {"eps": [5e-2, 2e-2, 1e-2, 5e-3, 2e-3, 1e-3, 5e-4, 2e-4], "fot_f64": [], "cfot_f64": []}
+        for key, cf in (("fot_f64", False), ("cfot_f64", True)):
+            plan = F.Plan(n5, 1, "f64", max_iters=200, cfot=cf)
+            for e5 in sweep["eps"]:
+                ph5, _, st5 = plan.solve(g5d, G5d, e5, 200, check=False)
+                if st5 == F.FOT_OK:
+                    _, l5 = plan.output_beam(g5d, ph5, G5d, intensity=False)
+                    sweep[key].append(round(float(l5[0]), 5))
+                else:
+                    sweep[key].append(F.STATUS_NAMES.get(st5, str(st5)))
+            plan.close()
+        sweep["workload"] = "twogauss_to_shapes 512x512, 200 iterations, L1 intensity loss of the output beam"
+        out["eps_sweep_512"] = sweep
+        log(f"bench: eps sweep 512^2 (L1 loss): eps {sweep['eps']}; FOT {sweep['fot_f64']}; cFOT {sweep['cfot_f64']}")
+
         # small-grid latency (the paper's 128^2, 200 iterations): one whole solve per call,
         # inputs resident, timed wall-clock around the call
         ns = 128
