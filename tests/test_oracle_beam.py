@@ -161,3 +161,19 @@ def test_planted_beam_mistakes_fail_a_pin(monkeypatch, name, wrong, pins):
         except AssertionError:
             failed += 1
     assert failed > 0, f"no pin caught the planted mistake in {name}"
+
+
+def test_l1_loss_of_a_delta_beam():
+    """A linear phase puts a uniform beam on one pixel: the loss against a target on that pixel is
+    0 and against a target on another pixel 2 (two unit masses that do not overlap)."""
+    n, a, b = 16, 2, 5
+    c = n // 2
+    j = np.arange(n)[:, None] - c
+    k = np.arange(n)[None, :] - c
+    ph = (a * j + b * k) / n
+    G = np.zeros((n, n))
+    G[c + a, c + b] = 3.0
+    assert Bm.l1_loss(np.ones((n, n)), ph, G) < 1e-12
+    G2 = np.zeros((n, n))
+    G2[c - 1, c] = 1.0
+    assert abs(Bm.l1_loss(np.ones((n, n)), ph, G2) - 2.0) < 1e-12
