@@ -56,9 +56,20 @@ constexpr int cfot_tw_count(int N) { return cfot_tw_offset(N); }
 // (stride 8 and 64 entries) free of bank conflicts
 __device__ __forceinline__ int zp(int i) { return i + (i >> 4); }
 
-// Dynamic LDS of a cFOT pass: the padded sequence and the stage twiddles.
+// Up to N = 2048 the stages alternate between two sequence buffers (one barrier per stage); at
+// N = 4096 a second buffer would leave one workgroup per CU, so the stages run in place (two
+// barriers per stage).
+constexpr bool cfot_two_buffers(int N) { return N <= 2048; }
+constexpr int cfot_seq_len(int N) { return N + N / 16; }   // padded sequence, in complex entries
+
+// Dynamic LDS of a cFOT pass: the padded sequence buffer(s) and the stage twiddles.
 inline size_t cfot_lds_bytes(int N) {
-  return (size_t)(N + N / 16) * sizeof(cplx) + (size_t)cfot_tw_count(N) * sizeof(cplx);
+  return (size_t)(cfot_two_buffers(N) ? 2 : 1) * cfot_seq_len(N) * sizeof(cplx) +
+         (size_t)cfot_tw_count(N) * sizeof(cplx);
+}
+// twiddle table of the dynamic LDS
+__device__ __forceinline__ cplx* cfot_lds_tw(cplx* lds, int N) {
+  return lds + (cfot_two_buffers(N) ? 2 : 1) * cfot_seq_len(N);
 }
 
 // The stage twiddle table of a length-N transform (cfot_tw_count(N) entries).
@@ -116,10 +127,11 @@ __device__ __forceinline__ void dft_small(cplx* v) {
 }
 
 // One Stockham stage of radix R after sub-transforms of size NS: work item j reads
-// z[j + r N/R], multiplies entry r by w^r with w = exp(DIR 2 pi i (j mod NS) / (NS R)), transforms,
-// and writes z[(j / NS) NS R + (j mod NS) + r NS].  All reads finish before the writes (in place).
-template <int N, int R, int NS, int DIR>
-__device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tws) {
+// zin[j + r N/R], multiplies entry r by w^r with w = exp(DIR 2 pi i (j mod NS) / (NS R)),
+// transforms, and writes zout[(j / NS) NS R + (j mod NS) + r NS].  In place (zin == zout) all reads
+// finish before the writes.
+template <int N, int R, int NS, int DIR, bool INPLACE>
+__device__ __forceinline__ void stockham_stage(const cplx* zin, cplx* zout, const cplx* tws) {
   constexpr int T = N / R;                           // work items
   constexpr int IPT = (T + CFOT_THREADS - 1) / CFOT_THREADS;
   cplx v[IPT][R];
@@ -136,7 +148,7 @@ __device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tws) {
       cplx wr = w;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const cplx x = z[zp(j + r * T)];
+        const cplx x = zin[zp(j + r * T)];
         if (NS == 1 || r == 0) {
           v[it][r] = x;
         } else {
@@ -147,7 +159,7 @@ __device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tws) {
       dft_small<R, DIR>(v[it]);
     }
   }
-  __syncthreads();
+  if constexpr (INPLACE) __syncthreads();
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     const int j = threadIdx.x + it * CFOT_THREADS;
@@ -155,19 +167,28 @@ __device__ __forceinline__ void stockham_stage(cplx* z, const cplx* tws) {
       const int k = j & (NS - 1);
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) z[zp(base + r * NS)] = v[it][r];
+      for (int r = 0; r < R; ++r) zout[zp(base + r * NS)] = v[it][r];
     }
   }
   __syncthreads();
 }
 
 // FFT of length N in LDS, natural order in and out (DIR = -1 forward; +1 inverse without 1/N).
+// The input is in a; returns the buffer that holds the result (a or b; b is unused when the
+// stages run in place).
 template <int N, int DIR, int NS = 1>
-__device__ __forceinline__ void fft_lds(cplx* z, const cplx* tw) {
+__device__ __forceinline__ cplx* fft_lds(cplx* a, cplx* b, const cplx* tw) {
   if constexpr (NS < N) {
     constexpr int R = (N / NS) >= 8 ? 8 : N / NS;
-    stockham_stage<N, R, NS, DIR>(z, tw);
-    fft_lds<N, DIR, NS * R>(z, tw);
+    if constexpr (cfot_two_buffers(N)) {
+      stockham_stage<N, R, NS, DIR, false>(a, b, tw);
+      return fft_lds<N, DIR, NS * R>(b, a, tw);
+    } else {
+      stockham_stage<N, R, NS, DIR, true>(a, a, tw);
+      return fft_lds<N, DIR, NS * R>(a, b, tw);
+    }
+  } else {
+    return a;
   }
 }
 
@@ -183,7 +204,8 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_lamhat(int n, double inv_
                                                               double* lamhat) {
   extern __shared__ cplx cf_lds[];
   cplx* z = cf_lds;
-  cplx* tw_s = cf_lds + N + N / 16;
+  cplx* z2 = cf_lds + cfot_seq_len(N);
+  cplx* tw_s = cfot_lds_tw(cf_lds, N);
   cfot_load_twiddles(tw_s, tw, N);
   const double s = inv_eps / (2.0 * (double)n * (double)n);
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -191,8 +213,8 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_lamhat(int n, double inv_
     z[zp(i)] = cplx{d >= 0 ? exp(-(double)d * (double)d * s) : 0.0, 0.0};
   }
   __syncthreads();
-  fft_lds<N, -1>(z, tw_s);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) lamhat[i] = z[zp(i)].re;
+  const cplx* r = fft_lds<N, -1>(z, z2, tw_s);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) lamhat[i] = r[zp(i)].re;
 }
 
 // Row maxima of two rows at once (a in .re, b in .im) over the first n entries.
@@ -226,13 +248,16 @@ __device__ __forceinline__ int cfot_pair() {
 }
 
 // Shared body of both passes: rows r0 = 2 cfot_pair() and r0 + 1 of X (log values times
-// `scale`, row pitch np, batch stride sX), convolved with lambda; on return z[zp(k)] holds the
-// convolution of row r0 (.re) and row r0 + 1 (.im) times N, and ma, mb the row shifts (-inf for
-// a row without mass).
+// `scale`, row pitch np, batch stride sX), convolved with lambda, in the dynamic LDS `lds`; returns
+// the buffer whose entry zp(k) holds the convolution of row r0 (.re) and row r0 + 1 (.im) times
+// N, and sets ma, mb to the row shifts (-inf for a row without mass).
 template <int N>
-__device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale, int n, int np, const cplx* tw,
-                                                   const double* lamhat, cplx* z, cplx* tw_s, double* scratch,
-                                                   double& ma, double& mb) {
+__device__ __forceinline__ const cplx* cfot_convolve_pair(const double* X, double scale, int n, int np,
+                                                          const cplx* tw, const double* lamhat, cplx* lds,
+                                                          double* scratch, double& ma, double& mb) {
+  cplx* z = lds;
+  cplx* z2 = lds + cfot_seq_len(N);
+  cplx* tw_s = cfot_lds_tw(lds, N);
   static_assert(N % CFOT_THREADS == 0, "whole sequence entries per thread");
   constexpr int PT = N / 2 / CFOT_THREADS > 0 ? N / 2 / CFOT_THREADS : 1;   // row values per thread (n <= N/2)
   constexpr int LT = N / CFOT_THREADS;                                      // sequence entries per thread
@@ -272,14 +297,14 @@ __device__ __forceinline__ void cfot_convolve_pair(const double* X, double scale
     z[zp(tid + q * CFOT_THREADS)] = cplx{va, vb};
   }
   __syncthreads();
-  fft_lds<N, -1>(z, tw_s);
+  cplx* zf = fft_lds<N, -1>(z, z2, tw_s);
 #pragma unroll
   for (int q = 0; q < LT; ++q) {
     const int i = zp(tid + q * CFOT_THREADS);
-    z[i] = cplx{z[i].re * lh[q], z[i].im * lh[q]};
+    zf[i] = cplx{zf[i].re * lh[q], zf[i].im * lh[q]};
   }
   __syncthreads();
-  fft_lds<N, 1>(z, tw_s);
+  return fft_lds<N, 1>(zf, zf == z ? z2 : z, tw_s);
 }
 
 // m + ln y, -inf for y <= 0 (lost to rounding) or m = -inf (a row without mass)
@@ -296,8 +321,6 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, lo
                                                              int pend_cnt, double* pend_out) {
   extern __shared__ cplx cf_lds[];
   __shared__ double scratch[8];
-  cplx* z = cf_lds;
-  cplx* tw_s = cf_lds + N + N / 16;
   const int bz = blockIdx.y;
   // pending partials, read now so that their latency hides behind the transforms
   const bool pend = pend_parts != nullptr && blockIdx.x == 0;
@@ -305,7 +328,7 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass1(const double* P, lo
   if (pend)
     for (int i = threadIdx.x; i < pend_cnt; i += CFOT_THREADS) pv += pend_parts[(size_t)bz * pend_cnt + i];
   double ma, mb;
-  cfot_convolve_pair<N>(P + (size_t)bz * sP, inv_eps, n, np, tw, lamhat, z, tw_s, scratch, ma, mb);
+  const cplx* z = cfot_convolve_pair<N>(P + (size_t)bz * sP, inv_eps, n, np, tw, lamhat, cf_lds, scratch, ma, mb);
   const int r0 = 2 * cfot_pair();
   const bool has1 = r0 + 1 < n;
   const double invN = 1.0 / (double)N;
@@ -333,8 +356,6 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass2(const double* Yt, l
                                                              double* partials, int* flag, int err_on) {
   extern __shared__ cplx cf_lds[];
   __shared__ double scratch[8];
-  cplx* z = cf_lds;
-  cplx* tw_s = cf_lds + N + N / 16;
   const int bz = blockIdx.y;
   const int r0 = 2 * cfot_pair();
   constexpr int PT = N / 2 / CFOT_THREADS > 0 ? N / 2 / CFOT_THREADS : 1;
@@ -350,7 +371,7 @@ __global__ __launch_bounds__(CFOT_THREADS) void k_cfot_pass2(const double* Yt, l
       fo_v[q][t] = (ok && err_on) ? pot[(size_t)bz * sP + (size_t)r * np + j] : 0.0;
     }
   double ma, mb;
-  cfot_convolve_pair<N>(Yt + (size_t)bz * sY, 1.0, n, np, tw, lamhat, z, tw_s, scratch, ma, mb);
+  const cplx* z = cfot_convolve_pair<N>(Yt + (size_t)bz * sY, 1.0, n, np, tw, lamhat, cf_lds, scratch, ma, mb);
   const double invN = 1.0 / (double)N, inv_eps = 1.0 / eps;
   double err = 0.0;
   bool bad = false;
