@@ -397,6 +397,16 @@ def main():
             f"FP64 GEMM {conv['gemm_f64']['value']:.1f}, {prec0} GEMM {conv['gemm_' + prec0]['value']:.1f}; "
             f"cFOT f error vs FP64 GEMM {conv['cfot_f_err_vs_f64_gemm']:.1e}; at 2048^2 (us/it): {big}")
 
+        # the paper's regime (eps = 2e-4, Sec. 4): FP64 operands, where Lambda's band (the |i - k| at
+        # which it is nonzero in FP64) is about 0.55 n and the fused kernels skip the zero K stages
+        el, rp = run_variant(F, W, torch, "f64", g, G, 2e-4, iters, max(2, args.steps // 2), 1, profile=False,
+                             graph=graph)
+        out["paper_eps_f64"] = {"eps": 2e-4, "value": round(n * n * iters * max(2, args.steps // 2) / el / 1e6, 3),
+                                "us_per_iteration": round(1e3 * float(np.median([r.ms_iterations for r in rp])) / iters, 2),
+                                "final_err_a": float(rp[-1].err_a[0])}
+        log(f"bench: FP64 at eps 2e-4 (1024^2): {out['paper_eps_f64']['value']:.1f} Mpx.it/s, "
+            f"{out['paper_eps_f64']['us_per_iteration']:.1f} us/it")
+
         # synthetic re-run of the eps sweep of Fig. 3: the L1 intensity loss of the output beam of
         # 200 iterations at 512^2, for matrix products (FP64 operands, valid down to the paper's
         # 2e-4) and for cFOT (FP64 FFT convolutions), on the two-Gaussian -> shapes stand-in

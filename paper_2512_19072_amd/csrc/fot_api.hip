@@ -283,6 +283,16 @@ struct Ops {
     return FOT_OK;
   }
 
+  // The largest |i - k| at which Lambda = exp(-(i - k)^2 / (2 n^2 eps)) is nonzero in the operand
+  // type (n: no zero entries).  exp(-x) rounds to zero in FP64 for x > 745.2, in FP32 and BF16
+  // (and the BF16x3 halves) for x > 104 at the latest, in FP16 for x > 17.4; each bound is taken
+  // with a margin, so the band is never too narrow.
+  static int lambda_band(const fot_plan_s* p, double eps) {
+    const double L = sizeof(T) == 8 ? 746.0 : std::is_same<T, _Float16>::value ? 18.0 : 105.0;
+    const double w = (double)p->n * std::sqrt(2.0 * eps * L) + 2.0;
+    return w >= (double)p->n ? p->n : (int)w;
+  }
+
   // One half-step: Pout = eps (lnm - ln(Lambda . exp(Pin/eps) . Lambda)) (Eq. 7 or Eq. 8), the
   // marginal error of the entering plan to hist[batch] (finished by the next pass 1), and, if
   // next_eps > 0, the block-normalised operand of Pout for the next half-step.  The operand of
@@ -298,6 +308,7 @@ struct Ops {
     a.nbA = p->nbA;
     a.nbT = p->nbT;
     a.xcd_swizzle = 1;
+    a.band = lambda_band(p, eps);
     // pass 1: W = At . Lambda
     a.A = p->opA;
     a.sA = plane;
@@ -320,6 +331,7 @@ struct Ops {
     b.nbA = p->nbA;
     b.nbT = p->nbT;
     b.xcd_swizzle = 1;
+    b.band = a.band;
     b.A = p->lam;
     b.sA = 0;
     b.B = p->opB;

@@ -59,6 +59,7 @@ struct FusedArgs {
   double* partials;         // [batch][tiles]
   int* flag;
   int err_on;               // pass 2: evaluate the marginal-error partial (reads the old potential)
+  int band;                 // Lambda[i][k] is zero in the operand type for |i - k| > band (>= n: no zeros)
 };
 
 // exp(x - K ln 2) rounded to the operand type, with the K of a block's maximum.  The prep
@@ -276,6 +277,18 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   tile_of(gridDim.x, gridDim.y, p.xcd_swizzle, &tr, &tc);
   const int row0 = tr * BM, col0 = tc * BN;
   const size_t plane = (size_t)np * np;
+  // K stages [k_lo, k_lo + nks) whose Lambda block can be nonzero for this tile: Lambda is the
+  // B operand of pass 1 (its rows are the output columns) and the A operand of pass 2 (rows =
+  // output rows), and its entries vanish in the operand type beyond the band.  The skipped
+  // stages would only add exact zeros, so the result is the same as with all stages.
+  constexpr int KPS = FROWB / (int)sizeof(T);      // K values per stage
+  int k_lo = 0, nks = p.nk;
+  if (p.band < n) {
+    const int lam0 = PASS == 1 ? col0 : row0, lamL = PASS == 1 ? BN : BM;
+    const int lo = max(0, lam0 - p.band), hi = lam0 + lamL - 1 + p.band;
+    k_lo = lo / KPS;
+    nks = min(p.nk, hi / KPS + 1) - k_lo;
+  }
 
   // ---- operand staging: each K stage of the tile (BM rows of A, then BN rows of B, FROWB bytes
   // per row) is copied global -> LDS by 16-byte direct loads (no register round trip).  A wave
@@ -300,7 +313,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   }
   auto stage_load = [&](int kk, unsigned char* dst) {
 #pragma unroll
-    for (int i = 0; i < UPW; ++i) dma16(dsrc[i] + (size_t)kk * FROWB, dst + (wave + C::NW * i) * 1024);
+    for (int i = 0; i < UPW; ++i) dma16(dsrc[i] + (size_t)(kk + k_lo) * FROWB, dst + (wave + C::NW * i) * 1024);
   };
 
   // ---- prologue: stage 0 and the exponent table first (the table build waits for its loads,
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   __syncthreads();
 #pragma unroll
   for (int kk = 1; kk < NBUF - 1; ++kk)
-    if (kk < p.nk) stage_load(kk, bufp(kk));
+    if (kk < nks) stage_load(kk, bufp(kk));
 
   // pass-2 epilogue inputs, prefetched so that their latency hides behind the K loop
   double la_v[CB][RB][4], fo_v[CB][RB][4];
@@ -406,14 +419,14 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) fb[hs][cb] = *(const u32x4*)(&lds0[brow + cb * 16 * FROWB + (sw ^ (hs << 6))]);
   }
-  for (int kt0 = 0; kt0 < p.nk; kt0 += NBUF)
+  for (int kt0 = 0; kt0 < nks; kt0 += NBUF)
 #pragma unroll
   for (int jb = 0; jb < NBUF; ++jb) {                // stage kt uses buffer jb = kt mod NBUF
     const int kt = kt0 + jb;
-    if (kt >= p.nk) break;
+    if (kt >= nks) break;
     const unsigned char* cur = bufp(jb);
-    const bool more = kt + 1 < p.nk;
-    const bool ahead = kt + NBUF - 1 < p.nk;       // a stage is requested NBUF - 1 ahead
+    const bool more = kt + 1 < nks;
+    const bool ahead = kt + NBUF - 1 < nks;        // a stage is requested NBUF - 1 ahead
     if (ahead) stage_load(kt + NBUF - 1, bufp((jb + NBUF - 1) % NBUF));
 #pragma unroll
     for (int h = 0; h < HPS; ++h) {
@@ -422,7 +435,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       const bool first = hl % HB == 0, lastb = (hl + 1) % HB == 0;
       const bool last = h + 1 == HPS;
       if (first) {
-        const int blk = (kt * HPS + h) / HB;
+        const int blk = ((kt + k_lo) * HPS + h) / HB;
 #pragma unroll
         for (int q = 0; q < ND; ++q) dcur[q] = dtab[blk * SR + srow(q)];
       }
@@ -505,7 +518,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   }
   {
     // flush the last block: it used set ((K steps - 1) / HB) & 1
-    const int lastpar = (((p.nk * HPS) - 1) / HB) & 1;
+    const int lastpar = (((nks * HPS) - 1) / HB) & 1;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll

@@ -310,3 +310,20 @@ def test_range_loss_is_reported():
     plan.close()
     _say(f"err_b f32 {rep.err_b[0]:.3e}, f64 {rep64.err_b[0]:.3e}")
     assert st64 == F.FOT_OK and rep64.err_b[0] < 1e-12
+
+
+@pytest.mark.parametrize("n,prec,eps", [(256, "f64", 2e-4), (320, "f32", 1e-3), (256, "bf16x3", 1e-3)])
+def test_small_eps_band_skipping(n, prec, eps):
+    """At small eps most of Lambda rounds to zero in the operand type and the fused kernels skip
+    the K stages whose Lambda block is zero (the band of |i - k| where it is not); the result must
+    still be the oracle's (FP64: the paper's eps = 2e-4, where the band is about half of n)."""
+    g, G = W.twogauss_to_shapes(n)
+    G = G if G.ndim == 2 else G[0]
+    T = 60
+    _say(f"case: band skipping n={n} {prec} eps={eps}")
+    gpu = run_gpu(g, G, eps, T, prec)
+    ref = O.solve_sep(g, G, eps, T)
+    e = compare(gpu, ref, g, G, precision=prec)
+    _say({k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in e.items()})
+    tol = {"f64": 1e-10, "f32": 1e-6, "bf16x3": 1e-5}[prec]
+    assert e["f"] < tol and e["psi"] < tol and e["phase"] < tol, e
