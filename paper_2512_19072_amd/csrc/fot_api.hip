@@ -104,6 +104,7 @@ struct fot_plan_s {
   double *bWa = nullptr, *bWb = nullptr, *bWca = nullptr, *bWcb = nullptr;
   double *bfc = nullptr, *bHt = nullptr, *bF = nullptr;
   double *bpow = nullptr, *bsumG = nullptr, *brow = nullptr, *bl1 = nullptr;
+  bool beam_ok = false;   // every buffer above allocated and the DFT operands written
   // cFOT (FOT_FLAG_CFOT): FFT length, twiddles, lambda's transform (for clam_eps), the transposed
   // intermediate of a half-step, f^T and ln a^T (the u-update's orientation), ln S^T of the last
   // u-update, and one marginal-error partial per workgroup
@@ -647,7 +648,8 @@ __global__ void k_flag_nonpositive(const double* v, int cnt, int* flag) {
 }
 
 fot_status beam_ready(fot_plan_s* p) {
-  if (p->bWa) return FOT_OK;
+  if (p->beam_ok) return FOT_OK;   // (after a failed attempt the pointers set so far are leaked to
+                                   // p->allocs and freed with the plan; a retry allocates afresh)
   const size_t wsz = (size_t)p->np * 2 * p->np, fsz = (size_t)p->B * wsz;
   fot_status s;
   double** w[4] = {&p->bWa, &p->bWb, &p->bWca, &p->bWcb};
@@ -666,6 +668,7 @@ fot_status beam_ready(fot_plan_s* p) {
   hipLaunchKernelGGL(k_dft_operands, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, p->stream, p->n, p->np,
                      p->bWa, p->bWb, p->bWca, p->bWcb);
   LAUNCH_CHECK();
+  p->beam_ok = true;
   return FOT_OK;
 }
 
