@@ -59,6 +59,7 @@ struct fot_plan_s {
   unsigned* colkey = nullptr;
   int *kexpA = nullptr, *kexpT = nullptr;   // exponent tables of the block-normalised loop operands
   int nbA = 0, nbT = 0;
+  bool t32 = false;                         // fused kernels on 32 x 32 tiles (small grids)
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
   void *lam = nullptr, *opA = nullptr, *opB = nullptr, *Z = nullptr;
@@ -223,6 +224,10 @@ struct Ops {
   // Tile configuration of the contraction GEMMs: 64 x 64 output tiles, 8 waves per workgroup
   // (two per SIMD, so one wave's LDS and barrier waits are covered by the other's MFMAs).
   typedef Cfg64x64w8 GC;
+  // Fused half-step kernels of grids too small to give every CU a 64 x 64 tile: 32 x 32 tiles of
+  // four waves (one per SIMD), whose exponent blocks are 32 wide.  Four times the workgroups
+  // and a quarter of the work each, so a launch's fixed latency (first stage, epilogue) is shorter.
+  typedef Cfg<32, 32, 4, 1, 1> GS;
 
   static fot_status gemm_launch(fot_plan_s* p, int epi, const GemmArgs& a) {
     dim3 grid(p->np / GC::BN, p->np / GC::BM, p->B);
@@ -259,18 +264,25 @@ struct Ops {
     return FOT_OK;
   }
 
+  template <typename C>
+  static void fused_launch_cfg(fot_plan_s* p, int pass, const FusedArgs& a, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 grid(p->np / C::BN, p->np / C::BM, p->B);
+    const dim3 block(C::THREADS);
+    if (pass == 1)
+      hipExtLaunchKernelGGL((k_fused<T, 1, C>), grid, block, (uint32_t)fused_dyn_lds<1, C>(p->np), p->stream, e0,
+                            e1, 0, a);
+    else
+      hipExtLaunchKernelGGL((k_fused<T, 2, C>), grid, block, (uint32_t)fused_dyn_lds<2, C>(p->np), p->stream, e0,
+                            e1, 0, a);
+  }
   static fot_status fused_launch(fot_plan_s* p, int pass, const FusedArgs& a) {
-    dim3 grid(p->np / GC::BN, p->np / GC::BM, p->B);
-    const dim3 block(GC::THREADS);
     const bool prof = (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
     hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
     hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
-    if (pass == 1)
-      hipExtLaunchKernelGGL((k_fused<T, 1, GC>), grid, block, (uint32_t)fused_dyn_lds<1, GC>(p->np), p->stream, e0,
-                            e1, 0, a);
+    if (p->t32)
+      fused_launch_cfg<GS>(p, pass, a, e0, e1);
     else
-      hipExtLaunchKernelGGL((k_fused<T, 2, GC>), grid, block, (uint32_t)fused_dyn_lds<2, GC>(p->np), p->stream, e0,
-                            e1, 0, a);
+      fused_launch_cfg<GC>(p, pass, a, e0, e1);
     LAUNCH_CHECK();
     if (prof) p->prof_used += 2;
     return FOT_OK;
@@ -278,8 +290,12 @@ struct Ops {
 
   // Block-normalised pass-1 operand of a potential (start of a solve or of a replayed segment).
   static fot_status prep(fot_plan_s* p, const double* P, double eps) {
-    hipLaunchKernelGGL((k_prep_blocks<T, GC::BN>), dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np,
-                       1.0 / eps, (T*)p->opA, p->kexpA);
+    if (p->t32)
+      hipLaunchKernelGGL((k_prep_blocks<T, GS::BN>), dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np,
+                         1.0 / eps, (T*)p->opA, p->kexpA);
+    else
+      hipLaunchKernelGGL((k_prep_blocks<T, GC::BN>), dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np,
+                         1.0 / eps, (T*)p->opA, p->kexpA);
     LAUNCH_CHECK();
     return FOT_OK;
   }
@@ -907,8 +923,6 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   p->np = ((d.n + align - 1) / align) * align;
   p->B = d.batch;
   p->prec = d.precision;
-  // one marginal-error partial per output tile of the fused pass-2 kernel
-  p->tiles = (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN);
   p->zsz = d.precision == FOT_F64 ? 8 : 4;
   p->plane = (size_t)p->np * p->np;
   p->stream = (hipStream_t)stream;
@@ -920,6 +934,18 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
     return s;
   };
   if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: no HIP device"));
+  // fused-kernel tiles: 64 x 64, or 32 x 32 when 64 x 64 tiles would occupy at most half of the
+  // CUs.  Measured FP32 half-steps (pass 1 + pass 2), 32 x 32 against 64 x 64 tiles on 256 CUs:
+  // 512^2 17 against 32 us, 640^2 27 against 38 us, 768^2 45 against 43 us (BF16 26 against
+  // 20 us), 1024^2 73 against 57 us.
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+    return bail(fail(FOT_E_HIP, "fot_plan: cannot query the device"));
+  p->t32 = 2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
+  const int tbm = p->t32 ? Ops<float>::GS::BM : Ops<float>::GC::BM;
+  const int tbn = p->t32 ? Ops<float>::GS::BN : Ops<float>::GC::BN;
+  // one marginal-error partial per output tile of the fused pass-2 kernel
+  p->tiles = (p->np / tbm) * (p->np / tbn);
   const size_t BP = (size_t)p->B * p->plane;
   fot_status s = FOT_OK;
 #define ALLOC(ptr, cnt)                                       \
@@ -945,8 +971,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   ALLOC(p->rparts, (size_t)5 * p->B * READOUT_BLOCKS);
   ALLOC(p->rsums, (size_t)5 * p->B);
   ALLOC(p->colkey, (size_t)p->B * p->np);
-  p->nbA = p->np / Ops<float>::GC::BN;
-  p->nbT = p->np / Ops<float>::GC::BM;
+  p->nbA = p->np / tbn;
+  p->nbT = p->np / tbm;
   ALLOC(p->kexpA, (size_t)p->B * p->np * p->nbA);
   ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
   ALLOC(p->flag, (size_t)1);

@@ -86,6 +86,35 @@ def test_batch_targets_are_independent():
         assert e["f"] < 1e-6 and e["psi"] < 1e-6 and e["phase"] < 1e-6, (b, e)
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_small_and_large_tile_configurations_agree(prec):
+    """The fused kernels run on 32 x 32 tiles when 64 x 64 tiles would occupy at most half of the
+    CUs (one 512^2 target: 64 tiles) and on 64 x 64 tiles otherwise (four 512^2 targets: 256
+    tiles).  The same target solved both ways agrees with the oracle to the precision's
+    tolerance."""
+    import torch
+    n, eps, T = 512, 1e-2, 40
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    if not (128 <= cus < 512):
+        pytest.skip(f"{cus} CUs: both 512^2 cases would use the same tile size")
+    g, G = _rand_case(n, 21)
+    _say(f"case: tile configurations n={n} {prec} B=1 and B=4")
+    one = run_gpu(g, G, eps, T, prec)
+    four = run_gpu(g, np.stack([G] * 4), eps, T, prec)
+    ref = O.solve_sep(g, G, eps, T)
+    tol = {"f32": 1e-6, "bf16": 1e-3}[prec]
+    e1 = compare(one, ref, g, G, precision=prec)
+    _say(e1)
+    for k in ("f", "psi", "phase"):
+        assert e1[k] < tol, (k, e1[k])
+    for b in range(4):
+        e4 = compare(four, ref, g, G, b_index=b, precision=prec)
+        for k in ("f", "psi", "phase"):
+            assert e4[k] < tol, (b, k, e4[k])
+    # the batch entries are bit-identical to each other (one code path, independent targets)
+    assert all(np.array_equal(four["psi"][0], four["psi"][b]) for b in range(1, 4))
+
+
 def test_deterministic_and_warm_start():
     """Two solves are bit-identical; 30 + 30 warm-started iterations equal 60 iterations."""
     from paper_2512_19072_amd import fot as F
