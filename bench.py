@@ -30,6 +30,17 @@ METRIC = "Mpixel·iter/s at 1024²; %MFMA/HBM peak; BF16 vs FP32 at equal margin
 # algorithmic FLOP/s is a third of BF16's
 PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "f64": 78.6, "bf16x3": 2500.0 / 3}
 HBM_PEAK_GBS = 8000.0
+# operand bytes per element of each precision (BF16x3: a hi and a lo half)
+OPERAND_BYTES = {"f32": 4, "bf16": 2, "f16": 2, "f64": 8, "bf16x3": 4}
+
+
+def alg_bytes_per_launch(n, prec):
+    """Algorithmic HBM bytes of one fused launch, the mean of the two passes of a half-step:
+    pass 1 reads the operand and writes the transposed intermediate (2 s bytes per pixel), pass 2
+    reads the intermediate, ln m and the potential, writes the potential and the next operand
+    (24 + 2 s).  Lambda (n^2 s) is shared by every launch and stays in the caches."""
+    s = OPERAND_BYTES[prec]
+    return n * n * (12 + 2 * s)
 
 
 def log(*a):
@@ -253,6 +264,7 @@ def main():
             if t_reach.get(prec) and t_f32.get(prec):
                 sp = round((t_f32[prec] * base["ms_it"]) / (t_reach[prec] * d["ms_it"]), 3)
             ach = flop / (d["gemm_us"] * 1e-6) / 1e12
+            hbm = alg_bytes_per_launch(n, prec) / (d["gemm_us"] * 1e-6) / 1e9
             variants[prec] = {"value": round(d["value"], 3), "ms_per_step": round(d["ms_per_step"], 4),
                               "speedup_vs_f32_per_iteration": round(base["ms_it"] / d["ms_it"], 3),
                               "equal_marginal_l1": {"err_level": levels[prec], "iters_f32": t_f32.get(prec),
@@ -261,7 +273,9 @@ def main():
                               "final_err_a": d.get("final_err_a", float(reps[-1].err_a[0])),
                               "kernel_avg_launch_us": round(d["gemm_us"], 3),
                               "kernel_tflops": round(ach, 2),
-                              "kernel_frac_of_peak": round(ach / PEAK_TFLOPS[prec], 4)}
+                              "kernel_frac_of_peak": round(ach / PEAK_TFLOPS[prec], 4),
+                              "kernel_hbm_gbs": round(hbm, 1),
+                              "kernel_hbm_frac": round(hbm / HBM_PEAK_GBS, 4)}
             log(f"bench: {prec} {d['value']:.1f} Mpx.it/s, kernel {d['gemm_us']:.1f} us, "
                 f"per-iteration speedup {base['ms_it'] / d['ms_it']:.2f}, equal-L1 speedup {sp} "
                 f"(E = {levels[prec]:.2e}: f32 {t_f32.get(prec)} its, {prec} {t_reach.get(prec)} its)")
