@@ -41,7 +41,9 @@ typedef enum {
   FOT_E_HIP = 3,         /* a HIP runtime call failed */
   FOT_E_NONFINITE = 4,   /* a potential of a positive-mass pixel became non-finite */
   FOT_E_STATE = 5,       /* call order violated (e.g. backward without a taped solve) */
-  FOT_E_UNSUPPORTED = 6, /* option not available in this build */
+  FOT_E_UNSUPPORTED = 6, /* option not available in this build (or, from fot_solve, an eps that
+                            needs the block-normalised Gibbs factor at an n whose exponent
+                            table does not fit in LDS: n > 4096 with 32- and 16-bit types) */
   FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the final plan's column
                             marginal error (fot_report.err_b, evaluated in FP64) exceeds what the
                             operand type allows (FP64 1e-8, FP32 1e-5, BF16x3 1e-4,
@@ -53,6 +55,11 @@ typedef enum {
 /* Element type of the contraction operands (the Gibbs factor and the shifted exponentials
  * that the per-axis matrix products consume).  Accumulation is FP32 (FP64 for FOT_F64);
  * potentials, logarithms of the marginals, and all reductions are FP64 in every mode.
+ * Every operand is stored in blocks normalised by an integer power of two that the products
+ * rescale exactly in FP64; the Gibbs factor too once eps is small enough that it has entries
+ * below the type's range.  The 32-bit and 16-bit types then reach down to eps = 2e-4 on
+ * 1024 x 1024 grids (the paper's regime; FP16 to about 1e-3); below that FOT_E_RANGE reports
+ * the loss and FOT_F64 applies.
  * FOT_BF16X3 splits each operand value v into hi = bf16(v) and lo = bf16(v - hi) and forms
  * every product as hi.hi + hi.lo + lo.hi with three BF16 matrix-core operations: about 16
  * significant bits per operand (between BF16's 8 and FP32's 24) at BF16 matrix-core rates,

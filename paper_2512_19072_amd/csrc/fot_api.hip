@@ -60,6 +60,8 @@ struct fot_plan_s {
   int *kexpA = nullptr, *kexpT = nullptr;   // exponent tables of the block-normalised loop operands
   int nbA = 0, nbT = 0;
   bool t32 = false;                         // fused kernels on 32 x 32 tiles (small grids)
+  int* kexpL = nullptr;                     // LN form: [np][nbA] exponents of the block-normalised Lambda
+  bool ln_ok = false;                       // the LN-form kernels fit in LDS at this n_p
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
   void *lam = nullptr, *opA = nullptr, *opB = nullptr, *Z = nullptr;
@@ -253,36 +255,94 @@ struct Ops {
     return a;
   }
 
+  // LN form of the fused kernels: Lambda stored block-normalised with an exponent table, used
+  // once Lambda has entries below the operand type's range (eps small for n); FP64 operands hold
+  // every entry that matters and never need it.
+  static bool lam_ln(const fot_plan_s* p, double eps) {
+    if constexpr (sizeof(T) == 8) {
+      (void)p;
+      (void)eps;
+      return false;
+    } else {
+      return raw_band(p, eps) < p->n;
+    }
+  }
+
+  // The LN form keeps Lambda's exponent table in LDS beside the stage buffers: whether the larger
+  // of the two kernels (pass 2: static and dynamic LDS) fits at this plan's n_p and tiles.
+  static bool ln_fits(fot_plan_s* p) {
+    if constexpr (sizeof(T) == 8) {
+      (void)p;
+      return true;
+    } else {
+      hipFuncAttributes fa{};
+      hipError_t e;
+      size_t dyn;
+      if (p->t32) {
+        e = hipFuncGetAttributes(&fa, (const void*)k_fused<T, 2, GS, FUSED_NBUF, true>);
+        dyn = fused_dyn_lds<2, GS, true>(p->np);
+      } else {
+        e = hipFuncGetAttributes(&fa, (const void*)k_fused<T, 2, GC, FUSED_NBUF, true>);
+        dyn = fused_dyn_lds<2, GC, true>(p->np);
+      }
+      int lim = 0;
+      if (e != hipSuccess || hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
+      return fa.sharedSizeBytes + dyn <= (size_t)lim;
+    }
+  }
+
   static fot_status fill_lambda(fot_plan_s* p, double eps, bool /*unused*/) {
-    const size_t total = p->plane;
-    const int blocks = (int)((total + 255) / 256);
-    hipLaunchKernelGGL(k_fill_lambda<T>, dim3(blocks), dim3(256), 0, p->stream, (T*)p->lam, (T*)nullptr, p->n,
-                       p->np, 1.0 / eps);
+    if (lam_ln(p, eps)) {
+      if (p->t32)
+        hipLaunchKernelGGL((k_lambda_blocks<T, GS::BN>), dim3(p->np), dim3(64), 0, p->stream, p->n, p->np, 1.0 / eps,
+                           (T*)p->lam, p->kexpL);
+      else
+        hipLaunchKernelGGL((k_lambda_blocks<T, GC::BN>), dim3(p->np), dim3(64), 0, p->stream, p->n, p->np, 1.0 / eps,
+                           (T*)p->lam, p->kexpL);
+    } else {
+      const size_t total = p->plane;
+      const int blocks = (int)((total + 255) / 256);
+      hipLaunchKernelGGL(k_fill_lambda<T>, dim3(blocks), dim3(256), 0, p->stream, (T*)p->lam, (T*)nullptr, p->n,
+                         p->np, 1.0 / eps);
+    }
     LAUNCH_CHECK();
     p->lam_eps = eps;
     p->lamH_valid = false;
     return FOT_OK;
   }
 
-  template <typename C>
+  template <typename C, bool LN>
   static void fused_launch_cfg(fot_plan_s* p, int pass, const FusedArgs& a, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(p->np / C::BN, p->np / C::BM, p->B);
     const dim3 block(C::THREADS);
     if (pass == 1)
-      hipExtLaunchKernelGGL((k_fused<T, 1, C>), grid, block, (uint32_t)fused_dyn_lds<1, C>(p->np), p->stream, e0,
-                            e1, 0, a);
+      hipExtLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, LN>), grid, block,
+                            (uint32_t)fused_dyn_lds<1, C, LN>(p->np), p->stream, e0, e1, 0, a);
     else
-      hipExtLaunchKernelGGL((k_fused<T, 2, C>), grid, block, (uint32_t)fused_dyn_lds<2, C>(p->np), p->stream, e0,
-                            e1, 0, a);
+      hipExtLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, LN>), grid, block,
+                            (uint32_t)fused_dyn_lds<2, C, LN>(p->np), p->stream, e0, e1, 0, a);
   }
   static fot_status fused_launch(fot_plan_s* p, int pass, const FusedArgs& a) {
     const bool prof = (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
     hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
     hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
-    if (p->t32)
-      fused_launch_cfg<GS>(p, pass, a, e0, e1);
-    else
-      fused_launch_cfg<GC>(p, pass, a, e0, e1);
+    bool ln = false;
+    if constexpr (sizeof(T) < 8) ln = a.kexpL != nullptr;
+    if (ln) {
+      if constexpr (sizeof(T) < 8) {
+        if (p->t32)
+          fused_launch_cfg<GS, true>(p, pass, a, e0, e1);
+        else
+          fused_launch_cfg<GC, true>(p, pass, a, e0, e1);
+      }
+    } else if (p->t32) {
+      fused_launch_cfg<GS, false>(p, pass, a, e0, e1);
+    } else {
+      fused_launch_cfg<GC, false>(p, pass, a, e0, e1);
+    }
     LAUNCH_CHECK();
     if (prof) p->prof_used += 2;
     return FOT_OK;
@@ -304,10 +364,16 @@ struct Ops {
   // type (n: no zero entries).  exp(-x) rounds to zero in FP64 for x > 745.2, in FP32 and BF16
   // (and the BF16x3 halves) for x > 104 at the latest, in FP16 for x > 17.4; each bound is taken
   // with a margin, so the band is never too narrow.
-  static int lambda_band(const fot_plan_s* p, double eps) {
-    const double L = sizeof(T) == 8 ? 746.0 : std::is_same<T, _Float16>::value ? 18.0 : 105.0;
+  static int band_for(const fot_plan_s* p, double eps, double L) {
     const double w = (double)p->n * std::sqrt(2.0 * eps * L) + 2.0;
     return w >= (double)p->n ? p->n : (int)w;
+  }
+  static int raw_band(const fot_plan_s* p, double eps) {
+    return band_for(p, eps, sizeof(T) == 8 ? 746.0 : std::is_same<T, _Float16>::value ? 18.0 : 105.0);
+  }
+  // The LN form keeps every entry above FP64's underflow (exponent plus normalised mantissa).
+  static int lambda_band(const fot_plan_s* p, double eps) {
+    return lam_ln(p, eps) ? band_for(p, eps, 746.0) : raw_band(p, eps);
   }
 
   // One half-step: Pout = eps (lnm - ln(Lambda . exp(Pin/eps) . Lambda)) (Eq. 7 or Eq. 8), the
@@ -326,6 +392,7 @@ struct Ops {
     a.nbT = p->nbT;
     a.xcd_swizzle = 1;
     a.band = lambda_band(p, eps);
+    a.kexpL = lam_ln(p, eps) ? p->kexpL : nullptr;
     // pass 1: W = At . Lambda
     a.A = p->opA;
     a.sA = plane;
@@ -349,6 +416,7 @@ struct Ops {
     b.nbT = p->nbT;
     b.xcd_swizzle = 1;
     b.band = a.band;
+    b.kexpL = a.kexpL;
     b.A = p->lam;
     b.sA = 0;
     b.B = p->opB;
@@ -376,6 +444,15 @@ struct Ops {
   static fot_status loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
     const long long plane = (long long)p->plane;
     const int B = p->B;
+    for (int t = 0; t < iters; ++t)
+      if (lam_ln(p, e[t]) && !p->ln_ok) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "fot_solve: at eps %.3g and n %d Lambda needs its block exponents, whose table does not fit "
+                      "in LDS with this operand type (use FOT_F64)",
+                      e[t], p->n);
+        return fail(FOT_E_UNSUPPORTED, msg);
+      }
     fot_status s = prep(p, p->psi, e[0]);
     if (s != FOT_OK) return s;
     for (int t = 0; t < iters; ++t) {
@@ -975,6 +1052,10 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   p->nbT = p->np / tbm;
   ALLOC(p->kexpA, (size_t)p->B * p->np * p->nbA);
   ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
+  if (d.precision != FOT_F64) ALLOC(p->kexpL, (size_t)p->np * p->nbA);
+  p->ln_ok = dispatch(d.precision, [&](auto tag) -> fot_status {
+               return Ops<decltype(tag)>::ln_fits(p) ? FOT_OK : FOT_E_UNSUPPORTED;
+             }) == FOT_OK;
   ALLOC(p->flag, (size_t)1);
   ALLOCV(p->lam, p->plane * p->esz);
   ALLOCV(p->opA, BP * p->esz);

@@ -16,6 +16,9 @@
 //
 //   pass 1  W~ = At . Lambda^T, W = W~ 2^{R_L}; epilogue writes Bt (block exponents by frexp, no
 //           transcendental) and the exponent table K'.
+// At small eps Lambda itself spans more than the operand type's range; it is then stored the same
+// way, Lambda[k][M] = Lambda~[k][M] 2^{KL[k][blk(M)]} (KL <= 0), and each block's partial sum is
+// rescaled by the sum of both operands' exponents (the LN form of the kernels).
 //   pass 2  S~ = Lambda . Bt^T, ln S = R'_k ln 2 + ln S~; epilogue updates the potential, the
 //           marginal-error partial, and writes the next pass-1 operand At and its exponents.
 #pragma once
@@ -62,6 +65,7 @@ struct FusedArgs {
   int* flag;
   int err_on;               // pass 2: evaluate the marginal-error partial (reads the old potential)
   int band;                 // Lambda[i][k] is zero in the operand type for |i - k| > band (>= n: no zeros)
+  const int* kexpL;         // LN form: [np][nb] exponents of the block-normalised Lambda (nb as kexp)
 };
 
 // exp(x - K ln 2) rounded to the operand type, with the K of a block's maximum.  The prep
@@ -207,6 +211,26 @@ __global__ __launch_bounds__(64) void k_prep_blocks(const double* P, int n, int 
   }
 }
 
+// Block-normalised Lambda (LN form): row i holds Lambda[i][k] = exp(-(i - k)^2 / (2 n^2 eps)) as
+// Lambda~ 2^{K} per block of XB columns, K the exponent of the block's largest entry; one wave per
+// row.  Rows and columns beyond n hold the same formula (the operands they meet there are zero).
+template <typename T, int XB>
+__global__ __launch_bounds__(64) void k_lambda_blocks(int n, int np, double inv_eps, T* out, int* kexp) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const int nb = np / XB;
+  const double c = inv_eps / (2.0 * (double)n * (double)n);
+  T* o = out + (size_t)i * np;
+  int* ko = kexp + (size_t)i * nb;
+  for (int c0 = 0; c0 < np; c0 += 64) {
+    const int k = c0 + lane;
+    const double d = (double)(i - k);
+    const double x = -(d * d) * c;
+    const int K = block_exponent(group_max<XB>(x));
+    store_op<T>(o, k, block_operand<T>(x, K));
+    if (lane % XB == 0) ko[k / XB] = K;
+  }
+}
+
 // Wait until at most N vector-memory loads of this wave are outstanding (direct LDS loads
 // included: they complete in issue order with the others).
 template <int N>
@@ -233,16 +257,18 @@ constexpr int FRAG_AHEAD = 2;  // LDS fragment reads issued this many MMA steps 
 constexpr int FROWB = 512;      // bytes of one operand row per K stage of the fused kernels
 constexpr int FUSED_NBUF = 2;   // K stages resident in LDS (one in flight while one is consumed)
 
-// Launch with dynamic LDS of fused_dyn_lds<PASS, C>(np) bytes (the exponent-difference table).
+// Launch with dynamic LDS of fused_dyn_lds<PASS, C, LN>(np) bytes (the exponent-difference
+// table, and in the LN form Lambda's exponent table for the tile's Lambda rows).
 template <int PASS, typename C>
 constexpr int fused_scaled_rows() { return PASS == 1 ? C::BM : C::BN; }
-template <int PASS, typename C>
+template <int PASS, typename C, bool LN = false>
 inline size_t fused_dyn_lds(int np) {
   const int xb = PASS == 1 ? C::BN : C::BM;
-  return (size_t)(np / xb) * fused_scaled_rows<PASS, C>() * sizeof(short);
+  const int lam_rows = LN ? (PASS == 1 ? C::BN : C::BM) : 0;
+  return (size_t)(np / xb) * (fused_scaled_rows<PASS, C>() + lam_rows) * sizeof(short);
 }
 
-template <typename T, int PASS, typename C, int NBUF = FUSED_NBUF>
+template <typename T, int PASS, typename C, int NBUF = FUSED_NBUF, bool LN = false>
 __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   static_assert(NBUF >= 2, "at least double buffering");
   typedef typename Mma<T>::acc_t acc_t;
@@ -264,6 +290,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   static_assert(NBUF <= 3, "three stage buffers at most");
   auto bufp = [](int j) -> unsigned char* { return j == 0 ? lds0 : j == 1 ? lds1 : lds2; };
   extern __shared__ short dtab[];                 // [np / XB][SR]: exponent - row reference
+  constexpr int LR = PASS == 1 ? BN : BM;         // LN: Lambda rows of the tile (output columns / rows)
   __shared__ int rref[SR];                        // reference exponent of each scaled row
   __shared__ double red[C::NW];
   __shared__ int kred[C::WGN][BM];                // pass 2: row exponents of the next operand
@@ -341,6 +368,15 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       }
     }
   }
+  short* const ltab = dtab + (size_t)nbk * SR;    // LN: [np / XB][LR] Lambda exponents (<= 0)
+  if constexpr (LN) {
+    const int lrow0 = (PASS == 1) ? col0 : row0;
+    const int* kl = p.kexpL + (size_t)lrow0 * nbk;
+    for (int idx = tid; idx < LR * nbk; idx += C::THREADS) {
+      const int r = idx / nbk, b = idx - r * nbk;
+      ltab[b * LR + r] = (short)max(kl[(size_t)r * nbk + b], -1100);
+    }
+  }
   vm_wait<0>();
   __syncthreads();
 #pragma unroll
@@ -396,6 +432,20 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   int dcur[ND], dprev[ND];
 #pragma unroll
   for (int q = 0; q < ND; ++q) dcur[q] = dprev[q] = 0;
+  // LN: Lambda's exponents of this lane's output columns (pass 1) or rows (pass 2)
+  constexpr int NL = LN ? ((PASS == 1) ? CB : RB * 4) : 1;
+  int lcur[NL], lprev[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) lcur[q] = lprev[q] = 0;
+  auto lrow = [&](int q) -> int {
+    return (PASS == 1) ? wn * C::WTN + q * 16 + r16 : wm * C::WTM + (q / 4) * 16 + Mma<T>::row(g, q % 4);
+  };
+  // exponent that scales accumulator element (rb, cb, e) of the block held in dprev / lprev
+  auto fscale = [&](int rb, int cb, int e) -> int {
+    const int dd = dprev[PASS == 1 ? rb * 4 + e : cb];
+    if constexpr (LN) return dd + lprev[PASS == 1 ? cb : rb * 4 + e];
+    return dd;
+  };
   // scaled row of exponent-difference entry q of this lane
   auto srow = [&](int q) -> int {
     return (PASS == 1) ? wm * C::WTM + (q / 4) * 16 + Mma<T>::row(g, q % 4) : wn * C::WTN + q * 16 + r16;
@@ -440,6 +490,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         const int blk = ((kt + k_lo) * HPS + h) / HB;
 #pragma unroll
         for (int q = 0; q < ND; ++q) dcur[q] = dtab[blk * SR + srow(q)];
+        if constexpr (LN) {
+#pragma unroll
+          for (int q = 0; q < NL; ++q) lcur[q] = ltab[blk * LR + lrow(q)];
+        }
       }
       if (h + FA < HPS) {
         const int ha = h + FA;                     // step whose fragments are requested now
@@ -488,13 +542,15 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           for (int cb = 0; cb < CB; ++cb) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-              accd[rb][cb][e] += ldexp((double)acc[par ^ 1][rb][cb][e], dprev[PASS == 1 ? rb * 4 + e : cb]);
+              accd[rb][cb][e] += ldexp((double)acc[par ^ 1][rb][cb][e], fscale(rb, cb, e));
             acc[par ^ 1][rb][cb] = acc_t{};
           }
       }
       if (lastb) {
 #pragma unroll
         for (int q = 0; q < ND; ++q) dprev[q] = dcur[q];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) lprev[q] = lcur[q];
       }
       if (last) {
         if (ahead && NBUF > 2)
@@ -531,7 +587,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const double v = lastpar ? (double)acc[1][rb][cb][e] : (double)acc[0][rb][cb][e];
-          accd[rb][cb][e] += ldexp((double)v, dprev[PASS == 1 ? rb * 4 + e : cb]);
+          accd[rb][cb][e] += ldexp((double)v, fscale(rb, cb, e));
         }
   }
 

@@ -33,7 +33,8 @@ def run_gpu(g, G, eps, iters, precision, checkpoint_every=0, max_iters=None, pro
                   profile=profile)
     phase, rep, st = plan.solve(to_dev(g), to_dev(G), eps, iters)
     f, psi = plan.potentials()
-    out = dict(phase=phase.cpu().numpy(), f=f.cpu().numpy(), psi=psi.cpu().numpy(), rep=rep, plan=plan)
+    out = dict(phase=phase.cpu().numpy(), f=f.cpu().numpy(), psi=psi.cpu().numpy(), rep=rep, plan=plan,
+               status=st)
     return out
 
 
