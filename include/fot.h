@@ -138,7 +138,9 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out);
  *   iters     1 <= iters <= max_iters
  *   phase_out device [batch][n][n] FP64 phase in cycles, or NULL to skip writing it
  *   rep       host report, or NULL
- * Returns FOT_E_INVALID for bad arguments or amplitudes (nothing is run),
+ * Returns FOT_E_INVALID for bad arguments or amplitudes (nothing is run), FOT_E_UNSUPPORTED
+ * (nothing is run) if an eps of the schedule needs the block-normalised Gibbs factor at an n whose
+ * exponent table does not fit in LDS (32- and 16-bit types with n > 4096),
  * FOT_E_NONFINITE if a positive-mass potential overflowed (outputs undefined, the plan
  * stays usable), FOT_E_RANGE if the operand type could not represent the products at this
  * eps (outputs written but inaccurate; see FOT_E_RANGE), FOT_E_HIP on a runtime error. */

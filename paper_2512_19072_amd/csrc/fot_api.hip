@@ -294,6 +294,21 @@ struct Ops {
     }
   }
 
+  // Every eps of a schedule must be runnable: one that needs the block-normalised Lambda needs its
+  // exponent table to fit in LDS.
+  static fot_status check_schedule(fot_plan_s* p, const std::vector<double>& e, int iters) {
+    for (int t = 0; t < iters; ++t)
+      if (lam_ln(p, e[t]) && !p->ln_ok) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "fot_solve: at eps %.3g and n %d Lambda needs its block exponents, whose table does not fit "
+                      "in LDS with this operand type (use FOT_F64)",
+                      e[t], p->n);
+        return fail(FOT_E_UNSUPPORTED, msg);
+      }
+    return FOT_OK;
+  }
+
   static fot_status fill_lambda(fot_plan_s* p, double eps, bool /*unused*/) {
     if (lam_ln(p, eps)) {
       if (p->t32)
@@ -444,16 +459,9 @@ struct Ops {
   static fot_status loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
     const long long plane = (long long)p->plane;
     const int B = p->B;
-    for (int t = 0; t < iters; ++t)
-      if (lam_ln(p, e[t]) && !p->ln_ok) {
-        char msg[200];
-        std::snprintf(msg, sizeof msg,
-                      "fot_solve: at eps %.3g and n %d Lambda needs its block exponents, whose table does not fit "
-                      "in LDS with this operand type (use FOT_F64)",
-                      e[t], p->n);
-        return fail(FOT_E_UNSUPPORTED, msg);
-      }
-    fot_status s = prep(p, p->psi, e[0]);
+    fot_status s = check_schedule(p, e, iters);
+    if (s != FOT_OK) return s;
+    s = prep(p, p->psi, e[0]);
     if (s != FOT_OK) return s;
     for (int t = 0; t < iters; ++t) {
       const double ep = e[t];
@@ -1222,6 +1230,12 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   if (warm_start && !p->has_state) return fail(FOT_E_STATE, "fot_solve: warm start without potentials");
   std::vector<double> e(iters);
   for (int t = 0; t < iters; ++t) e[t] = eps[n_eps == 1 ? 0 : t];
+  if (!p->cfot) {
+    const fot_status sc = dispatch(p->prec, [&](auto tag) -> fot_status {
+      return Ops<decltype(tag)>::check_schedule(p, e, iters);
+    });
+    if (sc != FOT_OK) return sc;
+  }
   const int n = p->n, np = p->np, B = p->B;
   p->prof_used = 0;
   p->tape_valid = false;

@@ -347,6 +347,24 @@ def test_range_loss_is_reported():
     assert st64 == F.FOT_OK and rep64.err_b[0] < 1e-12
 
 
+def test_small_eps_beyond_the_lds_table_is_unsupported():
+    """At n = 8192 the block-normalised Gibbs factor's exponent table no longer fits in LDS beside
+    the 64 x 64-tile stage buffers: a 32-bit solve at an eps that needs it returns
+    FOT_E_UNSUPPORTED before launching anything, and names FOT_F64."""
+    import torch
+    from paper_2512_19072_amd import fot as F
+    n = 8192
+    _say("case: n=8192 f32 eps=1e-4 (table beyond LDS)")
+    plan = F.Plan(n, 1, "f32", max_iters=1)
+    g = torch.ones((n, n), dtype=torch.float64, device="cuda")
+    G = torch.ones((1, n, n), dtype=torch.float64, device="cuda")
+    _, _, st = plan.solve(g, G, 1e-4, 1, check=False)
+    msg = F.fot_last_error()
+    plan.close()
+    assert st == F.FOT_E_UNSUPPORTED, st
+    assert "FOT_F64" in msg, msg
+
+
 @pytest.mark.parametrize("n,prec,eps", [(256, "f64", 2e-4), (320, "f32", 1e-3), (256, "bf16x3", 1e-3),
                                         (512, "f32", 2e-4), (1024, "f32", 2e-4), (1024, "bf16", 2e-4),
                                         (1024, "bf16x3", 2e-4)])
