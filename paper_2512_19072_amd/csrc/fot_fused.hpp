@@ -309,7 +309,8 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   // K stages [k_lo, k_lo + nks) whose Lambda block can be nonzero for this tile: Lambda is the
   // B operand of pass 1 (its rows are the output columns) and the A operand of pass 2 (rows =
   // output rows), and its entries vanish in the operand type beyond the band.  The skipped
-  // stages would only add exact zeros, so the result is the same as with all stages.
+  // stages would only add exact zeros, so the result is the same as with all stages (LN form: the
+  // band is FP64's, and a skipped block would add at most 2^-1070 of its row's reference).
   constexpr int KPS = FROWB / (int)sizeof(T);      // K values per stage
   int k_lo = 0, nks = p.nk;
   if (p.band < n) {
