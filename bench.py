@@ -119,7 +119,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-iters", type=int, default=200, help="oracle iterations in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -196,6 +196,12 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec0],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[prec0], 4),
                      "traffic": measured_traffic(prec0),
+                     # the same launches against HBM: algorithmic bytes (n^2 (12 + 2 s) per launch,
+                     # Lambda cache-resident) and, when counted, the HBM-side bytes
+                     "hbm_frac_algorithmic": round(alg_bytes_per_launch(n, prec0) / (ms_gemm * 1e-3) / 1e9
+                                                   / HBM_PEAK_GBS, 4),
+                     "hbm_frac_counted": (round(measured_traffic(prec0) / (ms_gemm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                          if measured_traffic(prec0) else None),
                      "kernel": "fot::k_fused (both passes of a half-step: per-axis contraction "
                                "with its fused epilogue, 2 n_p^3 flop per launch)",
                      "avg_launch_us": round(ms_gemm * 1e3, 3),
