@@ -134,8 +134,8 @@ def main():
                          "and one 256 MiB device-to-device copy whose bytes calibrate the counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the FOT solve is measured on one "
-              "MI355X; multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py: one GPU only: the FOT solve is measured on one MI355X (sharding across "
+              "GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

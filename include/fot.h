@@ -41,7 +41,7 @@ typedef enum {
   FOT_E_HIP = 3,         /* a HIP runtime call failed */
   FOT_E_NONFINITE = 4,   /* a potential of a positive-mass pixel became non-finite */
   FOT_E_STATE = 5,       /* call order violated (e.g. backward without a taped solve) */
-  FOT_E_UNSUPPORTED = 6, /* option not available in this build (or, from fot_solve, an eps that
+  FOT_E_UNSUPPORTED = 6, /* option not available in this library (or, from fot_solve, an eps that
                             needs the block-normalised Gibbs factor at an n whose exponent
                             table does not fit in LDS: n > 4096 with 32- and 16-bit types) */
   FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the final plan's column
