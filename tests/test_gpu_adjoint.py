@@ -70,15 +70,16 @@ def test_backward_annealed_f64():
     assert np.max(np.abs(got[0] - ref)) / np.max(np.abs(ref)) < 1e-9
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
-def test_checkpoint_interval_is_bit_invariant(prec):
+@pytest.mark.parametrize("prec,eps", [("f32", 2e-2), ("bf16x3", 2e-2), ("f32", 2e-3)])
+def test_checkpoint_interval_is_bit_invariant(prec, eps):
     """The replayed segments reproduce the forward iterations bit for bit whatever the operand
-    type, so the gradient does not depend on the checkpoint interval."""
+    type, so the gradient does not depend on the checkpoint interval (at eps = 2e-3 the FP32
+    operands use the block-normalised Gibbs factor, in the forward solve and in the replays)."""
     n, B, T = 40, 2, 12
     g, Gs = _case(n, B, 5)
     rng = np.random.default_rng(6)
     dphi = rng.standard_normal((B, n, n))
-    outs = [_gpu_grad(g, Gs, 2e-2, T, k, prec, [1.0, 0.5], dphi) for k in (1, 5, 12)]
+    outs = [_gpu_grad(g, Gs, eps, T, k, prec, [1.0, 0.5], dphi) for k in (1, 5, 12)]
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
