@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--cfot-run", action="store_true",
                     help="profiling aid: only the headline workload's solves with cFOT (FP64 FFT convolutions), "
                          "graph-replayed and then kernel by kernel, and one JSON line of their rates")
+    ap.add_argument("--eps", type=float, default=None,
+                    help="profiling aid: run the headline workload at this eps instead of its own (the "
+                         "config then names it); e.g. the paper's 2e-4")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware-counter passes: two solves launched kernel by kernel "
                          "and one 256 MiB device-to-device copy whose bytes calibrate the counters")
@@ -146,6 +149,8 @@ def main():
 
     wl = W.workload(1)
     n, iters, eps = wl.n, wl.iters, float(wl.eps[0])
+    if args.eps is not None:
+        eps = float(args.eps)
     g, G = wl.images()
     if args.pmc_run:
         run_variant(F, W, torch, args.precision, g, G, eps, iters, 1, 1, profile=False, graph=False)
