@@ -188,6 +188,14 @@ def main():
     flop = 2.0 * n ** 3
     achieved = flop / (ms_gemm * 1e-3) / 1e12
     ms_iter0 = float(np.median([r.ms_iterations for r in reps])) / iters
+    # device memory of one plan of the headline solve (its O(n^2) workspace: FP64 state, the
+    # operands, the FP64 read-out buffers), measured as the drop in free device memory
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    mplan = F.Plan(n, 1, prec0, max_iters=iters)
+    torch.cuda.synchronize()
+    plan_mib = (free0 - torch.cuda.mem_get_info()[0]) / 2 ** 20
+    mplan.close()
     log(f"bench: {prec0} {value:.1f} Mpx.it/s, {ms_per_step:.2f} ms/step, fused kernel {ms_gemm * 1e3:.1f} us "
         f"({achieved:.1f} TFLOP/s), iteration loop {ms_iter0 * 1e3:.1f} us/it, final err_a {reps[-1].err_a[0]:.3e}")
 
@@ -216,6 +224,7 @@ def main():
                                f"{args.steps} steps launched kernel by kernel "
                                f"({1e3 * el_prof / args.steps:.2f} ms/step)"},
         "final_err_a": float(reps[-1].err_a[0]),
+        "plan_device_mib": round(plan_mib, 1),
     }
 
     if not args.no_variants:
