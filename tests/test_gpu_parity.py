@@ -115,6 +115,42 @@ def test_small_and_large_tile_configurations_agree(prec):
     assert all(np.array_equal(four["psi"][0], four["psi"][b]) for b in range(1, 4))
 
 
+@pytest.mark.parametrize("n,prec", [(600, "f32"), (700, "f32"), (700, "bf16")])
+def test_ragged_sizes_around_the_tile_threshold(n, prec):
+    """Ragged sizes on both sides of the tile-size choice: 600^2 pads to 640 (100 tiles of 64 x 64,
+    under half of the CUs: 32 x 32 tiles), 700^2 to 768 (144 tiles: 64 x 64).  Two-Gaussian
+    workload, eps 5e-3, against the oracle."""
+    g, G = W.twogauss_to_shapes(n)
+    G = G if G.ndim == 2 else G[0]
+    T = 40
+    _say(f"case: ragged around the tile threshold n={n} {prec}")
+    gpu = run_gpu(g, G, 5e-3, T, prec)
+    ref = O.solve_sep(g, G, 5e-3, T)
+    e = compare(gpu, ref, g, G, precision=prec)
+    _say({k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in e.items()})
+    tol = {"f32": 1e-6, "bf16": 1e-3}[prec]
+    for k in ("f", "psi", "phase"):
+        assert e[k] < tol, (k, e[k])
+    assert e["dual"] < tol
+
+
+def test_batch_at_the_papers_eps():
+    """Two targets at eps = 2e-4 on 512^2 in FP32: small-grid tiles, the block-normalised Gibbs
+    factor (shared by the batch) and per-target operands together, each against the oracle."""
+    n, T, eps = 512, 40, 2e-4
+    g, G1 = W.twogauss_to_shapes(n)
+    G1 = G1 if G1.ndim == 2 else G1[0]
+    G2 = np.ascontiguousarray(G1[::-1, :])
+    Gs = np.stack([G1, G2])
+    _say("case: batch of 2 at eps 2e-4, n=512 f32")
+    gpu = run_gpu(g, Gs, eps, T, "f32")
+    for b in range(2):
+        ref = O.solve_sep(g, Gs[b], eps, T)
+        e = compare(gpu, ref, g, Gs[b], b_index=b, precision="f32")
+        _say(b, {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in e.items()})
+        assert e["f"] < 1e-6 and e["psi"] < 1e-6 and e["phase"] < 1e-6, (b, e)
+
+
 def test_deterministic_and_warm_start():
     """Two solves are bit-identical; 30 + 30 warm-started iterations equal 60 iterations."""
     from paper_2512_19072_amd import fot as F
