@@ -77,7 +77,7 @@ enum {
                             practice of running a fixed number of iterations without a loss,
                             Sec. 3 after Algorithm 1): err_*_history is filled with NaN; the
                             potentials, phase and final report values are bit-identical */
-  FOT_FLAG_CFOT = 8      /* cFOT (Sec. 3, convolutional speedup, Eq. 11): apply Lambda . X .
+  FOT_FLAG_CFOT = 8,     /* cFOT (Sec. 3, convolutional speedup, Eq. 11): apply Lambda . X .
                             Lambda in the iterations as two 1-D linear convolutions with
                             lambda_j = exp(-j^2 / (2 n^2 eps)) by FP64 FFTs of length N =
                             2^ceil(log2(2n - 1)), O(n^2 log n) per half-step instead of the
@@ -89,6 +89,14 @@ enum {
                             largest lose accuracy: at small eps fot_solve may return
                             FOT_E_NONFINITE, or FOT_E_RANGE when the final column-marginal L1
                             exceeds 1e-6 */
+  FOT_FLAG_SMALL_TILES = 16 /* run the iteration kernels on 32 x 32 output tiles, with operands
+                            normalised in 32-wide instead of 64-wide blocks.  fot_plan chooses
+                            these tiles by itself when 64 x 64 tiles would occupy at most half of
+                            the GPU's compute units (small grids); on larger grids the flag
+                            trades speed (about 1.3x the time per iteration at 1024 x 1024) for
+                            range: the 32- and 16-bit operand types then reach about half the
+                            eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian 1024 x 1024
+                            workload).  No effect with FOT_FLAG_CFOT */
 };
 
 typedef struct {

@@ -985,7 +985,7 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   if (d.precision < FOT_F64 || d.precision > FOT_BF16X3) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
-  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT))
+  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES))
     return fail(FOT_E_INVALID, "fot_plan: unknown flag bits");
   int cN = 0;
   if (d.flags & FOT_FLAG_CFOT) {
@@ -1026,7 +1026,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
     return bail(fail(FOT_E_HIP, "fot_plan: cannot query the device"));
-  p->t32 = 2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
+  p->t32 = (d.flags & FOT_FLAG_SMALL_TILES) ||
+           2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
   const int tbm = p->t32 ? Ops<float>::GS::BM : Ops<float>::GC::BM;
   const int tbn = p->t32 ? Ops<float>::GS::BN : Ops<float>::GC::BN;
   // one marginal-error partial per output tile of the fused pass-2 kernel
@@ -1344,7 +1345,8 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
                                 "convolutions lost the small values at eps %.3g (use the matrix-product "
                                 "contraction or a larger eps)"
                               : "fot_solve: target %d: final column-marginal L1 %.3g exceeds %.0e: the Gibbs "
-                                "products underflowed in the operand type at eps %.3g (use FOT_F64 or a larger eps)",
+                                "products underflowed in the operand type at eps %.3g (FOT_FLAG_SMALL_TILES "
+                                "reaches about half the eps; otherwise use FOT_F64 or a larger eps)",
                       b, err_b, bound, e[iters - 1]);
         return fail(FOT_E_RANGE, msg);
       }

@@ -24,6 +24,7 @@ FOT_FLAG_PROFILE = 1
 FOT_FLAG_NO_GRAPH = 2
 FOT_FLAG_NO_HISTORY = 4
 FOT_FLAG_CFOT = 8
+FOT_FLAG_SMALL_TILES = 16
 PRECISIONS = {"f64": FOT_F64, "f32": FOT_F32, "bf16": FOT_BF16, "f16": FOT_F16, "bf16x3": FOT_BF16X3}
 STATUS_NAMES = {0: "FOT_OK", 1: "FOT_E_INVALID", 2: "FOT_E_NOMEM", 3: "FOT_E_HIP", 4: "FOT_E_NONFINITE",
                 5: "FOT_E_STATE", 6: "FOT_E_UNSUPPORTED", 7: "FOT_E_RANGE"}
@@ -230,12 +231,13 @@ class Plan:
 
     def __init__(self, n: int, batch: int = 1, precision="f32", max_iters: int = 1000,
                  checkpoint_every: int = 0, profile: bool = False, graph: bool = True, history: bool = True,
-                 cfot: bool = False):
+                 cfot: bool = False, small_tiles: bool = False):
         self.n, self.batch, self.precision = n, batch, precision
         self.max_iters = max_iters
         self.checkpoint_every = checkpoint_every
         flags = ((FOT_FLAG_PROFILE if profile else 0) | (0 if graph else FOT_FLAG_NO_GRAPH)
-                 | (0 if history else FOT_FLAG_NO_HISTORY) | (FOT_FLAG_CFOT if cfot else 0))
+                 | (0 if history else FOT_FLAG_NO_HISTORY) | (FOT_FLAG_CFOT if cfot else 0)
+                 | (FOT_FLAG_SMALL_TILES if small_tiles else 0))
         self.handle = fot_plan(n, batch, precision, max_iters, checkpoint_every, flags)
 
     def solve(self, g, G, eps, iters: int, warm_start: bool = False, phase: bool = True, check: bool = True,

@@ -383,6 +383,31 @@ def test_range_loss_is_reported():
     assert st64 == F.FOT_OK and rep64.err_b[0] < 1e-12
 
 
+def test_small_tiles_flag_reaches_half_the_eps():
+    """FOT_FLAG_SMALL_TILES runs a 1024^2 solve on 32 x 32 tiles with 32-wide operand blocks: at
+    eps = 1e-4, where 64-wide blocks lose FP32's range (test_range_loss_is_reported), FP32
+    operands then match the oracle."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n, T, eps = 1024, 40, 1e-4
+    g, G = W.twogauss_to_shapes(n)
+    G = G if G.ndim == 2 else G[0]
+    _say("case: FOT_FLAG_SMALL_TILES n=1024 f32 eps=1e-4")
+    plan = F.Plan(n, 1, "f32", max_iters=T, small_tiles=True)
+    _, rep, st = plan.solve(to_dev(g), to_dev(G[None]), eps, T, check=False)
+    f, psi = plan.potentials()
+    plan.close()
+    assert st == F.FOT_OK, (st, F.fot_last_error())
+    gpu = dict(f=f.cpu().numpy(), psi=psi.cpu().numpy(), phase=None, rep=rep)
+    ref = O.solve_sep(g, G, eps, T)
+    from tests.parity_util import gauge_rel
+    a = g ** 2 / np.sum(g ** 2)
+    b = G ** 2 / np.sum(G ** 2)
+    ef, ep = gauge_rel(gpu["f"][0], ref.f, a), gauge_rel(gpu["psi"][0], ref.psi, b)
+    _say(f"f {ef:.2e} psi {ep:.2e} err_b {rep.err_b[0]:.2e}")
+    assert ef < 1e-6 and ep < 1e-6, (ef, ep)
+
+
 def test_small_eps_beyond_the_lds_table_is_unsupported():
     """At n = 8192 the block-normalised Gibbs factor's exponent table no longer fits in LDS beside
     the 64 x 64-tile stage buffers: a 32-bit solve at an eps that needs it returns
