@@ -58,8 +58,8 @@ typedef enum {
  * Every operand is stored in blocks normalised by an integer power of two that the products
  * rescale exactly in FP64; the Gibbs factor too once eps is small enough that it has entries
  * below the type's range.  The 32-bit and 16-bit types then reach down to eps = 2e-4 on
- * 1024 x 1024 grids (the paper's regime; FP16 to about 1e-3); below that FOT_E_RANGE reports
- * the loss and FOT_F64 applies.
+ * 1024 x 1024 grids (the paper's regime; 1e-4 with FOT_FLAG_SMALL_TILES; FP16 to about 1e-3);
+ * below that FOT_E_RANGE reports the loss and FOT_F64 applies.
  * FOT_BF16X3 splits each operand value v into hi = bf16(v) and lo = bf16(v - hi) and forms
  * every product as hi.hi + hi.lo + lo.hi with three BF16 matrix-core operations: about 16
  * significant bits per operand (between BF16's 8 and FP32's 24) at BF16 matrix-core rates,
