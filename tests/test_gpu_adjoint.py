@@ -59,6 +59,22 @@ def test_backward_matches_oracle_f64(with_phase):
     assert got[0, 2, 3] == 0.0
 
 
+def test_backward_f32_forward_block_normalised_lambda():
+    """FP32 forward at an eps where Lambda is stored block-normalised (n = 64, eps = 2e-3: Lambda's
+    raw FP32 band is 43 px), FP64 reverse sweep, against the oracle's FP64 gradient: within the
+    FP32 target of 1e-4 of the gradient's largest magnitude."""
+    n, B, T, k, eps = 64, 1, 12, 4, 2e-3
+    g, Gs = _case(n, B, 7, zero=False)
+    rng = np.random.default_rng(8)
+    dphi = rng.standard_normal((B, n, n))
+    _say(f"case: backward f32 forward n={n} eps={eps} T={T} k={k}")
+    got = _gpu_grad(g, Gs, eps, T, k, "f32", [0.9], dphi)
+    ref = O.grad_G(g, Gs[0], eps, T, 0.9, dphi[0])
+    err = np.max(np.abs(got[0] - ref)) / np.max(np.abs(ref))
+    _say(f"rel err {err:.2e}")
+    assert err < 1e-4, err
+
+
 def test_backward_annealed_f64():
     n, B, T, k = 20, 1, 9, 4
     g, Gs = _case(n, B, 3, zero=False)
