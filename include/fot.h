@@ -47,7 +47,7 @@ typedef enum {
   FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the final plan's column
                             marginal error (fot_report.err_b, evaluated in FP64) exceeds what the
                             operand type allows (FP64 1e-8, FP32 1e-5, BF16x3 1e-4,
-                            BF16/FP16 2e-2): at this
+                            BF16 2e-2, FP16 5e-4): at this
                             eps the Gibbs products underflowed in the operand type; use FOT_F64
                             or a larger eps */
 } fot_status;

@@ -426,6 +426,29 @@ def test_small_eps_beyond_the_lds_table_is_unsupported():
     assert "FOT_F64" in msg, msg
 
 
+def test_f16_systematic_underflow_is_reported():
+    """FP16's exponent range is narrow: on a 65^2 grid at eps = 5e-3 the operand blocks (32 wide:
+    half the grid) span more than it holds, the lost small values bias the fixed point (potentials
+    off by several 1e-3) while the last update's column marginal stays near 8e-4, and FP16's own
+    bound (5e-4) reports FOT_E_RANGE; at eps = 1e-2 the same grid matches the oracle to 1e-3."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n, T = 65, 30
+    g, G = W.twogauss_to_shapes(n)
+    G = G if G.ndim == 2 else G[0]
+    gd, Gd = to_dev(g), to_dev(G[None])
+    _say("case: f16 n=65 eps=5e-3 (range loss) and 1e-2")
+    plan = F.Plan(n, 1, "f16", max_iters=T)
+    _, rep, st = plan.solve(gd, Gd, 5e-3, T, check=False)
+    assert st == F.FOT_E_RANGE and rep.err_b[0] > 5e-4, (st, rep.err_b[0])
+    plan.close()
+    gpu = run_gpu(g, G, 1e-2, T, "f16")
+    ref = O.solve_sep(g, G, 1e-2, T)
+    e = compare(gpu, ref, g, G, precision="f16")
+    _say(e)
+    assert e["f"] < 1e-3 and e["psi"] < 1e-3 and e["phase"] < 1e-3, e
+
+
 @pytest.mark.parametrize("n,prec,eps", [(256, "f64", 2e-4), (320, "f32", 1e-3), (256, "bf16x3", 1e-3),
                                         (512, "f32", 2e-4), (1024, "f32", 2e-4), (1024, "bf16", 2e-4),
                                         (1024, "bf16x3", 2e-4)])
