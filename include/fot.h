@@ -47,7 +47,9 @@ typedef enum {
   FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the final plan's column
                             marginal error (fot_report.err_b, evaluated in FP64) exceeds what the
                             operand type allows (FP64 1e-8, FP32 1e-5, BF16x3 1e-4,
-                            BF16 2e-2, FP16 5e-4): at this
+                            BF16 5e-3, FP16 5e-4; the larger of the final column-
+                            marginal L1 and a check of the u-direction products at the final
+                            potentials, fot_report.err_products): at this
                             eps the Gibbs products underflowed in the operand type; use FOT_F64
                             or a larger eps */
 } fot_status;
@@ -127,6 +129,11 @@ typedef struct {
   double ms_contract;     /* FOT_FLAG_PROFILE: summed HIP-event time of the iteration kernels */
   int n_contract;         /* FOT_FLAG_PROFILE: number of iteration-kernel launches timed */
   int graph;              /* 1 if the iteration loop was replayed as a HIP graph */
+  double* err_products;   /* [batch] or NULL: the check of the operand type's products at the
+                             final potentials against FP64, the larger of err_b and the row-
+                             marginal L1 that one more u-update would make through its products
+                             alone; FOT_E_RANGE when it exceeds the type's bound (0 beyond err_b
+                             for FOT_F64 and cFOT, whose products need no probe) */
 } fot_report;
 
 /* Create a plan: validates desc, allocates O(n^2 * batch) device workspace once (no later

@@ -641,18 +641,21 @@ __global__ __launch_bounds__(NTHREADS) void k_lnS_raw(const double* S, const uns
 // ------------------------------------------------------------------ read-out (Eq. 9-10)
 // Inputs per pixel p = (j,k): S, Sx, Sy, Scx, Scy are the pass-2 outputs for V_T divided by
 // exp(m'_k); lnS_prev = ln(Lambda V_{T-1} Lambda) from the final u-update.  u/a = 1/S_prev.
+// lnS_probe (or nullptr) = ln S(V_T) as the loop's operand type forms it.
 // Writes Tx, Ty and per-block partial sums of: |row mass - a|, row mass, transport cost,
-// <f,a> + <psi,b>, column-mass error.
+// <f,a> + <psi,b>, column-mass error, and sum a |S_probe / S - 1| (the row-marginal error that
+// one more u-update in the operand type would make through its products alone).
 template <typename ZT>
 __global__ __launch_bounds__(NTHREADS) void k_readout(
     const ZT* S, const ZT* Sx, const ZT* Sy, const ZT* Scx, const ZT* Scy, const unsigned* colkey,
     const double* lnS_prev, const double* lna, const double* lnb, const double* f, const double* psi,
-    const double* lnSp, int n, int np, double eps, double* Tx, double* Ty, double* part /*[5][batch][blocks]*/) {
+    const double* lnSp, const double* lnS_probe, int n, int np, double eps, double* Tx, double* Ty,
+    double* part /*[6][batch][blocks]*/) {
   __shared__ double red[4];
   const int bz = blockIdx.y;
   const size_t plane = (size_t)np * np;
   const int nblk = gridDim.x;
-  double acc[5] = {0, 0, 0, 0, 0};
+  double acc[6] = {0, 0, 0, 0, 0, 0};
   const double inv_eps = 1.0 / eps;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
        idx += (size_t)nblk * blockDim.x) {
@@ -670,6 +673,12 @@ __global__ __launch_bounds__(NTHREADS) void k_readout(
       acc[1] += rm;
       acc[2] += a * scale * ((double)Scx[o] + (double)Scy[o]);
       acc[3] += a * f[o];
+      if (lnS_probe) {
+        // ln S(V_T) in FP64 against the operand type's value (both -inf: no term)
+        const double lnS64 = key_to_shift(colkey[(size_t)bz * np + k]) + log((double)S[o]);
+        const double d = lnS_probe[o] - lnS64;
+        acc[5] += (d == d) ? a * fabs(expm1(d)) : 0.0;
+      }
     }
     const double lb = lnb[o];
     const double cmass = exp(psi[o] * inv_eps + lnSp[o]);
@@ -681,7 +690,7 @@ __global__ __launch_bounds__(NTHREADS) void k_readout(
     }
   }
   const int B = gridDim.y;
-  for (int q = 0; q < 5; ++q) {
+  for (int q = 0; q < 6; ++q) {
     const double s = block_sum(acc[q], red);
     if (threadIdx.x == 0) part[((size_t)q * B + bz) * nblk + blockIdx.x] = s;
   }

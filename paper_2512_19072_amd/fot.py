@@ -42,7 +42,8 @@ class fot_report(ctypes.Structure):
     _fields_ = [("err_a", _dp), ("err_b", _dp), ("dual", _dp), ("transport_cost", _dp),
                 ("err_a_history", _dp), ("err_b_history", _dp), ("iters_done", ctypes.c_int),
                 ("nonfinite", ctypes.c_int), ("ms_total", ctypes.c_double), ("ms_iterations", ctypes.c_double),
-                ("ms_contract", ctypes.c_double), ("n_contract", ctypes.c_int), ("graph", ctypes.c_int)]
+                ("ms_contract", ctypes.c_double), ("n_contract", ctypes.c_int), ("graph", ctypes.c_int),
+                ("err_products", _dp)]
 
 
 class FOTError(RuntimeError):
@@ -213,6 +214,7 @@ class Report:
         self.transport_cost = np.zeros(batch)
         self.err_a_history = np.zeros((iters, batch))
         self.err_b_history = np.zeros((iters, batch))
+        self.err_products = np.zeros(batch)
         self.raw = fot_report()
         r = self.raw
         r.err_a = self.err_a.ctypes.data_as(_dp)
@@ -221,6 +223,7 @@ class Report:
         r.transport_cost = self.transport_cost.ctypes.data_as(_dp)
         r.err_a_history = self.err_a_history.ctypes.data_as(_dp)
         r.err_b_history = self.err_b_history.ctypes.data_as(_dp)
+        r.err_products = self.err_products.ctypes.data_as(_dp)
 
     def __getattr__(self, name):
         return getattr(self.__dict__["raw"], name)

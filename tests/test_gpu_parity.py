@@ -426,6 +426,39 @@ def test_small_eps_beyond_the_lds_table_is_unsupported():
     assert "FOT_F64" in msg, msg
 
 
+def test_u_direction_range_loss_is_reported():
+    """On 129^2 at eps = 5e-4 (32-wide blocks: a quarter of the grid) the potential psi comes to
+    span more than FP32 holds within one block from about the 27th iteration, so the u-updates'
+    products lose values and the iterates drift from the oracle's while the last V-update's
+    column marginal stays at 1e-7.  The end-of-solve probe (one more u-direction product in the
+    operand type against FP64) reports FOT_E_RANGE at 30 iterations; at 20 the solve is exact."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n, eps = 129, 5e-4
+    g, G = W.twogauss_to_shapes(n)
+    G = G if G.ndim == 2 else G[0]
+    gd, Gd = to_dev(g), to_dev(G[None])
+    _say("case: u-direction range loss n=129 f32 eps=5e-4, 30 and 20 iterations")
+    plan = F.Plan(n, 1, "f32", max_iters=30)
+    _, rep, st = plan.solve(gd, Gd, eps, 30, check=False)
+    msg = F.fot_last_error()
+    assert st == F.FOT_E_RANGE, (st, rep.err_b[0])
+    assert "use FOT_F64" in msg, msg
+    assert rep.err_b[0] < 1e-5          # the column marginal alone would not have shown it
+    plan.close()
+    # the same drift in BF16 operands: its product check reads about 1e-2, above BF16's 5e-3
+    plan = F.Plan(n, 1, "bf16", max_iters=30)
+    _, rep16, st16 = plan.solve(gd, Gd, eps, 30, check=False)
+    plan.close()
+    _say(f"bf16 err_b {rep16.err_b[0]:.2e} products {rep16.err_products[0]:.2e}")
+    assert st16 == F.FOT_E_RANGE and rep16.err_products[0] > 5e-3, (st16, rep16.err_products[0])
+    gpu = run_gpu(g, G, eps, 20, "f32")
+    ref = O.solve_sep(g, G, eps, 20)
+    e = compare(gpu, ref, g, G, precision="f32")
+    _say(e)
+    assert e["f"] < 1e-6 and e["psi"] < 1e-6, e
+
+
 def test_f16_systematic_underflow_is_reported():
     """FP16's exponent range is narrow: on a 65^2 grid at eps = 5e-3 the operand blocks (32 wide:
     half the grid) span more than it holds, the lost small values bias the fixed point (potentials
