@@ -44,14 +44,13 @@ typedef enum {
   FOT_E_UNSUPPORTED = 6, /* option not available in this library (or, from fot_solve, an eps that
                             needs the block-normalised Gibbs factor at an n whose exponent
                             table does not fit in LDS: n > 4096 with 32- and 16-bit types) */
-  FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the final plan's column
-                            marginal error (fot_report.err_b, evaluated in FP64) exceeds what the
-                            operand type allows (FP64 1e-8, FP32 1e-5, BF16x3 1e-4,
-                            BF16 5e-3, FP16 5e-4; the larger of the final column-
-                            marginal L1 and a check of the u-direction products at the final
-                            potentials, fot_report.err_products): at this
-                            eps the Gibbs products underflowed in the operand type; use FOT_F64
-                            or a larger eps */
+  FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the check of the
+                            operand type's products (fot_report.err_products: the larger of the
+                            final column-marginal L1, evaluated in FP64, and the discrepancy of
+                            one more u-direction product at the final potentials against FP64)
+                            exceeds what the type allows (FP64 1e-8, FP32 1e-5, BF16x3 1e-4,
+                            BF16 5e-3, FP16 5e-4): at this eps the Gibbs products lost values
+                            below the operand type's range; use FOT_F64 or a larger eps */
 } fot_status;
 
 /* Element type of the contraction operands (the Gibbs factor and the shifted exponentials
