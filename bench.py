@@ -320,10 +320,11 @@ def main():
             log(f"bench: {prec} without per-iteration errors {nh[prec]['value']:.1f} Mpx.it/s, "
                 f"{nh[prec]['us_per_iteration']:.1f} us/it")
         out["no_history"] = nh
-        out["equal_l1_protocol"] = ("err(T) = FP64 read-out row-marginal L1 after fresh solves of T = 5..iters "
-                                    "step 5; E = 1.1 x the lowest error all of f32, bf16, f16 reach (bf16x3: "
-                                    "the lowest error both f32 and bf16x3 reach); speedup = "
-                                    "T_f32(E) t_it,f32 / (T(E) t_it)")
+        out["equal_l1_protocol"] = ("err(T) = FP64 read-out row-marginal L1 after fresh solves of T = 1..60, "
+                                    "then every 5th T up to iters; for each operand type p, E_p = 1.1 x "
+                                    "max(lowest err of p, err of f32 at T = iters); speedup = "
+                                    "T_f32(E_p) t_it,f32 / (T_p(E_p) t_it,p), t_it from graph-replayed solves "
+                                    "with per-iteration errors")
 
     if not args.no_variants:
         # A10: the reverse mode on its own workload (512^2, 8 targets, FP32 operands, 100
