@@ -381,6 +381,9 @@ def test_range_loss_is_reported():
     plan.close()
     _say(f"err_b f32 {rep.err_b[0]:.3e}, f64 {rep64.err_b[0]:.3e}")
     assert st64 == F.FOT_OK and rep64.err_b[0] < 1e-12
+    # the product check is the larger of err_b and the u-direction probe (none in FP64)
+    assert not rep.err_products[0] < rep.err_b[0], (rep.err_products[0], rep.err_b[0])
+    assert rep64.err_products[0] == rep64.err_b[0]
 
 
 def test_small_tiles_flag_reaches_half_the_eps():
