@@ -320,6 +320,15 @@ def main():
             log(f"bench: {prec} without per-iteration errors {nh[prec]['value']:.1f} Mpx.it/s, "
                 f"{nh[prec]['us_per_iteration']:.1f} us/it")
         out["no_history"] = nh
+        # the equal-L1 comparison again with these iteration times: err(T) above is the read-out's,
+        # which a solve without the per-iteration history reports just the same
+        for prec in ("bf16", "bf16x3"):
+            eq = variants.get(prec, {}).get("equal_marginal_l1")
+            if eq and eq["iters"] and eq["iters_f32"]:
+                eq["speedup_vs_f32_no_history"] = round(
+                    (eq["iters_f32"] * nh["f32"]["us_per_iteration"]) / (eq["iters"] * nh[prec]["us_per_iteration"]), 3)
+                log(f"bench: {prec} equal-L1 speedup without per-iteration errors "
+                    f"{eq['speedup_vs_f32_no_history']}")
         out["equal_l1_protocol"] = ("err(T) = FP64 read-out row-marginal L1 after fresh solves of T = 1..60, "
                                     "then every 5th T up to iters; for each operand type p, E_p = 1.1 x "
                                     "max(lowest err of p, err of f32 at T = iters); speedup = "
