@@ -329,6 +329,49 @@ def main():
                     (eq["iters_f32"] * nh["f32"]["us_per_iteration"]) / (eq["iters"] * nh[prec]["us_per_iteration"]), 3)
                 log(f"bench: {prec} equal-L1 speedup without per-iteration errors "
                     f"{eq['speedup_vs_f32_no_history']}")
+        # A precision schedule through the C ABI: T - k BF16 iterations, then the potentials into an
+        # FP32 plan (fot_potentials) and k FP32 iterations from them (warm start).  Its err(T) is
+        # the FP32 solve's read-out; its time to a level E counts iterations at the no-history
+        # iteration times of each type, like the comparison above (the chained calls' extra
+        # read-out and copies would not exist inside one solve).
+        dev = torch.device("cuda", 0)
+        gd = torch.tensor(g, dtype=torch.float64, device=dev)
+        Gd = torch.tensor(G, dtype=torch.float64, device=dev)
+        p16 = F.Plan(n, G.shape[0], "bf16", max_iters=iters)
+        p32 = F.Plan(n, G.shape[0], "f32", max_iters=iters)
+
+        def chained(T, k):
+            p16.solve(gd, Gd, eps, T - k, phase=False)
+            f_, psi_ = p16.potentials()
+            p32.set_potentials(f_, psi_)
+            return float(p32.solve(gd, Gd, eps, k, warm_start=True, phase=False)[1].err_a[0])
+
+        t16, t32 = nh["bf16"]["us_per_iteration"], nh["f32"]["us_per_iteration"]
+        sched = {}
+        for name, lev in (("1.1x_bf16_floor", levels.get("bf16")),
+                          ("f32_err_at_T40", float(curves["f32"][grid.index(40)]) if 40 in grid else None)):
+            T32 = reach(curves["f32"], lev) if lev else None
+            if not T32:
+                continue
+            best = None
+            for k in (1, 2, 3):
+                for T in range(max(k + 1, T32 - 4), T32 + 6):
+                    e_ = chained(T, k)
+                    if e_ <= lev:
+                        us = (T - k) * t16 + k * t32
+                        if best is None or us < best["us"]:
+                            best = {"T": T, "k_f32": k, "err_a": e_, "us": round(us, 1)}
+                        break
+            if best:
+                best["err_level"] = lev
+                best["iters_f32"] = T32
+                best["speedup_vs_f32"] = round(T32 * t32 / best["us"], 3)
+                sched[name] = best
+                log(f"bench: bf16 then f32 at E = {lev:.2e}: {best['T'] - best['k_f32']} + {best['k_f32']} "
+                    f"iterations (f32 alone {T32}), {best['speedup_vs_f32']}x f32")
+        p16.close()
+        p32.close()
+        out["precision_schedule_bf16_f32"] = sched
         out["equal_l1_protocol"] = ("err(T) = FP64 read-out row-marginal L1 after fresh solves of T = 1..60, "
                                     "then every 5th T up to iters; for each operand type p, E_p = 1.1 x "
                                     "max(lowest err of p, err of f32 at T = iters); speedup = "
