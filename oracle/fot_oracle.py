@@ -30,9 +30,16 @@ Two levels:
 O1 ``solve_dense``  the definition written out: the full N x N cost and log-sum-exp over
                     every pixel pair (N = n^2; practical for n <= 32).
 O2 ``solve_sep``    the same iteration with every N x N contraction replaced by the exact
-                    separable identity K.V = Lambda . V . Lambda (Sec. 3, Eq. 7), evaluated
-                    in FP64 with a max shift per row before the first product and per column
-                    before the second.  Practical at n = 1024.
+                    separable identity K.V = Lambda . V . Lambda (Sec. 3, Eq. 7).  Each of
+                    the two per-axis products is, by definition, a log-sum-exp over one index
+                    of ln Lambda = -H / eps plus the log-operand; ``sep_log_apply_exact``
+                    writes exactly that (chunked, no shifted exponentials, any range).  The
+                    fast evaluation ``sep_log_apply`` shifts by the row maximum before the
+                    first product and by the column maximum before the second (two FP64
+                    matrix products), and checks its own sums: a shifted sum below e^-690
+                    could be missing terms lost to FP64 underflow (each off by less than
+                    e^-744 after the shift), so each line holding one is re-evaluated by
+                    its exact log-sum-exp (with weights, the whole contraction is).  The shifted form is practical at n = 1024.
 
 Readings of the paper used here (where it is silent, garbled or ambiguous):
 
@@ -59,7 +66,8 @@ import numpy as np
 
 __all__ = [
     "normalise", "log_intensity", "coords", "cost_1d", "gibbs_1d", "cost_dense", "eps_schedule",
-    "solve_dense", "solve_sep", "sep_log_apply", "integrate", "integrate_adjoint",
+    "solve_dense", "solve_sep", "sep_log_apply", "sep_log_apply_exact", "log_gibbs_1d", "integrate",
+    "integrate_adjoint",
     "grad_G", "lp_ot_cost", "entropy", "primal_entropic", "Result",
 ]
 
@@ -107,6 +115,11 @@ def cost_1d(n: int) -> np.ndarray:
 def gibbs_1d(n: int, eps: float) -> np.ndarray:
     """Lambda_jK = exp(-H_jK / eps) (Sec. 3, after Eq. 6)."""
     return np.exp(-cost_1d(n) / eps)
+
+
+def log_gibbs_1d(n: int, eps: float) -> np.ndarray:
+    """ln Lambda_jK = -H_jK / eps, without forming Lambda (no underflow at any eps)."""
+    return -cost_1d(n) / eps
 
 
 def cost_dense(n: int) -> np.ndarray:
@@ -293,36 +306,137 @@ def _signed_exp_scale(W: np.ndarray, shift: np.ndarray) -> np.ndarray:
         return np.sign(W) * np.exp(np.log(np.abs(W)) + shift)
 
 
-def sep_log_apply(X: np.ndarray, lam_left: np.ndarray, lam_right: np.ndarray,
-                  weights=()):
-    """Separable contraction of exp(X) with per-line shifts, in FP64.
+# A factor in a weight entry: None (Lambda) or "H" (Lambda o H, the cost-weighted factor).
+def _factor(n: int, eps: float, kind):
+    lam = gibbs_1d(n, eps)
+    if kind is None:
+        return lam
+    if kind == "H":
+        return lam * cost_1d(n)
+    raise ValueError("factor must be None (Lambda) or 'H' (Lambda o H)")
 
-    Returns ``(lnS, ratios)`` where ``lnS = ln(lam_left . exp(X) . lam_right)`` and, for every
-    entry ``(left, right, w)`` of ``weights``, ``ratios[i] = (left . (exp(X) * w) . right) /
-    (lam_left . exp(X) . lam_right)`` (``w`` may be None for 1 and ``left``/``right`` None for
-    the lam matrices).  The first product contracts the second index of X; the second product
-    contracts the first.  Row and column shifts come from the positive product, so signed
-    weights stay well scaled.
+
+_LSE_CHUNK = 1 << 22     # elements of one [rows][M][k] block of the exact log-sum-exp
+
+
+def _lse_pass(X: np.ndarray, lnR: np.ndarray, weights=()):
+    """One per-axis product in log form, by its definition.
+
+    ``out[L, k] = ln sum_M exp(X[L, M] + lnR[M, k])`` as a log-sum-exp over M for every
+    (L, k): the largest term of each sum is taken out before exponentiating, so the terms
+    that matter never underflow, whatever the range of X and lnR.  An all -inf sum gives
+    -inf.  For each ``(w, h)`` in ``weights`` (either may be None for 1) also returns the
+    weighted mean ``sum_M exp(X[L,M] + lnR[M,k] - out[L,k]) w[L,M] h[M,k]`` (0 where the
+    sum is empty)."""
+    rows, m = X.shape
+    k = lnR.shape[1]
+    out = np.empty((rows, k))
+    avgs = [np.zeros((rows, k)) for _ in weights]
+    step = max(1, _LSE_CHUNK // (m * k))
+    for r0 in range(0, rows, step):
+        r1 = min(rows, r0 + step)
+        T = X[r0:r1, :, None] + lnR[None, :, :]            # [rows][M][k]
+        mx = T.max(axis=1)                                  # largest term of each sum
+        safe = np.where(np.isfinite(mx), mx, 0.0)
+        E = np.exp(T - safe[:, None, :])
+        tot = E.sum(axis=1)
+        with np.errstate(divide="ignore"):
+            out[r0:r1] = np.log(tot) + safe
+        for i, (w, h) in enumerate(weights):
+            Ew = E if w is None else E * w[r0:r1, :, None]
+            if h is not None:
+                Ew = Ew * h[None, :, :]
+            with np.errstate(invalid="ignore", divide="ignore"):
+                avgs[i][r0:r1] = np.where(tot > 0, Ew.sum(axis=1) / np.where(tot > 0, tot, 1.0), 0.0)
+    return out, avgs
+
+
+def sep_log_apply_exact(X: np.ndarray, eps: float, weights=()):
+    """The separable contraction of exp(X) by its definition, at any range (Sec. 3, Eq. 7).
+
+    ``lnS[j, k] = ln sum_L sum_M Lambda[j, L] exp(X[L, M]) Lambda[M, k]`` is evaluated as two
+    exact per-axis log-sum-exps over ln Lambda = -H / eps: first over M (the second index of
+    X), then over L.  For each ``(left, right, w)`` in ``weights`` (``left``/``right``: None
+    for Lambda or "H" for Lambda o H; ``w`` an [n][n] weight on X or None) the ratio
+    ``(left . (exp(X) * w) . right) / (Lambda . exp(X) . Lambda)`` is returned, formed as a
+    weighted mean of each pass's terms (so signed weights cancel at the size of the sum)."""
+    n = X.shape[0]
+    H = cost_1d(n)
+    lnL = log_gibbs_1d(n, eps)
+    for left, right, _ in weights:
+        if left not in (None, "H") or right not in (None, "H"):
+            raise ValueError("factor must be None (Lambda) or 'H' (Lambda o H)")
+    # first product: W[L, k] = sum_M exp(X[L, M]) right[M, k]
+    lnW, mean1 = _lse_pass(X, lnL, [(w, H if right == "H" else None) for _, right, w in weights])
+    # second product: S[j, k] = sum_L left[j, L] W[L, k], written as (W^T . left^T)[k, j]
+    # (Lambda and H are symmetric)
+    lnST, mean2 = _lse_pass(lnW.T, lnL, [(r.T, H if left == "H" else None)
+                                         for r, (left, _, _) in zip(mean1, weights)])
+    return lnST.T, [r.T for r in mean2]
+
+
+# ln of the smallest shifted sum that the row- and column-shifted products accept.  After the
+# shifts every factor is at most 1, and a term that FP64 cannot hold exactly (a factor or the
+# product below the smallest normal number, e^-708) is off by less than 2^-1074 (about e^-744)
+# in absolute value, or is lost only if it was below that; n such terms change a sum of at least
+# e^-690 by less than 2 n e^-54 relative, far below FP64 rounding for any grid here.  A line
+# with a smaller sum is evaluated by the exact log-sum-exp.
+SHIFT_SAFE_LOG = -690.0
+
+
+def _unsafe_lines(sums: np.ndarray, mass: np.ndarray, axis: int) -> np.ndarray:
+    """Lines (along ``axis``) with mass holding a shifted sum below e^SHIFT_SAFE_LOG."""
+    with np.errstate(divide="ignore"):
+        low = np.log(sums) < SHIFT_SAFE_LOG
+    return mass & np.any(low, axis=axis)
+
+
+def sep_log_apply(X: np.ndarray, eps: float, weights=()):
+    """Separable contraction of exp(X) in FP64, with per-line shifts (checked against range).
+
+    Returns ``(lnS, ratios)`` with ``lnS = ln(Lambda . exp(X) . Lambda)`` and, for every entry
+    ``(left, right, w)`` of ``weights``, ``ratios[i] = (left . (exp(X) * w) . right) /
+    (Lambda . exp(X) . Lambda)`` (``left``/``right``: None for Lambda or "H" for Lambda o H;
+    ``w`` may be None for 1).  The first product contracts the second index of X after
+    shifting each row by its maximum; the second contracts the first index after shifting
+    each column by its maximum.  Row and column shifts come from the positive product, so
+    signed weights stay well scaled.  A line with mass whose shifted sums fall below
+    e^SHIFT_SAFE_LOG somewhere could be missing terms lost to underflow: such a row of the
+    first product (column of the second) is evaluated by its exact log-sum-exp instead, and
+    with weights the whole contraction goes to ``sep_log_apply_exact``.
     """
+    n = X.shape[0]
+    lam = gibbs_1d(n, eps)
+    lnL = log_gibbs_1d(n, eps)
     m = _rowmax(X)                                            # per-row shift
     A = np.exp(X - m[:, None])                                # in [0, 1]
-    W = A @ lam_right
+    W = A @ lam
+    row_mass = np.any(X > -np.inf, axis=1)
+    bad_rows = _unsafe_lines(W, row_mass, axis=1)
+    if weights and np.any(bad_rows):
+        return sep_log_apply_exact(X, eps, weights)
     with np.errstate(divide="ignore"):
-        Z = m[:, None] + np.log(W)                            # ln(exp(X) . lam_right)
+        Z = m[:, None] + np.log(W)                            # ln(exp(X) . Lambda)
+    if np.any(bad_rows):
+        Z[bad_rows] = _lse_pass(X[bad_rows], lnL)[0]
     m2 = _colmax(Z)                                           # per-column shift
     B = np.exp(Z - m2[None, :])
-    S = lam_left @ B
+    S = lam @ B
     with np.errstate(divide="ignore"):
         lnS = m2[None, :] + np.log(S)
+    bad_cols = _unsafe_lines(S, np.full(n, np.any(row_mass)), axis=0)
+    if np.any(bad_cols):
+        if weights:
+            return sep_log_apply_exact(X, eps, weights)
+        # S[j, k] = sum_L Lambda[j, L] exp(Z[L, k]), as (Z^T . Lambda)[k, j] in log form
+        lnS[:, bad_cols] = _lse_pass(Z[:, bad_cols].T, lnL)[0].T
     ratios = []
     for left, right, w in weights:
-        left = lam_left if left is None else left
-        right = lam_right if right is None else right
         Aw = A if w is None else A * w
-        Ww = Aw @ right
+        Ww = Aw @ _factor(n, eps, right)
         Bw = _signed_exp_scale(Ww, m[:, None] - m2[None, :])
         with np.errstate(invalid="ignore", divide="ignore"):
-            ratios.append(np.where(S > 0, (left @ Bw) / S, 0.0))
+            ratios.append(np.where(S > 0, (_factor(n, eps, left) @ Bw) / S, 0.0))
     return lnS, ratios
 
 
@@ -347,17 +461,13 @@ def _solve_sep_one(a, b, la, lb, e, iters, keep_tape=False, start=None):
     dual_hist = np.zeros(iters)
     tape = [] if keep_tape else None
     am, bm = la > NEG_INF, lb > NEG_INF
-    lam = None
-    lam_eps = None
     psi_prev = psi
     lnS = None
     lnSp = None
     for t in range(iters):
         ep = e[t]
-        if lam_eps != ep:
-            lam, lam_eps = gibbs_1d(n, ep), ep
         # Eq. 7 in log form: f = eps (ln a - ln(Lambda . V . Lambda))
-        lnS, _ = sep_log_apply(psi / ep, lam, lam)
+        lnS, _ = sep_log_apply(psi / ep, ep)
         f_new = np.where(am, ep * (la - lnS), NEG_INF)
         # marginal identity: row sums of the entering plan are u_old S = a exp((f_old - f_new)/eps)
         # where a > 0, and exp(f_old/eps + ln S) where a = 0 (nonzero only while f_old is finite)
@@ -366,7 +476,7 @@ def _solve_sep_one(a, b, la, lb, e, iters, keep_tape=False, start=None):
                              + np.sum(np.exp(f[~am] / ep + lnS[~am])))
         f = f_new
         # Eq. 8 in log form
-        lnSp, _ = sep_log_apply(f / ep, lam, lam)
+        lnSp, _ = sep_log_apply(f / ep, ep)
         psi_new = np.where(bm, ep * (lb - lnSp), NEG_INF)
         with np.errstate(invalid="ignore", over="ignore"):
             err_b_hist[t] = (_mass_minus_marginal(b[bm], lb[bm], (psi[bm] - psi_new[bm]) / ep)
@@ -382,18 +492,16 @@ def _solve_sep_one(a, b, la, lb, e, iters, keep_tape=False, start=None):
 def _readout(a, b, la, lb, f, psi, lnS_last, lnSp_last, ep):
     """Final plan statistics and Eq. 9-10 for potentials (f, psi) = (f_T, psi_T)."""
     n = a.shape[0]
-    lam = gibbs_1d(n, ep)
-    lamH = lam * cost_1d(n)
     X = coords(n)
     am = la > NEG_INF
     ones = np.ones((n, n))
     # ln(Lambda.V_T.Lambda) and the ratios needed for Eq. 9-10 and for <Gamma, c>
     lnS_T, (rx, ry, rcx, rcy) = sep_log_apply(
-        psi / ep, lam, lam,
+        psi / ep, ep,
         weights=[(None, None, X[:, None] * ones),      # Lambda diag(X) V Lambda
                  (None, None, X[None, :] * ones),      # Lambda V diag(Y) Lambda
-                 (lamH, None, None),                   # (Lambda o H) V Lambda
-                 (None, lamH, None)])                  # Lambda V (Lambda o H)
+                 ("H", None, None),                    # (Lambda o H) V Lambda
+                 (None, "H", None)])                   # Lambda V (Lambda o H)
     # u / a = 1 / S(V_{T-1});  Eq. 9: Tx = u (Lambda diag(X) V Lambda) / a
     scale = np.exp(lnS_T - lnS_last)                   # S(V_T) / S(V_{T-1})
     Tx = rx * scale
@@ -433,11 +541,11 @@ def solve_sep(g: np.ndarray, G: np.ndarray, eps, iters: int, start=None):
 # reverse mode through the unrolled iterations (O2 form)
 # ----------------------------------------------------------------------------------
 
-def _Kt_weighted(h_over_eps, w, lam):
+def _Kt_weighted(h_over_eps, w, eps):
     """Return (ln K^T e^{h/eps}, ratio) with ratio = K^T(e^{h/eps} w) / K^T e^{h/eps}.
 
     K is symmetric and separable, so K^T = K = Lambda (.) Lambda."""
-    lnK, (r,) = sep_log_apply(h_over_eps, lam, lam, weights=[(None, None, w)])
+    lnK, (r,) = sep_log_apply(h_over_eps, eps, weights=[(None, None, w)])
     return lnK, r
 
 
@@ -470,8 +578,7 @@ def grad_G(g: np.ndarray, G: np.ndarray, eps, iters: int, dD: float,
     psibar_prev = np.zeros((n, n))
     if dphi is not None:
         epT = e[-1]
-        lam = gibbs_1d(n, epT)
-        lnS_T, (rx, ry) = sep_log_apply(psi / epT, lam, lam,
+        lnS_T, (rx, ry) = sep_log_apply(psi / epT, epT,
                                         weights=[(None, None, X[:, None] * ones),
                                                  (None, None, X[None, :] * ones)])
         scale = np.exp(lnS_T - lnS)
@@ -479,27 +586,26 @@ def grad_G(g: np.ndarray, G: np.ndarray, eps, iters: int, dD: float,
         Txb, Tyb = integrate_adjoint(np.asarray(dphi, dtype=np.float64), a)
         # psibar_T += (V_T / eps) [X K^T(Txb / S_{T-1}) + Y K^T(Tyb / S_{T-1})]
         h = -lnS                                          # 1/S_{T-1} = e^{h}
-        lnKx, rxb = _Kt_weighted(h, Txb, lam)
-        lnKy, ryb = _Kt_weighted(h, Tyb, lam)
+        lnKx, rxb = _Kt_weighted(h, Txb, epT)
+        lnKy, ryb = _Kt_weighted(h, Tyb, epT)
         VT = psi / epT
         psibar = psibar + np.where(
             bm, (X[:, None] * np.exp(VT + lnKx) * rxb + X[None, :] * np.exp(VT + lnKy) * ryb) / epT,
             0.0)
         # psibar_{T-1} += -(V_{T-1}/eps) K^T((Txb Tx + Tyb Ty) / S_{T-1})
-        lnKp, rp = _Kt_weighted(h, Txb * Tx + Tyb * Ty, lam)
+        lnKp, rp = _Kt_weighted(h, Txb * Tx + Tyb * Ty, epT)
         psibar_prev = np.where(bm, -np.exp(psi_prev / epT + lnKp) * rp / epT, 0.0)
 
     for t in range(iters - 1, -1, -1):
         f_t, psi_t, lnS_t, lnSp_t, ep = tape[t]
-        lam = gibbs_1d(n, ep)
         # V-update reverse: psi_t = eps (lb - lnS'(f_t))
         lbbar += np.where(bm, ep * psibar, 0.0)
-        lnK, r = _Kt_weighted(-lnSp_t, psibar, lam)
+        lnK, r = _Kt_weighted(-lnSp_t, psibar, ep)
         fbar = fbar + np.where(am, -np.exp(f_t / ep + lnK) * r, 0.0)
         # u-update reverse: f_t = eps (la - lnS(psi_{t-1}))
         psi_tm1 = tape[t - 1][1] if t > 0 else None
         if t > 0:
-            lnK2, r2 = _Kt_weighted(-lnS_t, fbar, lam)
+            lnK2, r2 = _Kt_weighted(-lnS_t, fbar, ep)
             psibar = np.where(bm, -np.exp(psi_tm1 / ep + lnK2) * r2, 0.0)
             if t == iters - 1:
                 psibar = psibar + psibar_prev

@@ -35,8 +35,8 @@ def _wrong_log_intensity(amp):
 _real_sep = F.sep_log_apply
 
 
-def _transposed_sep(X, lam_left, lam_right, weights=()):
-    return _real_sep(X.T, lam_left, lam_right, weights)          # transposed operand
+def _transposed_sep(X, eps, weights=()):
+    return _real_sep(X.T, eps, weights)                          # transposed operand
 
 
 _real_integrate = F.integrate
@@ -60,6 +60,8 @@ CASES = [
     ("log_intensity", _wrong_log_intensity, [P.test_two_by_two_first_iteration]),
     ("normalise", _wrong_normalise, [P.test_two_by_two_first_iteration]),
     ("sep_log_apply", _transposed_sep, [lambda: P.test_dense_equals_separable(7, 1e-2)]),
+    # the range guard of the shifted products removed (never fall back to the exact form)
+    ("SHIFT_SAFE_LOG", -np.inf, [P.test_guarded_oracle_stays_finite_past_the_shifted_range]),
     ("integrate", _wrong_step_integrate, [P.test_phase_matches_continuum_closed_form]),
     ("integrate_adjoint", _no_mean_adjoint, [P.test_integrate_adjoint_is_transpose]),
 ]

@@ -3,7 +3,9 @@
 The paper prints no worked values of u, V, phi or the marginal errors, so the oracle is
 pinned by identities, closed forms, brute force and invariants instead:
 
-* dense definition == separable evaluation (Sec. 3, Eq. 6-8 with the factorisation after Eq. 6)
+* dense definition == separable evaluation (Sec. 3, Eq. 6-8 with the factorisation after Eq. 6),
+  also where the potentials span more than FP64's exponential range (the exact log-sum-exp
+  form of each per-axis product, against a four-index brute force and against the dense run)
 * product measures reduce to two independent one-dimensional Sinkhorn runs
 * Gaussian -> Gaussian has a closed-form entropic barycentric map (affine)
 * linear-programming brute force bounds the entropic transport cost (Sec. 2, Eq. 2)
@@ -278,8 +280,7 @@ def test_phase_matches_continuum_closed_form():
     g, G = W.gauss_to_disk(n)
     G = np.sqrt(np.maximum(G * G, 1e-6))
     r = O.solve_sep(g, G, eps, 300)
-    lam = O.gibbs_1d(n, eps)
-    lnS, _ = O.sep_log_apply(r.psi / eps, lam, lam)
+    lnS, _ = O.sep_log_apply(r.psi / eps, eps)
     j, k = W.grid(n)
     closed = n * (((j - c) ** 2 + (k - c) ** 2) / (2.0 * n * n) + eps * lnS)
     a = O.normalise(g)
@@ -426,3 +427,124 @@ def test_history_with_tiny_marginals_matches_dense():
     assert np.all(np.isfinite(sep.err_a_hist)) and np.all(np.isfinite(sep.err_b_hist))
     np.testing.assert_allclose(sep.err_a_hist, dense.err_a_hist, rtol=1e-9, atol=1e-15)
     np.testing.assert_allclose(sep.err_b_hist, dense.err_b_hist, rtol=1e-9, atol=1e-15)
+
+
+# ---------------------------------------------------------------- P1 beyond the shifted range
+def _brute_contraction(X, eps, weights):
+    """ln sum_{L,M} Lambda[j,L] e^{X[L,M]} Lambda[M,k] by one log-sum-exp over the full
+    four-index tensor, and the weighted ratios as means over the same terms: the contraction
+    of Eq. 7 written out with no factorisation at all (tiny n only)."""
+    n = X.shape[0]
+    H = O.cost_1d(n)
+    E = (-H / eps)[:, :, None, None] + X[None, :, :, None] + (-H / eps)[None, None, :, :]  # [j,L,M,k]
+    mx = E.max(axis=(1, 2))
+    safe = np.where(np.isfinite(mx), mx, 0.0)
+    P = np.exp(E - safe[:, None, None, :])
+    tot = P.sum(axis=(1, 2))
+    with np.errstate(divide="ignore"):
+        lnS = np.log(tot) + safe
+    ratios = []
+    for left, right, w in weights:
+        Q = P.copy()
+        if left == "H":
+            Q = Q * H[:, :, None, None]
+        if w is not None:
+            Q = Q * w[None, :, :, None]
+        if right == "H":
+            Q = Q * H[None, None, :, :]
+        ratios.append(Q.sum(axis=(1, 2)) / tot)
+    return lnS, ratios
+
+
+def test_exact_contraction_is_the_definition():
+    """Both evaluations of the separable contraction equal its four-index definition where the
+    operand spans 1000 nats (beyond FP64's exponential range) and Lambda's own range is larger;
+    the shifted form alone is far off there, so its guard must engage."""
+    n, eps = 7, 2e-4                              # ln Lambda reaches -H/eps = -36/(98 * 2e-4) = -1837
+    rng = np.random.default_rng(7)
+    # each row falls by about 1000 nats from its first to its last column: an output column
+    # near the last one is carried by operand entries that underflow after the row shift
+    X = -1000.0 * np.arange(n)[None, :] / (n - 1) + rng.uniform(-5.0, 5.0, (n, n))
+    X[2, :] = -np.inf                             # an empty row
+    X[4, 5] = -np.inf                             # an empty pixel
+    x = O.coords(n)
+    wts = [(None, None, x[:, None] * np.ones((n, n))), (None, None, x[None, :] * np.ones((n, n))),
+           ("H", None, None), (None, "H", None)]
+    lnS0, r0 = _brute_contraction(X, eps, wts)
+    assert np.all(np.isfinite(lnS0))
+    for fn in (O.sep_log_apply_exact, O.sep_log_apply):
+        lnS, rs = fn(X, eps, wts)
+        assert np.max(np.abs(lnS - lnS0)) <= 1e-14 * np.max(np.abs(lnS0))
+        for r, q in zip(rs, r0):
+            assert np.max(np.abs(r - q)) <= 1e-13 * max(1.0, np.max(np.abs(q)))
+        lnS, _ = fn(X, eps)
+        assert np.max(np.abs(lnS - lnS0)) <= 1e-14 * np.max(np.abs(lnS0))
+    # without its guard the shifted form loses whole rows to underflow here
+    saved = O.fot_oracle.SHIFT_SAFE_LOG
+    O.fot_oracle.SHIFT_SAFE_LOG = -np.inf
+    try:
+        with np.errstate(all="ignore"):
+            lnS, _ = O.sep_log_apply(X, eps)
+    finally:
+        O.fot_oracle.SHIFT_SAFE_LOG = saved
+    bad = ~np.isfinite(lnS) | (np.abs(lnS - lnS0) > 1e-6 * np.max(np.abs(lnS0)))
+    assert np.any(bad)
+
+
+def test_separable_equals_dense_beyond_shift_range(monkeypatch):
+    """O1 (the N x N log-sum-exp) and O2 agree iterate by iterate on a trajectory whose
+    potentials outgrow FP64's exponential range: 33 x 33, eps = 3e-5, 60 iterations.  The
+    per-line shifts alone turn non-finite there; O2 must have used the exact form."""
+    n, eps, T = 33, 3e-5, 60
+    g, G = W.twogauss_to_shapes(n)
+    exact_lines = []
+    real = O.fot_oracle._lse_pass
+    monkeypatch.setattr(O.fot_oracle, "_lse_pass",
+                        lambda X, lnR, weights=(): exact_lines.append(X.shape[0]) or real(X, lnR, weights))
+    r2 = O.solve_sep(g, G, eps, T)
+    assert sum(exact_lines) > 0, "the trajectory never left the shifted form's range"
+    monkeypatch.undo()
+    r1 = O.solve_dense(g, G, eps, T)
+    a, b = O.normalise(g), O.normalise(G)
+    for x1, x2, w in ((r1.f, r2.f, a), (r1.psi, r2.psi, b)):
+        m = np.isfinite(x1)
+        assert np.array_equal(m, np.isfinite(x2))
+        d = (x1[m] - np.sum(w[m] * x1[m])) - (x2[m] - np.sum(w[m] * x2[m]))
+        assert np.max(np.abs(d)) <= 1e-13 * np.ptp(x1[m])
+    np.testing.assert_allclose(r2.err_a_hist, r1.err_a_hist, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(r2.dual_hist, r1.dual_hist, rtol=1e-12, atol=1e-14)
+    assert abs(r2.dual - r1.dual) <= 1e-13 * abs(r1.dual)
+    assert abs(r2.err_a - r1.err_a) <= 1e-12
+    assert np.max(np.abs(r2.phase - r1.phase)) <= 1e-11 * np.ptp(r1.phase)
+
+
+@pytest.mark.parametrize("eps,T", [(2e-4, 200), (1e-4, 100)])
+def test_shifted_form_is_exact_where_it_is_used(eps, T):
+    """Along the two-Gaussian trajectories at 257 x 257 the fast evaluation equals the exact
+    log-sum-exp to a few FP64 ulps in both directions (ln S reaches 400-570 nats here)."""
+    n = 257
+    g, G = W.twogauss_to_shapes(n)
+    r = O.solve_sep(g, G, eps, T)
+    for X in (r.psi / eps, r.f / eps):
+        l1, _ = O.sep_log_apply(X, eps)
+        l2, _ = O.sep_log_apply_exact(X, eps)
+        m = np.isfinite(l2)
+        assert np.array_equal(m, np.isfinite(l1))
+        assert np.max(np.abs(l1[m] - l2[m])) <= 1e-14 * np.max(np.abs(l2[m]))
+
+
+def test_guarded_oracle_stays_finite_past_the_shifted_range():
+    """257 x 257, eps = 1e-4, 240 iterations: from about iteration 130 some rows of psi/eps span
+    more than 700 nats, and the per-line shifts alone turn non-finite at iteration 234.  With
+    the exact form where it is needed the run stays finite and keeps the invariants: the dual
+    value never decreases (block coordinate ascent), the column marginal after a V-update is
+    exact, and the final row-marginal error is below the first iteration's."""
+    n, eps, T = 257, 1e-4, 240
+    g, G = W.twogauss_to_shapes(n)
+    r = O.solve_sep(g, G, eps, T)
+    a = O.normalise(g)
+    for x in (r.f, r.psi, r.phase):
+        assert np.all(np.isfinite(x[a > 0] if x is r.f else x))
+    assert np.all(np.diff(r.dual_hist) >= -1e-14 * np.abs(r.dual_hist[1:]))
+    assert r.err_b < 1e-12
+    assert r.err_a < 0.5 * r.err_a_hist[0]
