@@ -240,17 +240,13 @@ __device__ __forceinline__ void vm_wait() {
 }
 
 // 16-byte global -> LDS load of this lane's source; the wave's 64 lanes fill the 1 KB at
-// lds_dst (wave-uniform) in lane order.  Written in assembly so that the compiler does not
-// track it (it would wait for every such load before any LDS read): completion is awaited
-// explicitly (vm_wait) before the workgroup barrier that publishes the stage, so the next stage
-// stays in flight while the current one is read.
-__device__ __forceinline__ void dma16(const void* src, const unsigned char* lds_dst) {
-  const unsigned lds_addr =
-      __builtin_amdgcn_readfirstlane((unsigned)(size_t)(const __attribute__((address_space(3))) unsigned char*)lds_dst);
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-               :
-               : "v"(src), "s"(lds_addr)
-               : "memory", "m0");
+// lds_dst (wave-uniform) in lane order (the compiler sets M0 to the LDS base).  The stage buffers
+// are distinct LDS objects, so the compiler's wait insertion does not make reads of one buffer wait
+// for loads into another: completion is awaited explicitly (vm_wait) before the workgroup barrier
+// that publishes a stage, and the next stage stays in flight while the current one is read.
+__device__ __forceinline__ void dma16(const void* src, unsigned char* lds_dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)lds_dst, 16, 0, 0);
 }
 
 constexpr int FRAG_AHEAD = 2;  // LDS fragment reads issued this many MMA steps ahead
