@@ -7,9 +7,10 @@ and the final reductions), with inputs resident in HBM.  The value is whole-job 
 Mpixel.iterations/s = n^2 * iterations * steps / elapsed.
 
 Also reported:
-  roofline      the contraction GEMM kernel (the dominant kernel): 2 n^3 flop per launch over
+  roofline      the dominant kernel, pass 2 of the fused half-step: 2 n^3 flop per launch over
                 its HIP-event-timed average launch duration on the solve's stream, against the
-                FP32 MFMA peak (157.3 TFLOP/s).
+                FP32 MFMA peak (157.3 TFLOP/s); pass 1 and the two-pass mean beside it, and the
+                committed rocprofv3 trace's figures for the same kernels.
   cpu_baseline  the FP64 oracle (separable form) timed on the host cores on a bounded sample
                 of the same workload (first `--cpu-iters` iterations).
   variants      the same workload with BF16 and FP16 operands, and the BF16/FP32 speed ratio
@@ -48,6 +49,7 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_fused_twogauss_1024.md")
+TRACE_FILE = os.path.join(ROOT, "profiles", "k_fused_{prec}_twogauss_1024.md")
 
 
 # the sources the fused half-step kernels are compiled from (their launch code in fot_api.hip
@@ -82,14 +84,43 @@ def measured_traffic(prec):
     return round(float(blob[prec]["bytes_per_launch"]))
 
 
+def traced_passes(prec):
+    """Per-pass average launch times of the fused kernels from the committed rocprofv3 kernel-trace
+    summary of this workload (its json block), or None when it is missing or was taken on other
+    kernel sources."""
+    try:
+        with open(TRACE_FILE.format(prec=prec)) as fh:
+            text = fh.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(blob["pass1_avg_us"]), float(blob["pass2_avg_us"])
+
+
+def pass_times(reps):
+    """Mean HIP-event time (ms) of pass-1 and pass-2 launches over profiled solves: the launches
+    alternate pass 1, pass 2 (two per half-step)."""
+    import numpy as np
+    l1, l2 = [], []
+    for r in reps:
+        ms = np.asarray(r.ms_launches[:r.n_contract])
+        l1.append(ms[0::2])
+        l2.append(ms[1::2])
+    return float(np.mean(np.concatenate(l1))), float(np.mean(np.concatenate(l2)))
+
+
 def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True, graph=True, history=True,
-                cfot=False):
+                cfot=False, keep=None, tail=None, tail_iters=0):
+    """Time `steps` solves after `warmup`; returns (elapsed s, reports).  With a dict `keep`, the last
+    solve's potentials and phase of target 0 are copied into it (after the timed region)."""
     n = g.shape[-1]
     dev = torch.device("cuda", 0)
     gd = torch.tensor(g, dtype=torch.float64, device=dev)
     Gd = torch.tensor(G, dtype=torch.float64, device=dev)
     plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph, history=history,
-                  cfot=cfot)
+                  cfot=cfot, tail_precision=tail, tail_iters=tail_iters)
     phase = torch.empty((G.shape[0], n, n), dtype=torch.float64, device=dev)
     try:
         for _ in range(warmup):
@@ -109,10 +140,35 @@ def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile
             reps.append(rep)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        if keep is not None:
+            f_, psi_ = plan.potentials()
+            keep.update(f=f_[0].cpu().numpy(), psi=psi_[0].cpu().numpy(), phase=phase[0].cpu().numpy(),
+                        dual=float(reps[-1].dual[0]), cost=float(reps[-1].transport_cost[0]))
     finally:
         gc.enable()
         plan.close()
     return elapsed, reps
+
+
+def gauge_rel(x, ref, w):
+    """max |x - ref| / (max ref - min ref) over finite entries after removing each one's w-weighted
+    mean (potentials are defined up to (f + k, psi - k)); inf if the finite sets differ."""
+    import numpy as np
+    m = np.isfinite(ref)
+    if not np.array_equal(np.isfinite(x), m):
+        return float("inf")
+    xs = x[m] - np.sum(w[m] * x[m]) / np.sum(w[m])
+    rs = ref[m] - np.sum(w[m] * ref[m]) / np.sum(w[m])
+    return float(np.max(np.abs(xs - rs)) / np.ptp(rs))
+
+
+def errors_vs_oracle(out, ref, a, b):
+    """Range-normalised, gauge-fixed errors of one solve's outputs against the oracle's."""
+    import numpy as np
+    return {"f": gauge_rel(out["f"], ref.f, a), "psi": gauge_rel(out["psi"], ref.psi, b),
+            "phase": float(np.max(np.abs(out["phase"] - ref.phase)) / np.ptp(ref.phase)),
+            "dual": abs(out["dual"] - ref.dual) / abs(ref.dual),
+            "transport_cost": abs(out["cost"] - ref.cost) / abs(ref.cost)}
 
 
 def main():
@@ -176,8 +232,9 @@ def main():
     log(f"bench: workload {wl.name} n={n} iters={iters} eps={eps} {prec0}, steps={args.steps} warmup={args.warmup}")
     graph = not args.no_graph
     # timed region 1: the production launch path (graph replay of the iteration loop)
+    finals = {prec0: {}}
     elapsed, reps = run_variant(F, W, torch, args.precision, g, G, eps, iters, args.steps, args.warmup,
-                                profile=False, graph=graph)
+                                profile=False, graph=graph, keep=finals[prec0])
     ms_per_step = 1e3 * elapsed / args.steps
     value = n * n * iters * args.steps / elapsed / 1e6
     # timed region 2: the same steps launched kernel by kernel with HIP events around every
@@ -185,8 +242,12 @@ def main():
     el_prof, reps_prof = run_variant(F, W, torch, args.precision, g, G, eps, iters, args.steps, args.warmup,
                                      profile=True, graph=False)
     ms_gemm = sum(r.ms_contract for r in reps_prof) / max(1, sum(r.n_contract for r in reps_prof))
+    ms_p1, ms_p2 = pass_times(reps_prof)
     flop = 2.0 * n ** 3
-    achieved = flop / (ms_gemm * 1e-3) / 1e12
+    # the dominant kernel is pass 2 (the longer of the two launches of every half-step)
+    achieved = flop / (ms_p2 * 1e-3) / 1e12
+    achieved_mean = flop / (ms_gemm * 1e-3) / 1e12
+    traced = traced_passes(prec0)
     ms_iter0 = float(np.median([r.ms_iterations for r in reps])) / iters
     # device memory of one plan of the headline solve (its O(n^2) workspace: FP64 state, the
     # operands, the FP64 read-out buffers), measured as the drop in free device memory
@@ -196,8 +257,9 @@ def main():
     torch.cuda.synchronize()
     plan_mib = (free0 - torch.cuda.mem_get_info()[0]) / 2 ** 20
     mplan.close()
-    log(f"bench: {prec0} {value:.1f} Mpx.it/s, {ms_per_step:.2f} ms/step, fused kernel {ms_gemm * 1e3:.1f} us "
-        f"({achieved:.1f} TFLOP/s), iteration loop {ms_iter0 * 1e3:.1f} us/it, final err_a {reps[-1].err_a[0]:.3e}")
+    log(f"bench: {prec0} {value:.1f} Mpx.it/s, {ms_per_step:.2f} ms/step, fused kernel pass 1 {ms_p1 * 1e3:.2f} us, "
+        f"pass 2 {ms_p2 * 1e3:.2f} us ({achieved:.1f} TFLOP/s), iteration loop {ms_iter0 * 1e3:.1f} us/it, "
+        f"final err_a {reps[-1].err_a[0]:.3e}; trace {traced}")
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpixel·iter/s", "n_gpus": 1,
@@ -209,15 +271,27 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec0],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[prec0], 4),
                      "traffic": measured_traffic(prec0),
+                     "kernel": "fot::k_fused pass 2 (Lambda . Bt^T with the fused potential update, marginal-"
+                               "error partial and next operand; 2 n_p^3 flop per launch): the longer of the "
+                               "two launches of every half-step",
+                     "avg_launch_us": round(ms_p2 * 1e3, 3),
+                     "pass1_avg_launch_us": round(ms_p1 * 1e3, 3),
+                     "pass1_frac": round(flop / (ms_p1 * 1e-3) / 1e12 / PEAK_TFLOPS[prec0], 4),
+                     "two_pass_mean_frac": round(achieved_mean / PEAK_TFLOPS[prec0], 4),
+                     "trace": (None if traced is None else {
+                         "pass1_avg_us": traced[0], "pass2_avg_us": traced[1],
+                         "frac": round(flop / (traced[1] * 1e-6) / 1e12 / PEAK_TFLOPS[prec0], 4),
+                         "two_pass_mean_frac": round(flop / (0.5 * (traced[0] + traced[1]) * 1e-6) / 1e12
+                                                     / PEAK_TFLOPS[prec0], 4),
+                         "source": f"profiles/k_fused_{prec0}_twogauss_1024.md (rocprofv3 kernel trace of the "
+                                   "same command, on the current kernel sources)"}),
                      # the same launches against HBM: algorithmic bytes (n^2 (12 + 2 s) per launch,
                      # Lambda cache-resident) and, when counted, the HBM-side bytes
                      "hbm_frac_algorithmic": round(alg_bytes_per_launch(n, prec0) / (ms_gemm * 1e-3) / 1e9
                                                    / HBM_PEAK_GBS, 4),
                      "hbm_frac_counted": (round(measured_traffic(prec0) / (ms_gemm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                                           if measured_traffic(prec0) else None),
-                     "kernel": "fot::k_fused (both passes of a half-step: per-axis contraction "
-                               "with its fused epilogue, 2 n_p^3 flop per launch)",
-                     "avg_launch_us": round(ms_gemm * 1e3, 3),
+                     "hbm_note": "the HBM fractions and traffic are per launch over both passes (mean)",
                      "traffic_note": "HBM-side bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
                                      "mean of the two passes) from profiles/traffic_k_fused_twogauss_1024.md",
                      "timing": "HIP events around every fused-kernel launch over a second timed region of "
@@ -250,8 +324,9 @@ def main():
         for prec in ("f32", "bf16", "f16", "bf16x3"):
             if prec in per_prec:
                 continue
+            finals[prec] = {}
             el, rp = run_variant(F, W, torch, prec, g, G, eps, iters, args.steps, args.warmup,
-                                 profile=False, graph=graph)
+                                 profile=False, graph=graph, keep=finals[prec])
             _, rpp = run_variant(F, W, torch, prec, g, G, eps, iters, max(1, args.steps // 2), 1,
                                  profile=True, graph=False)
             per_prec[prec] = {"ms_it": float(np.median([r.ms_iterations for r in rp])) / iters,
@@ -329,24 +404,21 @@ def main():
                     (eq["iters_f32"] * nh["f32"]["us_per_iteration"]) / (eq["iters"] * nh[prec]["us_per_iteration"]), 3)
                 log(f"bench: {prec} equal-L1 speedup without per-iteration errors "
                     f"{eq['speedup_vs_f32_no_history']}")
-        # A precision schedule through the C ABI: T - k BF16 iterations, then the potentials into an
-        # FP32 plan (fot_potentials) and k FP32 iterations from them (warm start).  Its err(T) is
-        # the FP32 solve's read-out; its time to a level E counts iterations at the no-history
-        # iteration times of each type, like the comparison above (the chained calls' extra
-        # read-out and copies would not exist inside one solve).
+        # The precision schedule inside one solve (fot_plan_desc.tail_precision / tail_iters): T - k
+        # BF16 iterations, then k FP32 ones.  For each level E the smallest (T, k) whose read-out
+        # err_a reaches E is timed end to end as real solves, against FP32 solves of the iteration
+        # count FP32 needs for E; both without the per-iteration history (the read-out's err_a is
+        # what the comparison uses).  Times are the medians of the iteration loop's HIP-event time
+        # (and of the whole solve, read-out included) over repeated graph-replayed solves.
+        def timed(prec, T, tail=None, k=0, reps_=7):
+            el_, rp_ = run_variant(F, W, torch, prec, g, G, eps, T, reps_, 2, profile=False, graph=graph,
+                                   history=False, tail=tail, tail_iters=k)
+            return (float(np.median([r.ms_iterations for r in rp_])), float(np.median([r.ms_total for r in rp_])),
+                    float(rp_[-1].err_a[0]))
+
         dev = torch.device("cuda", 0)
         gd = torch.tensor(g, dtype=torch.float64, device=dev)
         Gd = torch.tensor(G, dtype=torch.float64, device=dev)
-        p16 = F.Plan(n, G.shape[0], "bf16", max_iters=iters)
-        p32 = F.Plan(n, G.shape[0], "f32", max_iters=iters)
-
-        def chained(T, k):
-            p16.solve(gd, Gd, eps, T - k, phase=False)
-            f_, psi_ = p16.potentials()
-            p32.set_potentials(f_, psi_)
-            return float(p32.solve(gd, Gd, eps, k, warm_start=True, phase=False)[1].err_a[0])
-
-        t16, t32 = nh["bf16"]["us_per_iteration"], nh["f32"]["us_per_iteration"]
         sched = {}
         for name, lev in (("1.1x_bf16_floor", levels.get("bf16")),
                           ("f32_err_at_T40", float(curves["f32"][grid.index(40)]) if 40 in grid else None)):
@@ -355,22 +427,29 @@ def main():
                 continue
             best = None
             for k in (1, 2, 3):
+                ps = F.Plan(n, G.shape[0], "bf16", max_iters=iters, tail_precision="f32", tail_iters=k)
+                found = None
                 for T in range(max(k + 1, T32 - 4), T32 + 6):
-                    e_ = chained(T, k)
-                    if e_ <= lev:
-                        us = (T - k) * t16 + k * t32
-                        if best is None or us < best["us"]:
-                            best = {"T": T, "k_f32": k, "err_a": e_, "us": round(us, 1)}
+                    if float(ps.solve(gd, Gd, eps, T, phase=False)[1].err_a[0]) <= lev:
+                        found = T
                         break
+                ps.close()
+                if found is None:
+                    continue
+                ms_it, ms_tot, e_ = timed("bf16", found, tail="f32", k=k)
+                if best is None or ms_it < best["ms_iterations"]:
+                    best = {"T": found, "k_f32": k, "err_a": e_, "ms_iterations": round(ms_it, 4),
+                            "ms_solve": round(ms_tot, 4)}
             if best:
-                best["err_level"] = lev
-                best["iters_f32"] = T32
-                best["speedup_vs_f32"] = round(T32 * t32 / best["us"], 3)
+                ms32, ms32_tot, e32 = timed("f32", T32)
+                best.update({"err_level": lev, "iters_f32": T32, "f32_ms_iterations": round(ms32, 4),
+                             "f32_ms_solve": round(ms32_tot, 4), "f32_err_a": e32,
+                             "speedup_vs_f32": round(ms32 / best["ms_iterations"], 3),
+                             "speedup_vs_f32_whole_solve": round(ms32_tot / best["ms_solve"], 3)})
                 sched[name] = best
-                log(f"bench: bf16 then f32 at E = {lev:.2e}: {best['T'] - best['k_f32']} + {best['k_f32']} "
-                    f"iterations (f32 alone {T32}), {best['speedup_vs_f32']}x f32")
-        p16.close()
-        p32.close()
+                log(f"bench: bf16 then f32 in one solve at E = {lev:.2e}: {best['T'] - best['k_f32']} + "
+                    f"{best['k_f32']} iterations in {best['ms_iterations']:.3f} ms against f32 alone {T32} in "
+                    f"{ms32:.3f} ms: {best['speedup_vs_f32']}x (whole solves {best['speedup_vs_f32_whole_solve']}x)")
         out["precision_schedule_bf16_f32"] = sched
         out["equal_l1_protocol"] = ("err(T) = FP64 read-out row-marginal L1 after fresh solves of T = 1..60, "
                                     "then every 5th T up to iters; for each operand type p, E_p = 1.1 x "
@@ -567,7 +646,7 @@ def main():
             cores = os.cpu_count()
         k = args.cpu_iters
         t0 = time.perf_counter()
-        oracle.solve_sep(g, G[0], eps, k)
+        ref_cpu = oracle.solve_sep(g, G[0], eps, k)
         t_cpu = time.perf_counter() - t0
         cpu_model = "unknown CPU"
         try:
@@ -594,6 +673,21 @@ def main():
         except ImportError:
             pass
         log(f"bench: cpu oracle {out['cpu_baseline']['value']} Mpx.it/s on {cores} threads ({t_cpu:.1f} s)")
+        # every operand type's final outputs against the oracle's (outside any timed region)
+        ref = ref_cpu if k == iters else oracle.solve_sep(g, G[0], eps, iters)
+        a_, b_ = oracle.normalise(g), oracle.normalise(G[0])
+        for prec, fin in finals.items():
+            if not fin:
+                continue
+            ev = {key: float(f"{val:.3e}") for key, val in errors_vs_oracle(fin, ref, a_, b_).items()}
+            if prec == prec0:
+                out["err_vs_oracle"] = ev
+            elif prec in out.get("variants", {}):
+                out["variants"][prec]["err_vs_oracle"] = ev
+            log(f"bench: {prec} against the oracle: {ev}")
+        out["err_vs_oracle_note"] = ("range-normalised, gauge-fixed max errors of f, psi and the phase, and relative "
+                                     "errors of the dual and transport cost, against the FP64 oracle's solve of the "
+                                     "same workload")
     print(json.dumps(out), flush=True)
 
 

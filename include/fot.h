@@ -44,13 +44,21 @@ typedef enum {
   FOT_E_UNSUPPORTED = 6, /* option not available in this library (or, from fot_solve, an eps that
                             needs the block-normalised Gibbs factor at an n whose exponent
                             table does not fit in LDS: n > 4096 with 32- and 16-bit types) */
-  FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the check of the
-                            operand type's products (fot_report.err_products: the larger of the
-                            final column-marginal L1, evaluated in FP64, and the discrepancy of
-                            one more u-direction product at the final potentials against FP64)
-                            exceeds what the type allows (FP64 1e-8, FP32 1e-5, BF16x3 1e-4,
-                            BF16 5e-3, FP16 5e-4): at this eps the Gibbs products lost values
-                            below the operand type's range; use FOT_F64 or a larger eps */
+  FOT_E_RANGE = 7        /* fot_solve finished and filled its outputs, but the Gibbs products
+                            may have lost values below the operand type's range at this eps.
+                            Two checks: (1) in every iteration each output of the per-axis
+                            products is compared with the largest block scale it was formed
+                            from, which bounds what terms dropped below the type's range could
+                            have cost it (fot_report.range_loss, a worst case); the check fails
+                            when the bound exceeds 2^-7 (FP32, BF16x3), 2^13 (BF16) or 2^20
+                            (FP64), levels calibrated against the oracle between accurate and
+                            inaccurate solves (fot_report.range_iter gives the first such
+                            iteration; FP16 has no such check); (2) after the
+                            solve, fot_report.err_products (the larger of the final column-
+                            marginal L1, evaluated in FP64, and the discrepancy of one more
+                            u-direction product at the final potentials against FP64) must stay
+                            within the type's bound (FP64 1e-8, FP32 1e-5, BF16x3 1e-4, BF16
+                            5e-3, FP16 5e-4).  Use FOT_F64, FOT_FLAG_SMALL_TILES or a larger eps */
 } fot_status;
 
 /* Element type of the contraction operands (the Gibbs factor and the shifted exponentials
@@ -90,7 +98,7 @@ enum {
                             largest lose accuracy: at small eps fot_solve may return
                             FOT_E_NONFINITE, or FOT_E_RANGE when the final column-marginal L1
                             exceeds 1e-6 */
-  FOT_FLAG_SMALL_TILES = 16 /* run the iteration kernels on 32 x 32 output tiles, with operands
+  FOT_FLAG_SMALL_TILES = 16, /* run the iteration kernels on 32 x 32 output tiles, with operands
                             normalised in 32-wide instead of 64-wide blocks.  fot_plan chooses
                             these tiles by itself when 64 x 64 tiles would occupy at most half of
                             the GPU's compute units (small grids); on larger grids the flag
@@ -98,6 +106,12 @@ enum {
                             range: the 32- and 16-bit operand types then reach about half the
                             eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian 1024 x 1024
                             workload).  No effect with FOT_FLAG_CFOT */
+  FOT_FLAG_TWO_PASS = 32 /* on small grids (padded side <= 256, on the 32 x 32 tiles) a half-step
+                            with 32- or 16-bit operands and the raw Gibbs factor runs as one launch
+                            (each workgroup computes both per-axis products for a panel of 32
+                            output columns); this flag keeps the two launches per half-step
+                            instead.  The potentials are bit-identical either way; only the
+                            grouping of the per-iteration marginal-error sums differs */
 };
 
 typedef struct {
@@ -108,6 +122,17 @@ typedef struct {
   int checkpoint_every;  /* > 0: keep psi every k iterations so fot_backward can replay;
                             0: no tape (fot_backward then returns FOT_E_STATE) */
   int flags;             /* FOT_FLAG_* */
+  int tail_precision;    /* precision schedule (with tail_iters > 0): the operand type of the last
+                            tail_iters iterations of every fot_solve; the first iters - tail_iters
+                            use `precision` (Algorithm 1 is unchanged; only the type of the
+                            contraction operands changes between the two segments, and each
+                            segment builds its operands from the potentials it starts from).
+                            Must differ from `precision`; `precision` must not be FOT_F64; no
+                            FOT_FLAG_CFOT and no reverse mode (checkpoint_every = 0), else
+                            FOT_E_UNSUPPORTED.  The end-of-solve range check uses the tail type.
+                            Example: BF16 iterations then one or two FP32 ones reach FP32's
+                            marginal error at BF16's iteration cost */
+  int tail_iters;        /* >= 0; 0 = no schedule (zero-initialised descriptors keep one type) */
 } fot_plan_desc;
 
 /* Results of fot_solve.  All pointers are HOST arrays owned by the caller; any may be NULL. */
@@ -133,6 +158,18 @@ typedef struct {
                              marginal L1 that one more u-update would make through its products
                              alone; FOT_E_RANGE when it exceeds the type's bound (0 beyond err_b
                              for FOT_F64 and cFOT, whose products need no probe) */
+  int* range_iter;        /* [batch] or NULL: the first iteration (0-based; iters = the check
+                             after the last one) in which an output of the operand type's
+                             products fell below its range floor (see FOT_E_RANGE), or -1 */
+  double* range_loss;     /* [batch] or NULL: the largest relative loss that terms dropped below
+                             the operand type's range could have caused in any output of the
+                             per-axis products during the solve (a bound: n 2^-125 times 2 to the
+                             output's distance below the largest block scale it was formed from;
+                             2^-1021 for FP64, 2^-23 for FP16); see FOT_E_RANGE */
+  double* ms_launches;    /* [4 * iters] or NULL: FOT_FLAG_PROFILE: the HIP-event time of each
+                             timed iteration-kernel launch in issue order (pass 1 and pass 2 of
+                             the u-half, then of the V-half, per iteration; one launch per half-
+                             step where FOT_FLAG_TWO_PASS describes it); n_contract entries */
 } fot_report;
 
 /* Create a plan: validates desc, allocates O(n^2 * batch) device workspace once (no later

@@ -12,8 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "fot_api.hip")
-DEPS = [os.path.join(HERE, "csrc", "fot_kernels.hpp"), os.path.join(ROOT, "include", "fot.h")]
+SRC = os.path.join(HERE, "csrc", "fot_api.hip")   # includes every other source under csrc/
 LIB = os.path.join(HERE, "libfot.so")
 ARCH = "gfx950"
 

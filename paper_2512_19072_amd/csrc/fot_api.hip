@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "fot_fused.hpp"
+#include "fot_panel.hpp"
 #include "fot_beam.hpp"
 #include "fot_cfot.hpp"
 
@@ -61,12 +62,22 @@ struct fot_plan_s {
   int nbA = 0, nbT = 0;
   bool t32 = false;                         // fused kernels on 32 x 32 tiles (small grids)
   int* kexpL = nullptr;                     // LN form: [np][nbA] exponents of the block-normalised Lambda
-  int* probe_flag = nullptr;                // non-finite flag of the end-of-solve probe (not reported)
+  int* probe_flag = nullptr;                // non-finite flag of the end-of-solve probe
+  int* range_iter = nullptr;                // [batch] first iteration whose products failed the range check
+  int* range_min = nullptr;                 // [2][batch] lowest range margin (head, tail type of a schedule)
   bool probing = false;                     // the probe's launches are not iteration kernels (no timing)
-  bool ln_ok = false;                       // the LN-form kernels fit in LDS at this n_p
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
   void *lam = nullptr, *opA = nullptr, *opB = nullptr, *Z = nullptr;
+  // precision schedule: the last tail_iters iterations of a solve run with tail_prec operands,
+  // which have their own Lambda and operand buffers (op_set[1]; op_set[0] holds the head type's).
+  // lam / opA / opB point at the set of the segment being issued.
+  int tail_prec = -1, tail_iters = 0;
+  void* op_set[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
+  // the one-launch half-step (k_panel) reads opA / kexpA in every workgroup while it writes the
+  // next operand: it writes op_alt / kexp_alt instead, and the host swaps the pairs afterwards
+  void* op_alt = nullptr;
+  int* kexp_alt = nullptr;
   double* tape = nullptr;
   int n_ckpt = 0;
   // reverse mode (allocated when checkpoint_every > 0)
@@ -86,6 +97,11 @@ struct fot_plan_s {
   bool* flamH_valid = nullptr;  // -> lamH_valid or flamH_valid_sep
   double lam_eps = -1.0;
   double* pending_hist = nullptr;   // marginal-error sum still to be finished by the next row-exp
+  const double* pending_parts = nullptr;  // the partials of that sum (written by the last half-step)
+  int pending_tiles = 0;                  // and their count per target
+  double* partials2 = nullptr;      // second partials buffer: a one-launch half-step reads the
+                                    // preceding partials while it writes its own
+  bool panel = false;               // small grid: one launch per half-step (k_panel) where it applies
   bool lamH_valid = false;
   bool has_state = false;
   bool tape_valid = false;
@@ -100,6 +116,8 @@ struct fot_plan_s {
   bool graph_tape = false;
   int graph_prof = 0;          // profiler events captured inside the graph
   bool graph_broken = false;   // capture/instantiate failed once: launch eagerly from then on
+  const double* graph_pending_parts = nullptr;
+  int graph_pending_tiles = 0;
   bool used_graph = false;
   std::vector<hipEvent_t> prof;
   int prof_used = 0;
@@ -119,6 +137,9 @@ struct fot_plan_s {
   double *clamhat = nullptr, *cY = nullptr, *cfT = nullptr, *clnaT = nullptr, *cS = nullptr, *cparts = nullptr;
   double clam_eps = -1.0;
   std::vector<void*> allocs;
+  // workspace carved from a caller-independent device array instead of hipMalloc (see plan_init)
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
 };
 
 namespace {
@@ -126,6 +147,17 @@ namespace {
 fot_status dalloc(fot_plan_s* p, void** out, size_t bytes) {
   void* ptr = nullptr;
   if (bytes == 0) bytes = 16;
+  if (p->arena) {
+    // carve 256-byte aligned pieces from the static scratch array
+    const size_t off = (p->arena_used + 255) & ~(size_t)255;
+    if (off > p->arena_cap || bytes > p->arena_cap - off)
+      return fail(FOT_E_INVALID, "the plan's workspace (over " + std::to_string(off + bytes) +
+                                     " bytes) exceeds the static scratch array of " + std::to_string(p->arena_cap) +
+                                     " bytes");
+    p->arena_used = off + bytes;
+    *out = p->arena + off;
+    return FOT_OK;
+  }
   hipError_t e = hipMalloc(&ptr, bytes);
   if (e != hipSuccess) return fail(FOT_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   p->allocs.push_back(ptr);
@@ -164,9 +196,9 @@ void release(fot_plan_s* p) {
 // ------------------------------------------------------------------ launch helpers
 // The marginal-error partials of the last potential update, to be summed by the next row-exp.
 PendingSum take_pending(fot_plan_s* p) {
-  PendingSum ps{nullptr, p->tiles, nullptr};
+  PendingSum ps{nullptr, p->pending_tiles, nullptr};
   if (p->pending_hist) {
-    ps.parts = p->partials;
+    ps.parts = p->pending_parts;
     ps.out = p->pending_hist;
     p->pending_hist = nullptr;
   }
@@ -213,8 +245,12 @@ fot_status run_graph(fot_plan_s* p, const std::vector<double>& e, int iters, Loo
     p->graph_eps = e;
     p->graph_tape = tape;
     p->graph_prof = p->prof_used;
+    p->graph_pending_parts = p->pending_parts;
+    p->graph_pending_tiles = p->pending_tiles;
   } else {
     p->prof_used = p->graph_prof;
+    p->pending_parts = p->graph_pending_parts;   // (which buffer the replayed loop leaves pending)
+    p->pending_tiles = p->graph_pending_tiles;
   }
   HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
   p->used_graph = true;
@@ -296,11 +332,13 @@ struct Ops {
     }
   }
 
-  // Every eps of a schedule must be runnable: one that needs the block-normalised Lambda needs its
-  // exponent table to fit in LDS.
-  static fot_status check_schedule(fot_plan_s* p, const std::vector<double>& e, int iters) {
-    for (int t = 0; t < iters; ++t)
-      if (lam_ln(p, e[t]) && !p->ln_ok) {
+  // Every eps of iterations [t0, t1) must be runnable with this operand type: one that needs the
+  // block-normalised Lambda needs its exponent table to fit in LDS.
+  static fot_status check_schedule(fot_plan_s* p, const std::vector<double>& e, int t0, int t1) {
+    for (int t = t0; t < t1; ++t) {
+      if (!lam_ln(p, e[t])) continue;
+      if (ln_fits(p)) return FOT_OK;   // (the table's size does not depend on eps)
+      {
         char msg[200];
         std::snprintf(msg, sizeof msg,
                       "fot_solve: at eps %.3g and n %d Lambda needs its block exponents, whose table does not fit "
@@ -308,6 +346,7 @@ struct Ops {
                       e[t], p->n);
         return fail(FOT_E_UNSUPPORTED, msg);
       }
+    }
     return FOT_OK;
   }
 
@@ -393,13 +432,106 @@ struct Ops {
     return lam_ln(p, eps) ? band_for(p, eps, 746.0) : raw_band(p, eps);
   }
 
+  // Range check of the products (see range_margin in fot_fused.hpp): a term the operand type cannot
+  // hold is off by less than 2^unit_log2 of its block's scale, so an output may lose at most
+  // n 2^unit_log2 2^-margin of itself.  That bound takes every term at its block's largest scale and
+  // is loose by orders of magnitude; the check fails when it exceeds 2^allowed_loss_log2, levels
+  // set between the bounds of accurate and of inaccurate solves in a sweep of the two-Gaussian
+  // workload over n = 65 ... 1024 and eps = 1e-2 ... 1e-4 (30 and 60 iterations) against the
+  // oracle: FP32 and BF16x3 accurate up to 2.4e-4, inaccurate from 4; BF16 accurate up to 260,
+  // inaccurate from 3.4e7; FP64 at 257^2 and eps 1e-4 within 1e-11 of the oracle at 1.4e11 and
+  // off where outputs vanished.  FP16 (accurate up to 128, inaccurate from 64) is checked only
+  // after the solve.
+  static int unit_log2() {
+    return sizeof(T) == 8 ? -1021 : std::is_same<T, _Float16>::value ? -23 : -125;
+  }
+  static int allowed_loss_log2() {
+    return sizeof(T) == 8 ? 20 : std::is_same<T, __bf16>::value ? 13 : -7;
+  }
+  static int range_threshold(int n) {
+    if (std::is_same<T, _Float16>::value) return INT_MIN;
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;          // ceil(log2 n)
+    return lg + unit_log2() - allowed_loss_log2();
+  }
+  // the bound n 2^unit_log2 2^-margin for a recorded margin (0 if no output was recorded)
+  static double loss_bound(int n, int margin) {
+    if (margin == 0x7f7f7f7f) return 0.0;
+    return std::ldexp((double)n, unit_log2() - std::max(margin, -2000));
+  }
+
   // One half-step: Pout = eps (lnm - ln(Lambda . exp(Pin/eps) . Lambda)) (Eq. 7 or Eq. 8), the
   // marginal error of the entering plan to hist[batch] (finished by the next pass 1), and, if
   // next_eps > 0, the block-normalised operand of Pout for the next half-step.  The operand of
   // Pin must be in p->opA / p->kexpA.
+  // One launch per half-step (k_panel) on small grids with raw Lambda and 32- or 16-bit operands.
+  static bool use_panel(const fot_plan_s* p, double eps) {
+    if constexpr (sizeof(T) <= 4 && !Mma<T>::PAIRED) return p->panel && !lam_ln(p, eps);
+    (void)p;
+    (void)eps;
+    return false;
+  }
+
+  static fot_status half_panel(fot_plan_s* p, double* Pout, const double* lnm, long long sMarg, double* hist,
+                               double* lnS_out, double eps, double next_eps, int* flag, int iter, int* range_iter,
+                               int* range_min) {
+    if constexpr (sizeof(T) <= 4 && !Mma<T>::PAIRED) {
+      PanelArgs a{};
+      a.A = p->opA;
+      a.kexpA = p->kexpA;
+      a.lam = p->lam;
+      a.n = p->n;
+      a.np = p->np;
+      a.nb = p->np / PANEL;
+      a.band = raw_band(p, eps);
+      a.lnmarg = lnm;
+      a.sMarg = sMarg;
+      a.pot = Pout;
+      a.lnS_out = lnS_out;
+      a.eps = eps;
+      a.inv_eps = 1.0 / eps;
+      a.next_inv_eps = next_eps > 0.0 ? 1.0 / next_eps : 0.0;
+      a.nextA = p->op_alt;   // (every workgroup reads all of opA and kexpA)
+      a.kexpN = p->kexp_alt;
+      a.flag = flag ? flag : p->flag;
+      a.err_on = hist != nullptr;
+      PendingSum ps = take_pending(p);
+      a.pend_parts = ps.parts;
+      a.pend_tiles = ps.tiles;
+      a.pend_out = ps.out;
+      a.partials = (ps.parts == p->partials) ? p->partials2 : p->partials;
+      a.range_iter = range_iter;
+      a.iter = iter;
+      a.range_min = range_min;
+      a.range_thr = range_threshold(p->n);
+      const bool prof = !p->probing && (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
+      hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
+      hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
+      hipExtLaunchKernelGGL(k_panel<T>, dim3(p->np / PANEL, 1, p->B), dim3(PANEL_THREADS),
+                            (uint32_t)PanelLds<T>::bytes(p->np), p->stream, e0, e1, 0, a);
+      LAUNCH_CHECK();
+      if (prof) p->prof_used += 2;
+      p->pending_hist = hist;
+      p->pending_parts = a.partials;
+      p->pending_tiles = p->np / PANEL;
+      if (a.next_inv_eps > 0.0) {
+        std::swap(p->opA, p->op_alt);
+        std::swap(p->kexpA, p->kexp_alt);
+      }
+      return FOT_OK;
+    } else {
+      (void)p; (void)Pout; (void)lnm; (void)sMarg; (void)hist; (void)lnS_out; (void)eps; (void)next_eps;
+      (void)flag; (void)iter; (void)range_iter; (void)range_min;
+      return fail(FOT_E_UNSUPPORTED, "one-launch half-step: unsupported operand type");
+    }
+  }
+
   static fot_status half(fot_plan_s* p, const double* Pin, double* Pout, const double* lnm, long long sMarg,
-                         double* hist, double* lnS_out, double eps, double next_eps, int* flag = nullptr) {
+                         double* hist, double* lnS_out, double eps, double next_eps, int* flag = nullptr,
+                         int iter = 0, int* range_iter = nullptr, int* range_min = nullptr) {
     (void)Pin;
+    if (use_panel(p, eps))
+      return half_panel(p, Pout, lnm, sMarg, hist, lnS_out, eps, next_eps, flag, iter, range_iter, range_min);
     const long long plane = (long long)p->plane;
     FusedArgs a{};
     a.n = p->n;
@@ -410,6 +542,10 @@ struct Ops {
     a.xcd_swizzle = 1;
     a.band = lambda_band(p, eps);
     a.kexpL = lam_ln(p, eps) ? p->kexpL : nullptr;
+    a.range_iter = range_iter;
+    a.iter = iter;
+    a.range_min = range_min;
+    a.range_thr = range_threshold(p->n);
     // pass 1: W = At . Lambda
     a.A = p->opA;
     a.sA = plane;
@@ -434,6 +570,10 @@ struct Ops {
     b.xcd_swizzle = 1;
     b.band = a.band;
     b.kexpL = a.kexpL;
+    b.range_iter = range_iter;
+    b.iter = iter;
+    b.range_min = range_min;
+    b.range_thr = a.range_thr;
     b.A = p->lam;
     b.sA = 0;
     b.B = p->opB;
@@ -453,21 +593,23 @@ struct Ops {
     b.err_on = hist != nullptr;
     s = fused_launch(p, 2, b);
     p->pending_hist = hist;   // nullptr: no marginal-error sum to finish
+    p->pending_parts = p->partials;
+    p->pending_tiles = p->tiles;
     return s;
   }
 
-  // The iteration loop of Algorithm 1 on p->stream: Lambda is regenerated whenever eps
-  // changes (and at the start), psi is checkpointed every k iterations if a tape exists.
-  static fot_status loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
+  // Iterations [t0, t1) of a solve of `iters` iterations (Algorithm 1) on p->stream, all with
+  // operands of type T in p->lam / p->opA / p->opB: the segment starts from the pass-1 operand of
+  // psi and Lambda at its first eps; Lambda is regenerated whenever eps changes, psi is
+  // checkpointed every k iterations if a tape exists.
+  static fot_status segment(fot_plan_s* p, const std::vector<double>& e, int t0, int t1, int iters, int seg = 0) {
     const long long plane = (long long)p->plane;
     const int B = p->B;
-    fot_status s = check_schedule(p, e, iters);
+    fot_status s = prep(p, p->psi, e[t0]);
     if (s != FOT_OK) return s;
-    s = prep(p, p->psi, e[0]);
-    if (s != FOT_OK) return s;
-    for (int t = 0; t < iters; ++t) {
+    for (int t = t0; t < t1; ++t) {
       const double ep = e[t];
-      if (t == 0 || ep != e[t - 1])
+      if (t == t0 || ep != e[t - 1])
         if ((s = fill_lambda(p, ep, false)) != FOT_OK) return s;
       if (p->tape && (t % p->d.checkpoint_every) == 0) {
         const size_t cnt = (size_t)B * p->plane;
@@ -478,13 +620,23 @@ struct Ops {
       const bool last = (t == iters - 1);
       const bool hist = !(p->d.flags & FOT_FLAG_NO_HISTORY);
       if ((s = half(p, p->psi, p->f, p->lna, 0, hist ? p->hist_a + (size_t)t * B : nullptr, last ? p->lnS : nullptr,
-                    ep, ep)) != FOT_OK)
+                    ep, ep, nullptr, t, p->range_iter, p->range_min + (size_t)seg * B)) != FOT_OK)
         return s;
+      // the last half-step of a segment builds no next operand: the next segment (another type)
+      // builds its own from psi
       if ((s = half(p, p->f, p->psi, p->lnb, plane, hist ? p->hist_b + (size_t)t * B : nullptr,
-                    last ? p->lnSp : nullptr, ep, last ? 0.0 : e[t + 1])) != FOT_OK)
+                    last ? p->lnSp : nullptr, ep, t + 1 == t1 ? 0.0 : e[t + 1], nullptr, t, p->range_iter,
+                    p->range_min + (size_t)seg * B)) != FOT_OK)
         return s;
     }
     return FOT_OK;
+  }
+
+  // The iteration loop of Algorithm 1 with one operand type.
+  static fot_status loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
+    fot_status s = check_schedule(p, e, 0, iters);
+    if (s != FOT_OK) return s;
+    return segment(p, e, 0, iters, iters);
   }
 
   // End-of-solve probe of the operand type's u-direction products: ln S(psi_T) formed as a u-half
@@ -492,17 +644,21 @@ struct Ops {
   // read-out), for the read-out to compare with the FP64 value.  The final column marginal checks
   // only the last V-half's products; a loss of range in the u-direction products (the potential
   // psi spanning more than the type holds within one operand block) would otherwise go unseen
-  // while the iterates drift.  FP64 operands need no probe.
-  static fot_status probe(fot_plan_s* p, double eps) {
+  // while the iterates drift.  FP64 operands need no probe.  Its own range check is recorded as
+  // iteration `iters` (the state after the last iteration).
+  static fot_status probe(fot_plan_s* p, double eps, int iters, int seg) {
     if constexpr (sizeof(T) == 8) {
       (void)p;
       (void)eps;
+      (void)iters;
+      (void)seg;
       return FOT_OK;
     } else {
       fot_status s = prep(p, p->psi, eps);
       if (s != FOT_OK) return s;
       p->probing = true;
-      s = half(p, p->psi, p->Tx, p->lna, 0, nullptr, p->phi, eps, 0.0, p->probe_flag);
+      s = half(p, p->psi, p->Tx, p->lna, 0, nullptr, p->phi, eps, 0.0, p->probe_flag, iters, p->range_iter,
+               p->range_min + (size_t)seg * p->B);
       p->probing = false;
       return s;
     }
@@ -631,6 +787,36 @@ struct Ops {
   }
 
 };
+
+// ------------------------------------------------------------------ precision schedule
+// Make operand set `which` (0: the head type's, 1: the tail type's) the one the kernels use.
+void activate(fot_plan_s* p, int which) {
+  p->lam = p->op_set[which][0];
+  p->opA = p->op_set[which][1];
+  p->opB = p->op_set[which][2];
+  p->op_alt = p->op_set[which][3];
+}
+
+// A solve's iterations with the precision schedule: iters - k iterations with H operands, then the
+// last k = min(tail_iters, iters) with L operands (each segment builds its own operands from psi).
+template <typename H, typename L>
+fot_status sched_loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
+  const int t1 = iters - std::min(p->tail_iters, iters);
+  fot_status s = FOT_OK;
+  if (t1 > 0) {
+    activate(p, 0);
+    if ((s = Ops<H>::segment(p, e, 0, t1, iters)) != FOT_OK) return s;
+  }
+  activate(p, 1);
+  return Ops<L>::segment(p, e, t1, iters, iters, 1);
+}
+
+template <typename H, typename L>
+fot_status sched_check(fot_plan_s* p, const std::vector<double>& e, int iters) {
+  const int t1 = iters - std::min(p->tail_iters, iters);
+  fot_status s = Ops<H>::check_schedule(p, e, 0, t1);
+  return s != FOT_OK ? s : Ops<L>::check_schedule(p, e, t1, iters);
+}
 
 // ------------------------------------------------------------------ FP64 read-out and reverse sweep
 // Lambda (and Lambda o H) with FP64 elements for the read-out and the reverse sweep.
@@ -976,6 +1162,49 @@ fot_status cfot_loop_graph(fot_plan_s* p, const std::vector<double>& e, int iter
   return s;
 }
 
+fot_status sched_loop_graph_state(fot_plan_s* p, const std::vector<double>& e, int iters) {
+  // state after a replayed loop, as if it had been launched directly
+  p->pending_hist = (p->d.flags & FOT_FLAG_NO_HISTORY) ? nullptr : p->hist_b + (size_t)(iters - 1) * p->B;
+  p->lam_eps = e[iters - 1];
+  p->lamH_valid = false;
+  return FOT_OK;
+}
+
+// One solve after set-up: the iteration loop (operand type H throughout, or the precision schedule
+// H then L), the end-of-solve probe of the final type's products, and the FP64 read-out.
+template <typename H, typename L>
+fot_status solve_body(fot_plan_s* p, const std::vector<double>& e, int iters, double* phase_out) {
+  constexpr bool sched = !std::is_same<H, L>::value;
+  if (p->ev[1]) HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+  const bool graph = !(p->d.flags & (FOT_FLAG_NO_GRAPH | FOT_FLAG_PROFILE)) && !p->graph_broken && p->cap;
+  p->used_graph = false;
+  fot_status s;
+  if (p->cfot) {
+    s = graph ? cfot_loop_graph(p, e, iters) : cfot_loop(p, e, iters);
+  } else if constexpr (sched) {
+    if (graph) {
+      s = run_graph(p, e, iters, [](fot_plan_s* q, const std::vector<double>& ee, int it) {
+        return sched_loop<H, L>(q, ee, it);
+      });
+      if (s == FOT_OK && p->used_graph) s = sched_loop_graph_state(p, e, iters);
+    } else {
+      s = sched_loop<H, L>(p, e, iters);
+    }
+    activate(p, 1);   // the final iterations' operand type (a replayed graph issues nothing here)
+  } else {
+    s = graph ? Ops<H>::loop_graph(p, e, iters) : Ops<H>::loop(p, e, iters);
+  }
+  if (s == FOT_OK && p->ev[2])
+    s = (hipEventRecord(p->ev[2], p->stream) == hipSuccess) ? FOT_OK : fail(FOT_E_HIP, "event record");
+  const bool probed = !p->cfot && sizeof(L) != 8;
+  if (s == FOT_OK && probed) s = Ops<L>::probe(p, e[iters - 1], iters, sched ? 1 : 0);
+  if (s == FOT_OK) s = readout64(p, e[iters - 1], phase_out, probed ? p->phi : nullptr);
+  if (s == FOT_OK && p->ev[3])
+    s = (hipEventRecord(p->ev[3], p->stream) == hipSuccess) ? FOT_OK : fail(FOT_E_HIP, "event record");
+  activate(p, 0);
+  return s;
+}
+
 template <typename F>
 fot_status dispatch(int prec, F&& fn) {
   switch (prec) {
@@ -992,24 +1221,28 @@ bool finite_positive(double x) { return std::isfinite(x) && x > 0.0; }
 
 }  // namespace
 
-// ====================================================================== C ABI
-extern "C" {
-
-const char* fot_last_error(void) { return g_err.c_str(); }
-
-const char* fot_version(void) { return "fot 0.1 gfx950"; }
-
-fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
-  g_err.clear();
-  if (!desc || !out) return fail(FOT_E_INVALID, "fot_plan: null argument");
-  const fot_plan_desc d = *desc;
+// Checks of a plan descriptor (fot_plan's argument errors); *cN_out gets the cFOT FFT length (0: none).
+static fot_status validate_desc(const fot_plan_desc& d, int* cN_out) {
   if (d.n < 1 || d.n > 8192) return fail(FOT_E_INVALID, "fot_plan: n must be in [1, 8192]");
   if (d.batch < 1 || d.batch > 65535) return fail(FOT_E_INVALID, "fot_plan: batch must be in [1, 65535]");
   if (d.precision < FOT_F64 || d.precision > FOT_BF16X3) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
-  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES))
+  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES |
+                  FOT_FLAG_TWO_PASS))
     return fail(FOT_E_INVALID, "fot_plan: unknown flag bits");
+  if (d.tail_iters < 0) return fail(FOT_E_INVALID, "fot_plan: tail_iters must be >= 0");
+  if (d.tail_iters > 0) {
+    if (d.tail_precision < FOT_F64 || d.tail_precision > FOT_BF16X3)
+      return fail(FOT_E_INVALID, "fot_plan: unknown tail_precision");
+    if (d.tail_precision == d.precision)
+      return fail(FOT_E_INVALID, "fot_plan: tail_precision equals precision (use tail_iters = 0)");
+    if (d.precision == FOT_F64)
+      return fail(FOT_E_UNSUPPORTED, "fot_plan: a precision schedule starts with a 32- or 16-bit operand type");
+    if (d.flags & FOT_FLAG_CFOT) return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT has no precision schedule");
+    if (d.checkpoint_every > 0)
+      return fail(FOT_E_UNSUPPORTED, "fot_plan: no reverse mode with a precision schedule (checkpoint_every must be 0)");
+  }
   int cN = 0;
   if (d.flags & FOT_FLAG_CFOT) {
     if (d.precision != FOT_F64) return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT needs FOT_F64 (FP64 FFTs)");
@@ -1019,28 +1252,40 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
     while (cN < 2 * d.n - 1) cN <<= 1;
     if (cN > CFOT_MAX_N) return fail(FOT_E_UNSUPPORTED, "fot_plan: FOT_FLAG_CFOT supports n <= 2048");
   }
-  fot_plan_s* p = new (std::nothrow) fot_plan_s();
-  if (!p) return fail(FOT_E_NOMEM, "fot_plan: host allocation failed");
+  *cN_out = cN;
+  return FOT_OK;
+}
+
+// Build plan *p (default-constructed) for descriptor d (already validated; cN its FFT length) on
+// `stream`.  With `arena` non-null every device buffer is carved from its `cap` bytes instead of
+// hipMalloc, and no HIP event or capture stream is created (such a plan launches eagerly and
+// reports no timing).  On failure the caller releases *p.
+static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipStream_t stream, unsigned char* arena,
+                            size_t cap) {
+  const bool tail = d.tail_iters > 0;
+  p->arena = arena;
+  p->arena_cap = cap;
+  p->arena_used = 0;
   p->d = d;
   p->n = d.n;
-  p->esz = d.precision == FOT_F64 ? 8 : (d.precision == FOT_F32 || d.precision == FOT_BF16X3) ? 4 : 2;
+  auto esz_of = [](int prec) -> size_t {
+    return prec == FOT_F64 ? 8 : (prec == FOT_F32 || prec == FOT_BF16X3) ? 4 : 2;
+  };
+  p->tail_prec = tail ? d.tail_precision : -1;
+  p->tail_iters = tail ? d.tail_iters : 0;
+  p->esz = tail ? std::max(esz_of(d.precision), esz_of(d.tail_precision)) : esz_of(d.precision);
+  const size_t esz_min = tail ? std::min(esz_of(d.precision), esz_of(d.tail_precision)) : p->esz;
   // padded side: whole 64-pixel tiles and whole K stages of the fused kernels (FROWB bytes,
-  // a multiple of the read-out GEMM's ROWB)
+  // a multiple of the read-out GEMM's ROWB) for every operand type of the plan
   static_assert(FROWB % ROWB == 0, "fused stages must also be whole read-out stages");
-  const int align = std::max(TILE, (int)(FROWB / p->esz));
+  const int align = std::max(TILE, (int)(FROWB / esz_min));
   p->np = ((d.n + align - 1) / align) * align;
   p->B = d.batch;
   p->prec = d.precision;
-  p->zsz = d.precision == FOT_F64 ? 8 : 4;
+  p->zsz = (d.precision == FOT_F64 || p->tail_prec == FOT_F64) ? 8 : 4;
   p->plane = (size_t)p->np * p->np;
-  p->stream = (hipStream_t)stream;
-  auto bail = [&](fot_status s) {
-    std::string msg = g_err;
-    release(p);
-    delete p;
-    g_err = msg;
-    return s;
-  };
+  p->stream = stream;
+  auto bail = [](fot_status s) { return s; };
   if (hipGetDevice(&p->device) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: no HIP device"));
   // fused-kernel tiles: 64 x 64, or 32 x 32 when 64 x 64 tiles would occupy at most half of the
   // CUs.  Measured FP32 half-steps (pass 1 + pass 2), 32 x 32 against 64 x 64 tiles on 256 CUs:
@@ -1051,6 +1296,8 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
     return bail(fail(FOT_E_HIP, "fot_plan: cannot query the device"));
   p->t32 = (d.flags & FOT_FLAG_SMALL_TILES) ||
            2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
+  // one launch per half-step on the 32 x 32 tiles' grids up to n_p = 256 (unless asked not to)
+  p->panel = p->t32 && p->np <= PANEL_MAX_NP && !(d.flags & FOT_FLAG_TWO_PASS);
   const int tbm = p->t32 ? Ops<float>::GS::BM : Ops<float>::GC::BM;
   const int tbn = p->t32 ? Ops<float>::GS::BN : Ops<float>::GC::BN;
   // one marginal-error partial per output tile of the fused pass-2 kernel
@@ -1075,24 +1322,39 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
   ALLOC(p->rowsum_G, (size_t)p->B * p->n);
   ALLOC(p->rowpart, (size_t)p->B * p->n);
   ALLOC(p->partials, (size_t)p->B * p->tiles);
+  ALLOC(p->partials2, (size_t)p->B * p->tiles);
+  p->pending_parts = p->partials;
+  p->pending_tiles = p->tiles;
   ALLOC(p->hist_a, (size_t)d.max_iters * p->B);
   ALLOC(p->hist_b, (size_t)d.max_iters * p->B);
   ALLOC(p->rparts, (size_t)6 * p->B * READOUT_BLOCKS);
   ALLOC(p->rsums, (size_t)6 * p->B);
   ALLOC(p->probe_flag, (size_t)1);
+  ALLOC(p->range_iter, (size_t)p->B);
+  ALLOC(p->range_min, (size_t)2 * p->B);
   ALLOC(p->colkey, (size_t)p->B * p->np);
   p->nbA = p->np / tbn;
   p->nbT = p->np / tbm;
   ALLOC(p->kexpA, (size_t)p->B * p->np * p->nbA);
   ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
   if (d.precision != FOT_F64) ALLOC(p->kexpL, (size_t)p->np * p->nbA);
-  p->ln_ok = dispatch(d.precision, [&](auto tag) -> fot_status {
-               return Ops<decltype(tag)>::ln_fits(p) ? FOT_OK : FOT_E_UNSUPPORTED;
-             }) == FOT_OK;
   ALLOC(p->flag, (size_t)1);
   ALLOCV(p->lam, p->plane * p->esz);
   ALLOCV(p->opA, BP * p->esz);
   ALLOCV(p->opB, BP * p->esz);
+  p->op_set[0][0] = p->lam;
+  p->op_set[0][1] = p->opA;
+  p->op_set[0][2] = p->opB;
+  if (tail) {
+    ALLOCV(p->op_set[1][0], p->plane * p->esz);
+    ALLOCV(p->op_set[1][1], BP * p->esz);
+    ALLOCV(p->op_set[1][2], BP * p->esz);
+  }
+  if (p->panel) {
+    for (int set = 0; set < (tail ? 2 : 1); ++set) ALLOCV(p->op_set[set][3], BP * p->esz);
+    ALLOC(p->kexp_alt, (size_t)p->B * p->np * p->nbA);
+    p->op_alt = p->op_set[0][3];
+  }
   ALLOCV(p->Z, BP * p->zsz);
   if (d.precision == FOT_F64) {
     p->flam = (double*)p->lam;
@@ -1174,17 +1436,23 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
 #undef ALLOC
 #undef ALLOCV
   // the fused loop kernels never write the padded borders of their operands: zero them once
-  if (hipMemsetAsync(p->opA, 0, BP * p->esz, p->stream) != hipSuccess ||
-      hipMemsetAsync(p->opB, 0, BP * p->esz, p->stream) != hipSuccess ||
-      hipMemsetAsync(p->kexpA, 0, sizeof(int) * p->B * p->np * p->nbA, p->stream) != hipSuccess ||
+  for (int set = 0; set < (tail ? 2 : 1); ++set)
+    for (int k = 1; k < 4; ++k)
+      if (p->op_set[set][k] && hipMemsetAsync(p->op_set[set][k], 0, BP * p->esz, p->stream) != hipSuccess)
+        return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
+  if (p->kexp_alt && hipMemsetAsync(p->kexp_alt, 0, sizeof(int) * p->B * p->np * p->nbA, p->stream) != hipSuccess)
+    return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
+  if (hipMemsetAsync(p->kexpA, 0, sizeof(int) * p->B * p->np * p->nbA, p->stream) != hipSuccess ||
       hipMemsetAsync(p->kexpT, 0, sizeof(int) * p->B * p->np * p->nbT, p->stream) != hipSuccess ||
       hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
       hipMemsetAsync(p->flag, 0, sizeof(int), p->stream) != hipSuccess)
     return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
-  for (auto& e : p->ev)
-    if (hipEventCreate(&e) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: event create failed"));
-  if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
-    return bail(fail(FOT_E_HIP, "fot_plan: stream create failed"));
+  if (!arena) {
+    for (auto& e : p->ev)
+      if (hipEventCreate(&e) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: event create failed"));
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(FOT_E_HIP, "fot_plan: stream create failed"));
+  }
   if (d.flags & FOT_FLAG_PROFILE) {
     const size_t ne = 2 * ((size_t)d.max_iters * 4 + 16);
     p->prof.resize(ne, nullptr);
@@ -1192,6 +1460,33 @@ fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
       if (hipEventCreate(&e) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: event create failed"));
   }
   if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: sync failed"));
+  return FOT_OK;
+}
+
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* fot_last_error(void) { return g_err.c_str(); }
+
+const char* fot_version(void) { return "fot 0.1 gfx950"; }
+
+fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out) {
+  g_err.clear();
+  if (!desc || !out) return fail(FOT_E_INVALID, "fot_plan: null argument");
+  int cN = 0;
+  fot_status s = validate_desc(*desc, &cN);
+  if (s != FOT_OK) return s;
+  fot_plan_s* p = new (std::nothrow) fot_plan_s();
+  if (!p) return fail(FOT_E_NOMEM, "fot_plan: host allocation failed");
+  s = plan_init(p, *desc, cN, (hipStream_t)stream, nullptr, 0);
+  if (s != FOT_OK) {
+    const std::string msg = g_err;
+    release(p);
+    delete p;
+    g_err = msg;
+    return s;
+  }
   *out = p;
   return FOT_OK;
 }
@@ -1256,9 +1551,16 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   std::vector<double> e(iters);
   for (int t = 0; t < iters; ++t) e[t] = eps[n_eps == 1 ? 0 : t];
   if (!p->cfot) {
-    const fot_status sc = dispatch(p->prec, [&](auto tag) -> fot_status {
-      return Ops<decltype(tag)>::check_schedule(p, e, iters);
-    });
+    const fot_status sc =
+        p->tail_iters > 0
+            ? dispatch(p->prec, [&](auto h) -> fot_status {
+                return dispatch(p->tail_prec, [&](auto l) -> fot_status {
+                  return sched_check<decltype(h), decltype(l)>(p, e, iters);
+                });
+              })
+            : dispatch(p->prec, [&](auto tag) -> fot_status {
+                return Ops<decltype(tag)>::check_schedule(p, e, 0, iters);
+              });
     if (sc != FOT_OK) return sc;
   }
   const int n = p->n, np = p->np, B = p->B;
@@ -1266,8 +1568,11 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   p->tape_valid = false;
   p->pending_hist = nullptr;
 
-  HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+  if (p->ev[0]) HIP_TRY(hipEventRecord(p->ev[0], p->stream));
   HIP_TRY(hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
+  HIP_TRY(hipMemsetAsync(p->probe_flag, 0, sizeof(int), p->stream));
+  HIP_TRY(hipMemsetAsync(p->range_iter, 0x7f, sizeof(int) * B, p->stream));   // 0x7f7f7f7f: none
+  HIP_TRY(hipMemsetAsync(p->range_min, 0x7f, sizeof(int) * 2 * B, p->stream));
   hipLaunchKernelGGL(k_rowsumsq, dim3(n, 1), dim3(NTHREADS), 0, p->stream, g, n, p->rowsum_g, p->flag);
   hipLaunchKernelGGL(k_logmarg, dim3(np, 1), dim3(NTHREADS), 0, p->stream, g, p->rowsum_g, n, np, p->lna, p->flag);
   hipLaunchKernelGGL(k_rowsumsq, dim3(n, B), dim3(NTHREADS), 0, p->stream, G, n, p->rowsum_G, p->flag);
@@ -1288,32 +1593,23 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     LAUNCH_CHECK();
   }
 
-  fot_status st = dispatch(p->prec, [&](auto tag) -> fot_status {
-    typedef decltype(tag) T;
-    HIP_TRY(hipEventRecord(p->ev[1], p->stream));
-    const bool graph = !(p->d.flags & (FOT_FLAG_NO_GRAPH | FOT_FLAG_PROFILE)) && !p->graph_broken;
-    p->used_graph = false;
-    fot_status s0;
-    if (p->cfot)
-      s0 = graph ? cfot_loop_graph(p, e, iters) : cfot_loop(p, e, iters);
-    else
-      s0 = graph ? Ops<T>::loop_graph(p, e, iters) : Ops<T>::loop(p, e, iters);
-    if (s0 != FOT_OK) return s0;
-    HIP_TRY(hipEventRecord(p->ev[2], p->stream));
-    const bool probed = !p->cfot && p->prec != FOT_F64;
-    if (probed) {
-      fot_status sp = Ops<T>::probe(p, e[iters - 1]);
-      if (sp != FOT_OK) return sp;
-    }
-    fot_status s = readout64(p, e[iters - 1], phase_out, probed ? p->phi : nullptr);
-    if (s != FOT_OK) return s;
-    HIP_TRY(hipEventRecord(p->ev[3], p->stream));
-    return FOT_OK;
-  });
+  fot_status st = p->tail_iters > 0 ? dispatch(p->prec, [&](auto h) -> fot_status {
+    return dispatch(p->tail_prec, [&](auto l) -> fot_status {
+      return solve_body<decltype(h), decltype(l)>(p, e, iters, phase_out);
+    });
+  })
+                                     : dispatch(p->prec, [&](auto tag) -> fot_status {
+                                         return solve_body<decltype(tag), decltype(tag)>(p, e, iters, phase_out);
+                                       });
   if (st != FOT_OK) return st;
 
   std::vector<double> ha((size_t)iters * B), hb((size_t)iters * B), rs((size_t)6 * B);
+  std::vector<int> riter((size_t)B), rmin((size_t)2 * B);
+  int pflag = 0;
   HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(&pflag, p->probe_flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(riter.data(), p->range_iter, sizeof(int) * B, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(rmin.data(), p->range_min, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(ha.data(), p->hist_a, ha.size() * 8, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(hb.data(), p->hist_b, hb.size() * 8, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(rs.data(), p->rsums, rs.size() * 8, hipMemcpyDeviceToHost, p->stream));
@@ -1322,6 +1618,8 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   p->last_iters = iters;
   p->last_eps = e;
   p->tape_valid = (p->tape != nullptr);
+  for (int& r : riter)
+    if (r == 0x7f7f7f7f) r = -1;
 
   if (rep) {
     const double epT = e[iters - 1];
@@ -1333,6 +1631,23 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
       if (rep->err_products) rep->err_products[b] = (rs[5 * B + b] != rs[5 * B + b]) ? rs[5 * B + b] : std::max(err_b, rs[5 * B + b]);
       if (rep->dual) rep->dual[b] = dots - epT * mass;
       if (rep->transport_cost) rep->transport_cost[b] = cost;
+      if (rep->range_iter) rep->range_iter[b] = riter[b];
+      if (rep->range_loss && !p->cfot) {
+        auto bound = [&](auto tag, int m) { return Ops<decltype(tag)>::loss_bound(p->n, m); };
+        double lb = 0.0;
+        (void)dispatch(p->prec, [&](auto tag) -> fot_status {
+          lb = std::max(lb, bound(tag, rmin[b]));
+          return FOT_OK;
+        });
+        if (p->tail_iters > 0)
+          (void)dispatch(p->tail_prec, [&](auto tag) -> fot_status {
+            lb = std::max(lb, bound(tag, rmin[B + b]));
+            return FOT_OK;
+          });
+        rep->range_loss[b] = lb;
+      } else if (rep->range_loss) {
+        rep->range_loss[b] = 0.0;
+      }
     }
     if (p->d.flags & FOT_FLAG_NO_HISTORY) {
       std::fill(ha.begin(), ha.end(), std::numeric_limits<double>::quiet_NaN());
@@ -1343,15 +1658,19 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     rep->iters_done = iters;
     rep->nonfinite = (hflag & 1) ? 1 : 0;
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[3]));
-    rep->ms_total = ms;
-    HIP_TRY(hipEventElapsedTime(&ms, p->ev[1], p->ev[2]));
-    rep->ms_iterations = ms;
+    rep->ms_total = rep->ms_iterations = 0.0;   // (no events in a plan on the static scratch array)
+    if (p->ev[0]) {
+      HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[3]));
+      rep->ms_total = ms;
+      HIP_TRY(hipEventElapsedTime(&ms, p->ev[1], p->ev[2]));
+      rep->ms_iterations = ms;
+    }
     double tot = 0.0;
     int cnt = 0;
     for (int i = 0; i + 1 < p->prof_used; i += 2) {
       HIP_TRY(hipEventElapsedTime(&ms, p->prof[i], p->prof[i + 1]));
       tot += ms;
+      if (rep->ms_launches && cnt < 4 * iters) rep->ms_launches[cnt] = ms;
       ++cnt;
     }
     rep->ms_contract = tot;
@@ -1359,18 +1678,32 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     rep->graph = p->used_graph ? 1 : 0;
   }
   if (hflag & 1) return fail(FOT_E_NONFINITE, "fot_solve: a potential became non-finite");
+  for (int b = 0; b < B; ++b)
+    if (riter[b] >= 0) {
+      char msg[512];
+      std::snprintf(msg, sizeof msg,
+                    "fot_solve: target %d: at iteration %d%s a product of the Gibbs factor fell below what "
+                    "the operand type holds at eps %.3g (terms lost to underflow could matter; use FOT_F64, "
+                    "FOT_FLAG_SMALL_TILES or a larger eps)",
+                    b, riter[b], riter[b] == iters ? " (the check after the last one)" : "", e[riter[b] < iters ? riter[b] : iters - 1]);
+      return fail(FOT_E_RANGE, msg);
+    }
+  if (pflag & 1)
+    return fail(FOT_E_RANGE, "fot_solve: one more u-update in the operand type at the final potentials gave a "
+                             "non-finite potential: the products lost range at this eps");
   {
     // the final products (column marginal, and the probe's row discrepancy) are exact up to the
     // operand type's rounding.  Bounds from sweeps against the oracle over n and eps: above each
     // type's largest value in accurate solves (FP16 3.1e-4, BF16 7.8e-4) and below the values of
     // solves whose potentials had drifted (FP16 from 7.5e-4, BF16 1.3e-2).  FP16's range loss is
     // systematic (a biased error), so its bound is the tightest of the 16-bit types.
+    const int fprec = p->tail_iters > 0 ? p->tail_prec : p->prec;   // the final iterations' type
     const double bound = p->cfot                 ? 1e-6
-                         : p->prec == FOT_F64    ? 1e-8
-                         : p->prec == FOT_F32    ? 1e-5
-                         : p->prec == FOT_BF16X3 ? 1e-4
-                         : p->prec == FOT_F16    ? 5e-4
-                                                 : 5e-3;
+                         : fprec == FOT_F64    ? 1e-8
+                         : fprec == FOT_F32    ? 1e-5
+                         : fprec == FOT_BF16X3 ? 1e-4
+                         : fprec == FOT_F16    ? 5e-4
+                                               : 5e-3;
     for (int b = 0; b < B; ++b) {
       // the larger of the final column-marginal L1 (the last V-half's products) and the probe's
       // row-marginal discrepancy (the u-direction products at the final potentials)

@@ -23,6 +23,7 @@
 //           marginal-error partial, and writes the next pass-1 operand At and its exponents.
 #pragma once
 
+#include <climits>
 #include <type_traits>
 
 #include "fot_kernels.hpp"
@@ -66,7 +67,34 @@ struct FusedArgs {
   int err_on;               // pass 2: evaluate the marginal-error partial (reads the old potential)
   int band;                 // Lambda[i][k] is zero in the operand type for |i - k| > band (>= n: no zeros)
   const int* kexpL;         // LN form: [np][nb] exponents of the block-normalised Lambda (nb as kexp)
+  int* range_iter;          // [batch] or nullptr: lowest `iter` at which an output failed the range check
+  int iter;                 // iteration index recorded by the range check
+  int* range_min;           // [batch]: lowest range margin of any output (see range_margin)
+  int range_thr;            // an output whose margin is below this fails the range check
 };
+
+// Range check of a contraction output.  Each term of a block's partial sum is a product of two
+// factors that are at most 1 after the block normalisation; a term the operand type cannot hold
+// (a factor or the product below the type's smallest normal number, flushed or rounded) is off by
+// less than 2^-125 (FP32, BF16, BF16x3), 2^-1021 (FP64) or 2^-23 (FP16) of its block's scale.  An
+// output formed from n terms therefore loses less than n 2^-125 (...) of the largest block scale
+// it was formed from.  Its margin is the binary exponent of the output relative to that scale
+// (frexp, so an output of 2^e x [1/2, 1) with scale 2^s has margin e - s; an output of zero
+// from a line with mass has margin RANGE_ZERO): the relative loss is below n 2^-125 2^-margin.
+// The kernels record the lowest margin of every target, and the iteration at which a margin first
+// fell below a threshold the host derives from the type's tolerance.
+constexpr int RANGE_ZERO = -100000;
+__device__ __forceinline__ int range_margin(double v, int scale) {
+  int ex;
+  (void)frexp(v, &ex);
+  return v > 0.0 ? ex - scale : RANGE_ZERO;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
 
 // exp(x - K ln 2) rounded to the operand type, with the K of a block's maximum.  The prep
 // kernel and the pass-2 epilogue both use these two functions, so the operand built after a
@@ -434,6 +462,15 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   int lcur[NL], lprev[NL];
 #pragma unroll
   for (int q = 0; q < NL; ++q) lcur[q] = lprev[q] = 0;
+  // LN: the largest block scale 2^(K + KL) each output was formed from (the range check's
+  // reference; without Lambda's exponents it is 2^0, the reference exponent's own block)
+  int emx[LN ? RB : 1][LN ? CB : 1][4];
+#pragma unroll
+  for (int i = 0; i < (LN ? RB : 1); ++i)
+#pragma unroll
+    for (int j = 0; j < (LN ? CB : 1); ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) emx[i][j][e] = KSENT;
   auto lrow = [&](int q) -> int {
     return (PASS == 1) ? wn * C::WTN + q * 16 + r16 : wm * C::WTM + (q / 4) * 16 + Mma<T>::row(g, q % 4);
   };
@@ -538,8 +575,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < 4; ++e) {
               accd[rb][cb][e] += ldexp((double)acc[par ^ 1][rb][cb][e], fscale(rb, cb, e));
+              if constexpr (LN) emx[rb][cb][e] = max(emx[rb][cb][e], fscale(rb, cb, e));
+            }
             acc[par ^ 1][rb][cb] = acc_t{};
           }
       }
@@ -585,8 +624,25 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         for (int e = 0; e < 4; ++e) {
           const double v = lastpar ? (double)acc[1][rb][cb][e] : (double)acc[0][rb][cb][e];
           accd[rb][cb][e] += ldexp((double)v, fscale(rb, cb, e));
+          if constexpr (LN) emx[rb][cb][e] = max(emx[rb][cb][e], fscale(rb, cb, e));
         }
   }
+  // range margins of the outputs (see range_margin): the largest block scale is 2^0 without
+  // Lambda's exponents (the reference block of the row), 2^emx with them
+  auto margin_of = [&](int rb, int cb, int e, double v) -> int {
+    if constexpr (LN)
+      return range_margin(v, emx[rb][cb][e]);
+    else
+      return range_margin(v, 0);
+  };
+  auto range_report = [&](int mmin) {
+    if (!p.range_min) return;
+    mmin = wave_min_int(mmin);
+    if (lane == 0 && mmin < INT_MAX) {
+      atomicMin(p.range_min + bz, mmin);
+      if (mmin < p.range_thr) atomicMin(p.range_iter + bz, p.iter);
+    }
+  };
 
   // ---------------------------------------------------------------- epilogues
   // accd[rb][cb][e] belongs to output row row0 + wm*WTM + rb*16 + Mma<T>::row(g, e) and column
@@ -596,6 +652,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     // W[L][k] = accd 2^{R_L}.  Column block exponent K'[k] = max over this tile's rows of the
     // binary exponent of W; Bt[k][L] = W 2^{-K'} in (0, 1).
     int ecol[CB];
+    int mmin = INT_MAX;
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) ecol[cb] = KSENT;
 #pragma unroll
@@ -610,7 +667,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           int ex;
           (void)frexp(v, &ex);
           ecol[cb] = max(ecol[cb], (i < n && j < n && v > 0.0) ? rref[lr] + ex : KSENT);
+          // a row with mass has a positive product with Lambda at every column
+          if (i < n && j < n && rref[lr] != KSENT) mmin = min(mmin, margin_of(rb, cb, e, v));
         }
+    range_report(mmin);
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
       ecol[cb] = max(ecol[cb], __shfl_xor(ecol[cb], 16, 64));
@@ -695,6 +755,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     double* lns = p.lnS_out ? p.lnS_out + (size_t)bz * plane : nullptr;
     double err = 0.0;
     bool bad = false;
+    int mmin = INT_MAX;
     double fnew_v[CB][RB][4];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -728,6 +789,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
             err += ok ? (double)(zm ? tz : ta) : 0.0;
           }
           bad = bad || (ok && !zm && !(fabs(fnew) < INFINITY));
+          if (ok && !zm && rref[lc] != KSENT) mmin = min(mmin, margin_of(rb, cb, e, v));
           const size_t o = (size_t)i * np + j;
           if (ok) {
             pot[o] = fnew;
@@ -737,6 +799,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         }
     }
     if (bad) atomicOr(p.flag, 1);
+    range_report(mmin);
     if (p.err_on) {
       err = wave_sum_dpp(err);
       if (lane == 0) red[wave] = err;

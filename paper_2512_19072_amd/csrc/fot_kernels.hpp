@@ -1,18 +1,19 @@
-// Device code of the FOT library for gfx950 (CDNA4).
+// Device code of the FOT library for gfx950 (CDNA4), apart from the fused iteration kernels.
 //
-// The hot loop of Algorithm 1 (arXiv 2512.19072, Sec. 3) is the Gibbs-kernel application
-// S = Lambda . V . Lambda of Eq. 7 (and Lambda . u . Lambda of Eq. 8).  Here it runs in the
-// log domain as two dense per-axis products, each an MFMA GEMM C = A . B^T with both
-// operands stored K-contiguous:
-//
-//   pass 1  W[L][k]   = sum_M  At[L][M] * Lambda[k][M]    At = exp(psi/eps - m_L)  (row shift m_L)
-//   pass 2  S[j][k]   = sum_L  Lambda[j][L] * Bt[k][L]    Bt = exp(ln W - m'_k)^T  (column shift m'_k)
-//
-// so ln S = m'_k + ln(C).  The potential update f = eps (ln a - ln S) and the row-marginal
-// error of the entering plan are fused into the pass-2 epilogue (Sec. 3, convergence
-// criterion), reduced per workgroup and finished in fixed order by the last workgroup, so
-// every result is bit-reproducible.  Arrays are padded to np = ceil(n / 64) * 64 with
-// zeros in the operands, so tiles never need bounds checks inside the main loop.
+// The iteration loop of Algorithm 1 (arXiv 2512.19072, Sec. 3) runs in fot_fused.hpp.  This file
+// holds what the solve needs around it:
+//   * element conversions to the operand types and the MFMA traits (16 x 16 tiles; fragment
+//     layouts and accumulator row maps) shared with the fused kernels;
+//   * a general MFMA GEMM C = A . B^T (both operands K-contiguous, 64 x 64 output tiles) for the
+//     once-per-solve FP64 products: the read-out of the final potentials (ln S, the phase moments
+//     of Eq. 9-10, the transport cost), the reverse sweep's signed contractions, and the DFT of
+//     the output beam.  Its operands are shifted per row (k_rowexp, k_rowexp_signed) before the
+//     first product and per column (k_colexpT) before the second; the column maxima are gathered
+//     across workgroups with atomicMax on order-preserving integer keys of their FP32 roundings
+//     (a shift only has to keep the sums in range, so its rounding does not matter);
+//   * set-up kernels (row sums of the squared amplitudes, ln a and ln b, Lambda, initial
+//     potentials), the read-out's reductions (k_readout, k_sum_parts, fixed-order partial sums),
+//     the trapezoid integration of the phase, and the reverse sweep's elementwise kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -674,10 +675,12 @@ __global__ __launch_bounds__(NTHREADS) void k_readout(
       acc[2] += a * scale * ((double)Scx[o] + (double)Scy[o]);
       acc[3] += a * f[o];
       if (lnS_probe) {
-        // ln S(V_T) in FP64 against the operand type's value (both -inf: no term)
+        // ln S(V_T) in FP64 against the operand type's value
         const double lnS64 = key_to_shift(colkey[(size_t)bz * np + k]) + log((double)S[o]);
         const double d = lnS_probe[o] - lnS64;
-        acc[5] += (d == d) ? a * fabs(expm1(d)) : 0.0;
+        // both -inf: no term; any other NaN (a non-finite probe) counts as the pixel's whole mass
+        const bool none = lnS_probe[o] == -INFINITY && lnS64 == -INFINITY;
+        acc[5] += none ? 0.0 : (d == d) ? a * fabs(expm1(d)) : a;
       }
     }
     const double lb = lnb[o];

@@ -25,6 +25,7 @@ FOT_FLAG_NO_GRAPH = 2
 FOT_FLAG_NO_HISTORY = 4
 FOT_FLAG_CFOT = 8
 FOT_FLAG_SMALL_TILES = 16
+FOT_FLAG_TWO_PASS = 32
 PRECISIONS = {"f64": FOT_F64, "f32": FOT_F32, "bf16": FOT_BF16, "f16": FOT_F16, "bf16x3": FOT_BF16X3}
 STATUS_NAMES = {0: "FOT_OK", 1: "FOT_E_INVALID", 2: "FOT_E_NOMEM", 3: "FOT_E_HIP", 4: "FOT_E_NONFINITE",
                 5: "FOT_E_STATE", 6: "FOT_E_UNSUPPORTED", 7: "FOT_E_RANGE"}
@@ -32,7 +33,8 @@ STATUS_NAMES = {0: "FOT_OK", 1: "FOT_E_INVALID", 2: "FOT_E_NOMEM", 3: "FOT_E_HIP
 
 class fot_plan_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("batch", ctypes.c_int), ("precision", ctypes.c_int),
-                ("max_iters", ctypes.c_int), ("checkpoint_every", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("max_iters", ctypes.c_int), ("checkpoint_every", ctypes.c_int), ("flags", ctypes.c_int),
+                ("tail_precision", ctypes.c_int), ("tail_iters", ctypes.c_int)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -43,7 +45,8 @@ class fot_report(ctypes.Structure):
                 ("err_a_history", _dp), ("err_b_history", _dp), ("iters_done", ctypes.c_int),
                 ("nonfinite", ctypes.c_int), ("ms_total", ctypes.c_double), ("ms_iterations", ctypes.c_double),
                 ("ms_contract", ctypes.c_double), ("n_contract", ctypes.c_int), ("graph", ctypes.c_int),
-                ("err_products", _dp)]
+                ("err_products", _dp), ("range_iter", ctypes.POINTER(ctypes.c_int)), ("range_loss", _dp),
+                ("ms_launches", _dp)]
 
 
 class FOTError(RuntimeError):
@@ -151,9 +154,13 @@ def fot_last_error() -> str:
 
 
 def fot_plan(n: int, batch: int = 1, precision="f32", max_iters: int = 1000, checkpoint_every: int = 0,
-             flags: int = 0, stream=None) -> int:
+             flags: int = 0, stream=None, tail_precision=None, tail_iters: int = 0) -> int:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    d = fot_plan_desc(n, batch, prec, max_iters, checkpoint_every, flags)
+    if tail_precision is None:
+        tprec = 0
+    else:
+        tprec = PRECISIONS[tail_precision] if isinstance(tail_precision, str) else int(tail_precision)
+    d = fot_plan_desc(n, batch, prec, max_iters, checkpoint_every, flags, tprec, int(tail_iters))
     h = ctypes.c_void_p()
     _check(load().fot_plan(ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h)), "fot_plan")
     return h.value
@@ -215,6 +222,9 @@ class Report:
         self.err_a_history = np.zeros((iters, batch))
         self.err_b_history = np.zeros((iters, batch))
         self.err_products = np.zeros(batch)
+        self.range_iter = np.zeros(batch, dtype=np.int32)
+        self.range_loss = np.zeros(batch)
+        self.ms_launches = np.zeros(4 * iters)
         self.raw = fot_report()
         r = self.raw
         r.err_a = self.err_a.ctypes.data_as(_dp)
@@ -224,6 +234,9 @@ class Report:
         r.err_a_history = self.err_a_history.ctypes.data_as(_dp)
         r.err_b_history = self.err_b_history.ctypes.data_as(_dp)
         r.err_products = self.err_products.ctypes.data_as(_dp)
+        r.range_iter = self.range_iter.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        r.range_loss = self.range_loss.ctypes.data_as(_dp)
+        r.ms_launches = self.ms_launches.ctypes.data_as(_dp)
 
     def __getattr__(self, name):
         return getattr(self.__dict__["raw"], name)
@@ -234,14 +247,20 @@ class Plan:
 
     def __init__(self, n: int, batch: int = 1, precision="f32", max_iters: int = 1000,
                  checkpoint_every: int = 0, profile: bool = False, graph: bool = True, history: bool = True,
-                 cfot: bool = False, small_tiles: bool = False):
+                 cfot: bool = False, small_tiles: bool = False, tail_precision=None, tail_iters: int = 0,
+                 two_pass: bool = False):
+        """``tail_precision``/``tail_iters``: the precision schedule of fot_plan_desc (the last
+        ``tail_iters`` iterations of every solve with ``tail_precision`` operands)."""
         self.n, self.batch, self.precision = n, batch, precision
         self.max_iters = max_iters
         self.checkpoint_every = checkpoint_every
         flags = ((FOT_FLAG_PROFILE if profile else 0) | (0 if graph else FOT_FLAG_NO_GRAPH)
                  | (0 if history else FOT_FLAG_NO_HISTORY) | (FOT_FLAG_CFOT if cfot else 0)
-                 | (FOT_FLAG_SMALL_TILES if small_tiles else 0))
-        self.handle = fot_plan(n, batch, precision, max_iters, checkpoint_every, flags)
+                 | (FOT_FLAG_SMALL_TILES if small_tiles else 0) | (FOT_FLAG_TWO_PASS if two_pass else 0))
+        self.handle = fot_plan(n, batch, precision, max_iters, checkpoint_every, flags,
+                               tail_precision=tail_precision, tail_iters=tail_iters)
+        # bumped by every call that replaces the state fot_backward would differentiate
+        self.state_version = 0
 
     def solve(self, g, G, eps, iters: int, warm_start: bool = False, phase: bool = True, check: bool = True,
               out=None):
@@ -253,6 +272,7 @@ class Plan:
         else:
             phase_out = torch.empty((self.batch, self.n, self.n), dtype=torch.float64, device=g.device) if phase else None
         rep = Report(self.batch, iters)
+        self.state_version += 1
         st = fot_solve(self.handle, g, G, eps, iters, warm_start, phase_out, rep.raw, check=check)
         return phase_out, rep, st
 
@@ -265,6 +285,7 @@ class Plan:
         return f, psi
 
     def set_potentials(self, f=None, psi=None):
+        self.state_version += 1
         fot_potentials(self.handle, None, None, f, psi)
 
     def backward(self, dL_dDual, dL_dphase):
@@ -307,17 +328,25 @@ def _autograd_function():
         """(dual [B], phase [B][n][n]) = FOT(G) for a fixed input amplitude g.
 
         The forward pass runs fot_solve on ``plan`` (which must have checkpoint_every > 0);
-        the backward pass runs fot_backward, replaying the iterations from the checkpoints."""
+        the backward pass runs fot_backward, replaying the iterations from the checkpoints.
+        fot_backward differentiates the plan's last solve, so a backward after another solve
+        (or a potentials write) on the same plan raises instead of returning that solve's
+        gradient."""
 
         @staticmethod
         def forward(ctx, G, g, plan, eps, iters):
             phase, rep, _ = plan.solve(g, G.detach().contiguous(), eps, iters)
             ctx.plan = plan
+            ctx.state_version = plan.state_version
             dual = torch.tensor(rep.dual, dtype=torch.float64, device=G.device)
             return dual, phase
 
         @staticmethod
         def backward(ctx, grad_dual, grad_phase):
+            if ctx.plan.state_version != ctx.state_version:
+                raise RuntimeError("fot_apply: the plan ran another solve (or its potentials were set) after this "
+                                   "forward pass; its tape no longer belongs to this node (use one plan per "
+                                   "differentiated solve)")
             dd = None if grad_dual is None else grad_dual.detach().double().cpu().numpy()
             gp = None if grad_phase is None else grad_phase.detach().double().contiguous()
             dG = ctx.plan.backward(dd, gp)

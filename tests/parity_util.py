@@ -89,3 +89,14 @@ def compare(gpu, ref, g, G, b_index=0, precision="f64"):
     e["err_b_gpu"] = float(rep.err_b[b_index])
     e["err_a_values"] = (float(rep.err_a[b_index]), float(ref.err_a))
     return e
+
+
+_WL1_REF = {}
+
+
+def workload1_ref(g, G):
+    """The oracle's solve of the 1024 x 1024 two-Gaussian workload (eps 5e-3, 200 iterations),
+    computed once per test session and shared by the tests that compare against it."""
+    if "ref" not in _WL1_REF:
+        _WL1_REF["ref"] = O.solve_sep(g, G, 5e-3, 200)
+    return _WL1_REF["ref"]

@@ -162,11 +162,31 @@ def test_autograd_function_matches_backward():
     assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-9
 
 
+def test_autograd_stale_tape_raises():
+    """Two differentiable solves on one plan: the plan's tape belongs to the second, so the
+    backward of the first must raise instead of returning the second's gradient."""
+    import torch
+    from paper_2512_19072_amd import fot as F
+    n, T, eps = 32, 6, 2e-2
+    g, Gs = _case(n, 1, 11)
+    gd = to_dev(g)
+    G1 = to_dev(Gs).requires_grad_(True)
+    G2 = to_dev(Gs * 0.9 + 0.05).requires_grad_(True)
+    plan = F.Plan(n, 1, "f64", max_iters=T, checkpoint_every=3)
+    d1, _ = F.fot_apply(G1, gd, plan, eps, T)
+    d2, _ = F.fot_apply(G2, gd, plan, eps, T)
+    d2.sum().backward()                     # the latest solve: fine
+    assert G2.grad is not None and torch.all(torch.isfinite(G2.grad))
+    with pytest.raises(RuntimeError, match="tape no longer belongs"):
+        d1.sum().backward()
+    plan.close()
+
+
 def test_workload4_full_size_adjoint():
     """512 x 512, 8 targets, FP32 operands, 100 iterations, checkpoints every 10.
     L = D + 1/2 sum_p a_p (phi_p - phi0_p)^2 with phi0 = 0 per target.  Checked against
-    central differences (h = 1e-4 on G, FP64 solves) on 64 pixels of targets 0 and 5, and
-    against the oracle's gradient of target 0."""
+    central differences (h = 1e-4 on G, FP64 solves) on 64 pixels of each of the 8 targets,
+    and against the oracle's gradient of target 0."""
     import torch
     from paper_2512_19072_amd import fot as F
     wl = W.workload(4)
@@ -181,7 +201,7 @@ def test_workload4_full_size_adjoint():
     dG = plan.backward(np.ones(B), dphi).cpu().numpy()
     assert np.all(np.isfinite(dG))
     plan.close()
-    for b in (0, 5):
+    for b in range(B):
         pix = W.fd_pixels(n, b, 64)
         Gp = np.repeat(Gs[b:b + 1], 2 * len(pix), axis=0)
         for i, q in enumerate(pix):

@@ -130,23 +130,23 @@ def test_cfot_batch_and_warm_start():
 
 
 def test_workload1_full_size_cfot():
-    """1024^2, eps 5e-3, 200 iterations by FFT convolutions, against the FP64 matrix-product path
-    (itself within 1e-15 of the oracle)."""
+    """1024^2, eps 5e-3, 200 iterations by FFT convolutions, against the oracle (FP64 matrix
+    products on the CPU).  The FFT's rounding is relative to each row, so convolution values far
+    below their row's largest keep fewer digits: 1e-8 is the measured accuracy with margin."""
     from paper_2512_19072_amd import fot as F
-    from tests.parity_util import gauge_rel, range_rel
+    from tests.parity_util import workload1_ref
     wl = W.workload(1)
     g, G = wl.images()
-    _say("case: twogauss_to_shapes n=1024 cfot vs f64 GEMM, 200 it")
+    _say("case: twogauss_to_shapes n=1024 cfot vs oracle, 200 it")
     gpu = _run_cfot(g, G, 5e-3, 200)
-    ref = run_gpu(g, G, 5e-3, 200, "f64")
-    a, b = O.normalise(g), O.normalise(G[0])
-    ef = gauge_rel(gpu["f"][0], ref["f"][0], a)
-    ep = gauge_rel(gpu["psi"][0], ref["psi"][0], b)
-    eph = range_rel(gpu["phase"][0], ref["phase"][0])
-    _say(f"  status {gpu['st']}, f {ef:.2e}, psi {ep:.2e}, phase {eph:.2e}, err_a {gpu['rep'].err_a[0]:.3e} "
-         f"(GEMM {ref['rep'].err_a[0]:.3e}), err_b {gpu['rep'].err_b[0]:.3e}")
     assert gpu["st"] == F.FOT_OK, gpu["msg"]
-    assert ef < 1e-8 and ep < 1e-8 and eph < 1e-8
+    _say("gpu done; oracle running")
+    ref = workload1_ref(g, G[0])
+    e = compare(gpu, ref, g, G[0], precision="f64")
+    _say(f"  f {e['f']:.2e}, psi {e['psi']:.2e}, phase {e['phase']:.2e}, dual {e['dual']:.2e}, "
+         f"cost {e['cost']:.2e}, err_a {gpu['rep'].err_a[0]:.3e} (oracle {ref.err_a:.3e})")
+    assert e["f"] < 1e-8 and e["psi"] < 1e-8 and e["phase"] < 1e-8
+    assert e["dual"] < 1e-8 and e["cost"] < 1e-8
 
 
 def test_cfot_annealed_schedule_and_profiling():

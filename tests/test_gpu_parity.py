@@ -17,7 +17,7 @@ import pytest
 
 import oracle as O
 from paper_2512_19072_amd import workloads as W
-from tests.parity_util import compare, run_gpu
+from tests.parity_util import compare, run_gpu, workload1_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -265,23 +265,22 @@ def test_annealed_schedule_scaled_lattice():
     assert err["dual"] < 1e-6
 
 
-_WL1_REF = {}
-
-
 def _workload1_ref(g, G):
-    if "ref" not in _WL1_REF:
-        _WL1_REF["ref"] = O.solve_sep(g, G, 5e-3, 200)
-    return _WL1_REF["ref"]
+    return workload1_ref(g, G)
 
 
-# potentials and phase, scalars, and the final row-marginal L1 the read-out must reach
-WL1_TOL = {"f32": (1e-6, 1e-6, None), "bf16x3": (1e-5, 1e-5, 1e-5)}
+# potentials and phase, scalars, and the final row-marginal L1 the read-out must reach.  FP16
+# carries three more significand bits than BF16 (its narrower exponent range is what the
+# range checks watch), so BF16's stated 1e-3 bounds its rounding too.
+WL1_TOL = {"f32": (1e-6, 1e-6, None), "bf16x3": (1e-5, 1e-5, 1e-5), "bf16": (1e-3, 1e-3, None),
+           "f16": (1e-3, 1e-3, None)}
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16", "f16"])
 def test_workload1_full_size(prec):
-    """1024 x 1024 two-Gaussian -> ellipses and rings, eps 5e-3, 200 its, FP32 and BF16x3
-    operands.  BF16x3 must also reach a final marginal error far below BF16's floor (~8e-4)."""
+    """1024 x 1024 two-Gaussian -> ellipses and rings, eps 5e-3, 200 its, in every 32- and
+    16-bit operand type (the mixed-precision workload is the same images and schedule).
+    BF16x3 must also reach a final marginal error far below BF16's floor (~8e-4)."""
     wl = W.workload(1)
     g, G = wl.images()
     _say(f"case: twogauss_to_shapes n=1024 {prec} 200 it")
@@ -330,7 +329,8 @@ def test_graph_replays_match_eager(profile):
         assert bool((ph == r[0]).all()) and bool((f == r[1]).all()) and bool((psi == r[2]).all()), (it, key)
         assert np.array_equal(rep.err_a_history, r[3]) and np.array_equal(rep.dual, r[4]), (it, key)
         if profile:
-            assert rep.n_contract == 4 * T and rep.ms_contract > 0   # the iteration kernels only
+            # the iteration kernels only: one launch per half-step on this small grid
+            assert rep.n_contract == 2 * T and rep.ms_contract > 0
 
 
 def test_no_history_flag_changes_nothing_else():
@@ -433,8 +433,9 @@ def test_u_direction_range_loss_is_reported():
     """On 129^2 at eps = 5e-4 (32-wide blocks: a quarter of the grid) the potential psi comes to
     span more than FP32 holds within one block from about the 27th iteration, so the u-updates'
     products lose values and the iterates drift from the oracle's while the last V-update's
-    column marginal stays at 1e-7.  The end-of-solve probe (one more u-direction product in the
-    operand type against FP64) reports FOT_E_RANGE at 30 iterations; at 20 the solve is exact."""
+    column marginal stays at 1e-7.  FOT_E_RANGE at 30 iterations (the in-loop check flags it from
+    iteration 18, ahead of the drift; the end-of-solve probe, one more u-direction product in the
+    operand type against FP64, sees it too); at 15 the solve is exact and not flagged."""
     from paper_2512_19072_amd import fot as F
     from tests.parity_util import to_dev
     n, eps = 129, 5e-4
@@ -455,11 +456,12 @@ def test_u_direction_range_loss_is_reported():
     plan.close()
     _say(f"bf16 err_b {rep16.err_b[0]:.2e} products {rep16.err_products[0]:.2e}")
     assert st16 == F.FOT_E_RANGE and rep16.err_products[0] > 5e-3, (st16, rep16.err_products[0])
-    gpu = run_gpu(g, G, eps, 20, "f32")
-    ref = O.solve_sep(g, G, eps, 20)
+    gpu = run_gpu(g, G, eps, 15, "f32")
+    ref = O.solve_sep(g, G, eps, 15)
     e = compare(gpu, ref, g, G, precision="f32")
     _say(e)
     assert e["f"] < 1e-6 and e["psi"] < 1e-6, e
+    assert gpu["rep"].range_iter[0] == -1
 
 
 def test_f16_systematic_underflow_is_reported():
@@ -542,3 +544,206 @@ def test_bf16_then_f32_schedule_reaches_f32_error():
     ep = gauge_rel(psis.cpu().numpy()[0], ref.psi, b)
     _say(f"f {ef:.2e} psi {ep:.2e}")
     assert ef < 1e-3 and ep < 1e-3, (ef, ep)
+
+
+def test_precision_schedule_in_one_solve():
+    """The schedule inside the library (fot_plan_desc.tail_precision / tail_iters): 29 BF16 then 1
+    FP32 iteration of workload 1 in one fot_solve equals the same schedule chained through two
+    plans and fot_potentials bit for bit (each segment builds its operands from psi), in graph
+    replays and eager launches alike; with tail_iters >= iters it is an FP32 solve bit for bit."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    n, T, k, eps = 1024, 30, 1, 5e-3
+    g, G = W.twogauss_to_shapes(n)
+    G = G if G.ndim == 2 else G[0]
+    gd, Gd = to_dev(g), to_dev(G[None])
+    _say("case: schedule bf16 29 + f32 1 in one solve, 1024^2 eps 5e-3")
+    p16 = F.Plan(n, 1, "bf16", max_iters=T)
+    p32 = F.Plan(n, 1, "f32", max_iters=T)
+    p16.solve(gd, Gd, eps, T - k)
+    f, psi = p16.potentials()
+    p32.set_potentials(f, psi)
+    ph_c, rep_c, _ = p32.solve(gd, Gd, eps, k, warm_start=True)
+    f_c, psi_c = p32.potentials()
+    ph_32, rep_32, _ = p32.solve(gd, Gd, eps, T)
+    f_32, psi_32 = p32.potentials()
+    p16.close()
+    p32.close()
+    for graph in (True, False):
+        ps = F.Plan(n, 1, "bf16", max_iters=T, graph=graph, tail_precision="f32", tail_iters=k)
+        for rep_i in range(2):           # a second solve replays the cached graph
+            ph, rep, st = ps.solve(gd, Gd, eps, T)
+            fs, psis = ps.potentials()
+            assert st == F.FOT_OK and rep.graph == (1 if graph else 0)
+            assert bool((fs == f_c).all()) and bool((psis == psi_c).all()), (graph, rep_i)
+            assert bool((ph == ph_c).all()), (graph, rep_i)
+            assert rep.err_a[0] == rep_c.err_a[0] and rep.dual[0] == rep_c.dual[0]
+        ps.close()
+    _say(f"err_a: schedule {rep.err_a[0]:.3e}, f32 alone {rep_32.err_a[0]:.3e}")
+    assert rep.err_a[0] <= 1.02 * rep_32.err_a[0]
+    # all iterations in the tail type: an FP32 solve
+    pt = F.Plan(n, 1, "bf16", max_iters=T, tail_precision="f32", tail_iters=T + 5)
+    ph_t, rep_t, _ = pt.solve(gd, Gd, eps, T)
+    f_t, psi_t = pt.potentials()
+    pt.close()
+    assert bool((f_t == f_32).all()) and bool((psi_t == psi_32).all()) and bool((ph_t == ph_32).all())
+    assert np.array_equal(rep_t.err_a_history, rep_32.err_a_history)
+    # against the oracle's 30 iterations: BF16's tolerance (the last iteration is FP32's)
+    from tests.parity_util import gauge_rel
+    ref = O.solve_sep(g, G, eps, T)
+    a, b = O.normalise(g), O.normalise(G)
+    ef = gauge_rel(fs.cpu().numpy()[0], ref.f, a)
+    ep = gauge_rel(psis.cpu().numpy()[0], ref.psi, b)
+    _say(f"f {ef:.2e} psi {ep:.2e}")
+    assert ef < 1e-3 and ep < 1e-3, (ef, ep)
+
+
+@pytest.mark.parametrize("head,tail,n,k", [("bf16", "f32", 200, 3), ("f16", "bf16x3", 130, 2), ("bf16", "f64", 72, 4)])
+def test_precision_schedule_ragged(head, tail, n, k):
+    """Schedules on ragged grids (each type's own padding and tiles share the plan) against the
+    oracle to the head type's tolerance, with the final iterations' type doing the range check."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev, gauge_rel
+    T, eps = 40, 1e-2
+    g, G = _rand_case(n, 70 + n)
+    _say(f"case: schedule {head} -> {tail} n={n} k={k}")
+    ps = F.Plan(n, 1, head, max_iters=T, tail_precision=tail, tail_iters=k)
+    ph, rep, st = ps.solve(to_dev(g), to_dev(G[None]), eps, T)
+    f, psi = ps.potentials()
+    ps.close()
+    assert st == F.FOT_OK
+    ref = O.solve_sep(g, G, eps, T)
+    e = max(gauge_rel(f.cpu().numpy()[0], ref.f, O.normalise(g)),
+            gauge_rel(psi.cpu().numpy()[0], ref.psi, O.normalise(G)))
+    _say(f"  potentials {e:.2e}")
+    assert e < 1e-3
+
+
+def test_precision_schedule_rejections():
+    from paper_2512_19072_amd import fot as F
+    for kw, status in ((dict(precision="f32", tail_precision="f32", tail_iters=1), F.FOT_E_INVALID),
+                       (dict(precision="f64", tail_precision="f32", tail_iters=1), F.FOT_E_UNSUPPORTED),
+                       (dict(precision="bf16", tail_precision="f32", tail_iters=1, checkpoint_every=5),
+                        F.FOT_E_UNSUPPORTED),
+                       (dict(precision="f64", tail_precision="f32", tail_iters=1, cfot=True), F.FOT_E_UNSUPPORTED),
+                       (dict(precision="bf16", tail_precision=9, tail_iters=1), F.FOT_E_INVALID),
+                       (dict(precision="bf16", tail_precision="f32", tail_iters=-1), F.FOT_E_INVALID)):
+        prec = kw.pop("precision")
+        with pytest.raises(F.FOTError) as ei:
+            F.Plan(64, 1, prec, max_iters=10, **kw)
+        assert ei.value.status == status, (kw, ei.value)
+
+
+def _panel_pair(n, B, prec, eps, T, graph=True, profile=False, seed=0):
+    """Solve the same case with one launch per half-step (the default on small grids) and with
+    FOT_FLAG_TWO_PASS; returns both results."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    g, G = _rand_case(n, 200 + n + seed)
+    Gs = np.stack([G * (1.0 + 0.1 * b) + 0.01 * b for b in range(B)])
+    out = []
+    for two in (False, True):
+        plan = F.Plan(n, B, prec, max_iters=T, graph=graph, profile=profile, two_pass=two)
+        ph, rep, st = plan.solve(to_dev(g), to_dev(Gs), eps, T, check=False)
+        f, psi = plan.potentials()
+        out.append(dict(ph=ph.cpu().numpy(), f=f.cpu().numpy(), psi=psi.cpu().numpy(), rep=rep, st=st))
+        plan.close()
+    return g, Gs, out
+
+
+@pytest.mark.parametrize("n,B,prec", [(64, 1, "f32"), (100, 1, "f32"), (128, 2, "f32"), (200, 1, "f32"),
+                                      (256, 1, "f32"), (128, 1, "bf16"), (130, 2, "bf16"), (96, 1, "f16")])
+def test_one_launch_half_steps_equal_two_launches(n, B, prec):
+    """On small grids a half-step runs as one launch (each workgroup both per-axis products of a
+    32-column panel).  It forms every block sum, rescale and epilogue value as the two 32 x 32
+    launches do, so the potentials, phase, dual and cost are the same bits; the marginal-error
+    history is summed in other groups (FP64 rounding)."""
+    from paper_2512_19072_amd import fot as F
+    _say(f"case: one-launch half-steps n={n} B={B} {prec}")
+    g, Gs, (one, two) = _panel_pair(n, B, prec, 1e-2, 30)
+    assert one["st"] == F.FOT_OK and two["st"] == F.FOT_OK, (one["st"], two["st"])
+    for k in ("f", "psi", "ph"):
+        assert np.array_equal(one[k], two[k]), k
+    for k in ("dual", "transport_cost", "err_a", "err_b", "err_products", "range_loss"):
+        assert np.array_equal(getattr(one["rep"], k), getattr(two["rep"], k)), k
+    np.testing.assert_allclose(one["rep"].err_a_history, two["rep"].err_a_history, rtol=1e-12, atol=1e-300)
+    ref = O.solve_sep(g, Gs[0], 1e-2, 30)
+    e = compare(dict(f=one["f"], psi=one["psi"], phase=one["ph"], rep=one["rep"]), ref, g, Gs[0], precision=prec)
+    tol = {"f32": 1e-6, "bf16": 1e-3, "f16": 1e-3}[prec]
+    assert e["f"] < tol and e["psi"] < tol and e["phase"] < tol, e
+
+
+def test_one_launch_half_steps_mixed_with_two_launch_ones():
+    """An annealed schedule on 200^2 from eps 1e-2, where Lambda is held raw (one launch per
+    half-step), down to 5e-4, where its entries leave FP32's range and it is held block-normalised
+    (two launches per half-step): both kinds of half-step in one solve, graph-replayed and eager,
+    equal the two-launch solve bit for bit; the profile counts one launch per half-step where the
+    single launch applies."""
+    from paper_2512_19072_amd import fot as F
+    n, T = 200, 60
+    sched = W.anneal_schedule(1e-2, 5e-4, T)
+    _say("case: one-launch and two-launch half-steps in one annealed solve, n=200 f32")
+    for graph in (True, False):
+        g, Gs, (one, two) = _panel_pair(n, 1, "f32", sched, T, graph=graph)
+        assert one["st"] == two["st"]
+        for k in ("f", "psi", "ph"):
+            assert np.array_equal(one[k], two[k]), (graph, k)
+    _, _, (one, two) = _panel_pair(n, 1, "f32", sched, T, graph=False, profile=True)
+    n_raw = sum(1 for e in sched if (n * np.sqrt(2.0 * e * 105.0) + 2.0) >= n)
+    assert two["rep"].n_contract == 4 * T
+    assert one["rep"].n_contract == 2 * n_raw + 4 * (T - n_raw), (one["rep"].n_contract, n_raw)
+    assert 0 < n_raw < T
+
+
+def test_f64_range_boundary():
+    """FP64 operands on the 257^2 two-Gaussian workload at eps = 1e-4: the products keep every term
+    that matters through 100 iterations (FOT_OK, within 1e-10 of the oracle, whose exact log-sum-
+    exp form engages from about iteration 130), and by 200 iterations some outputs have lost their
+    terms to underflow: FOT_E_RANGE, reported at the first iteration whose bound crossed the level,
+    with potentials that are indeed off the oracle's."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev, gauge_rel
+    n, eps = 257, 1e-4
+    g, G = W.twogauss_to_shapes(n)
+    gd, Gd = to_dev(g), to_dev(G[None])
+    a, b = O.normalise(g), O.normalise(G)
+    _say("case: f64 range boundary 257^2 eps 1e-4, 100 and 200 iterations")
+    plan = F.Plan(n, 1, "f64", max_iters=200)
+    _, rep, st = plan.solve(gd, Gd, eps, 100, check=False)
+    f, psi = plan.potentials()
+    ref = O.solve_sep(g, G, eps, 100)
+    e = max(gauge_rel(f.cpu().numpy()[0], ref.f, a), gauge_rel(psi.cpu().numpy()[0], ref.psi, b))
+    _say(f"  T=100: status {st}, range_loss {rep.range_loss[0]:.2e}, potentials {e:.2e}")
+    assert st == F.FOT_OK and rep.range_iter[0] == -1 and e < 1e-10
+    _, rep, st = plan.solve(gd, Gd, eps, 200, check=False)
+    f, psi = plan.potentials()
+    plan.close()
+    ref = O.solve_sep(g, G, eps, 200)
+    e = max(gauge_rel(f.cpu().numpy()[0], ref.f, a), gauge_rel(psi.cpu().numpy()[0], ref.psi, b))
+    _say(f"  T=200: status {st}, first iteration {rep.range_iter[0]}, potentials {e:.2e}")
+    assert st == F.FOT_E_RANGE and 100 <= rep.range_iter[0] < 200
+    assert e > 1e-3
+
+
+@pytest.mark.parametrize("n,prec,eps,T,reported", [
+    (257, "bf16", 2e-4, 30, True), (513, "bf16", 2e-4, 30, True), (1024, "bf16", 1e-4, 30, True),
+    (513, "f32", 1e-4, 30, True), (513, "bf16x3", 1e-4, 30, True), (1024, "bf16x3", 1e-4, 30, True),
+    (1024, "f32", 2e-4, 60, False), (1024, "bf16x3", 2e-4, 60, False), (1024, "bf16", 2e-4, 60, False)])
+def test_mid_trajectory_range_losses_are_reported(n, prec, eps, T, reported):
+    """Solves whose iterates lost products mid-trajectory while the final state stayed self-
+    consistent (the end-of-solve checks see nothing: potentials off the oracle's by 1e-3 to 3e-2)
+    are reported by the in-loop range check; the paper's eps = 2e-4 at 1024^2, where FP32, BF16x3
+    and BF16 stay within their tolerances, is not."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import to_dev
+    g, G = W.twogauss_to_shapes(n)
+    _say(f"case: mid-trajectory range n={n} {prec} eps={eps} T={T}")
+    plan = F.Plan(n, 1, prec, max_iters=T)
+    _, rep, st = plan.solve(to_dev(g), to_dev(G[None]), eps, T, check=False)
+    plan.close()
+    _say(f"  status {st}, range_loss {rep.range_loss[0]:.2e}, first iteration {rep.range_iter[0]}, "
+         f"err_products {rep.err_products[0]:.2e}")
+    if reported:
+        assert st == F.FOT_E_RANGE and 0 <= rep.range_iter[0] < T
+    else:
+        assert st == F.FOT_OK and rep.range_iter[0] == -1
