@@ -199,6 +199,25 @@ fot_status fot_solve(fot_plan_t plan, const double* g, const double* G,
                      const double* eps, int n_eps, int iters, int warm_start,
                      double* phase_out, fot_report* rep);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): one solve as fot_plan + fot_solve + fot_potentials + fot_destroy would do it, with
+ * the same kernels and bit-identical results, but with every device buffer carved from a static
+ * array of 32 MiB per GPU that the library holds until the process ends.  Nothing is allocated
+ * (no hipMalloc, no graph, no events); the iteration loop is launched kernel by kernel and the
+ * report's timing fields are 0.
+ *   desc      as for fot_plan; checkpoint_every must be 0 and FOT_FLAG_PROFILE unset
+ *             (FOT_E_INVALID otherwise); a plan whose workspace exceeds 32 MiB (about n <= 384 for
+ *             one target) is rejected with FOT_E_INVALID before anything runs
+ *   stream..rep as for fot_plan / fot_solve (a cold start: u = V = 1/n^2)
+ *   f_out, psi_out  device [batch][n][n] FP64 final potentials, or NULL; written also when the
+ *             status is FOT_E_RANGE or FOT_E_NONFINITE
+ * Every call on a GPU uses that GPU's one array and leaves its contents behind (each call clears
+ * what must start at zero): calls that overlap on one GPU (other streams or threads) race and
+ * must be serialised by the caller.  Synchronises the stream before returning. */
+fot_status fot_solve_noalloc(const fot_plan_desc* desc, void* stream, const double* g, const double* G,
+                             const double* eps, int n_eps, int iters, double* f_out, double* psi_out,
+                             double* phase_out, fot_report* rep);
+
 /* Read and/or write the potentials held by the plan (device [batch][n][n] FP64 each).
  * Outputs are written before inputs are read, so the same call can swap states.
  * Any pointer may be NULL to skip it.  Writing potentials invalidates the backward tape. */

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "fot_fused.hpp"
@@ -1464,6 +1465,34 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
 }
 
 
+// ------------------------------------------------------------------ static scratch (fot_solve_noalloc)
+// Device workspace for callers that cannot allocate: one array per GPU, held until the process
+// ends.  Host code never uses the array's name as an address (it is a host-side stand-in); the
+// device address comes from hipGetSymbolAddress, once per device with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static fot_status scratch_of_current_device(unsigned char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(FOT_E_HIP, "fot_solve_noalloc: no usable HIP device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FOT_E_HIP, std::string("fot_solve_noalloc: hipGetSymbolAddress of the scratch array: ") +
+                                 hipGetErrorString(e));
+    g_scratch_ptr[dev] = (unsigned char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FOT_OK;
+}
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1724,6 +1753,39 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
     }
   }
   return FOT_OK;
+}
+
+fot_status fot_solve_noalloc(const fot_plan_desc* desc, void* stream, const double* g, const double* G,
+                             const double* eps, int n_eps, int iters, double* f_out, double* psi_out,
+                             double* phase_out, fot_report* rep) {
+  g_err.clear();
+  if (!desc) return fail(FOT_E_INVALID, "fot_solve_noalloc: null descriptor");
+  fot_plan_desc d = *desc;
+  if (d.checkpoint_every != 0)
+    return fail(FOT_E_INVALID, "fot_solve_noalloc: no reverse mode (checkpoint_every must be 0)");
+  if (d.flags & FOT_FLAG_PROFILE) return fail(FOT_E_INVALID, "fot_solve_noalloc: FOT_FLAG_PROFILE needs events");
+  d.flags |= FOT_FLAG_NO_GRAPH;   // (a graph's instantiation would allocate)
+  int cN = 0;
+  fot_status s = validate_desc(d, &cN);
+  if (s != FOT_OK) return s;
+  unsigned char* base = nullptr;
+  if ((s = scratch_of_current_device(&base)) != FOT_OK) return s;
+  fot_plan_s plan;
+  s = plan_init(&plan, d, cN, (hipStream_t)stream, base, NOALLOC_SCRATCH_BYTES);
+  if (s == FOT_OK) s = fot_solve(&plan, g, G, eps, n_eps, iters, 0, phase_out, rep);
+  // the potentials are written also when the solve reports FOT_E_RANGE or FOT_E_NONFINITE
+  if (s == FOT_OK || s == FOT_E_RANGE || s == FOT_E_NONFINITE) {
+    const std::string msg = g_err;
+    const fot_status sp = fot_potentials(&plan, f_out, psi_out, nullptr, nullptr);
+    if (sp != FOT_OK) s = sp;
+    else g_err = msg;
+    if (hipStreamSynchronize(plan.stream) != hipSuccess && s == FOT_OK)
+      s = fail(FOT_E_HIP, "fot_solve_noalloc: stream synchronisation failed");
+  }
+  const std::string msg = g_err;
+  release(&plan);   // (frees nothing: no device buffer of this plan came from hipMalloc)
+  g_err = msg;
+  return s;
 }
 
 fot_status fot_backward(fot_plan_t p, const double* dL_dDual, const double* dL_dphase, double* dL_dG) {

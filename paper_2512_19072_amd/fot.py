@@ -102,6 +102,9 @@ def load(path: str = LIB_PATH):
     lib.fot_plan.restype = ip
     lib.fot_solve.argtypes = [vp, vp, vp, ctypes.POINTER(dp), ip, ip, ip, vp, ctypes.POINTER(fot_report)]
     lib.fot_solve.restype = ip
+    lib.fot_solve_noalloc.argtypes = [ctypes.POINTER(fot_plan_desc), vp, vp, vp, ctypes.POINTER(dp), ip, ip, vp, vp,
+                                      vp, ctypes.POINTER(fot_report)]
+    lib.fot_solve_noalloc.restype = ip
     lib.fot_potentials.argtypes = [vp, vp, vp, vp, vp]
     lib.fot_potentials.restype = ip
     lib.fot_backward.argtypes = [vp, ctypes.POINTER(dp), vp, vp]
@@ -174,6 +177,25 @@ def fot_solve(plan: int, g, G, eps, iters: int, warm_start: bool = False, phase_
                           ctypes.c_void_p(_ptr(phase_out)), ctypes.byref(report) if report is not None else None)
     if check:
         _check(st, "fot_solve")
+    return st
+
+
+def fot_solve_noalloc(n: int, batch: int, precision, g, G, eps, iters: int, f_out=None, psi_out=None,
+                      phase_out=None, report: Optional[fot_report] = None, flags: int = 0, max_iters=None,
+                      tail_precision=None, tail_iters: int = 0, stream=None, check: bool = True) -> int:
+    """fot_solve_noalloc: one cold-start solve on the library's static scratch array."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tprec = 0 if tail_precision is None else (PRECISIONS[tail_precision] if isinstance(tail_precision, str)
+                                              else int(tail_precision))
+    d = fot_plan_desc(n, batch, prec, int(max_iters or iters), 0, flags, tprec, int(tail_iters))
+    e = np.ascontiguousarray(np.atleast_1d(np.asarray(eps, dtype=np.float64)))
+    st = load().fot_solve_noalloc(ctypes.byref(d), ctypes.c_void_p(_stream_handle(stream)), ctypes.c_void_p(_ptr(g)),
+                                  ctypes.c_void_p(_ptr(G)), e.ctypes.data_as(_dp), int(e.size), int(iters),
+                                  ctypes.c_void_p(_ptr(f_out)), ctypes.c_void_p(_ptr(psi_out)),
+                                  ctypes.c_void_p(_ptr(phase_out)),
+                                  ctypes.byref(report) if report is not None else None)
+    if check:
+        _check(st, "fot_solve_noalloc")
     return st
 
 
