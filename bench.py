@@ -112,7 +112,7 @@ def pass_times(reps):
 
 
 def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile=True, graph=True, history=True,
-                cfot=False, keep=None, tail=None, tail_iters=0):
+                cfot=False, keep=None, tail=None, tail_iters=0, check=True, small_tiles=False):
     """Time `steps` solves after `warmup`; returns (elapsed s, reports).  With a dict `keep`, the last
     solve's potentials and phase of target 0 are copied into it (after the timed region)."""
     n = g.shape[-1]
@@ -120,11 +120,11 @@ def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile
     gd = torch.tensor(g, dtype=torch.float64, device=dev)
     Gd = torch.tensor(G, dtype=torch.float64, device=dev)
     plan = F.Plan(n, G.shape[0], precision, max_iters=iters, profile=profile, graph=graph, history=history,
-                  cfot=cfot, tail_precision=tail, tail_iters=tail_iters)
+                  cfot=cfot, tail_precision=tail, tail_iters=tail_iters, small_tiles=small_tiles)
     phase = torch.empty((G.shape[0], n, n), dtype=torch.float64, device=dev)
     try:
         for _ in range(warmup):
-            plan.solve(gd, Gd, eps, iters, out=phase)
+            plan.solve(gd, Gd, eps, iters, out=phase, check=check)
     except Exception:
         plan.close()
         raise
@@ -136,7 +136,8 @@ def run_variant(F, W, torch, precision, g, G, eps, iters, steps, warmup, profile
         t0 = time.perf_counter()
         reps = []
         for _ in range(steps):
-            _, rep, _ = plan.solve(gd, Gd, eps, iters, out=phase)
+            _, rep, st = plan.solve(gd, Gd, eps, iters, out=phase, check=check)
+            rep.status = st
             reps.append(rep)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -565,6 +566,33 @@ def main():
                 big[name] = f"failed: {exc}"[:160]
         conv["us_per_iteration_2048"] = big
         out["contraction_by_fft"] = conv
+
+        # the lattice workload at its own configuration: 2048^2, eps annealed 5e-2 -> 2e-3 over 400
+        # iterations (Lambda regenerated at every eps, held block-normalised once its entries leave
+        # the 32- and 16-bit range), FP32 and BF16 operands; each against its roofline: FP32 against
+        # the FP32 matrix cores (8 n^3 flop per iteration), BF16 against HBM (four launches of
+        # n^2 (12 + 2 s) algorithmic bytes per iteration) and its matrix cores
+        wl3 = W.workload(3)
+        g3, G3 = wl3.images()
+        n3, T3 = wl3.n, wl3.iters
+        lattice = {"workload": f"{wl3.name} {n3}x{n3}, eps annealed {wl3.eps[0]:g} -> {wl3.eps[-1]:g} over {T3} "
+                               "iterations, read-out included"}
+        for pp in ("f32", "bf16"):
+            el, rp = run_variant(F, W, torch, pp, g3, G3, wl3.eps, T3, 2, 1, profile=False, graph=graph, check=False)
+            ms_it = float(np.median([r.ms_iterations for r in rp])) / T3
+            tflops = 8.0 * n3 ** 3 / (ms_it * 1e-3) / 1e12
+            gbs = 4 * alg_bytes_per_launch(n3, pp) / (ms_it * 1e-3) / 1e9
+            lattice[pp] = {"value": round(n3 * n3 * T3 * 2 / el / 1e6, 3), "ms_per_solve": round(1e3 * el / 2, 3),
+                           "us_per_iteration": round(1e3 * ms_it, 2), "tflops": round(tflops, 2),
+                           "frac_mfma": round(tflops / PEAK_TFLOPS[pp], 4),
+                           "frac_hbm_algorithmic": round(gbs / HBM_PEAK_GBS, 4),
+                           "status": F.STATUS_NAMES.get(rp[-1].status, str(rp[-1].status)),
+                           "final_err_a": float(rp[-1].err_a[0]), "final_err_b": float(rp[-1].err_b[0])}
+        out["lattice_2048_annealed"] = lattice
+        log(f"bench: lattice 2048^2 annealed, 400 its: " + ", ".join(
+            f"{pp} {lattice[pp]['value']:.1f} Mpx.it/s ({lattice[pp]['ms_per_solve']:.1f} ms/solve, "
+            f"MFMA {lattice[pp]['frac_mfma']:.3f}, HBM {lattice[pp]['frac_hbm_algorithmic']:.3f}, "
+            f"{lattice[pp]['status']})" for pp in ("f32", "bf16")))
         log(f"bench: cFOT (FP64 FFT) {conv['cfot_f64_fft']['value']:.1f} Mpx.it/s "
             f"({conv['cfot_f64_fft']['us_per_iteration']:.1f} us/it, pass {conv['cfot_f64_fft']['pass_avg_us']:.1f} us), "
             f"FP64 GEMM {conv['gemm_f64']['value']:.1f}, {prec0} GEMM {conv['gemm_' + prec0]['value']:.1f}; "
@@ -575,16 +603,19 @@ def main():
         # the 32- and 16-bit forms with Lambda block-normalised (its entries span more than their
         # range there) and the same band
         paper = {"eps": 2e-4, "workload": f"twogauss_to_shapes {n}x{n}, {iters} iterations"}
-        for pp in ("f64", "f32", "bf16"):
+        for pp in ("f64", "f32", "bf16", "f32_small_tiles"):
             ks = max(2, args.steps // 2)
-            el, rp = run_variant(F, W, torch, pp, g, G, 2e-4, iters, ks, 1, profile=False, graph=graph)
+            el, rp = run_variant(F, W, torch, pp.split("_")[0], g, G, 2e-4, iters, ks, 1, profile=False, graph=graph,
+                                 check=False, small_tiles=pp.endswith("small_tiles"))
             paper[pp] = {"value": round(n * n * iters * ks / el / 1e6, 3),
                          "us_per_iteration": round(1e3 * float(np.median([r.ms_iterations for r in rp])) / iters, 2),
-                         "final_err_a": float(rp[-1].err_a[0]), "final_err_b": float(rp[-1].err_b[0])}
+                         "final_err_a": float(rp[-1].err_a[0]), "final_err_b": float(rp[-1].err_b[0]),
+                         "status": F.STATUS_NAMES.get(rp[-1].status, str(rp[-1].status)),
+                         "range_loss": float(rp[-1].range_loss[0]), "range_iter": int(rp[-1].range_iter[0])}
         out["paper_eps"] = paper
         log("bench: eps 2e-4 (1024^2): " + ", ".join(
             f"{pp} {paper[pp]['value']:.1f} Mpx.it/s ({paper[pp]['us_per_iteration']:.1f} us/it, "
-            f"err_b {paper[pp]['final_err_b']:.1e})" for pp in ("f64", "f32", "bf16")))
+            f"err_b {paper[pp]['final_err_b']:.1e}, {paper[pp]['status']})" for pp in paper if pp not in ("eps", "workload")))
 
         # synthetic re-run of the eps sweep of Fig. 3: the L1 intensity loss of the output beam of
         # 200 iterations at 512^2, for matrix products (FP64 operands, valid down to the paper's

@@ -98,7 +98,7 @@ enum {
                             largest lose accuracy: at small eps fot_solve may return
                             FOT_E_NONFINITE, or FOT_E_RANGE when the final column-marginal L1
                             exceeds 1e-6 */
-  FOT_FLAG_SMALL_TILES = 16, /* run the iteration kernels on 32 x 32 output tiles, with operands
+  FOT_FLAG_SMALL_TILES = 16 /* run the iteration kernels on 32 x 32 output tiles, with operands
                             normalised in 32-wide instead of 64-wide blocks.  fot_plan chooses
                             these tiles by itself when 64 x 64 tiles would occupy at most half of
                             the GPU's compute units (small grids); on larger grids the flag
@@ -106,12 +106,6 @@ enum {
                             range: the 32- and 16-bit operand types then reach about half the
                             eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian 1024 x 1024
                             workload).  No effect with FOT_FLAG_CFOT */
-  FOT_FLAG_TWO_PASS = 32 /* on small grids (padded side <= 256, on the 32 x 32 tiles) a half-step
-                            with 32- or 16-bit operands and the raw Gibbs factor runs as one launch
-                            (each workgroup computes both per-axis products for a panel of 32
-                            output columns); this flag keeps the two launches per half-step
-                            instead.  The potentials are bit-identical either way; only the
-                            grouping of the per-iteration marginal-error sums differs */
 };
 
 typedef struct {
@@ -168,8 +162,7 @@ typedef struct {
                              2^-1021 for FP64, 2^-23 for FP16); see FOT_E_RANGE */
   double* ms_launches;    /* [4 * iters] or NULL: FOT_FLAG_PROFILE: the HIP-event time of each
                              timed iteration-kernel launch in issue order (pass 1 and pass 2 of
-                             the u-half, then of the V-half, per iteration; one launch per half-
-                             step where FOT_FLAG_TWO_PASS describes it); n_contract entries */
+                             the u-half, then of the V-half, per iteration); n_contract entries */
 } fot_report;
 
 /* Create a plan: validates desc, allocates O(n^2 * batch) device workspace once (no later

@@ -16,7 +16,6 @@
 #include <vector>
 
 #include "fot_fused.hpp"
-#include "fot_panel.hpp"
 #include "fot_beam.hpp"
 #include "fot_cfot.hpp"
 
@@ -64,8 +63,10 @@ struct fot_plan_s {
   bool t32 = false;                         // fused kernels on 32 x 32 tiles (small grids)
   int* kexpL = nullptr;                     // LN form: [np][nbA] exponents of the block-normalised Lambda
   int* probe_flag = nullptr;                // non-finite flag of the end-of-solve probe
-  int* range_iter = nullptr;                // [batch] first iteration whose products failed the range check
-  int* range_min = nullptr;                 // [2][batch] lowest range margin (head, tail type of a schedule)
+  // range check: per wave of the fused kernels, the lowest margin and the first iteration below the
+  // level, [2 (head, tail type of a schedule)][batch][range_spt][2]
+  int* range_slots = nullptr;
+  int range_spt = 0;
   bool probing = false;                     // the probe's launches are not iteration kernels (no timing)
   int* flag = nullptr;
   // contraction operands (element type of the precision) and pass outputs (float / double)
@@ -74,11 +75,7 @@ struct fot_plan_s {
   // which have their own Lambda and operand buffers (op_set[1]; op_set[0] holds the head type's).
   // lam / opA / opB point at the set of the segment being issued.
   int tail_prec = -1, tail_iters = 0;
-  void* op_set[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
-  // the one-launch half-step (k_panel) reads opA / kexpA in every workgroup while it writes the
-  // next operand: it writes op_alt / kexp_alt instead, and the host swaps the pairs afterwards
-  void* op_alt = nullptr;
-  int* kexp_alt = nullptr;
+  void* op_set[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   double* tape = nullptr;
   int n_ckpt = 0;
   // reverse mode (allocated when checkpoint_every > 0)
@@ -100,9 +97,6 @@ struct fot_plan_s {
   double* pending_hist = nullptr;   // marginal-error sum still to be finished by the next row-exp
   const double* pending_parts = nullptr;  // the partials of that sum (written by the last half-step)
   int pending_tiles = 0;                  // and their count per target
-  double* partials2 = nullptr;      // second partials buffer: a one-launch half-step reads the
-                                    // preceding partials while it writes its own
-  bool panel = false;               // small grid: one launch per half-step (k_panel) where it applies
   bool lamH_valid = false;
   bool has_state = false;
   bool tape_valid = false;
@@ -465,74 +459,10 @@ struct Ops {
   // marginal error of the entering plan to hist[batch] (finished by the next pass 1), and, if
   // next_eps > 0, the block-normalised operand of Pout for the next half-step.  The operand of
   // Pin must be in p->opA / p->kexpA.
-  // One launch per half-step (k_panel) on small grids with raw Lambda and 32- or 16-bit operands.
-  static bool use_panel(const fot_plan_s* p, double eps) {
-    if constexpr (sizeof(T) <= 4 && !Mma<T>::PAIRED) return p->panel && !lam_ln(p, eps);
-    (void)p;
-    (void)eps;
-    return false;
-  }
-
-  static fot_status half_panel(fot_plan_s* p, double* Pout, const double* lnm, long long sMarg, double* hist,
-                               double* lnS_out, double eps, double next_eps, int* flag, int iter, int* range_iter,
-                               int* range_min) {
-    if constexpr (sizeof(T) <= 4 && !Mma<T>::PAIRED) {
-      PanelArgs a{};
-      a.A = p->opA;
-      a.kexpA = p->kexpA;
-      a.lam = p->lam;
-      a.n = p->n;
-      a.np = p->np;
-      a.nb = p->np / PANEL;
-      a.band = raw_band(p, eps);
-      a.lnmarg = lnm;
-      a.sMarg = sMarg;
-      a.pot = Pout;
-      a.lnS_out = lnS_out;
-      a.eps = eps;
-      a.inv_eps = 1.0 / eps;
-      a.next_inv_eps = next_eps > 0.0 ? 1.0 / next_eps : 0.0;
-      a.nextA = p->op_alt;   // (every workgroup reads all of opA and kexpA)
-      a.kexpN = p->kexp_alt;
-      a.flag = flag ? flag : p->flag;
-      a.err_on = hist != nullptr;
-      PendingSum ps = take_pending(p);
-      a.pend_parts = ps.parts;
-      a.pend_tiles = ps.tiles;
-      a.pend_out = ps.out;
-      a.partials = (ps.parts == p->partials) ? p->partials2 : p->partials;
-      a.range_iter = range_iter;
-      a.iter = iter;
-      a.range_min = range_min;
-      a.range_thr = range_threshold(p->n);
-      const bool prof = !p->probing && (p->d.flags & FOT_FLAG_PROFILE) && p->prof_used + 2 <= (int)p->prof.size();
-      hipEvent_t e0 = prof ? p->prof[p->prof_used] : nullptr;
-      hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
-      hipExtLaunchKernelGGL(k_panel<T>, dim3(p->np / PANEL, 1, p->B), dim3(PANEL_THREADS),
-                            (uint32_t)PanelLds<T>::bytes(p->np), p->stream, e0, e1, 0, a);
-      LAUNCH_CHECK();
-      if (prof) p->prof_used += 2;
-      p->pending_hist = hist;
-      p->pending_parts = a.partials;
-      p->pending_tiles = p->np / PANEL;
-      if (a.next_inv_eps > 0.0) {
-        std::swap(p->opA, p->op_alt);
-        std::swap(p->kexpA, p->kexp_alt);
-      }
-      return FOT_OK;
-    } else {
-      (void)p; (void)Pout; (void)lnm; (void)sMarg; (void)hist; (void)lnS_out; (void)eps; (void)next_eps;
-      (void)flag; (void)iter; (void)range_iter; (void)range_min;
-      return fail(FOT_E_UNSUPPORTED, "one-launch half-step: unsupported operand type");
-    }
-  }
-
   static fot_status half(fot_plan_s* p, const double* Pin, double* Pout, const double* lnm, long long sMarg,
                          double* hist, double* lnS_out, double eps, double next_eps, int* flag = nullptr,
-                         int iter = 0, int* range_iter = nullptr, int* range_min = nullptr) {
+                         int iter = 0, int* range_slots = nullptr) {
     (void)Pin;
-    if (use_panel(p, eps))
-      return half_panel(p, Pout, lnm, sMarg, hist, lnS_out, eps, next_eps, flag, iter, range_iter, range_min);
     const long long plane = (long long)p->plane;
     FusedArgs a{};
     a.n = p->n;
@@ -543,9 +473,9 @@ struct Ops {
     a.xcd_swizzle = 1;
     a.band = lambda_band(p, eps);
     a.kexpL = lam_ln(p, eps) ? p->kexpL : nullptr;
-    a.range_iter = range_iter;
+    a.range_slots = range_slots;
+    a.range_spt = p->range_spt;
     a.iter = iter;
-    a.range_min = range_min;
     a.range_thr = range_threshold(p->n);
     // pass 1: W = At . Lambda
     a.A = p->opA;
@@ -571,9 +501,9 @@ struct Ops {
     b.xcd_swizzle = 1;
     b.band = a.band;
     b.kexpL = a.kexpL;
-    b.range_iter = range_iter;
+    b.range_slots = range_slots;
+    b.range_spt = p->range_spt;
     b.iter = iter;
-    b.range_min = range_min;
     b.range_thr = a.range_thr;
     b.A = p->lam;
     b.sA = 0;
@@ -621,13 +551,13 @@ struct Ops {
       const bool last = (t == iters - 1);
       const bool hist = !(p->d.flags & FOT_FLAG_NO_HISTORY);
       if ((s = half(p, p->psi, p->f, p->lna, 0, hist ? p->hist_a + (size_t)t * B : nullptr, last ? p->lnS : nullptr,
-                    ep, ep, nullptr, t, p->range_iter, p->range_min + (size_t)seg * B)) != FOT_OK)
+                    ep, ep, nullptr, t, p->range_slots + (size_t)seg * B * p->range_spt * 2)) != FOT_OK)
         return s;
       // the last half-step of a segment builds no next operand: the next segment (another type)
       // builds its own from psi
       if ((s = half(p, p->f, p->psi, p->lnb, plane, hist ? p->hist_b + (size_t)t * B : nullptr,
-                    last ? p->lnSp : nullptr, ep, t + 1 == t1 ? 0.0 : e[t + 1], nullptr, t, p->range_iter,
-                    p->range_min + (size_t)seg * B)) != FOT_OK)
+                    last ? p->lnSp : nullptr, ep, t + 1 == t1 ? 0.0 : e[t + 1], nullptr, t,
+                    p->range_slots + (size_t)seg * B * p->range_spt * 2)) != FOT_OK)
         return s;
     }
     return FOT_OK;
@@ -658,8 +588,8 @@ struct Ops {
       fot_status s = prep(p, p->psi, eps);
       if (s != FOT_OK) return s;
       p->probing = true;
-      s = half(p, p->psi, p->Tx, p->lna, 0, nullptr, p->phi, eps, 0.0, p->probe_flag, iters, p->range_iter,
-               p->range_min + (size_t)seg * p->B);
+      s = half(p, p->psi, p->Tx, p->lna, 0, nullptr, p->phi, eps, 0.0, p->probe_flag, iters,
+               p->range_slots + (size_t)seg * p->B * p->range_spt * 2);
       p->probing = false;
       return s;
     }
@@ -795,7 +725,6 @@ void activate(fot_plan_s* p, int which) {
   p->lam = p->op_set[which][0];
   p->opA = p->op_set[which][1];
   p->opB = p->op_set[which][2];
-  p->op_alt = p->op_set[which][3];
 }
 
 // A solve's iterations with the precision schedule: iters - k iterations with H operands, then the
@@ -1229,8 +1158,7 @@ static fot_status validate_desc(const fot_plan_desc& d, int* cN_out) {
   if (d.precision < FOT_F64 || d.precision > FOT_BF16X3) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
-  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES |
-                  FOT_FLAG_TWO_PASS))
+  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES))
     return fail(FOT_E_INVALID, "fot_plan: unknown flag bits");
   if (d.tail_iters < 0) return fail(FOT_E_INVALID, "fot_plan: tail_iters must be >= 0");
   if (d.tail_iters > 0) {
@@ -1297,8 +1225,6 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
     return bail(fail(FOT_E_HIP, "fot_plan: cannot query the device"));
   p->t32 = (d.flags & FOT_FLAG_SMALL_TILES) ||
            2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
-  // one launch per half-step on the 32 x 32 tiles' grids up to n_p = 256 (unless asked not to)
-  p->panel = p->t32 && p->np <= PANEL_MAX_NP && !(d.flags & FOT_FLAG_TWO_PASS);
   const int tbm = p->t32 ? Ops<float>::GS::BM : Ops<float>::GC::BM;
   const int tbn = p->t32 ? Ops<float>::GS::BN : Ops<float>::GC::BN;
   // one marginal-error partial per output tile of the fused pass-2 kernel
@@ -1323,7 +1249,6 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   ALLOC(p->rowsum_G, (size_t)p->B * p->n);
   ALLOC(p->rowpart, (size_t)p->B * p->n);
   ALLOC(p->partials, (size_t)p->B * p->tiles);
-  ALLOC(p->partials2, (size_t)p->B * p->tiles);
   p->pending_parts = p->partials;
   p->pending_tiles = p->tiles;
   ALLOC(p->hist_a, (size_t)d.max_iters * p->B);
@@ -1331,8 +1256,9 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   ALLOC(p->rparts, (size_t)6 * p->B * READOUT_BLOCKS);
   ALLOC(p->rsums, (size_t)6 * p->B);
   ALLOC(p->probe_flag, (size_t)1);
-  ALLOC(p->range_iter, (size_t)p->B);
-  ALLOC(p->range_min, (size_t)2 * p->B);
+  // (the most waves any iteration kernel has per target: 32 x 32 tiles of 4 waves)
+  p->range_spt = (p->np / 32) * (p->np / 32) * 4;
+  ALLOC(p->range_slots, (size_t)2 * p->B * p->range_spt * 2);
   ALLOC(p->colkey, (size_t)p->B * p->np);
   p->nbA = p->np / tbn;
   p->nbT = p->np / tbm;
@@ -1351,12 +1277,7 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
     ALLOCV(p->op_set[1][1], BP * p->esz);
     ALLOCV(p->op_set[1][2], BP * p->esz);
   }
-  if (p->panel) {
-    for (int set = 0; set < (tail ? 2 : 1); ++set) ALLOCV(p->op_set[set][3], BP * p->esz);
-    ALLOC(p->kexp_alt, (size_t)p->B * p->np * p->nbA);
-    p->op_alt = p->op_set[0][3];
-  }
-  ALLOCV(p->Z, BP * p->zsz);
+  if (d.precision == FOT_F64) ALLOCV(p->Z, BP * p->zsz);   // (the FP64 read-out's fZ)
   if (d.precision == FOT_F64) {
     p->flam = (double*)p->lam;
     p->fA = (double*)p->opA;
@@ -1379,11 +1300,14 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   ALLOC(p->fBc, BP);
   ALLOC(p->fZy, BP);
   ALLOC(p->fZc, BP);
-  ALLOC(p->fS, BP);
-  ALLOC(p->fSx, BP);
-  ALLOC(p->fSy, BP);
-  ALLOC(p->fScx, BP);
-  ALLOC(p->fScy, BP);
+  // The five pass-2 outputs of the read-out (and the reverse sweep's fS) are written only after
+  // their inputs have been formed from fA, fA2, fZ, fZy and fZc, which are then dead (the launches
+  // are stream-ordered): they share those buffers.
+  p->fS = p->fA;
+  p->fSx = p->fA2;
+  p->fSy = p->fZ;
+  p->fScx = p->fZy;
+  p->fScy = p->fZc;
   if (cN > 0) {
     p->cfot = true;
     p->cN = cN;
@@ -1438,11 +1362,9 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
 #undef ALLOCV
   // the fused loop kernels never write the padded borders of their operands: zero them once
   for (int set = 0; set < (tail ? 2 : 1); ++set)
-    for (int k = 1; k < 4; ++k)
+    for (int k = 1; k < 3; ++k)
       if (p->op_set[set][k] && hipMemsetAsync(p->op_set[set][k], 0, BP * p->esz, p->stream) != hipSuccess)
         return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
-  if (p->kexp_alt && hipMemsetAsync(p->kexp_alt, 0, sizeof(int) * p->B * p->np * p->nbA, p->stream) != hipSuccess)
-    return bail(fail(FOT_E_HIP, "fot_plan: memset failed"));
   if (hipMemsetAsync(p->kexpA, 0, sizeof(int) * p->B * p->np * p->nbA, p->stream) != hipSuccess ||
       hipMemsetAsync(p->kexpT, 0, sizeof(int) * p->B * p->np * p->nbT, p->stream) != hipSuccess ||
       hipMemsetAsync(p->colkey, 0, sizeof(unsigned) * p->B * p->np, p->stream) != hipSuccess ||
@@ -1600,8 +1522,8 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   if (p->ev[0]) HIP_TRY(hipEventRecord(p->ev[0], p->stream));
   HIP_TRY(hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
   HIP_TRY(hipMemsetAsync(p->probe_flag, 0, sizeof(int), p->stream));
-  HIP_TRY(hipMemsetAsync(p->range_iter, 0x7f, sizeof(int) * B, p->stream));   // 0x7f7f7f7f: none
-  HIP_TRY(hipMemsetAsync(p->range_min, 0x7f, sizeof(int) * 2 * B, p->stream));
+  // 0x7f7f7f7f: nothing recorded
+  HIP_TRY(hipMemsetAsync(p->range_slots, 0x7f, sizeof(int) * 2 * B * p->range_spt * 2, p->stream));
   hipLaunchKernelGGL(k_rowsumsq, dim3(n, 1), dim3(NTHREADS), 0, p->stream, g, n, p->rowsum_g, p->flag);
   hipLaunchKernelGGL(k_logmarg, dim3(np, 1), dim3(NTHREADS), 0, p->stream, g, p->rowsum_g, n, np, p->lna, p->flag);
   hipLaunchKernelGGL(k_rowsumsq, dim3(n, B), dim3(NTHREADS), 0, p->stream, G, n, p->rowsum_G, p->flag);
@@ -1633,12 +1555,12 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   if (st != FOT_OK) return st;
 
   std::vector<double> ha((size_t)iters * B), hb((size_t)iters * B), rs((size_t)6 * B);
-  std::vector<int> riter((size_t)B), rmin((size_t)2 * B);
+  std::vector<int> riter((size_t)B, 0x7f7f7f7f), rmin((size_t)2 * B, 0x7f7f7f7f);
+  std::vector<int> slots((size_t)2 * B * p->range_spt * 2);
   int pflag = 0;
   HIP_TRY(hipMemcpyAsync(&hflag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(&pflag, p->probe_flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipMemcpyAsync(riter.data(), p->range_iter, sizeof(int) * B, hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipMemcpyAsync(rmin.data(), p->range_min, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipMemcpyAsync(slots.data(), p->range_slots, sizeof(int) * slots.size(), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(ha.data(), p->hist_a, ha.size() * 8, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(hb.data(), p->hist_b, hb.size() * 8, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipMemcpyAsync(rs.data(), p->rsums, rs.size() * 8, hipMemcpyDeviceToHost, p->stream));
@@ -1647,6 +1569,13 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   p->last_iters = iters;
   p->last_eps = e;
   p->tape_valid = (p->tape != nullptr);
+  for (int seg = 0; seg < 2; ++seg)
+    for (int b = 0; b < B; ++b)
+      for (int w = 0; w < p->range_spt; ++w) {
+        const int* sl = &slots[2 * (((size_t)seg * B + b) * p->range_spt + w)];
+        rmin[(size_t)seg * B + b] = std::min(rmin[(size_t)seg * B + b], sl[0]);
+        riter[b] = std::min(riter[b], sl[1]);
+      }
   for (int& r : riter)
     if (r == 0x7f7f7f7f) r = -1;
 

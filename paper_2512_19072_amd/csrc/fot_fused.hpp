@@ -67,9 +67,11 @@ struct FusedArgs {
   int err_on;               // pass 2: evaluate the marginal-error partial (reads the old potential)
   int band;                 // Lambda[i][k] is zero in the operand type for |i - k| > band (>= n: no zeros)
   const int* kexpL;         // LN form: [np][nb] exponents of the block-normalised Lambda (nb as kexp)
-  int* range_iter;          // [batch] or nullptr: lowest `iter` at which an output failed the range check
+  int* range_slots;         // [batch][range_spt][2] or nullptr: per wave of a launch, the lowest range
+                            // margin of its outputs (see range_margin) and the lowest `iter` at which
+                            // one fell below range_thr (one slot per wave: no two waves share an address)
+  int range_spt;            // slots per target
   int iter;                 // iteration index recorded by the range check
-  int* range_min;           // [batch]: lowest range margin of any output (see range_margin)
   int range_thr;            // an output whose margin is below this fails the range check
 };
 
@@ -81,8 +83,8 @@ struct FusedArgs {
 // it was formed from.  Its margin is the binary exponent of the output relative to that scale
 // (frexp, so an output of 2^e x [1/2, 1) with scale 2^s has margin e - s; an output of zero
 // from a line with mass has margin RANGE_ZERO): the relative loss is below n 2^-125 2^-margin.
-// The kernels record the lowest margin of every target, and the iteration at which a margin first
-// fell below a threshold the host derives from the type's tolerance.
+// Each wave records the lowest margin of its outputs, and the iteration at which a margin first fell
+// below a threshold the host derives from the type, in a slot of its own; the host reduces them.
 constexpr int RANGE_ZERO = -100000;
 __device__ __forceinline__ int range_margin(double v, int scale) {
   int ex;
@@ -90,10 +92,15 @@ __device__ __forceinline__ int range_margin(double v, int scale) {
   return v > 0.0 ? ex - scale : RANGE_ZERO;
 }
 
+// minimum over the 64 lanes of a wave: rows of 16 by DPP, then the four row results by readlane
+// (no LDS traffic); every lane returns it
 __device__ __forceinline__ int wave_min_int(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return v;
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));   // row_mirror
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // exp(x - K ln 2) rounded to the operand type, with the K of a block's maximum.  The prep
@@ -268,13 +275,21 @@ __device__ __forceinline__ void vm_wait() {
 }
 
 // 16-byte global -> LDS load of this lane's source; the wave's 64 lanes fill the 1 KB at
-// lds_dst (wave-uniform) in lane order (the compiler sets M0 to the LDS base).  The stage buffers
-// are distinct LDS objects, so the compiler's wait insertion does not make reads of one buffer wait
-// for loads into another: completion is awaited explicitly (vm_wait) before the workgroup barrier
-// that publishes a stage, and the next stage stays in flight while the current one is read.
-__device__ __forceinline__ void dma16(const void* src, unsigned char* lds_dst) {
-  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                   (__attribute__((address_space(3))) void*)lds_dst, 16, 0, 0);
+// lds_dst (wave-uniform) in lane order.  Written in assembly so that the compiler does not track
+// it: its wait insertion would otherwise assume the load may overwrite LDS that fragment reads in
+// flight still use and wait for all of them before every such load (measured: twice the time per
+// launch).  Completion is awaited explicitly (vm_wait) before the workgroup barrier that
+// publishes the stage, so the next stage stays in flight while the current one is read.  M0 (the
+// LDS base of the load) is saved and restored inside the block, so the compiler's own use of M0
+// is undisturbed and nothing reserved is clobbered; the load writes no VGPR.
+__device__ __forceinline__ void dma16(const void* src, const unsigned char* lds_dst) {
+  const unsigned lds_addr =
+      __builtin_amdgcn_readfirstlane((unsigned)(size_t)(const __attribute__((address_space(3))) unsigned char*)lds_dst);
+  unsigned saved;
+  asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+               : "=&s"(saved)
+               : "v"(src), "s"(lds_addr)
+               : "memory");
 }
 
 constexpr int FRAG_AHEAD = 2;  // LDS fragment reads issued this many MMA steps ahead
@@ -636,11 +651,13 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       return range_margin(v, 0);
   };
   auto range_report = [&](int mmin) {
-    if (!p.range_min) return;
+    if (!p.range_slots) return;
     mmin = wave_min_int(mmin);
     if (lane == 0 && mmin < INT_MAX) {
-      atomicMin(p.range_min + bz, mmin);
-      if (mmin < p.range_thr) atomicMin(p.range_iter + bz, p.iter);
+      // (atomics without a result on addresses no other wave uses: nothing waits for them)
+      int* sl = p.range_slots + 2 * ((size_t)bz * p.range_spt + (size_t)(blockIdx.x + gridDim.x * blockIdx.y) * C::NW + wave);
+      atomicMin(sl, mmin);
+      if (mmin < p.range_thr) atomicMin(sl + 1, p.iter);
     }
   };
 
