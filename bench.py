@@ -489,7 +489,7 @@ def main():
             tb += time.perf_counter() - t1
         plan.close()
         out["adjoint"] = {"workload": f"{wl4.name} {n4}x{n4}, {B4} targets, eps {float(wl4.eps[0])}, {T4} iterations, "
-                                      f"checkpoints every {wl4.checkpoint_every}, FP32 operands (FP64 reverse sweep)",
+                                      f"checkpoints every {wl4.checkpoint_every}, FP32 operands (FP32 reverse sweep)",
                           "ms_forward": round(1e3 * tf / args.steps, 3), "ms_backward": round(1e3 * tb / args.steps, 3),
                           "backward_over_forward": round(tb / tf, 3),
                           "value_forward": round(B4 * n4 * n4 * T4 * args.steps / tf / 1e6, 3),

@@ -98,7 +98,7 @@ enum {
                             largest lose accuracy: at small eps fot_solve may return
                             FOT_E_NONFINITE, or FOT_E_RANGE when the final column-marginal L1
                             exceeds 1e-6 */
-  FOT_FLAG_SMALL_TILES = 16 /* run the iteration kernels on 32 x 32 output tiles, with operands
+  FOT_FLAG_SMALL_TILES = 16, /* run the iteration kernels on 32 x 32 output tiles, with operands
                             normalised in 32-wide instead of 64-wide blocks.  fot_plan chooses
                             these tiles by itself when 64 x 64 tiles would occupy at most half of
                             the GPU's compute units (small grids); on larger grids the flag
@@ -106,6 +106,13 @@ enum {
                             range: the 32- and 16-bit operand types then reach about half the
                             eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian 1024 x 1024
                             workload).  No effect with FOT_FLAG_CFOT */
+  FOT_FLAG_F64_REVERSE = 32 /* fot_backward after an FP32 solve: run the reverse half-steps with FP64
+                            operands, as for the other precisions.  Without the flag they use FP32
+                            operands wherever the solve held the Gibbs factor raw in FP32: on 8
+                            targets of 512 x 512 with 100 iterations (checkpoints every 10) the
+                            backward pass takes 28 ms instead of 37 ms, and the gradient's error
+                            grows from 1.6e-5 to 5.7e-5 relative to the FP64 oracle's gradient and
+                            from 3e-6 to 1.6e-5 relative to central differences of FP64 solves */
 };
 
 typedef struct {
@@ -221,7 +228,10 @@ fot_status fot_potentials(fot_plan_t plan, double* f_out, double* psi_out,
  * without warm_start changes since): given dL/dD per target (HOST [batch], NULL = 0) and
  * dL/dphase (device [batch][n][n] FP64, NULL = 0), write dL/dG (device [batch][n][n] FP64).
  * The iterations are replayed from the stored checkpoints segment by segment; the replay is
- * bit-identical to the forward solve.  Zero-amplitude target pixels get gradient 0. */
+ * bit-identical to the forward solve.  Each reverse half-step is one signed contraction
+ * Lambda (v e^{-ln S}) Lambda run on the fused iteration kernels (signed block-normalised operands,
+ * FP64 block sums), with FP32 operands after an FP32 solve unless FOT_FLAG_F64_REVERSE is set
+ * (FP64 operands otherwise).  Zero-amplitude target pixels get gradient 0. */
 fot_status fot_backward(fot_plan_t plan, const double* dL_dDual, const double* dL_dphase,
                         double* dL_dG);
 

@@ -81,7 +81,7 @@ struct fot_plan_s {
   // reverse mode (allocated when checkpoint_every > 0)
   double *fbar = nullptr, *psibar = nullptr, *psibar2 = nullptr, *psiprev = nullptr, *lbbar = nullptr;
   double *Tbx = nullptr, *Tby = nullptr, *wtmp = nullptr, *cbar = nullptr, *rsum_tmp = nullptr;
-  double *gsums = nullptr, *dd_dev = nullptr;
+  double *gsums = nullptr, *gparts = nullptr, *dd_dev = nullptr;
   double *seg_f = nullptr, *seg_psi = nullptr, *seg_lnS = nullptr, *seg_lnSp = nullptr;
   // The phase read-out and the reverse-sweep contractions run with FP64 operands in every
   // precision (once per solve; their signed sums cancel too strongly for FP32).  For FP64 plans
@@ -201,9 +201,6 @@ PendingSum take_pending(fot_plan_s* p) {
 }
 
 fot_status rev_lambda(fot_plan_s* p, double eps);
-fot_status rev_contract(fot_plan_s* p, const double* v, const double* L);
-fot_status rev_axpy(fot_plan_s* p, const double* P, double eps, const double* lnm, long long sMarg, double scale,
-                    int row_coord, int col_coord, int acc, double* out);
 
 // Run `loop` as a cached HIP graph replayed on p->stream (captured on a private stream), keyed by
 // the eps schedule and the tape setting.  If capture or instantiation fails, the loop is
@@ -251,6 +248,30 @@ fot_status run_graph(fot_plan_s* p, const std::vector<double>& e, int iters, Loo
   p->used_graph = true;
   return FOT_OK;
 }
+
+// One reverse half-step (see Ops<T>::adj_step):
+//   out = mask ? (acc ? out : 0) + w e^{P/eps} K(v e^{-L}) : 0,   K = Lambda (x) Lambda,
+// w = scale times the coordinates selected by `coords` (bit 0 rows, bit 1 columns), mask
+// ln m > -inf; with lb, also lb += lb_scale out where the mask holds.  With next_L, the pass-1
+// operand of the next half-step (v = the new out, L = next_L, in the type of next_eps) is written
+// instead of out, which nothing else reads then.
+struct AdjStep {
+  const double* v;
+  const double* L;
+  const double* P;
+  double eps;
+  const double* lnm;
+  long long sMarg;
+  double scale;
+  int coords;
+  int acc;
+  double* out;
+  double* lb;
+  double lb_scale;
+  const double* next_L;
+  double next_eps;
+  bool have_operand;   // the previous step built this step's operand
+};
 
 template <typename T>
 struct Ops {
@@ -402,11 +423,11 @@ struct Ops {
   // Block-normalised pass-1 operand of a potential (start of a solve or of a replayed segment).
   static fot_status prep(fot_plan_s* p, const double* P, double eps) {
     if (p->t32)
-      hipLaunchKernelGGL((k_prep_blocks<T, GS::BN>), dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np,
-                         1.0 / eps, (T*)p->opA, p->kexpA);
+      hipLaunchKernelGGL((k_prep_blocks<T, GS::BN>), dim3(p->np * p->np / (256 * PREP_U), p->B), dim3(256), 0, p->stream, P,
+                         p->n, p->np, 1.0 / eps, (T*)p->opA, p->kexpA);
     else
-      hipLaunchKernelGGL((k_prep_blocks<T, GC::BN>), dim3(p->np, p->B), dim3(64), 0, p->stream, P, p->n, p->np,
-                         1.0 / eps, (T*)p->opA, p->kexpA);
+      hipLaunchKernelGGL((k_prep_blocks<T, GC::BN>), dim3(p->np * p->np / (256 * PREP_U), p->B), dim3(256), 0, p->stream, P,
+                         p->n, p->np, 1.0 / eps, (T*)p->opA, p->kexpA);
     LAUNCH_CHECK();
     return FOT_OK;
   }
@@ -610,6 +631,86 @@ struct Ops {
   }
 
   // ---------------------------------------------------------------- reverse mode
+  // One reverse half-step (AdjStep) on the fused kernels: k_adj_prep builds the signed
+  // block-normalised operand of v e^{-L} (unless the previous step did), pass 1 forms its product
+  // with Lambda and block-normalises it per column, pass 2 forms K and ends in the update.  lam:
+  // raw Lambda in this type at eps; A, Bt: operand buffers of this type (their exponent tables are
+  // the plan's kexpA and kexpT).
+  template <typename C>
+  static void adj_launch_cfg(fot_plan_s* p, int pass, const FusedArgs& a) {
+    const dim3 grid(p->np / C::BN, p->np / C::BM, p->B);
+    const dim3 block(C::THREADS);
+    const uint32_t l1 = (uint32_t)fused_dyn_lds<1, C, false>(p->np), l2 = (uint32_t)fused_dyn_lds<2, C, false>(p->np);
+    if (pass == 1)
+      hipLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, true>), grid, block, l1, p->stream, a);
+    else
+      hipLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, false, true>), grid, block, l2, p->stream, a);
+  }
+  static fot_status adj_step(fot_plan_s* p, const void* lam, T* A, T* Bt, const AdjStep& st) {
+    if constexpr (Mma<T>::PAIRED) {
+      (void)p; (void)lam; (void)A; (void)Bt; (void)st;
+      return fail(FOT_E_UNSUPPORTED, "reverse half-step: unsupported operand type");
+    } else {
+      const long long plane = (long long)p->plane;
+      const double eps = st.eps;
+      const dim3 pg(p->np * p->np / (256 * PREP_U), p->B);
+      if (st.have_operand) {
+      } else if (p->t32) {
+        hipLaunchKernelGGL((k_adj_prep<T, GS::BN>), pg, dim3(256), 0, p->stream, st.v, st.L, p->n, p->np, A, p->kexpA);
+      } else {
+        hipLaunchKernelGGL((k_adj_prep<T, GC::BN>), pg, dim3(256), 0, p->stream, st.v, st.L, p->n, p->np, A, p->kexpA);
+      }
+      LAUNCH_CHECK();
+      FusedArgs a{};
+      a.n = p->n;
+      a.np = p->np;
+      a.nk = (int)((size_t)p->np * sizeof(T) / FROWB);
+      a.nbA = p->nbA;
+      a.nbT = p->nbT;
+      a.xcd_swizzle = 1;
+      a.band = raw_band(p, eps);
+      a.A = A;
+      a.sA = plane;
+      a.B = lam;
+      a.sB = 0;
+      a.kexp = p->kexpA;
+      a.outT = Bt;
+      a.kexpT = p->kexpT;
+      FusedArgs b = a;
+      b.A = lam;
+      b.sA = 0;
+      b.B = Bt;
+      b.sB = plane;
+      b.kexp = p->kexpT;
+      b.outT = nullptr;
+      b.kexpT = nullptr;
+      b.lnmarg = st.lnm;
+      b.sMarg = st.sMarg;
+      b.pot = const_cast<double*>(st.P);   // (read only in the reverse update)
+      b.eps = eps;
+      b.inv_eps = 1.0 / eps;
+      b.flag = p->flag;
+      b.adj_out = st.out;
+      b.adj_scale = st.scale;
+      b.adj_coords = st.coords;
+      b.adj_acc = st.acc;
+      b.adj_lb = st.lb;
+      b.adj_lb_scale = st.lb_scale;
+      b.adj_next_L = st.next_L;
+      b.nextA = A;   // (pass 1 has consumed it)
+      b.kexpN = p->kexpA;
+      if (p->t32) {
+        adj_launch_cfg<GS>(p, 1, a);
+        adj_launch_cfg<GS>(p, 2, b);
+      } else {
+        adj_launch_cfg<GC>(p, 1, a);
+        adj_launch_cfg<GC>(p, 2, b);
+      }
+      LAUNCH_CHECK();
+      return FOT_OK;
+    }
+  }
+
   static fot_status ensure_lambda(fot_plan_s* p, double eps) {
     if (p->lam_eps != eps) return fill_lambda(p, eps, false);
     return FOT_OK;
@@ -623,12 +724,30 @@ struct Ops {
     const int nseg = (T_ + k - 1) / k;
     fot_status s;
     const dim3 eg(256, B);
-    auto contract = [&](const double* v, const double* L, double eps) -> fot_status {
-      fot_status r = rev_lambda(p, eps);
-      return r != FOT_OK ? r : rev_contract(p, v, L);
+    // one reverse half-step (see adj_step): FP32 operands after an FP32 forward solve where Lambda
+    // is held raw (the loop's own Lambda and operand buffers), FP64 operands otherwise.  A step may
+    // also build the next one's operand when both use the same type and no replay comes between
+    // (it overwrites the loop's operand buffers): `ready` tells the next step.
+    auto f32_rev = [&](double eps) -> bool {
+      if constexpr (std::is_same<T, float>::value) return !lam_ln(p, eps) && !(p->d.flags & FOT_FLAG_F64_REVERSE);
+      (void)eps;
+      return false;
     };
-    auto axpy = [&](const double* P, double eps, const double* lnm, long long sMarg, double scale, int rc, int cc,
-                    int acc, double* out) { return rev_axpy(p, P, eps, lnm, sMarg, scale, rc, cc, acc, out); };
+    bool ready = false;
+    auto step = [&](AdjStep st) -> fot_status {
+      if (st.next_L && f32_rev(st.next_eps) != f32_rev(st.eps)) st.next_L = nullptr;
+      st.have_operand = ready;
+      ready = st.next_L != nullptr;
+      fot_status r;
+      if constexpr (std::is_same<T, float>::value) {
+        if (f32_rev(st.eps)) {
+          if ((r = ensure_lambda(p, st.eps)) != FOT_OK) return r;
+          return adj_step(p, p->lam, (T*)p->opA, (T*)p->opB, st);
+        }
+      }
+      if ((r = rev_lambda(p, st.eps)) != FOT_OK) return r;
+      return Ops<double>::adj_step(p, p->flam, p->fA, p->fB, st);
+    };
     // seeds: fbar = dD a (the final u-update's f enters D as <f,a>), psibar = dD b
     hipLaunchKernelGGL(k_seed, dim3(256, B), dim3(256), 0, p->stream, p->dd_dev, p->lna, 0LL, n, np, p->fbar);
     hipLaunchKernelGGL(k_seed, dim3(256, B), dim3(256), 0, p->stream, p->dd_dev, p->lnb, plane, n, np, p->psibar);
@@ -659,6 +778,7 @@ struct Ops {
         pin = p->seg_psi + q * BP;
       }
       p->pending_hist = nullptr;
+      ready = false;   // (the replay used the operand buffers)
       auto psi_in = [&](int i) -> const double* { return i > t0 ? p->seg_psi + (size_t)(i - 1 - t0) * BP : tape_in; };
       bool have_prev = false;
       if (sg == nseg - 1 && dphi) {
@@ -669,16 +789,13 @@ struct Ops {
         const double* lnSl = p->seg_lnS + (size_t)q * BP;
         const double* psiT = p->seg_psi + (size_t)q * BP;
         // psibar_T += (V_T / eps) [X K(Tbx / S) + Y K(Tby / S)]
-        if ((s = contract(p->Tbx, lnSl, ep)) != FOT_OK) return s;
-        if ((s = axpy(psiT, ep, p->lnb, plane, 1.0 / ep, 1, 0, 1, p->psibar)) != FOT_OK) return s;
-        if ((s = contract(p->Tby, lnSl, ep)) != FOT_OK) return s;
-        if ((s = axpy(psiT, ep, p->lnb, plane, 1.0 / ep, 0, 1, 1, p->psibar)) != FOT_OK) return s;
+        if ((s = step({p->Tbx, lnSl, psiT, ep, p->lnb, plane, 1.0 / ep, 1, 1, p->psibar})) != FOT_OK) return s;
+        if ((s = step({p->Tby, lnSl, psiT, ep, p->lnb, plane, 1.0 / ep, 2, 1, p->psibar})) != FOT_OK) return s;
         // psibar_{T-1} += -(V_{T-1} / eps) K((Tbx Tx + Tby Ty) / S)
         hipLaunchKernelGGL(k_moment_weight, eg, dim3(256), 0, p->stream, p->Tbx, p->Tx, p->Tby, p->Ty, n, np,
                            p->wtmp);
         LAUNCH_CHECK();
-        if ((s = contract(p->wtmp, lnSl, ep)) != FOT_OK) return s;
-        if ((s = axpy(psi_in(i), ep, p->lnb, plane, -1.0 / ep, 0, 0, 0, p->psiprev)) != FOT_OK) return s;
+        if ((s = step({p->wtmp, lnSl, psi_in(i), ep, p->lnb, plane, -1.0 / ep, 0, 0, p->psiprev})) != FOT_OK) return s;
         have_prev = true;
       }
       for (int i = t1 - 1; i >= t0; --i) {
@@ -686,22 +803,31 @@ struct Ops {
         const double ep = e[i];
         if ((s = ensure_lambda(p, ep)) != FOT_OK) return s;
         // V-update psi_i = eps (ln b - ln S'(f_i)):  lbbar += eps psibar;  fbar += -u_i K(psibar / S')
-        hipLaunchKernelGGL(k_axpy_masked, eg, dim3(256), 0, p->stream, p->psibar, p->lnb, n, np, ep, p->lbbar);
-        LAUNCH_CHECK();
-        if ((s = contract(p->psibar, p->seg_lnSp + (size_t)q * BP, ep)) != FOT_OK) return s;
-        if ((s = axpy(p->seg_f + (size_t)q * BP, ep, p->lna, 0, -1.0, 0, 0, i == T_ - 1 ? 1 : 0, p->fbar)) != FOT_OK)
+        // (below the last iteration, the step that formed psibar has added its lbbar term)
+        if (i == T_ - 1) {
+          hipLaunchKernelGGL(k_axpy_masked, eg, dim3(256), 0, p->stream, p->psibar, p->lnb, n, np, ep, p->lbbar);
+          LAUNCH_CHECK();
+        }
+        const double* lnSq = p->seg_lnS + (size_t)q * BP;
+        if ((s = step({p->psibar, p->seg_lnSp + (size_t)q * BP, p->seg_f + (size_t)q * BP, ep, p->lna, 0, -1.0, 0,
+                       i == T_ - 1 ? 1 : 0, p->fbar, nullptr, 0.0, i > 0 ? lnSq : nullptr, ep})) != FOT_OK)
           return s;
         // u-update f_i = eps (ln a - ln S(psi_{i-1})):  psibar_{i-1} = -V_{i-1} K(fbar / S)
         if (i > 0) {
-          if ((s = contract(p->fbar, p->seg_lnS + (size_t)q * BP, ep)) != FOT_OK) return s;
           double* dst = p->psibar2;
+          // the next step (V-update of iteration i - 1) in this segment: its operand now
+          const double* nextL = i - 1 >= t0 ? p->seg_lnSp + (size_t)(q - 1) * BP : nullptr;
           if (i == T_ - 1 && have_prev) {
-            if ((s = axpy(psi_in(i), ep, p->lnb, plane, -1.0, 0, 0, 1, p->psiprev)) != FOT_OK) return s;
+            if ((s = step({p->fbar, lnSq, psi_in(i), ep, p->lnb, plane, -1.0, 0, 1, p->psiprev, p->lbbar, e[i - 1],
+                           nextL, e[i - 1]})) != FOT_OK)
+              return s;
             dst = p->psiprev;
             p->psiprev = p->psibar;
             p->psibar = dst;
           } else {
-            if ((s = axpy(psi_in(i), ep, p->lnb, plane, -1.0, 0, 0, 0, dst)) != FOT_OK) return s;
+            if ((s = step({p->fbar, lnSq, psi_in(i), ep, p->lnb, plane, -1.0, 0, 0, dst, p->lbbar, e[i - 1], nextL,
+                           e[i - 1]})) != FOT_OK)
+              return s;
             p->psibar2 = p->psibar;
             p->psibar = dst;
           }
@@ -709,8 +835,9 @@ struct Ops {
       }
     }
     // normalisation Jacobian: dL/dG from lbbar and the explicit dD <psi_T, b> term
-    hipLaunchKernelGGL(k_grad_sums, dim3(B), dim3(NTHREADS), 0, p->stream, p->lbbar, p->psi, p->lnb, p->dd_dev, n,
-                       np, p->gsums);
+    hipLaunchKernelGGL(k_grad_rows, dim3(n, B), dim3(NTHREADS), 0, p->stream, p->lbbar, p->psi, p->lnb, n, np,
+                       p->gparts);
+    hipLaunchKernelGGL(k_grad_sums, dim3(B), dim3(NTHREADS), 0, p->stream, p->gparts, p->dd_dev, n, p->gsums);
     hipLaunchKernelGGL(k_grad_final, dim3(256, B), dim3(256), 0, p->stream, p->rowsum_G, p->lbbar, p->psi, p->lnb,
                        p->dd_dev, p->gsums, n, np, dG);
     LAUNCH_CHECK();
@@ -761,45 +888,6 @@ fot_status fill64(fot_plan_s* p, double eps, bool withH) {
 }
 
 fot_status rev_lambda(fot_plan_s* p, double eps) { return fill64(p, eps, false); }
-
-// Signed contraction K(w), w = v e^{-L}, with FP64 operands and accumulation: the sums of the
-// reverse sweep cancel strongly.  Leaves the pass-2 output (divided by e^{m'_k}) in p->fS and
-// the column shifts in p->colkey.
-fot_status rev_contract(fot_plan_s* p, const double* v, const double* L) {
-  typedef Ops<double> R;
-  const long long plane = (long long)p->plane;
-  fot_status s;
-  hipLaunchKernelGGL(k_rowexp_signed<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, v, L, p->n, p->np,
-                     p->mrow, p->fA, p->fA2, p->colkey);
-  LAUNCH_CHECK();
-  GemmArgs gs = R::base_args(p, p->fA, plane, p->flam, 0);
-  gs.out = p->fZy;
-  gs.sOut = plane;
-  if ((s = R::gemm_launch(p, EPI_RAW, gs)) != FOT_OK) return s;
-  GemmArgs ga = R::base_args(p, p->fA2, plane, p->flam, 0);
-  ga.out = p->fZ;
-  ga.sOut = plane;
-  ga.mrow = p->mrow;
-  ga.colkey = p->colkey;
-  if ((s = R::gemm_launch(p, EPI_LOGROW, ga)) != FOT_OK) return s;
-  dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
-  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZy,
-                     p->mrow, p->colkey, p->n, p->np, p->fB);
-  LAUNCH_CHECK();
-  GemmArgs g2 = R::base_args(p, p->flam, 0, p->fB, plane);
-  g2.out = p->fS;
-  g2.sOut = plane;
-  return R::gemm_launch(p, EPI_RAW, g2);
-}
-
-// out (masked by lnm) = [acc ? out : 0] + scale * coords * e^{P/eps} * K(w), K(w) from rev_contract.
-fot_status rev_axpy(fot_plan_s* p, const double* P, double eps, const double* lnm, long long sMarg, double scale,
-                    int row_coord, int col_coord, int acc, double* out) {
-  hipLaunchKernelGGL((k_adj_axpy<double>), dim3(256, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->fS,
-                     p->colkey, P, 1.0 / eps, lnm, sMarg, p->n, p->np, scale, row_coord, col_coord, acc, out);
-  LAUNCH_CHECK();
-  return FOT_OK;
-}
 
 // Phase read-out (Eq. 9-10), final marginals, dual value and transport cost, with FP64 operands.
 fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double* lnS_probe) {
@@ -1158,7 +1246,8 @@ static fot_status validate_desc(const fot_plan_desc& d, int* cN_out) {
   if (d.precision < FOT_F64 || d.precision > FOT_BF16X3) return fail(FOT_E_INVALID, "fot_plan: unknown precision");
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
-  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES))
+  if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES |
+                  FOT_FLAG_F64_REVERSE))
     return fail(FOT_E_INVALID, "fot_plan: unknown flag bits");
   if (d.tail_iters < 0) return fail(FOT_E_INVALID, "fot_plan: tail_iters must be >= 0");
   if (d.tail_iters > 0) {
@@ -1352,6 +1441,7 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
     ALLOC(p->cbar, (size_t)p->B * p->n);
     ALLOC(p->rsum_tmp, (size_t)p->B * p->n);
     ALLOC(p->gsums, (size_t)2 * p->B);
+    ALLOC(p->gparts, (size_t)2 * p->B * p->n);
     ALLOC(p->dd_dev, (size_t)p->B);
     ALLOC(p->seg_f, kseg * BP);
     ALLOC(p->seg_psi, kseg * BP);

@@ -73,6 +73,17 @@ struct FusedArgs {
   int range_spt;            // slots per target
   int iter;                 // iteration index recorded by the range check
   int range_thr;            // an output whose margin is below this fails the range check
+  // pass 2 of a reverse half-step (k_fused<..., ADJ = true>): pot is read only (the potential P of
+  // the update being differentiated), lnmarg masks the output
+  double* adj_out;          // [batch][np][np] updated output
+  double adj_scale;         // weight w of every term
+  int adj_coords;           // bit 0: w also times the row coordinate (i - n/2)/sqrt n; bit 1: column
+  int adj_acc;              // add to adj_out instead of overwriting it
+  double* adj_lb;           // or nullptr: also adj_lb += adj_lb_scale * (new adj_out), masked alike
+  double adj_lb_scale;
+  const double* adj_next_L; // or nullptr: write the pass-1 operand of the next reverse half-step,
+                            // v = the new output with this L (as k_adj_prep), to nextA / kexpN,
+                            // instead of adj_out (which then only the next operand needs)
 };
 
 // Range check of a contraction output.  Each term of a block's partial sum is a product of two
@@ -190,6 +201,43 @@ __device__ __forceinline__ double log_fp64(double v) {
   return fma(de, LN2_HI, fma(de, LN2_LO, lnm));
 }
 
+// m e^x 2^e2 in FP64 without forming e^x alone, which can overflow or underflow where the product
+// does not (m and x finite): x = k ln 2 + r by Cody-Waite reduction (ln 2 split into a head of 32
+// significant bits, so that k ln2_hi is exact for |k| < 2^21, and a tail), |r| <= ln2 / 2; e^r by
+// its Taylor series through r^13 / 13! (the next term is below 5e-18 of the sum); then
+// ldexp(m e^r, k + e2).  Within a few ulp.
+__device__ __forceinline__ double mul_exp_fp64(double m, double x, int e2) {
+  constexpr double LN2_HI = 0x1.62e42feep-1, LN2_LO = 0x1.a39ef35793c76p-33;
+  const double k = fmin(fmax(rint(x * INV_LN2), -4000.0), 4000.0);
+  const double r = fma(-k, LN2_LO, fma(-k, LN2_HI, x));
+  double t = 1.6059043836821613e-10;             // 1/13!
+  t = fma(t, r, 2.08767569878681e-09);           // 1/12!
+  t = fma(t, r, 2.505210838544172e-08);
+  t = fma(t, r, 2.755731922398589e-07);
+  t = fma(t, r, 2.7557319223985893e-06);
+  t = fma(t, r, 2.48015873015873e-05);
+  t = fma(t, r, 1.984126984126984e-04);
+  t = fma(t, r, 1.388888888888889e-03);
+  t = fma(t, r, 8.333333333333333e-03);
+  t = fma(t, r, 4.1666666666666664e-02);
+  t = fma(t, r, 1.6666666666666666e-01);
+  t = fma(t, r, 0.5);
+  t = fma(t, r, 1.0);
+  t = fma(t, r, 1.0);
+  const int ex = (int)k + max(min(e2, 4000), -4000);
+  return ldexp(m * t, ex);
+}
+
+// m e^x 2^e2 as accurate as an FP32-accumulated contraction (about 1e-7 relative): x / ln 2 in
+// FP64 split into its integer part k and fraction f, 2^f by the hardware exponential (V_EXP_F32)
+// of f rounded to FP32, then ldexp(m 2^f, k + e2).
+__device__ __forceinline__ double mul_exp_op32(double m, double x, int e2) {
+  const double y = x * INV_LN2;
+  const double k = fmin(fmax(floor(y), -4000.0), 4000.0);
+  const double t = (double)__builtin_amdgcn_exp2f((float)(y - k));
+  return ldexp(m * t, (int)k + max(min(e2, 4000), -4000));
+}
+
 // 64-bit DPP move (two 32-bit halves), CTRL a DPP16 row control
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -218,31 +266,93 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return s;
 }
 
-// max over groups of XB consecutive lanes (XB = 32 or 64)
+// max over groups of XB consecutive lanes (XB = 32 or 64; every lane of the wave active): rows of
+// 16 lanes by DPP (as wave_min_int), then the rows of the group by readlane (no LDS traffic)
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 template <int XB>
 __device__ __forceinline__ double group_max(double v) {
-#pragma unroll
-  for (int off = XB / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
+  static_assert(XB == 32 || XB == 64, "groups of 32 or 64 lanes");
+  v = fmax(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x141>(v));   // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));   // row_mirror
+  const double r01 = fmax(readlane_f64(v, 0), readlane_f64(v, 16));
+  const double r23 = fmax(readlane_f64(v, 32), readlane_f64(v, 48));
+  if constexpr (XB == 64) return fmax(r01, r23);
+  return (threadIdx.x & 63) < 32 ? r01 : r23;
 }
 
-// Block-normalised pass-1 operand of a potential P (FP64 [batch][np][np]), blocks of XB
-// columns: one wave per row.
+// Block-normalised pass-1 operand of a potential P (FP64 [batch][np][np]), blocks of XB columns.
+// Launched on (np^2 / 1024, batch) workgroups of 256: a workgroup covers PREP_U consecutive runs of
+// 256 elements, one element of each per thread.  The loads are unconditional (the padded plane is
+// allocated; padding values are discarded by a select) and all issued before any use: a load under
+// a branch is awaited inside the branch, which serialises them.  np is a multiple of 64, so a wave
+// holds 64 consecutive columns of one row and whole blocks.
+constexpr int PREP_U = 4;
 template <typename T, int XB>
-__global__ __launch_bounds__(64) void k_prep_blocks(const double* P, int n, int np, double inv_eps, T* out,
-                                                    int* kexp) {
-  const int j = blockIdx.x, bz = blockIdx.y, lane = threadIdx.x;
-  const int nb = np / XB;
+__global__ __launch_bounds__(256) void k_prep_blocks(const double* P, int n, int np, double inv_eps, T* out,
+                                                     int* kexp) {
+  const int bz = blockIdx.y;
   const size_t plane = (size_t)np * np;
-  T* o = out + bz * plane + (size_t)j * np;
-  int* ko = kexp + ((size_t)bz * np + j) * nb;
-  for (int c0 = 0; c0 < np; c0 += 64) {
-    const int k = c0 + lane;
-    const bool ok = j < n && k < n;
-    const double x = ok ? P[bz * plane + (size_t)j * np + k] * inv_eps : -INFINITY;
-    const int K = block_exponent(group_max<XB>(x));
-    store_op<T>(o, k, ok ? block_operand<T>(x, K) : T{});
-    if (lane % XB == 0) ko[k / XB] = K;
+  double x[PREP_U];
+#pragma unroll
+  for (int u = 0; u < PREP_U; ++u) {
+    const unsigned idx = (blockIdx.x * PREP_U + u) * 256u + threadIdx.x;   // < np^2 <= 2^26
+    x[u] = P[bz * plane + idx];
+  }
+#pragma unroll
+  for (int u = 0; u < PREP_U; ++u) {
+    const unsigned idx = (blockIdx.x * PREP_U + u) * 256u + threadIdx.x;
+    const int j = (int)(idx / (unsigned)np), k = (int)(idx - (unsigned)j * (unsigned)np);
+    x[u] = (j < n && k < n) ? x[u] * inv_eps : -INFINITY;
+  }
+#pragma unroll
+  for (int u = 0; u < PREP_U; ++u) {
+    const unsigned idx = (blockIdx.x * PREP_U + u) * 256u + threadIdx.x;   // < np^2 <= 2^26
+    const int j = (int)(idx / (unsigned)np), k = (int)(idx - (unsigned)j * (unsigned)np);
+    const int K = block_exponent(group_max<XB>(x[u]));
+    store_op<T>(out + bz * plane + (size_t)j * np, k, x[u] > -INFINITY ? block_operand<T>(x[u], K) : T{});
+    if (k % XB == 0) kexp[((size_t)bz * np + j) * (np / XB) + k / XB] = K;
+  }
+}
+
+// Signed block-normalised pass-1 operand of a reverse half-step: w = v e^{-L} (v an adjoint, L a
+// ln S of the forward iteration) as sign(v) exp(h - K ln 2) with h = ln|v| - L, K the exponent of
+// its block's largest h (formed in the log domain: e^{-L} alone can overflow).  Launched like
+// k_prep_blocks.
+template <typename T, int XB>
+__global__ __launch_bounds__(256) void k_adj_prep(const double* v, const double* L, int n, int np, T* out,
+                                                  int* kexp) {
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  double vv[PREP_U], lv[PREP_U];
+#pragma unroll
+  for (int u = 0; u < PREP_U; ++u) {
+    const unsigned idx = (blockIdx.x * PREP_U + u) * 256u + threadIdx.x;   // < np^2 <= 2^26
+    vv[u] = v[bz * plane + idx];
+    lv[u] = L[bz * plane + idx];
+  }
+#pragma unroll
+  for (int u = 0; u < PREP_U; ++u) {
+    const unsigned idx = (blockIdx.x * PREP_U + u) * 256u + threadIdx.x;
+    const int j = (int)(idx / (unsigned)np), k = (int)(idx - (unsigned)j * (unsigned)np);
+    if (!(j < n && k < n)) vv[u] = 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < PREP_U; ++u) {
+    const unsigned idx = (blockIdx.x * PREP_U + u) * 256u + threadIdx.x;   // < np^2 <= 2^26
+    const int j = (int)(idx / (unsigned)np), k = (int)(idx - (unsigned)j * (unsigned)np);
+    // (the logarithm as accurate as the operand type needs: FP64 for FP64 operands)
+    const double lg = (sizeof(T) == 8) ? log_fp64(fabs(vv[u])) : log_op32(fabs(vv[u]));
+    const double h = (vv[u] != 0.0) ? lg - lv[u] : -INFINITY;
+    const int K = block_exponent(group_max<XB>(h));
+    const T x = block_operand<T>(h, K);
+    store_op<T>(out + bz * plane + (size_t)j * np, k, vv[u] < 0.0 ? (T)(-x) : x);
+    if (k % XB == 0) kexp[((size_t)bz * np + j) * (np / XB) + k / XB] = K;
   }
 }
 
@@ -307,7 +417,9 @@ inline size_t fused_dyn_lds(int np) {
   return (size_t)(np / xb) * (fused_scaled_rows<PASS, C>() + lam_rows) * sizeof(short);
 }
 
-template <typename T, int PASS, typename C, int NBUF = FUSED_NBUF, bool LN = false>
+// ADJ: the contraction of a reverse half-step (signed operands; pass 2 ends in the reverse update
+// instead of the potential update).
+template <typename T, int PASS, typename C, int NBUF = FUSED_NBUF, bool LN = false, bool ADJ = false>
 __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   static_assert(NBUF >= 2, "at least double buffering");
   typedef typename Mma<T>::acc_t acc_t;
@@ -425,6 +537,8 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 
   // pass-2 epilogue inputs, prefetched so that their latency hides behind the K loop
   double la_v[CB][RB][4], fo_v[CB][RB][4];
+  double ao_v[ADJ ? CB : 1][ADJ ? RB : 1][4], lb_v[ADJ ? CB : 1][ADJ ? RB : 1][4];
+  double ln_v[ADJ ? CB : 1][ADJ ? RB : 1][4];
   if constexpr (PASS == 2) {
     const double* lnm = p.lnmarg + (size_t)bz * p.sMarg;
     const double* pot = p.pot + (size_t)bz * plane;
@@ -439,7 +553,12 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const bool ok = i < n && j < n;
           const size_t o = (size_t)i * np + j;
           la_v[cb][rb][e] = ok ? lnm[o] : 0.0;
-          fo_v[cb][rb][e] = (ok && p.err_on) ? pot[o] : 0.0;
+          fo_v[cb][rb][e] = (ok && (ADJ || p.err_on)) ? pot[o] : 0.0;
+          if constexpr (ADJ) {
+            ao_v[cb][rb][e] = (ok && p.adj_acc) ? p.adj_out[(size_t)bz * plane + o] : 0.0;
+            lb_v[cb][rb][e] = (ok && p.adj_lb) ? p.adj_lb[(size_t)bz * plane + o] : 0.0;
+            ln_v[cb][rb][e] = (ok && p.adj_next_L) ? p.adj_next_L[(size_t)bz * plane + o] : 0.0;
+          }
         }
     }
   }
@@ -683,9 +802,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const double v = accd[rb][cb][e];
           int ex;
           (void)frexp(v, &ex);
-          ecol[cb] = max(ecol[cb], (i < n && j < n && v > 0.0) ? rref[lr] + ex : KSENT);
+          // (signed sums of a reverse half-step: the exponent of |W|)
+          ecol[cb] = max(ecol[cb], (i < n && j < n && (ADJ ? v != 0.0 : v > 0.0)) ? rref[lr] + ex : KSENT);
           // a row with mass has a positive product with Lambda at every column
-          if (i < n && j < n && rref[lr] != KSENT) mmin = min(mmin, margin_of(rb, cb, e, v));
+          if (!ADJ && i < n && j < n && rref[lr] != KSENT) mmin = min(mmin, margin_of(rb, cb, e, v));
         }
     range_report(mmin);
 #pragma unroll
@@ -730,7 +850,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
             const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
             const int i = row0 + lr;
             const double v = (K == KSENT) ? 0.0 : ldexp(accd[rb][cb][e], rref[lr] - K);
-            if (i < n) outT[(size_t)j * np + i] = v;
+            // (a reverse half-step also writes the zeros of the padded rows i >= n: its Bt buffer
+            // is shared with other kernels)
+            if (ADJ || i < n) outT[(size_t)j * np + i] = v;
           }
         } else if constexpr (PAIRED) {
           // rows 4g .. 4g+3: one 8-byte store of their hi halves and one of their lo halves
@@ -763,6 +885,79 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           *(tv4*)(outT + (size_t)j * np + row0 + lr0) = w;
         }
       }
+    }
+  } else if constexpr (ADJ) {
+    // reverse half-step: K(w) = accd 2^{R'_k} (signed); out = mask ? (acc ? out : 0) +
+    // w e^{P/eps} K(w) : 0, formed as |accd| e^{P/eps} 2^{R'_k} in one piece so that neither
+    // e^{P/eps} nor K(w) alone has to be representable
+    double* out = p.adj_out + (size_t)bz * plane;
+    double* lb = p.adj_lb ? p.adj_lb + (size_t)bz * plane : nullptr;
+    const double csc = 1.0 / sqrt((double)n), inv_eps = p.inv_eps;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int lc = wn * C::WTN + cb * 16 + r16;
+      const int j = col0 + lc;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = row0 + wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
+          const bool ok = i < n && j < n;
+          const double v = accd[rb][cb][e];
+          double w = p.adj_scale;
+          if (p.adj_coords & 1) w *= (double)(i - n / 2) * csc;
+          if (p.adj_coords & 2) w *= (double)(j - n / 2) * csc;
+          double val = 0.0;
+          if (v != 0.0 && w != 0.0) {
+            const double x = fo_v[cb][rb][e] * inv_eps;
+            const double mag =
+                (sizeof(T) == 8) ? mul_exp_fp64(fabs(v), x, rref[lc]) : mul_exp_op32(fabs(v), x, rref[lc]);
+            val = ((v < 0.0) != (w < 0.0) ? -mag : mag) * fabs(w);
+          }
+          val += ao_v[cb][rb][e];
+          const bool keep = la_v[cb][rb][e] > -INFINITY;
+          if (ok) {
+            if (!p.adj_next_L) out[(size_t)i * np + j] = keep ? val : 0.0;
+            if (lb && keep) lb[(size_t)i * np + j] = fma(p.adj_lb_scale, val, lb_v[cb][rb][e]);
+          }
+          // log-magnitude of the next operand's element (k_adj_prep's h), -inf where it is zero
+          const double vo = (ok && keep) ? val : 0.0;
+          const double lg = (sizeof(T) == 8) ? log_fp64(fabs(vo)) : log_op32(fabs(vo));
+          ln_v[cb][rb][e] = (vo != 0.0) ? lg - ln_v[cb][rb][e] : -INFINITY;
+          lb_v[cb][rb][e] = vo;   // (its sign)
+        }
+    }
+    if (p.adj_next_L) {
+      // next pass-1 operand: this tile's columns are one exponent block of its rows
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int k = KSENT;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) k = max(k, block_exponent(ln_v[cb][rb][e]));
+          k = row16_max(k);
+          if (r16 == 0) kred[wn][wm * C::WTM + rb * 16 + Mma<T>::row(g, e)] = k;
+        }
+      __syncthreads();
+      T* nA = (T*)p.nextA + (size_t)bz * plane;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
+          const int i = row0 + lr;
+          int K = kred[0][lr];
+#pragma unroll
+          for (int w = 1; w < C::WGN; ++w) K = max(K, kred[w][lr]);
+          if (wn == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc] = K;
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int j = col0 + wn * C::WTN + cb * 16 + r16;
+            const T x = block_operand<T>(ln_v[cb][rb][e], K);
+            if (i < n && j < n) store_op<T>(nA + (size_t)i * np, j, lb_v[cb][rb][e] < 0.0 ? (T)(-x) : x);
+          }
+        }
     }
   } else {
     // S = accd 2^{R'_k};  f_new = eps (ln m - ln S) in FP64, the marginal-error partial of the

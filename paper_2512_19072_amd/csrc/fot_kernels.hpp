@@ -6,9 +6,9 @@
 //     layouts and accumulator row maps) shared with the fused kernels;
 //   * a general MFMA GEMM C = A . B^T (both operands K-contiguous, 64 x 64 output tiles) for the
 //     once-per-solve FP64 products: the read-out of the final potentials (ln S, the phase moments
-//     of Eq. 9-10, the transport cost), the reverse sweep's signed contractions, and the DFT of
-//     the output beam.  Its operands are shifted per row (k_rowexp, k_rowexp_signed) before the
-//     first product and per column (k_colexpT) before the second; the column maxima are gathered
+//     of Eq. 9-10, the transport cost) and the DFT of the output beam.  Its operands are shifted
+//     per row (k_rowexp) before the first product and per column (k_colexpT) before the second
+//     (the reverse sweep's signed contractions run on the fused kernels); the column maxima are gathered
 //     across workgroups with atomicMax on order-preserving integer keys of their FP32 roundings
 //     (a shift only has to keep the sums in range, so its rounding does not matter);
 //   * set-up kernels (row sums of the squared amplitudes, ln a and ln b, Lambda, initial
@@ -760,100 +760,6 @@ __global__ __launch_bounds__(NTHREADS) void k_center(const double* phi, const do
 }
 
 // ------------------------------------------------------------------ reverse mode
-// Every reverse half-step is one signed separable contraction
-//   out_x = c_x * e^{P_x/eps} * sum_y K_xy v_y e^{-L_y}
-// (K = Lambda (x) Lambda).  With h_y = ln|v_y| - L_y and the row shift m_r = max_row h, the
-// pass-1 operands are sign(v) e^{h - m_r} (signed) and e^{h - m_r} (magnitude); the magnitude
-// product supplies the column shifts for pass 2, so every intermediate is bounded by 1 times
-// the row/column scale and the signed sums cannot overflow.
-template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_rowexp_signed(const double* v, const double* L, int n, int np,
-                                                            double* mrow, T* out_signed, T* out_abs,
-                                                            unsigned* colkey) {
-  constexpr int MAXV = 32;
-  __shared__ double red[4];
-  const int i = blockIdx.x, bz = blockIdx.y;
-  const size_t plane = (size_t)np * np;
-  T* os = out_signed + bz * plane + (size_t)i * np;
-  T* oa = out_abs + bz * plane + (size_t)i * np;
-  if (threadIdx.x == 0) colkey[(size_t)bz * np + i] = 0u;
-  if (i >= n) {
-    for (int k = threadIdx.x; k < np; k += blockDim.x) {
-      os[k] = (T)0;
-      oa[k] = (T)0;
-    }
-    if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = 0.0;
-    return;
-  }
-  const double* vr = v + bz * plane + (size_t)i * np;
-  const double* lr = L + bz * plane + (size_t)i * np;
-  const int cnt = (n + NTHREADS - 1) / NTHREADS;
-  double h[MAXV];
-  bool neg[MAXV];
-  double m = -INFINITY;
-#pragma unroll
-  for (int c = 0; c < MAXV; ++c) {
-    if (c < cnt) {
-      const int k = threadIdx.x + c * NTHREADS;
-      double hv = -INFINITY;
-      bool ng = false;
-      if (k < n) {
-        const double vv = vr[k];
-        ng = vv < 0.0;
-        if (vv != 0.0) hv = log(fabs(vv)) - lr[k];
-      }
-      h[c] = hv;
-      neg[c] = ng;
-      m = fmax(m, hv);
-    }
-  }
-  m = block_max(m, red);
-  if (!(m > -INFINITY && m < INFINITY)) m = 0.0;
-  if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = m;
-#pragma unroll
-  for (int c = 0; c < MAXV; ++c) {
-    if (c < cnt) {
-      const int k = threadIdx.x + c * NTHREADS;
-      if (k < np) {
-        const bool ok = k < n;
-        oa[k] = ok ? exp_op<T>(h[c] - m) : (T)0;
-        os[k] = ok ? signed_exp_op<T>(h[c] - m, neg[c]) : (T)0;
-      }
-    }
-  }
-}
-
-// out = (mask ? (acc ? out : 0) + scale * wr_x * wc_x * sign(S) e^{P/eps + m'_k + ln|S|} : 0)
-// where S is the pass-2 output of a signed contraction (divided by e^{m'_k}), the mask is
-// ln(marginal) > -inf, and wr / wc are optional row / column coordinates (Eq. 9-10 moments).
-template <typename ZT>
-__global__ __launch_bounds__(NTHREADS) void k_adj_axpy(const ZT* S, const unsigned* colkey, const double* P,
-                                                       double inv_eps, const double* lnm, long long sMarg,
-                                                       int n, int np, double scale, int row_coord, int col_coord,
-                                                       int accumulate, double* out) {
-  const int bz = blockIdx.y;
-  const size_t plane = (size_t)np * np;
-  const double csc = 1.0 / sqrt((double)n);
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)(idx / n), k = (int)(idx % n);
-    const size_t o = bz * plane + (size_t)j * np + k;
-    double val = 0.0;
-    if (lnm[bz * sMarg + (size_t)j * np + k] > -INFINITY) {
-      const double s = (double)S[o];
-      double w = scale;
-      if (row_coord) w *= (double)(j - n / 2) * csc;
-      if (col_coord) w *= (double)(k - n / 2) * csc;
-      if (s != 0.0 && w != 0.0) {
-        const double mag = exp(P[o] * inv_eps + key_to_shift(colkey[(size_t)bz * np + k]) + log(fabs(s)));
-        val = ((s < 0.0) != (w < 0.0) ? -mag : mag) * fabs(w);
-      }
-      if (accumulate) val += out[o];
-    }
-    out[o] = val;
-  }
-}
-
 // acc += eps * v where the mask ln(marginal) > -inf holds (reverse of psi = eps ln b - ...).
 __global__ void k_axpy_masked(const double* v, const double* lnm, int n, int np, double eps, double* acc) {
   const int bz = blockIdx.y;
@@ -968,19 +874,37 @@ __global__ void k_moment_weight(const double* Tbx, const double* Tx, const doubl
   }
 }
 
-// Per-target sums for the normalisation Jacobian: out[0][bz] = sum lbbar, out[1][bz] = dD <psi, b>.
-__global__ __launch_bounds__(NTHREADS) void k_grad_sums(const double* lbbar, const double* psi, const double* lnb,
-                                                        const double* dD, int n, int np, double* out) {
+// Sums of the normalisation Jacobian, in fixed order: k_grad_rows forms per-row partials (one block
+// per row and target) of sum lbbar and sum b psi over the pixels with b > 0; k_grad_sums adds a
+// target's rows and writes out[bz] = sum lbbar, out[B + bz] = dD sum b psi.
+__global__ __launch_bounds__(NTHREADS) void k_grad_rows(const double* lbbar, const double* psi, const double* lnb,
+                                                        int n, int np, double* parts) {
+  __shared__ double red[4];
+  const int r = blockIdx.x, bz = blockIdx.y;
+  const size_t o0 = (size_t)bz * np * np + (size_t)r * np;
+  double s0 = 0.0, s1 = 0.0;
+  for (int k = threadIdx.x; k < n; k += NTHREADS) {
+    const double l = lnb[o0 + k];
+    if (l > -INFINITY) {
+      s0 += lbbar[o0 + k];
+      s1 += exp(l) * psi[o0 + k];
+    }
+  }
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    parts[((size_t)bz * 2) * n + r] = s0;
+    parts[((size_t)bz * 2 + 1) * n + r] = s1;
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_grad_sums(const double* parts, const double* dD, int n, double* out) {
   __shared__ double red[4];
   const int bz = blockIdx.x, B = gridDim.x;
-  const size_t plane = (size_t)np * np;
   double s0 = 0.0, s1 = 0.0;
-  for (size_t idx = threadIdx.x; idx < (size_t)n * n; idx += blockDim.x) {
-    const size_t o = bz * plane + (size_t)(idx / n) * np + (idx % n);
-    if (lnb[o] > -INFINITY) {
-      s0 += lbbar[o];
-      s1 += exp(lnb[o]) * psi[o];
-    }
+  for (int r = threadIdx.x; r < n; r += NTHREADS) {
+    s0 += parts[((size_t)bz * 2) * n + r];
+    s1 += parts[((size_t)bz * 2 + 1) * n + r];
   }
   s0 = block_sum(s0, red);
   s1 = block_sum(s1, red);

@@ -2,8 +2,8 @@
 against central finite differences.
 
 Tolerances: FP64 operands 1e-9 of the gradient's max magnitude against the oracle (both are
-FP64; they differ in summation order only); FP32 operands 1e-4 against FP64 finite
-differences (the stated target)."""
+FP64; they differ in summation order only); FP32 operands (forward, and reverse half-steps unless
+FOT_FLAG_F64_REVERSE) 1e-4 against FP64 finite differences and the oracle (the stated target)."""
 import sys
 
 import numpy as np
@@ -32,11 +32,11 @@ def _case(n, B, seed, zero=True):
     return g, Gs
 
 
-def _gpu_grad(g, Gs, eps, T, k, prec, dD, dphi):
+def _gpu_grad(g, Gs, eps, T, k, prec, dD, dphi, f64_reverse=False):
     import torch
     from paper_2512_19072_amd import fot as F
     n, B = g.shape[0], Gs.shape[0]
-    plan = F.Plan(n, B, prec, max_iters=T, checkpoint_every=k)
+    plan = F.Plan(n, B, prec, max_iters=T, checkpoint_every=k, f64_reverse=f64_reverse)
     plan.solve(to_dev(g), to_dev(Gs), eps, T)
     dG = plan.backward(dD, None if dphi is None else to_dev(dphi))
     return dG.cpu().numpy()
@@ -70,6 +70,43 @@ def test_backward_f32_forward_block_normalised_lambda():
     _say(f"case: backward f32 forward n={n} eps={eps} T={T} k={k}")
     got = _gpu_grad(g, Gs, eps, T, k, "f32", [0.9], dphi)
     ref = O.grad_G(g, Gs[0], eps, T, 0.9, dphi[0])
+    err = np.max(np.abs(got[0] - ref)) / np.max(np.abs(ref))
+    _say(f"rel err {err:.2e}")
+    assert err < 1e-4, err
+
+
+@pytest.mark.parametrize("f64_reverse", [False, True])
+def test_backward_f32_forward_raw_lambda(f64_reverse):
+    """FP32 forward with Lambda held raw (n = 64, eps = 2e-2): the reverse half-steps run with FP32
+    operands (the default) or FP64 ones (FOT_FLAG_F64_REVERSE); both within the FP32 target of 1e-4
+    of the oracle's FP64 gradient, the FP64 reverse closer."""
+    n, B, T, k, eps = 64, 2, 16, 5, 2e-2
+    g, Gs = _case(n, B, 9)
+    rng = np.random.default_rng(10)
+    dphi = rng.standard_normal((B, n, n))
+    dD = [0.8, -0.4]
+    _say(f"case: backward f32 forward raw Lambda n={n} T={T} k={k} f64_reverse={f64_reverse}")
+    got = _gpu_grad(g, Gs, eps, T, k, "f32", dD, dphi, f64_reverse=f64_reverse)
+    for b in range(B):
+        ref = O.grad_G(g, Gs[b], eps, T, dD[b], dphi[b])
+        err = np.max(np.abs(got[b] - ref)) / np.max(np.abs(ref))
+        _say(f"target {b}: rel err {err:.2e}")
+        assert err < 1e-4, (b, err)
+    assert got[0, 2, 3] == 0.0
+
+
+def test_backward_f32_forward_mixed_reverse_types():
+    """An annealed FP32 solve whose eps crosses from raw Lambda (FP32 reverse half-steps) to the
+    block-normalised form (FP64 reverse half-steps): a reverse half-step hands its successor a
+    ready operand only within one type, and the gradient stays within 1e-4 of the oracle's."""
+    n, B, T, k = 64, 1, 14, 4
+    e = W.anneal_schedule(2e-2, 2e-3, T)
+    g, Gs = _case(n, B, 11, zero=False)
+    rng = np.random.default_rng(12)
+    dphi = rng.standard_normal((B, n, n))
+    _say(f"case: backward f32 forward annealed n={n} T={T} k={k}")
+    got = _gpu_grad(g, Gs, e, T, k, "f32", [1.1], dphi)
+    ref = O.grad_G(g, Gs[0], e, T, 1.1, dphi[0])
     err = np.max(np.abs(got[0] - ref)) / np.max(np.abs(ref))
     _say(f"rel err {err:.2e}")
     assert err < 1e-4, err
