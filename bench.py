@@ -172,6 +172,42 @@ def errors_vs_oracle(out, ref, a, b):
             "transport_cost": abs(out["cost"] - ref.cost) / abs(ref.cost)}
 
 
+def adjoint_steps(F, W, torch, np, steps, warmup):
+    """The reverse-mode workload (workload 4: 512^2, 8 targets, FP32 operands, 100 iterations,
+    checkpoints every 10): `warmup` then `steps` forward solves with tape and fot_backward of
+    L = D + 1/2 sum_p a_p phi_p^2, each timed wall-clock between stream synchronisations;
+    returns the summed forward and backward seconds."""
+    wl4 = W.workload(4)
+    g4, G4 = wl4.images()
+    dev = torch.device("cuda", 0)
+    g4d = torch.tensor(g4, dtype=torch.float64, device=dev)
+    G4d = torch.tensor(G4, dtype=torch.float64, device=dev)
+    a4 = torch.tensor(g4 ** 2 / np.sum(g4 ** 2), dtype=torch.float64, device=dev)
+    B4, n4, T4 = G4.shape[0], wl4.n, wl4.iters
+    plan = F.Plan(n4, B4, "f32", max_iters=T4, checkpoint_every=wl4.checkpoint_every)
+    ph4 = torch.empty((B4, n4, n4), dtype=torch.float64, device=dev)
+    dD = np.ones(B4)
+    try:
+        for _ in range(warmup):
+            plan.solve(g4d, G4d, float(wl4.eps[0]), T4, out=ph4)
+            plan.backward(dD, (a4[None] * ph4).contiguous())
+        torch.cuda.synchronize()
+        tf = tb = 0.0
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            plan.solve(g4d, G4d, float(wl4.eps[0]), T4, out=ph4)
+            dphi = (a4[None] * ph4).contiguous()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan.backward(dD, dphi)
+            torch.cuda.synchronize()
+            tf += t1 - t0
+            tb += time.perf_counter() - t1
+    finally:
+        plan.close()
+    return tf, tb
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +225,10 @@ def main():
     ap.add_argument("--eps", type=float, default=None,
                     help="profiling aid: run the headline workload at this eps instead of its own (the "
                          "config then names it); e.g. the paper's 2e-4")
+    ap.add_argument("--adjoint-run", action="store_true",
+                    help="profiling aid: only the reverse-mode workload (gauss_to_ellipses 512x512, 8 targets, "
+                         "100 iterations, checkpoints every 10, FP32): --warmup then --steps forward solves with "
+                         "their backward passes, and one JSON line of the times")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware-counter passes: two solves launched kernel by kernel "
                          "and one 256 MiB device-to-device copy whose bytes calibrate the counters")
@@ -218,6 +258,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"pmc_run": True, "precision": args.precision, "solves": 2, "iters": iters,
                           "copy_bytes": nbytes}), flush=True)
+        return
+    if args.adjoint_run:
+        tf, tb = adjoint_steps(F, W, torch, np, args.steps, args.warmup)
+        print(json.dumps({"adjoint_run": True, "steps": args.steps, "ms_forward": round(1e3 * tf / args.steps, 3),
+                          "ms_backward": round(1e3 * tb / args.steps, 3)}), flush=True)
         return
     if args.cfot_run:
         el, rp = run_variant(F, W, torch, "f64", g, G, eps, iters, args.steps, args.warmup, profile=False,
@@ -463,31 +508,8 @@ def main():
         # iterations, checkpoints every 10): forward solve with tape, then fot_backward of
         # L = D + 1/2 sum_p a_p phi_p^2, each timed over the same steps.
         wl4 = W.workload(4)
-        g4, G4 = wl4.images()
-        dev = torch.device("cuda", 0)
-        g4d = torch.tensor(g4, dtype=torch.float64, device=dev)
-        G4d = torch.tensor(G4, dtype=torch.float64, device=dev)
-        a4 = torch.tensor(g4 ** 2 / np.sum(g4 ** 2), dtype=torch.float64, device=dev)
-        B4, n4, T4 = G4.shape[0], wl4.n, wl4.iters
-        plan = F.Plan(n4, B4, "f32", max_iters=T4, checkpoint_every=wl4.checkpoint_every)
-        ph4 = torch.empty((B4, n4, n4), dtype=torch.float64, device=dev)
-        dD = np.ones(B4)
-        for _ in range(args.warmup):
-            plan.solve(g4d, G4d, float(wl4.eps[0]), T4, out=ph4)
-            plan.backward(dD, (a4[None] * ph4).contiguous())
-        torch.cuda.synchronize()
-        tf = tb = 0.0
-        for _ in range(args.steps):
-            t0 = time.perf_counter()
-            plan.solve(g4d, G4d, float(wl4.eps[0]), T4, out=ph4)
-            dphi = (a4[None] * ph4).contiguous()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            plan.backward(dD, dphi)
-            torch.cuda.synchronize()
-            tf += t1 - t0
-            tb += time.perf_counter() - t1
-        plan.close()
+        B4, n4, T4 = wl4.batch, wl4.n, wl4.iters
+        tf, tb = adjoint_steps(F, W, torch, np, args.steps, args.warmup)
         out["adjoint"] = {"workload": f"{wl4.name} {n4}x{n4}, {B4} targets, eps {float(wl4.eps[0])}, {T4} iterations, "
                                       f"checkpoints every {wl4.checkpoint_every}, FP32 operands (FP32 reverse sweep)",
                           "ms_forward": round(1e3 * tf / args.steps, 3), "ms_backward": round(1e3 * tb / args.steps, 3),
