@@ -384,6 +384,17 @@ __device__ __forceinline__ void vm_wait() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14));
 }
 
+// Workgroup barrier that publishes LDS writes only: it waits for this wave's LDS operations
+// (lgkmcnt) but not for its global stores, which __syncthreads' release fence would also wait for
+// (in an epilogue that had just stored the potential, that wait was the store latency).  The
+// compiler-only fences keep LDS accesses on their side of it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xF | (0x7 << 4) | (0x0 << 8) | (0x3 << 14));   // lgkmcnt(0)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // 16-byte global -> LDS load of this lane's source; the wave's 64 lanes fill the 1 KB at
 // lds_dst (wave-uniform) in lane order.  Written in assembly so that the compiler does not track
 // it: its wait insertion would otherwise assume the load may overwrite LDS that fragment reads in
@@ -403,6 +414,10 @@ __device__ __forceinline__ void dma16(const void* src, const unsigned char* lds_
 }
 
 constexpr int FRAG_AHEAD = 2;  // LDS fragment reads issued this many MMA steps ahead
+// Stage geometry (measured at 1024^2): 512-byte rows with two stages resident beat 256-byte rows
+// with four (FP32 K loop 20.1 against 21.9 us, BF16 4.7 against 5.6 us): each stage ends in a
+// workgroup barrier, after which the matrix cores idle until the next fragments arrive, and that
+// cost per stage outweighs the deeper prefetch.
 constexpr int FROWB = 512;      // bytes of one operand row per K stage of the fused kernels
 constexpr int FUSED_NBUF = 2;   // K stages resident in LDS (one in flight while one is consumed)
 
@@ -438,8 +453,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   __shared__ __attribute__((aligned(1024))) unsigned char lds0[(BM + BN) * FROWB];
   __shared__ __attribute__((aligned(1024))) unsigned char lds1[(BM + BN) * FROWB];
   __shared__ __attribute__((aligned(1024))) unsigned char lds2[(NBUF > 2 ? BM + BN : 1) * FROWB];
-  static_assert(NBUF <= 3, "three stage buffers at most");
-  auto bufp = [](int j) -> unsigned char* { return j == 0 ? lds0 : j == 1 ? lds1 : lds2; };
+  __shared__ __attribute__((aligned(1024))) unsigned char lds3[(NBUF > 3 ? BM + BN : 1) * FROWB];
+  static_assert(NBUF <= 4, "four stage buffers at most");
+  auto bufp = [](int j) -> unsigned char* { return j == 0 ? lds0 : j == 1 ? lds1 : j == 2 ? lds2 : lds3; };
   extern __shared__ short dtab[];                 // [np / XB][SR]: exponent - row reference
   constexpr int LR = PASS == 1 ? BN : BM;         // LN: Lambda rows of the tile (output columns / rows)
   __shared__ int rref[SR];                        // reference exponent of each scaled row
@@ -463,11 +479,12 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   // stages would only add exact zeros, so the result is the same as with all stages (LN form: the
   // band is FP64's, and a skipped block would add at most 2^-1070 of its row's reference).
   constexpr int KPS = FROWB / (int)sizeof(T);      // K values per stage
+  constexpr int SPB = XB > KPS ? XB / KPS : 1;     // stages per exponent block (FP64 operands: 2)
   int k_lo = 0, nks = p.nk;
   if (p.band < n) {
     const int lam0 = PASS == 1 ? col0 : row0, lamL = PASS == 1 ? BN : BM;
     const int lo = max(0, lam0 - p.band), hi = lam0 + lamL - 1 + p.band;
-    k_lo = lo / KPS;
+    k_lo = (lo / KPS) / SPB * SPB;   // the loop starts on an exponent block's first stage
     nks = min(p.nk, hi / KPS + 1) - k_lo;
   }
 
@@ -723,8 +740,12 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         for (int q = 0; q < NL; ++q) lprev[q] = lcur[q];
       }
       if (last) {
-        if (ahead && NBUF > 2)
-          vm_wait<(NBUF > 2 ? UPW : 0)>();         // stage kt+1 landed; kt+NBUF-1 may be in flight
+        // stage kt+1 landed; the stages requested after it may stay in flight
+        const int inflight = min(NBUF - 1, nks - 1 - kt);
+        if (NBUF > 3 && inflight >= 3)
+          vm_wait<(NBUF > 3 ? 2 * UPW : 0)>();
+        else if (NBUF > 2 && inflight >= 2)
+          vm_wait<(NBUF > 2 ? UPW : 0)>();
         else
           vm_wait<0>();
         // workgroup barrier without a memory fence (a fence would wait for the stage still in
@@ -807,7 +828,6 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           // a row with mass has a positive product with Lambda at every column
           if (!ADJ && i < n && j < n && rref[lr] != KSENT) mmin = min(mmin, margin_of(rb, cb, e, v));
         }
-    range_report(mmin);
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
       ecol[cb] = max(ecol[cb], __shfl_xor(ecol[cb], 16, 64));
@@ -824,7 +844,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       pend = wave_sum_dpp(pend);
       if (lane == 0) red[wave] = pend;
     }
-    __syncthreads();
+    lds_barrier();
     if (pend_wg && tid == 0) {
       double v = 0.0;
 #pragma unroll
@@ -886,6 +906,8 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         }
       }
     }
+    // (the range atomics go last: the workgroup barriers above wait for every outstanding store)
+    range_report(mmin);
   } else if constexpr (ADJ) {
     // reverse half-step: K(w) = accd 2^{R'_k} (signed); out = mask ? (acc ? out : 0) +
     // w e^{P/eps} K(w) : 0, formed as |accd| e^{P/eps} 2^{R'_k} in one piece so that neither
@@ -939,7 +961,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           k = row16_max(k);
           if (r16 == 0) kred[wn][wm * C::WTM + rb * 16 + Mma<T>::row(g, e)] = k;
         }
-      __syncthreads();
+      lds_barrier();
       T* nA = (T*)p.nextA + (size_t)bz * plane;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -1011,7 +1033,6 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         }
     }
     if (bad) atomicOr(p.flag, 1);
-    range_report(mmin);
     if (p.err_on) {
       err = wave_sum_dpp(err);
       if (lane == 0) red[wave] = err;
@@ -1031,7 +1052,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           if (r16 == 0) kred[wn][wm * C::WTM + rb * 16 + Mma<T>::row(g, e)] = k;
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (p.err_on && tid == 0) {
       double v = 0.0;
 #pragma unroll
@@ -1059,6 +1080,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           }
         }
     }
+    range_report(mmin);   // (last: the workgroup barriers above wait for every outstanding store)
   }
 }
 
