@@ -277,16 +277,21 @@ def main():
     prec0 = args.precision
     log(f"bench: workload {wl.name} n={n} iters={iters} eps={eps} {prec0}, steps={args.steps} warmup={args.warmup}")
     graph = not args.no_graph
+    # (a profiling run at another eps keeps going past a reported loss of range: its status is
+    # printed, and the kernels are what it is for)
+    check = args.eps is None
     # timed region 1: the production launch path (graph replay of the iteration loop)
     finals = {prec0: {}}
     elapsed, reps = run_variant(F, W, torch, args.precision, g, G, eps, iters, args.steps, args.warmup,
-                                profile=False, graph=graph, keep=finals[prec0])
+                                profile=False, graph=graph, keep=finals[prec0], check=check)
+    if not check:
+        log(f"bench: status {F.STATUS_NAMES.get(reps[-1].status, reps[-1].status)} at eps {eps}")
     ms_per_step = 1e3 * elapsed / args.steps
     value = n * n * iters * args.steps / elapsed / 1e6
     # timed region 2: the same steps launched kernel by kernel with HIP events around every
     # contraction GEMM on the solve's stream (events cannot be timed inside a graph)
     el_prof, reps_prof = run_variant(F, W, torch, args.precision, g, G, eps, iters, args.steps, args.warmup,
-                                     profile=True, graph=False)
+                                     profile=True, graph=False, check=check)
     ms_gemm = sum(r.ms_contract for r in reps_prof) / max(1, sum(r.n_contract for r in reps_prof))
     ms_p1, ms_p2 = pass_times(reps_prof)
     flop = 2.0 * n ** 3
