@@ -83,6 +83,9 @@ struct fot_plan_s {
   double *Tbx = nullptr, *Tby = nullptr, *wtmp = nullptr, *cbar = nullptr, *rsum_tmp = nullptr;
   double *gsums = nullptr, *gparts = nullptr, *dd_dev = nullptr;
   double *seg_f = nullptr, *seg_psi = nullptr, *seg_lnS = nullptr, *seg_lnSp = nullptr;
+  // the segment buffers hold the last checkpoint segment's iterates as the last taped solve
+  // computed them (fot_backward then replays that segment no more)
+  bool seg_last_valid = false;
   // The phase read-out and the reverse-sweep contractions run with FP64 operands in every
   // precision (once per solve; their signed sums cancel too strongly for FP32).  For FP64 plans
   // these alias the loop's buffers, otherwise they are separate.
@@ -571,15 +574,34 @@ struct Ops {
       }
       const bool last = (t == iters - 1);
       const bool hist = !(p->d.flags & FOT_FLAG_NO_HISTORY);
-      if ((s = half(p, p->psi, p->f, p->lna, 0, hist ? p->hist_a + (size_t)t * B : nullptr, last ? p->lnS : nullptr,
-                    ep, ep, nullptr, t, p->range_slots + (size_t)seg * B * p->range_spt * 2)) != FOT_OK)
+      // with a tape, the iterations of the last checkpoint segment also go to the segment buffers,
+      // exactly as fot_backward's replay of that segment would write them
+      const int k = p->d.checkpoint_every;
+      const bool keep = p->tape && t >= (iters - 1) / k * k;
+      const size_t so = keep ? (size_t)(t - (iters - 1) / k * k) * B * p->plane : 0;
+      auto copy = [&](const double* src, double* dst) {
+        hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, p->stream, src, dst, (size_t)B * p->plane);
+      };
+      double* lnS_u = last ? p->lnS : keep ? p->seg_lnS + so : nullptr;
+      double* lnS_v = last ? p->lnSp : keep ? p->seg_lnSp + so : nullptr;
+      if ((s = half(p, p->psi, p->f, p->lna, 0, hist ? p->hist_a + (size_t)t * B : nullptr, lnS_u, ep, ep, nullptr,
+                    t, p->range_slots + (size_t)seg * B * p->range_spt * 2)) != FOT_OK)
         return s;
+      if (keep) {
+        copy(p->f, p->seg_f + so);
+        if (last) copy(p->lnS, p->seg_lnS + so);
+      }
       // the last half-step of a segment builds no next operand: the next segment (another type)
       // builds its own from psi
-      if ((s = half(p, p->f, p->psi, p->lnb, plane, hist ? p->hist_b + (size_t)t * B : nullptr,
-                    last ? p->lnSp : nullptr, ep, t + 1 == t1 ? 0.0 : e[t + 1], nullptr, t,
-                    p->range_slots + (size_t)seg * B * p->range_spt * 2)) != FOT_OK)
+      if ((s = half(p, p->f, p->psi, p->lnb, plane, hist ? p->hist_b + (size_t)t * B : nullptr, lnS_v, ep,
+                    t + 1 == t1 ? 0.0 : e[t + 1], nullptr, t, p->range_slots + (size_t)seg * B * p->range_spt * 2)) !=
+          FOT_OK)
         return s;
+      if (keep) {
+        copy(p->psi, p->seg_psi + so);
+        if (last) copy(p->lnSp, p->seg_lnSp + so);
+        LAUNCH_CHECK();
+      }
     }
     return FOT_OK;
   }
@@ -763,10 +785,13 @@ struct Ops {
     for (int sg = nseg - 1; sg >= 0; --sg) {
       const int t0 = sg * k, t1 = std::min(T_, t0 + k);
       const double* tape_in = p->tape + (size_t)sg * BP;
-      // replay the segment from its checkpoint (bit-identical to the forward solve)
+      // replay the segment from its checkpoint (bit-identical to the forward solve), unless the
+      // forward solve left this one, the last, in the segment buffers
       const double* pin = tape_in;
-      if ((s = prep(p, tape_in, e[t0])) != FOT_OK) return s;
-      for (int i = t0; i < t1; ++i) {
+      const bool replay = !(sg == nseg - 1 && p->seg_last_valid);
+      p->seg_last_valid = false;   // (the next segments' replays overwrite the buffers)
+      if (replay && (s = prep(p, tape_in, e[t0])) != FOT_OK) return s;
+      for (int i = t0; i < t1 && replay; ++i) {
         const int q = i - t0;
         if ((s = ensure_lambda(p, e[i])) != FOT_OK) return s;
         // (the replay needs no marginal-error partials; the potentials do not depend on them)
@@ -1607,6 +1632,7 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   const int n = p->n, np = p->np, B = p->B;
   p->prof_used = 0;
   p->tape_valid = false;
+  p->seg_last_valid = false;
   p->pending_hist = nullptr;
 
   if (p->ev[0]) HIP_TRY(hipEventRecord(p->ev[0], p->stream));
@@ -1659,6 +1685,7 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   p->last_iters = iters;
   p->last_eps = e;
   p->tape_valid = (p->tape != nullptr);
+  p->seg_last_valid = p->tape_valid;
   for (int seg = 0; seg < 2; ++seg)
     for (int b = 0; b < B; ++b)
       for (int w = 0; w < p->range_spt; ++w) {

@@ -132,7 +132,9 @@ __device__ __forceinline__ float exp2_hw(double y) { return __builtin_amdgcn_exp
 template <typename T>
 __device__ __forceinline__ T block_operand(double x, int K) {
   if constexpr (sizeof(T) == 8)
-    return (K == KSENT) ? 0.0 : exp(x - (double)K * LN2);
+    // (an explicit FMA: the compiler may contract x - K ln2 differently where the function is
+    // inlined, and the prep kernel and the pass-2 epilogue must produce the same bits)
+    return (K == KSENT) ? 0.0 : exp(fma(-(double)K, LN2, x));
   else
     return (K == KSENT) ? T{} : from_float<T>(exp2_hw(fma(x, INV_LN2, -(double)K)));
 }

@@ -123,17 +123,39 @@ def test_backward_annealed_f64():
     assert np.max(np.abs(got[0] - ref)) / np.max(np.abs(ref)) < 1e-9
 
 
-@pytest.mark.parametrize("prec,eps", [("f32", 2e-2), ("bf16x3", 2e-2), ("f32", 2e-3)])
+@pytest.mark.parametrize("prec,eps", [("f32", 2e-2), ("bf16x3", 2e-2), ("f32", 2e-3), ("f64", 2e-2)])
 def test_checkpoint_interval_is_bit_invariant(prec, eps):
     """The replayed segments reproduce the forward iterations bit for bit whatever the operand
     type, so the gradient does not depend on the checkpoint interval (at eps = 2e-3 the FP32
-    operands use the block-normalised Gibbs factor, in the forward solve and in the replays)."""
+    operands use the block-normalised Gibbs factor, in the forward solve and in the replays; FP64
+    needs the operand's exp(x - K ln 2) as an explicit FMA, which the compiler would otherwise
+    contract differently in the prep kernel and in the pass-2 epilogue)."""
     n, B, T = 40, 2, 12
     g, Gs = _case(n, B, 5)
     rng = np.random.default_rng(6)
     dphi = rng.standard_normal((B, n, n))
     outs = [_gpu_grad(g, Gs, eps, T, k, prec, [1.0, 0.5], dphi) for k in (1, 5, 12)]
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_backward_twice_is_identical(prec):
+    """The forward solve leaves its last checkpoint segment's iterates in the segment buffers, and
+    the first backward pass uses them instead of replaying that segment; it then replays the others
+    into the same buffers, so a second backward pass on the same tape must replay the last segment
+    too. Both give the same bits."""
+    import torch
+    from paper_2512_19072_amd import fot as F
+    n, B, T, k, eps = 48, 2, 12, 5, 2e-2
+    g, Gs = _case(n, B, 13)
+    rng = np.random.default_rng(14)
+    dphi = to_dev(rng.standard_normal((B, n, n)))
+    plan = F.Plan(n, B, prec, max_iters=T, checkpoint_every=k)
+    plan.solve(to_dev(g), to_dev(Gs), eps, T)
+    d1 = plan.backward([0.5, 1.0], dphi).cpu().numpy()
+    d2 = plan.backward([0.5, 1.0], dphi).cpu().numpy()
+    plan.close()
+    assert np.all(np.isfinite(d1)) and np.array_equal(d1, d2)
 
 
 def test_backward_requires_tape():
