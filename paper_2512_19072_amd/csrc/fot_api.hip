@@ -1356,8 +1356,6 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   ALLOC(p->lnS, BP);
   ALLOC(p->lnSp, BP);
   ALLOC(p->mrow, (size_t)p->B * p->np);
-  ALLOC(p->Tx, BP);
-  ALLOC(p->Ty, BP);
   ALLOC(p->phi, BP);
   ALLOC(p->rowsum_g, (size_t)p->n);
   ALLOC(p->rowsum_G, (size_t)p->B * p->n);
@@ -1412,6 +1410,12 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   ALLOC(p->fBx, BP);
   ALLOC(p->fBy, BP);
   ALLOC(p->fBc, BP);
+  // T_x, T_y (Eq. 9-10) are written by k_readout after the GEMMs that read the read-out's moment
+  // operands fBx, fBy, and nothing writes those planes again before the next read-out (the end-of-
+  // solve probe writes its update to T_x before the read-out; the reverse sweep, which reads T_x
+  // and T_y, works in fA, fB and the loop's buffers): they share them.
+  p->Tx = p->fBx;
+  p->Ty = p->fBy;
   ALLOC(p->fZy, BP);
   ALLOC(p->fZc, BP);
   // The five pass-2 outputs of the read-out (and the reverse sweep's fS) are written only after
