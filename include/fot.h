@@ -106,13 +106,22 @@ enum {
                             range: the 32- and 16-bit operand types then reach about half the
                             eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian 1024 x 1024
                             workload).  No effect with FOT_FLAG_CFOT */
-  FOT_FLAG_F64_REVERSE = 32 /* fot_backward after an FP32 solve: run the reverse half-steps with FP64
+  FOT_FLAG_F64_REVERSE = 32, /* fot_backward after an FP32 solve: run the reverse half-steps with FP64
                             operands, as for the other precisions.  Without the flag they use FP32
                             operands wherever the solve held the Gibbs factor raw in FP32: on 8
                             targets of 512 x 512 with 100 iterations (checkpoints every 10) the
                             backward pass takes 28 ms instead of 37 ms, and the gradient's error
                             grows from 1.6e-5 to 5.7e-5 relative to the FP64 oracle's gradient and
                             from 3e-6 to 1.6e-5 relative to central differences of FP64 solves */
+  FOT_FLAG_STAGED_LAMBDA = 64 /* stage the Gibbs factor's tiles through LDS with every K stage of the
+                            per-axis contractions, as the other operand is, instead of reading
+                            them from one Toeplitz table per workgroup (Lambda[i][k] depends on
+                            i - k only).  The results are bit-identical; the table halves the
+                            bytes each workgroup fetches per stage.  The table is used wherever
+                            Lambda is held raw (not block-normalised for small eps) with FP64,
+                            FP32, BF16 or FP16 operands and its first row fits in a stage
+                            buffer (n_p * element size <= 32 KiB on 64 x 64 tiles, 16 KiB on
+                            32 x 32 tiles) */
 };
 
 typedef struct {

@@ -52,6 +52,7 @@ struct fot_plan_s {
   size_t esz = 0, zsz = 0, plane = 0;
   hipStream_t stream = nullptr;
   int device = 0;
+  int lds_limit = 0;   // LDS bytes per workgroup on the plan's device
   // FP64 state and scratch
   double *f = nullptr, *psi = nullptr, *lna = nullptr, *lnb = nullptr, *lnS = nullptr, *lnSp = nullptr;
   double *mrow = nullptr, *Tx = nullptr, *Ty = nullptr, *phi = nullptr;
@@ -382,6 +383,9 @@ struct Ops {
       const int blocks = (int)((total + 255) / 256);
       hipLaunchKernelGGL(k_fill_lambda<T>, dim3(blocks), dim3(256), 0, p->stream, (T*)p->lam, (T*)nullptr, p->n,
                          p->np, 1.0 / eps);
+      if constexpr (!Mma<T>::PAIRED)
+        hipLaunchKernelGGL(k_lam_chunks<T>, dim3((2 * p->np + 255) / 256), dim3(256), 0, p->stream, (T*)p->lam,
+                           p->np);
     }
     LAUNCH_CHECK();
     p->lam_eps = eps;
@@ -389,10 +393,46 @@ struct Ops {
     return FOT_OK;
   }
 
+  // Toeplitz form of Lambda's operand (k_fused<..., TZ = true>, see toeplitz_table_bytes): raw
+  // Lambda (its Toeplitz chunks are formed with it) in the plain element layout, not switched off
+  // by FOT_FLAG_STAGED_LAMBDA, and the kernel's LDS, static and dynamic, within the device's limit.
+  template <typename C, int PASS, bool ADJ>
+  static bool tz_fits(const fot_plan_s* p) {
+    if constexpr (Mma<T>::PAIRED) {
+      (void)p;
+      return false;
+    } else {
+      if (p->d.flags & FOT_FLAG_STAGED_LAMBDA) return false;
+      static const size_t st = [] {
+        hipFuncAttributes fa{};
+        if (hipFuncGetAttributes(&fa, (const void*)k_fused<T, PASS, C, FUSED_NBUF, false, ADJ, true>) != hipSuccess) {
+          (void)hipGetLastError();
+          return (size_t)-1;
+        }
+        return (size_t)fa.sharedSizeBytes;
+      }();
+      return st != (size_t)-1 && st + fused_dyn_lds<PASS, C, false, true>(p->np) <= (size_t)p->lds_limit;
+    }
+  }
+
   template <typename C, bool LN>
   static void fused_launch_cfg(fot_plan_s* p, int pass, const FusedArgs& a, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(p->np / C::BN, p->np / C::BM, p->B);
     const dim3 block(C::THREADS);
+    if constexpr (!LN && !Mma<T>::PAIRED) {
+      const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true>(p->np);
+      const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true>(p->np);
+      if (pass == 1 && tz_fits<C, 1, false>(p)) {
+        hipExtLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, false, true>), grid, block, t1, p->stream, e0, e1,
+                              0, a);
+        return;
+      }
+      if (pass == 2 && tz_fits<C, 2, false>(p)) {
+        hipExtLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, false, false, true>), grid, block, t2, p->stream, e0, e1,
+                              0, a);
+        return;
+      }
+    }
     if (pass == 1)
       hipExtLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, LN>), grid, block,
                             (uint32_t)fused_dyn_lds<1, C, LN>(p->np), p->stream, e0, e1, 0, a);
@@ -663,7 +703,13 @@ struct Ops {
     const dim3 grid(p->np / C::BN, p->np / C::BM, p->B);
     const dim3 block(C::THREADS);
     const uint32_t l1 = (uint32_t)fused_dyn_lds<1, C, false>(p->np), l2 = (uint32_t)fused_dyn_lds<2, C, false>(p->np);
-    if (pass == 1)
+    const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true>(p->np);
+    const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true>(p->np);
+    if (pass == 1 && tz_fits<C, 1, true>(p))
+      hipLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, true, true>), grid, block, t1, p->stream, a);
+    else if (pass == 2 && tz_fits<C, 2, true>(p))
+      hipLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, false, true, true>), grid, block, t2, p->stream, a);
+    else if (pass == 1)
       hipLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, true>), grid, block, l1, p->stream, a);
     else
       hipLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, false, true>), grid, block, l2, p->stream, a);
@@ -906,6 +952,7 @@ fot_status fill64(fot_plan_s* p, double eps, bool withH) {
   if (*p->flam_eps == eps && (!withH || *p->flamH_valid)) return FOT_OK;
   hipLaunchKernelGGL(k_fill_lambda<double>, dim3((unsigned)((p->plane + 255) / 256)), dim3(256), 0, p->stream,
                      p->flam, withH ? p->flamH : (double*)nullptr, p->n, p->np, 1.0 / eps);
+  hipLaunchKernelGGL(k_lam_chunks<double>, dim3((2 * p->np + 255) / 256), dim3(256), 0, p->stream, p->flam, p->np);
   LAUNCH_CHECK();
   *p->flam_eps = eps;
   *p->flamH_valid = withH;
@@ -1272,7 +1319,7 @@ static fot_status validate_desc(const fot_plan_desc& d, int* cN_out) {
   if (d.max_iters < 1) return fail(FOT_E_INVALID, "fot_plan: max_iters must be >= 1");
   if (d.checkpoint_every < 0) return fail(FOT_E_INVALID, "fot_plan: checkpoint_every must be >= 0");
   if (d.flags & ~(FOT_FLAG_PROFILE | FOT_FLAG_NO_GRAPH | FOT_FLAG_NO_HISTORY | FOT_FLAG_CFOT | FOT_FLAG_SMALL_TILES |
-                  FOT_FLAG_F64_REVERSE))
+                  FOT_FLAG_F64_REVERSE | FOT_FLAG_STAGED_LAMBDA))
     return fail(FOT_E_INVALID, "fot_plan: unknown flag bits");
   if (d.tail_iters < 0) return fail(FOT_E_INVALID, "fot_plan: tail_iters must be >= 0");
   if (d.tail_iters > 0) {
@@ -1335,7 +1382,8 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   // 512^2 17 against 32 us, 640^2 27 against 38 us, 768^2 45 against 43 us (BF16 26 against
   // 20 us), 1024^2 73 against 57 us.
   int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+      hipDeviceGetAttribute(&p->lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess)
     return bail(fail(FOT_E_HIP, "fot_plan: cannot query the device"));
   p->t32 = (d.flags & FOT_FLAG_SMALL_TILES) ||
            2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
@@ -1378,14 +1426,16 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
   if (d.precision != FOT_F64) ALLOC(p->kexpL, (size_t)p->np * p->nbA);
   ALLOC(p->flag, (size_t)1);
-  ALLOCV(p->lam, p->plane * p->esz);
+  // (each Lambda plane is followed by its Toeplitz chunks, see toeplitz_chunks_bytes)
+  const size_t lam_bytes = p->plane * p->esz + toeplitz_chunks_bytes(p->np);
+  ALLOCV(p->lam, lam_bytes);
   ALLOCV(p->opA, BP * p->esz);
   ALLOCV(p->opB, BP * p->esz);
   p->op_set[0][0] = p->lam;
   p->op_set[0][1] = p->opA;
   p->op_set[0][2] = p->opB;
   if (tail) {
-    ALLOCV(p->op_set[1][0], p->plane * p->esz);
+    ALLOCV(p->op_set[1][0], lam_bytes);
     ALLOCV(p->op_set[1][1], BP * p->esz);
     ALLOCV(p->op_set[1][2], BP * p->esz);
   }
@@ -1398,7 +1448,7 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
     p->flam_eps = &p->lam_eps;
     p->flamH_valid = &p->lamH_valid;
   } else {
-    ALLOC(p->flam, p->plane);
+    ALLOC(p->flam, p->plane + toeplitz_chunks_bytes(p->np) / sizeof(double));
     ALLOC(p->fA, BP);
     ALLOC(p->fB, BP);
     ALLOC(p->fZ, BP);

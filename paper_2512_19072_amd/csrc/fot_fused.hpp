@@ -423,20 +423,61 @@ constexpr int FRAG_AHEAD = 2;  // LDS fragment reads issued this many MMA steps 
 constexpr int FROWB = 512;      // bytes of one operand row per K stage of the fused kernels
 constexpr int FUSED_NBUF = 2;   // K stages resident in LDS (one in flight while one is consumed)
 
-// Launch with dynamic LDS of fused_dyn_lds<PASS, C, LN>(np) bytes (the exponent-difference
-// table, and in the LN form Lambda's exponent table for the tile's Lambda rows).
+// Toeplitz form of Lambda's operand (TZ): Lambda[i][k] depends on i - k only, so a tile's Lambda
+// fragments are read from one table per workgroup instead of being staged with every K stage,
+// which halves the bytes each workgroup fetches per stage.  Chunk c of the table is the 16 bytes
+// of the 16 / sizeof(T) consecutive values Lambda(d), d = c - (n_p - 1) ... (one chunk for every
+// starting distance, so that any fragment is one aligned 16-byte read, and the 16 rows of a
+// fragment read 16 consecutive chunks: no bank conflicts).  The full table (2 n_p chunks, entries
+// with |d| >= n_p zero) sits in device memory right after the n_p x n_p Lambda plane it is formed
+// from (k_lam_chunks); a workgroup copies the window of at most n_p + LR chunks its tile uses
+// (LR: its Lambda rows) into LDS, in 1 KB units.
+inline size_t toeplitz_chunks_bytes(int np) { return (size_t)32 * (size_t)np; }
+inline size_t toeplitz_table_bytes(int np, int lam_rows) {
+  return ((size_t)16 * (size_t)(np + lam_rows) + 1023) / 1024 * 1024;
+}
+
+// The Toeplitz chunks of a Lambda plane (row 0 holds Lambda(|d|) for every d: all rows are the same
+// function of i - k, padding included), written after the plane; one thread per chunk.
+template <typename T>
+__global__ void k_lam_chunks(T* lam, int np) {
+  typedef typename std::conditional<
+      sizeof(T) == 2, unsigned short,
+      typename std::conditional<sizeof(T) == 4, unsigned, unsigned long long>::type>::type EB;
+  constexpr int EPC = 16 / (int)sizeof(T);
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 2 * np) return;
+  const EB* row = (const EB*)lam;
+  EB v[EPC];
+#pragma unroll
+  for (int e = 0; e < EPC; ++e) {
+    const int d = abs(c - (np - 1) + e);
+    v[e] = d < np ? row[d] : (EB)0;
+  }
+  u32x4 w;
+  __builtin_memcpy(&w, v, 16);
+  ((u32x4*)((unsigned char*)lam + (size_t)np * np * sizeof(T)))[c] = w;
+}
+
+// Launch with dynamic LDS of fused_dyn_lds<PASS, C, LN, TZ>(np) bytes (the exponent-difference
+// table, in the LN form Lambda's exponent table for the tile's Lambda rows, and in the TZ form the
+// Toeplitz table of Lambda, 16-byte aligned).
 template <int PASS, typename C>
 constexpr int fused_scaled_rows() { return PASS == 1 ? C::BM : C::BN; }
-template <int PASS, typename C, bool LN = false>
+template <int PASS, typename C, bool LN = false, bool TZ = false>
 inline size_t fused_dyn_lds(int np) {
   const int xb = PASS == 1 ? C::BN : C::BM;
-  const int lam_rows = LN ? (PASS == 1 ? C::BN : C::BM) : 0;
-  return (size_t)(np / xb) * (fused_scaled_rows<PASS, C>() + lam_rows) * sizeof(short);
+  const int lam_rows = PASS == 1 ? C::BN : C::BM;
+  size_t bytes = (size_t)(np / xb) * (fused_scaled_rows<PASS, C>() + (LN ? lam_rows : 0)) * sizeof(short);
+  if (TZ) bytes = (bytes + 15) / 16 * 16 + toeplitz_table_bytes(np, lam_rows);
+  return bytes;
 }
 
 // ADJ: the contraction of a reverse half-step (signed operands; pass 2 ends in the reverse update
-// instead of the potential update).
-template <typename T, int PASS, typename C, int NBUF = FUSED_NBUF, bool LN = false, bool ADJ = false>
+// instead of the potential update).  TZ: Lambda's operand from the Toeplitz table (raw Lambda
+// only; the LN form's block-normalised Lambda is not Toeplitz).
+template <typename T, int PASS, typename C, int NBUF = FUSED_NBUF, bool LN = false, bool ADJ = false,
+          bool TZ = false>
 __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   static_assert(NBUF >= 2, "at least double buffering");
   typedef typename Mma<T>::acc_t acc_t;
@@ -450,16 +491,19 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   constexpr bool PAIRED = Mma<T>::PAIRED;
   static_assert(HB >= 1 && XB % EPH == 0, "exponent blocks must hold whole fragment steps");
   static_assert(!PAIRED || (HB % 2 == 0 && HPS % 2 == 0), "hi/lo step pairs within a block and a stage");
+  static_assert(!TZ || (!LN && !PAIRED), "the Toeplitz table holds raw Lambda in the plain element layout");
+  // rows staged per K stage: both operands, or (TZ) only the operand that is not Lambda
+  constexpr int SROWS = TZ ? (PASS == 1 ? BM : BN) : BM + BN;
   // K-stage buffers as distinct objects, so that the compiler can tell a direct load into one
   // buffer from reads of another (it would otherwise wait for every load in flight)
-  __shared__ __attribute__((aligned(1024))) unsigned char lds0[(BM + BN) * FROWB];
-  __shared__ __attribute__((aligned(1024))) unsigned char lds1[(BM + BN) * FROWB];
-  __shared__ __attribute__((aligned(1024))) unsigned char lds2[(NBUF > 2 ? BM + BN : 1) * FROWB];
-  __shared__ __attribute__((aligned(1024))) unsigned char lds3[(NBUF > 3 ? BM + BN : 1) * FROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds0[SROWS * FROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds1[SROWS * FROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds2[(NBUF > 2 ? SROWS : 1) * FROWB];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds3[(NBUF > 3 ? SROWS : 1) * FROWB];
   static_assert(NBUF <= 4, "four stage buffers at most");
   auto bufp = [](int j) -> unsigned char* { return j == 0 ? lds0 : j == 1 ? lds1 : j == 2 ? lds2 : lds3; };
-  extern __shared__ short dtab[];                 // [np / XB][SR]: exponent - row reference
-  constexpr int LR = PASS == 1 ? BN : BM;         // LN: Lambda rows of the tile (output columns / rows)
+  extern __shared__ __attribute__((aligned(16))) short dtab[];   // [np / XB][SR]: exponent - row reference
+  constexpr int LR = PASS == 1 ? BN : BM;         // Lambda rows of the tile (output columns / rows)
   __shared__ int rref[SR];                        // reference exponent of each scaled row
   __shared__ double red[C::NW];
   __shared__ int kred[C::WGN][BM];                // pass 2: row exponents of the next operand
@@ -491,16 +535,17 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   }
 
   // ---- operand staging: each K stage of the tile (BM rows of A, then BN rows of B, FROWB bytes
-  // per row) is copied global -> LDS by 16-byte direct loads (no register round trip).  A wave
-  // instruction fills 1 KB of LDS, lane l at byte 16 l: 1024 / FROWB whole rows.  LDS rows are
-  // unpadded; the 16-byte chunk c of row r sits in slot c ^ (r mod 16), so the fragment reads
-  // (16 rows, one chunk) hit 16 distinct slots, i.e. all banks once.
+  // per row; TZ: only the rows of the operand that is not Lambda) is copied global -> LDS by
+  // 16-byte direct loads (no register round trip).  A wave instruction fills 1 KB of LDS, lane l
+  // at byte 16 l: 1024 / FROWB whole rows.  LDS rows are unpadded; the 16-byte chunk c of row r
+  // sits in slot c ^ (r mod 16), so the fragment reads (16 rows, one chunk) hit 16 distinct
+  // slots, i.e. all banks once.
   const size_t pitch = (size_t)np * sizeof(T);
   const unsigned char* Ab = (const unsigned char*)p.A + ((size_t)bz * p.sA) * sizeof(T) + (size_t)row0 * pitch;
   const unsigned char* Bb = (const unsigned char*)p.B + ((size_t)bz * p.sB) * sizeof(T) + (size_t)col0 * pitch;
   constexpr int RPU = 1024 / FROWB;                // rows per 1 KB load unit
   constexpr int CPR = FROWB / 16;                 // 16-byte chunks per row
-  constexpr int UNITS = (BM + BN) / RPU;          // 1 KB load units per stage
+  constexpr int UNITS = SROWS / RPU;              // 1 KB load units per stage
   constexpr int UPW = UNITS / C::NW;              // units per wave
   static_assert(UNITS % C::NW == 0 && BM % RPU == 0, "stage staging: whole units per wave, A/B split on a unit");
   const unsigned char* dsrc[UPW];
@@ -509,7 +554,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     const int u = wave + C::NW * i;
     const int r = RPU * u + lane / CPR;
     const int c = (lane % CPR) ^ (r & 15);
-    dsrc[i] = (r < BM ? Ab + (size_t)r * pitch : Bb + (size_t)(r - BM) * pitch) + c * 16;
+    if constexpr (TZ)
+      dsrc[i] = (PASS == 1 ? Ab : Bb) + (size_t)r * pitch + c * 16;
+    else
+      dsrc[i] = (r < BM ? Ab + (size_t)r * pitch : Bb + (size_t)(r - BM) * pitch) + c * 16;
   }
   auto stage_load = [&](int kk, unsigned char* dst) {
 #pragma unroll
@@ -519,6 +567,22 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   // ---- prologue: stage 0 and the exponent table first (the table build waits for its loads,
   // and with them for stage 0), then the later stages and the epilogue inputs
   stage_load(0, bufp(0));
+
+  // TZ: the window of Lambda's Toeplitz chunks this tile uses, copied into LDS (16-byte aligned
+  // after the exponent table) like a stage.  The tile's Lambda rows are lam0 + lr (lr < LR) and its
+  // K range starts at k_lo KPS, so the distances K - (lam0 + lr) start at d_lo = k_lo KPS - lam0 -
+  // (LR - 1): the fragment of Lambda row lam0 + lr at K chunk c (K = c EPC ...) is window chunk
+  // x = c EPC - k_lo KPS + LR - 1 - lr, the window has nch chunks, and every |d| is below n_p.
+  constexpr int EPC = 16 / (int)sizeof(T);        // operand elements per 16-byte chunk
+  unsigned char* const tzt = (unsigned char*)dtab + ((size_t)nbk * SR * sizeof(short) + 15) / 16 * 16;
+  if constexpr (TZ) {
+    const int lam0 = PASS == 1 ? col0 : row0;
+    const int cbase = k_lo * KPS - lam0 - (LR - 1) + (np - 1);   // first chunk of the window (>= 0)
+    const int nch = nks * KPS + LR - EPC;
+    const u32x4* chunks = (const u32x4*)((const unsigned char*)(PASS == 1 ? p.B : p.A) + plane * sizeof(T));
+    for (int u = wave; u * 64 < nch; u += C::NW)   // (lanes past the window copy its last chunk again)
+      dma16(chunks + min(cbase + u * 64 + lane, 2 * np - 1), tzt + u * 1024);
+  }
 
   // exponent table of the block-normalised operand for this tile's scaled rows
   // (pass 1: A rows = output rows; pass 2: B rows = output columns)
@@ -643,8 +707,27 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   // step h run; at the end of a stage the workgroup waits for the next stage, synchronises and
   // requests the next stage's first fragments.
   static_assert((NBUF * HPS) % (2 * HB) == 0, "block parity must repeat with the unrolled stages");
-  const int arow = (wm * C::WTM + r16) * FROWB, brow = (BM + wn * C::WTN + r16) * FROWB;
+  const int arow = (wm * C::WTM + r16) * FROWB, brow = ((TZ ? 0 : BM) + wn * C::WTN + r16) * FROWB;
   const int sw = (g ^ r16) << 4;                  // slot of chunk 4h+g in this lane's rows, h = 0
+  // TZ: table offset of this lane's Lambda fragments (pass 1: B fragment cb, pass 2: A fragment
+  // rb) at the loop's first step; each step advances K by 4 EPC values, i.e. TZSTEP bytes
+  constexpr int NTZ = PASS == 1 ? CB : RB;
+  constexpr int TZSTEP = 64 * EPC;
+  int tzo[NTZ];
+#pragma unroll
+  for (int q = 0; q < NTZ; ++q) {
+    const int lr = (PASS == 1 ? wn * C::WTN : wm * C::WTM) + q * 16 + r16;
+    tzo[q] = 16 * (g * EPC + LR - 1 - lr);
+  }
+  // fragment reads: step s (from the loop's first K) of stage buffer buf at slot offset so
+  auto frag_a = [&](const unsigned char* buf, int rb, int so, int s) -> u32x4 {
+    if constexpr (TZ && PASS == 2) return *(const u32x4*)(tzt + tzo[rb] + s * TZSTEP);
+    return *(const u32x4*)(&buf[arow + rb * 16 * FROWB + so]);
+  };
+  auto frag_b = [&](const unsigned char* buf, int cb, int so, int s) -> u32x4 {
+    if constexpr (TZ && PASS == 1) return *(const u32x4*)(tzt + tzo[cb] + s * TZSTEP);
+    return *(const u32x4*)(&buf[brow + cb * 16 * FROWB + so]);
+  };
   // fragments of PD consecutive steps are live: slot h % PD holds step h of the stage (the
   // fragments of step h + FA are requested at step h; a BF16x3 pair step also reads step h - 1)
   constexpr int FA = FRAG_AHEAD;
@@ -654,9 +737,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
   for (int hs = 0; hs < FA; ++hs) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) fa[hs][rb] = *(const u32x4*)(&lds0[arow + rb * 16 * FROWB + (sw ^ (hs << 6))]);
+    for (int rb = 0; rb < RB; ++rb) fa[hs][rb] = frag_a(lds0, rb, sw ^ (hs << 6), hs);
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) fb[hs][cb] = *(const u32x4*)(&lds0[brow + cb * 16 * FROWB + (sw ^ (hs << 6))]);
+    for (int cb = 0; cb < CB; ++cb) fb[hs][cb] = frag_b(lds0, cb, sw ^ (hs << 6), hs);
   }
   for (int kt0 = 0; kt0 < nks; kt0 += NBUF)
 #pragma unroll
@@ -686,9 +769,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         const int ha = h + FA;                     // step whose fragments are requested now
         const int so = sw ^ (ha << 6);             // chunk 4 ha + g
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) fa[ha % PD][rb] = *(const u32x4*)(&cur[arow + rb * 16 * FROWB + so]);
+        for (int rb = 0; rb < RB; ++rb) fa[ha % PD][rb] = frag_a(cur, rb, so, kt * HPS + ha);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) fb[ha % PD][cb] = *(const u32x4*)(&cur[brow + cb * 16 * FROWB + so]);
+        for (int cb = 0; cb < CB; ++cb) fb[ha % PD][cb] = frag_b(cur, cb, so, kt * HPS + ha);
       }
       // FP32: keep these reads ahead of this step's MFMAs (the scheduler would otherwise sink
       // them next to their use and expose the LDS latency; measured 2-3% per launch)
@@ -760,11 +843,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
           for (int hs = 0; hs < FA; ++hs) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-              fa[hs][rb] = *(const u32x4*)(&nxt[arow + rb * 16 * FROWB + (sw ^ (hs << 6))]);
+            for (int rb = 0; rb < RB; ++rb) fa[hs][rb] = frag_a(nxt, rb, sw ^ (hs << 6), (kt + 1) * HPS + hs);
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-              fb[hs][cb] = *(const u32x4*)(&nxt[brow + cb * 16 * FROWB + (sw ^ (hs << 6))]);
+            for (int cb = 0; cb < CB; ++cb) fb[hs][cb] = frag_b(nxt, cb, sw ^ (hs << 6), (kt + 1) * HPS + hs);
           }
         }
       }

@@ -26,6 +26,7 @@ FOT_FLAG_NO_HISTORY = 4
 FOT_FLAG_CFOT = 8
 FOT_FLAG_SMALL_TILES = 16
 FOT_FLAG_F64_REVERSE = 32
+FOT_FLAG_STAGED_LAMBDA = 64
 PRECISIONS = {"f64": FOT_F64, "f32": FOT_F32, "bf16": FOT_BF16, "f16": FOT_F16, "bf16x3": FOT_BF16X3}
 STATUS_NAMES = {0: "FOT_OK", 1: "FOT_E_INVALID", 2: "FOT_E_NOMEM", 3: "FOT_E_HIP", 4: "FOT_E_NONFINITE",
                 5: "FOT_E_STATE", 6: "FOT_E_UNSUPPORTED", 7: "FOT_E_RANGE"}
@@ -270,7 +271,7 @@ class Plan:
     def __init__(self, n: int, batch: int = 1, precision="f32", max_iters: int = 1000,
                  checkpoint_every: int = 0, profile: bool = False, graph: bool = True, history: bool = True,
                  cfot: bool = False, small_tiles: bool = False, tail_precision=None, tail_iters: int = 0,
-                 f64_reverse: bool = False):
+                 f64_reverse: bool = False, staged_lambda: bool = False):
         """``tail_precision``/``tail_iters``: the precision schedule of fot_plan_desc (the last
         ``tail_iters`` iterations of every solve with ``tail_precision`` operands)."""
         self.n, self.batch, self.precision = n, batch, precision
@@ -278,7 +279,8 @@ class Plan:
         self.checkpoint_every = checkpoint_every
         flags = ((FOT_FLAG_PROFILE if profile else 0) | (0 if graph else FOT_FLAG_NO_GRAPH)
                  | (0 if history else FOT_FLAG_NO_HISTORY) | (FOT_FLAG_CFOT if cfot else 0)
-                 | (FOT_FLAG_SMALL_TILES if small_tiles else 0) | (FOT_FLAG_F64_REVERSE if f64_reverse else 0))
+                 | (FOT_FLAG_SMALL_TILES if small_tiles else 0) | (FOT_FLAG_F64_REVERSE if f64_reverse else 0)
+                 | (FOT_FLAG_STAGED_LAMBDA if staged_lambda else 0))
         self.handle = fot_plan(n, batch, precision, max_iters, checkpoint_every, flags,
                                tail_precision=tail_precision, tail_iters=tail_iters)
         # bumped by every call that replaces the state fot_backward would differentiate

@@ -23,14 +23,14 @@ def to_dev(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=device())
 
 
-def run_gpu(g, G, eps, iters, precision, checkpoint_every=0, max_iters=None, profile=False):
+def run_gpu(g, G, eps, iters, precision, checkpoint_every=0, max_iters=None, profile=False, **plan_kw):
     from paper_2512_19072_amd import fot as F
     G = np.asarray(G)
     if G.ndim == 2:
         G = G[None]
     n, B = g.shape[0], G.shape[0]
     plan = F.Plan(n, B, precision, max_iters=max_iters or iters, checkpoint_every=checkpoint_every,
-                  profile=profile)
+                  profile=profile, **plan_kw)
     phase, rep, st = plan.solve(to_dev(g), to_dev(G), eps, iters)
     f, psi = plan.potentials()
     out = dict(phase=phase.cpu().numpy(), f=f.cpu().numpy(), psi=psi.cpu().numpy(), rep=rep, plan=plan,

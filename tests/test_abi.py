@@ -33,7 +33,7 @@ def test_version_string():
     ((64, 1, 7, 10, 0, 0), "precision"),
     ((64, 1, 1, 0, 0, 0), "max_iters"),
     ((64, 1, 1, 10, -1, 0), "checkpoint_every"),
-    ((64, 1, 1, 10, 0, 64), "flag bits"),
+    ((64, 1, 1, 10, 0, 128), "flag bits"),
 ])
 def test_plan_rejects_invalid_desc(desc, msg):
     lib = F.load()
