@@ -147,7 +147,8 @@ constexpr float INV_LN2F = 1.44269504088896340736f;
 __device__ __forceinline__ float exp_err(float x) { return __builtin_amdgcn_exp2f(x * INV_LN2F); }
 __device__ __forceinline__ float expm1_err(float d) {
   const float series = d * (1.0f + d * (0.5f + d * (1.0f / 6.0f + d * (1.0f / 24.0f))));
-  return fabsf(d) < 0.03f ? series : exp_err(d) - 1.0f;
+  const float direct = exp_err(d) - 1.0f;
+  return fabsf(d) < 0.03f ? series : direct;
 }
 
 // ln v of an FP32-accumulated contraction: v = m 2^e exactly (frexp, m in [1/2, 1)), then
@@ -1094,15 +1095,16 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const bool zm = la == -INFINITY;
           const double fnew = (ok && !zm) ? eps * (la - lnS) : -INFINITY;
           if (p.err_on) {
-            // marginal-error term of the entering plan at this pixel: on a zero-mass pixel its
-            // mass u_old S; elsewhere a |u_old / u_new - 1| = a |exp(d) - 1| with
-            // d = (f_old - f_new)/eps, evaluated as exp(ln a + d) - a once d is large (a e^d is
-            // the pixel's entering mass, at most 1, while e^d alone can overflow FP32 for tiny a)
-            const float tz = exp_err((float)fma(fold, inv_eps, lnS));
-            const double d = (fold - fnew) * inv_eps;
-            const float df = (float)d, laf = (float)la;
-            const float av = exp_err(laf);
-            const float ta = (df < 10.0f) ? av * fabsf(expm1_err(df)) : exp_err(laf + df) - av;
+            // marginal-error term of the entering plan at this pixel.  Its mass there is
+            // u_old S = exp(x), x = f_old/eps + ln S; the term is that mass on a zero-mass pixel,
+            // elsewhere a |u_old / u_new - 1| = a |exp(d) - 1| with d = (f_old - f_new)/eps =
+            // x - ln a, taken as exp(x) - a once d is large (e^d alone can overflow FP32 for
+            // tiny a).  Every candidate is formed and one selected: no branches.
+            const double x = fma(fold, inv_eps, lnS);
+            const float tz = exp_err((float)x);
+            const float df = (float)(x - la);
+            const float av = exp_err((float)la);
+            const float ta = (df < 10.0f) ? av * fabsf(expm1_err(df)) : tz - av;
             err += ok ? (double)(zm ? tz : ta) : 0.0;
           }
           bad = bad || (ok && !zm && !(fabs(fnew) < INFINITY));
