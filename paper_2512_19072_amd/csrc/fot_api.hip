@@ -55,7 +55,7 @@ struct fot_plan_s {
   int lds_limit = 0;   // LDS bytes per workgroup on the plan's device
   // FP64 state and scratch
   double *f = nullptr, *psi = nullptr, *lna = nullptr, *lnb = nullptr, *lnS = nullptr, *lnSp = nullptr;
-  double *mrow = nullptr, *Tx = nullptr, *Ty = nullptr, *phi = nullptr;
+  double *mrow = nullptr, *Tx = nullptr, *Ty = nullptr;
   double *rowsum_g = nullptr, *rowsum_G = nullptr, *rowpart = nullptr, *partials = nullptr;
   double *hist_a = nullptr, *hist_b = nullptr, *rparts = nullptr, *rsums = nullptr;
   unsigned* colkey = nullptr;
@@ -90,9 +90,7 @@ struct fot_plan_s {
   // The phase read-out and the reverse-sweep contractions run with FP64 operands in every
   // precision (once per solve; their signed sums cancel too strongly for FP32).  For FP64 plans
   // these alias the loop's buffers, otherwise they are separate.
-  double *flam = nullptr, *flamH = nullptr, *fA = nullptr, *fA2 = nullptr, *fB = nullptr, *fBx = nullptr;
-  double *fBy = nullptr, *fBc = nullptr, *fZ = nullptr, *fZy = nullptr, *fZc = nullptr, *fS = nullptr;
-  double *fSx = nullptr, *fSy = nullptr, *fScx = nullptr, *fScy = nullptr;
+  double *flam = nullptr, *flamH = nullptr, *fA = nullptr, *fB = nullptr, *fZ = nullptr;
   double flam_eps_sep = -1.0;
   bool flamH_valid_sep = false;
   double* flam_eps = nullptr;   // -> lam_eps (FP64 plans) or flam_eps_sep
@@ -654,8 +652,8 @@ struct Ops {
   }
 
   // End-of-solve probe of the operand type's u-direction products: ln S(psi_T) formed as a u-half
-  // would form it (its update goes to scratch: Tx, its ln S to phi, both overwritten later by the
-  // read-out), for the read-out to compare with the FP64 value.  The final column marginal checks
+  // would form it (its update goes to read-out scratch, fA, its ln S to Ty, which the read-out
+  // reads before it writes T_y there), for the read-out to compare with the FP64 value.  The final column marginal checks
   // only the last V-half's products; a loss of range in the u-direction products (the potential
   // psi spanning more than the type holds within one operand block) would otherwise go unseen
   // while the iterates drift.  FP64 operands need no probe.  Its own range check is recorded as
@@ -671,7 +669,7 @@ struct Ops {
       fot_status s = prep(p, p->psi, eps);
       if (s != FOT_OK) return s;
       p->probing = true;
-      s = half(p, p->psi, p->Tx, p->lna, 0, nullptr, p->phi, eps, 0.0, p->probe_flag, iters,
+      s = half(p, p->psi, p->fA, p->lna, 0, nullptr, p->Ty, eps, 0.0, p->probe_flag, iters,
                p->range_slots + (size_t)seg * p->B * p->range_spt * 2);
       p->probing = false;
       return s;
@@ -985,15 +983,30 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
                        p->mrow, p->colkey, p->n, p->np, p->fB);
     LAUNCH_CHECK();
     GemmArgs gs = R::base_args(p, p->flam, 0, p->fB, plane);
-    gs.out = p->fS;
+    gs.out = p->fA;
     gs.sOut = plane;
     if ((s = R::gemm_launch(p, EPI_RAW, gs)) != FOT_OK) return s;
-    hipLaunchKernelGGL(k_lnS_raw, dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->fS,
+    hipLaunchKernelGGL(k_lnS_raw, dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->fA,
                        p->colkey, p->n, p->np, p->lnSp);
     LAUNCH_CHECK();
   }
+  // Moments of V_T (Eq. 9-10).  Each pass-2 output is consumed (k_readout) before the next is
+  // formed, so that the read-out works in three scratch planes besides T_x and T_y:
+  //   A0 = exp(psi/eps - m) -> fA, Z = ln(A0 Lambda) -> fZ (row shifts, column keys),
+  //   B0 = colexp(Z) -> fB: S = Lambda B0 and Scx = (Lambda o H) B0 -> Tx (consumed),
+  //   Bx = colexp_x(Z) -> fB: Sx = Lambda Bx -> Tx (T_x),
+  //   Zc = A0 (Lambda o H) -> fB, Bc = colexp(Zc) -> fZ: Scy = Lambda Bc -> fB (consumed),
+  //   A2 = A0 Y -> fA, Zy = A2 Lambda -> fZ, By = colexp(Zy) -> fB: Sy = Lambda By -> Ty (T_y).
+  // Ty holds the end-of-solve probe's ln S until the first k_readout has read it.
+  auto gemm = [&](const void* A, long long sA, const void* Bm, long long sB, double* out) -> fot_status {
+    GemmArgs g = R::base_args(p, A, sA, Bm, sB);
+    g.out = out;
+    g.sOut = plane;
+    return R::gemm_launch(p, EPI_RAW, g);
+  };
+  const dim3 rgrid(READOUT_BLOCKS, p->B), rblock(NTHREADS);
   hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np,
-                     1.0 / eps, p->mrow, p->fA, p->fA2, p->colkey, PendingSum{nullptr, 0, nullptr});
+                     1.0 / eps, p->mrow, p->fA, (double*)nullptr, p->colkey, PendingSum{nullptr, 0, nullptr});
   LAUNCH_CHECK();
   GemmArgs g1 = R::base_args(p, p->fA, plane, p->flam, 0);
   g1.out = p->fZ;
@@ -1001,41 +1014,47 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
   g1.mrow = p->mrow;
   g1.colkey = p->colkey;
   if ((s = R::gemm_launch(p, EPI_LOGROW, g1)) != FOT_OK) return s;
-  GemmArgs gy = R::base_args(p, p->fA2, plane, p->flam, 0);
-  gy.out = p->fZy;
-  gy.sOut = plane;
-  if ((s = R::gemm_launch(p, EPI_RAW, gy)) != FOT_OK) return s;
-  GemmArgs gc = R::base_args(p, p->fA, plane, p->flamH, 0);
-  gc.out = p->fZc;
-  gc.sOut = plane;
-  if ((s = R::gemm_launch(p, EPI_RAW, gc)) != FOT_OK) return s;
   hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
                      p->mrow, p->colkey, p->n, p->np, p->fB);
-  hipLaunchKernelGGL((k_colexpT<double, double, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
-                     p->mrow, p->colkey, p->n, p->np, p->fBx);
-  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZy,
-                     p->mrow, p->colkey, p->n, p->np, p->fBy);
-  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZc,
-                     p->mrow, p->colkey, p->n, p->np, p->fBc);
   LAUNCH_CHECK();
-  struct Job { const void* A; const void* Bm; void* out; } jobs[5] = {
-      {p->flam, p->fB, p->fS}, {p->flam, p->fBx, p->fSx}, {p->flam, p->fBy, p->fSy},
-      {p->flamH, p->fB, p->fScx}, {p->flam, p->fBc, p->fScy}};
-  for (auto& j : jobs) {
-    GemmArgs g = R::base_args(p, j.A, 0, j.Bm, plane);
-    g.out = j.out;
-    g.sOut = plane;
-    if ((s = R::gemm_launch(p, EPI_RAW, g)) != FOT_OK) return s;
-  }
-  hipLaunchKernelGGL((k_readout<double>), dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream,
-                     (const double*)p->fS, (const double*)p->fSx, (const double*)p->fSy, (const double*)p->fScx,
-                     (const double*)p->fScy, p->colkey, p->lnS, p->lna, p->lnb, p->f, p->psi, p->lnSp, lnS_probe,
-                     p->n, p->np, eps, p->Tx, p->Ty, p->rparts);
-  hipLaunchKernelGGL(k_sum_parts, dim3(6, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS, p->rsums);
+  if ((s = gemm(p->flam, 0, p->fB, plane, p->Tx)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_S>, rgrid, rblock, 0, p->stream, p->Tx, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, p->lnSp, lnS_probe, p->n, p->np, eps, p->rparts);
+  LAUNCH_CHECK();
+  if ((s = gemm(p->flamH, 0, p->fB, plane, p->Tx)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_CX>, rgrid, rblock, 0, p->stream, p->Tx, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
+  hipLaunchKernelGGL((k_colexpT<double, double, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
+                     p->mrow, p->colkey, p->n, p->np, p->fB);
+  LAUNCH_CHECK();
+  if ((s = gemm(p->flam, 0, p->fB, plane, p->Tx)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_TX>, rgrid, rblock, 0, p->stream, p->Tx, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
+  LAUNCH_CHECK();
+  if ((s = gemm(p->fA, plane, p->flamH, 0, p->fB)) != FOT_OK) return s;
+  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fB,
+                     p->mrow, p->colkey, p->n, p->np, p->fZ);
+  LAUNCH_CHECK();
+  if ((s = gemm(p->flam, 0, p->fZ, plane, p->fB)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_CY>, rgrid, rblock, 0, p->stream, p->fB, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
+  // (the moment operand A2 with the row shifts of A0, which the column keys above refer to)
+  hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np,
+                     1.0 / eps, p->mrow, (double*)nullptr, p->fA, p->colkey, PendingSum{nullptr, 0, nullptr});
+  LAUNCH_CHECK();
+  if ((s = gemm(p->fA, plane, p->flam, 0, p->fZ)) != FOT_OK) return s;
+  hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
+                     p->mrow, p->colkey, p->n, p->np, p->fB);
+  LAUNCH_CHECK();
+  if ((s = gemm(p->flam, 0, p->fB, plane, p->Ty)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_TY>, rgrid, rblock, 0, p->stream, p->Ty, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
+  hipLaunchKernelGGL(k_sum_parts, dim3(READOUT_SLOTS, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS,
+                     p->rsums);
   hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->Tx, p->Ty, p->lna, p->n, p->np,
-                     p->phi, p->rowpart);
+                     p->fZ, p->rowpart);
   if (phase_out)
-    hipLaunchKernelGGL(k_center, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->phi, p->rowpart, p->n, p->np,
+    hipLaunchKernelGGL(k_center, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->fZ, p->rowpart, p->n, p->np,
                        phase_out);
   LAUNCH_CHECK();
   return FOT_OK;
@@ -1288,7 +1307,7 @@ fot_status solve_body(fot_plan_s* p, const std::vector<double>& e, int iters, do
     s = (hipEventRecord(p->ev[2], p->stream) == hipSuccess) ? FOT_OK : fail(FOT_E_HIP, "event record");
   const bool probed = !p->cfot && sizeof(L) != 8;
   if (s == FOT_OK && probed) s = Ops<L>::probe(p, e[iters - 1], iters, sched ? 1 : 0);
-  if (s == FOT_OK) s = readout64(p, e[iters - 1], phase_out, probed ? p->phi : nullptr);
+  if (s == FOT_OK) s = readout64(p, e[iters - 1], phase_out, probed ? p->Ty : nullptr);
   if (s == FOT_OK && p->ev[3])
     s = (hipEventRecord(p->ev[3], p->stream) == hipSuccess) ? FOT_OK : fail(FOT_E_HIP, "event record");
   activate(p, 0);
@@ -1404,7 +1423,6 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   ALLOC(p->lnS, BP);
   ALLOC(p->lnSp, BP);
   ALLOC(p->mrow, (size_t)p->B * p->np);
-  ALLOC(p->phi, BP);
   ALLOC(p->rowsum_g, (size_t)p->n);
   ALLOC(p->rowsum_G, (size_t)p->B * p->n);
   ALLOC(p->rowpart, (size_t)p->B * p->n);
@@ -1413,8 +1431,8 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   p->pending_tiles = p->tiles;
   ALLOC(p->hist_a, (size_t)d.max_iters * p->B);
   ALLOC(p->hist_b, (size_t)d.max_iters * p->B);
-  ALLOC(p->rparts, (size_t)6 * p->B * READOUT_BLOCKS);
-  ALLOC(p->rsums, (size_t)6 * p->B);
+  ALLOC(p->rparts, (size_t)READOUT_SLOTS * p->B * READOUT_BLOCKS);
+  ALLOC(p->rsums, (size_t)READOUT_SLOTS * p->B);
   ALLOC(p->probe_flag, (size_t)1);
   // (the most waves any iteration kernel has per target: 32 x 32 tiles of 4 waves)
   p->range_spt = (p->np / 32) * (p->np / 32) * 4;
@@ -1456,26 +1474,8 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
     p->flamH_valid = &p->flamH_valid_sep;
   }
   ALLOC(p->flamH, p->plane);
-  ALLOC(p->fA2, BP);
-  ALLOC(p->fBx, BP);
-  ALLOC(p->fBy, BP);
-  ALLOC(p->fBc, BP);
-  // T_x, T_y (Eq. 9-10) are written by k_readout after the GEMMs that read the read-out's moment
-  // operands fBx, fBy, and nothing writes those planes again before the next read-out (the end-of-
-  // solve probe writes its update to T_x before the read-out; the reverse sweep, which reads T_x
-  // and T_y, works in fA, fB and the loop's buffers): they share them.
-  p->Tx = p->fBx;
-  p->Ty = p->fBy;
-  ALLOC(p->fZy, BP);
-  ALLOC(p->fZc, BP);
-  // The five pass-2 outputs of the read-out (and the reverse sweep's fS) are written only after
-  // their inputs have been formed from fA, fA2, fZ, fZy and fZc, which are then dead (the launches
-  // are stream-ordered): they share those buffers.
-  p->fS = p->fA;
-  p->fSx = p->fA2;
-  p->fSy = p->fZ;
-  p->fScx = p->fZy;
-  p->fScy = p->fZc;
+  ALLOC(p->Tx, BP);
+  ALLOC(p->Ty, BP);
   if (cN > 0) {
     p->cfot = true;
     p->cN = cN;
@@ -1724,7 +1724,7 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
                                        });
   if (st != FOT_OK) return st;
 
-  std::vector<double> ha((size_t)iters * B), hb((size_t)iters * B), rs((size_t)6 * B);
+  std::vector<double> ha((size_t)iters * B), hb((size_t)iters * B), rs((size_t)READOUT_SLOTS * B);
   std::vector<int> riter((size_t)B, 0x7f7f7f7f), rmin((size_t)2 * B, 0x7f7f7f7f);
   std::vector<int> slots((size_t)2 * B * p->range_spt * 2);
   int pflag = 0;
@@ -1753,7 +1753,7 @@ fot_status fot_solve(fot_plan_t p, const double* g, const double* G, const doubl
   if (rep) {
     const double epT = e[iters - 1];
     for (int b = 0; b < B; ++b) {
-      const double err_a = rs[0 * B + b], mass = rs[1 * B + b], cost = rs[2 * B + b], dots = rs[3 * B + b],
+      const double err_a = rs[0 * B + b], mass = rs[1 * B + b], cost = rs[2 * B + b] + rs[6 * B + b], dots = rs[3 * B + b],
                    err_b = rs[4 * B + b];
       if (rep->err_a) rep->err_a[b] = err_a;
       if (rep->err_b) rep->err_b[b] = err_b;

@@ -442,7 +442,8 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
 // Row shift and shifted exponentials of a potential (pass-1 operand):
 //   m_i = max_k P_ik / eps (0 if the row has no finite entry), out_ik = exp(P_ik/eps - m_i).
 // Optionally out2_ik = out_ik * Y_k with Y_k = (k - floor(n/2)) / sqrt(n) (Eq. 10 moment).
-// Also clears the column-max keys that the following pass 1 fills.
+// Also clears the column-max keys that the following pass 1 fills.  With out = nullptr only out2 is
+// written (the same values), and the row shifts and column keys are left as they are.
 //
 // Block 0 of each batch entry also finishes the marginal-error reduction of the preceding
 // potential update: red_out[bz] = sum of red_parts[bz][0..red_tiles) in index order.
@@ -468,15 +469,15 @@ __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int
   const int i = blockIdx.x, bz = blockIdx.y;
   if (i == 0 && pend.parts) finish_pending(pend, bz, red);
   const size_t plane = (size_t)np * np;
-  T* o = out + bz * plane + (size_t)i * np;
+  T* o = out ? out + bz * plane + (size_t)i * np : nullptr;
   T* o2 = out2 ? out2 + bz * plane + (size_t)i * np : nullptr;
-  if (threadIdx.x == 0) colkey[(size_t)bz * np + i] = 0u;
+  if (o && threadIdx.x == 0) colkey[(size_t)bz * np + i] = 0u;
   if (i >= n) {
     for (int k = threadIdx.x; k < np; k += blockDim.x) {
-      o[k] = (T)0;
+      if (o) o[k] = (T)0;
       if (o2) o2[k] = (T)0;
     }
-    if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = 0.0;
+    if (o && threadIdx.x == 0) mrow[(size_t)bz * np + i] = 0.0;
     return;
   }
   const double* row = P + bz * plane + (size_t)i * np;
@@ -493,7 +494,7 @@ __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int
   }
   m = block_max(m, red);
   if (!(m > -INFINITY && m < INFINITY)) m = 0.0;
-  if (threadIdx.x == 0) mrow[(size_t)bz * np + i] = m;
+  if (o && threadIdx.x == 0) mrow[(size_t)bz * np + i] = m;
   const double ysc = 1.0 / sqrt((double)n);
 #pragma unroll
   for (int c = 0; c < MAXV; ++c) {
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int
       const int k = threadIdx.x + c * NTHREADS;
       if (k < np) {
         const bool ok = k < n;
-        o[k] = ok ? exp_op<T>(v[c] - m) : (T)0;
+        if (o) o[k] = ok ? exp_op<T>(v[c] - m) : (T)0;
         if (o2) o2[k] = ok ? scaled_exp_op<T>(v[c] - m, (double)(k - n / 2) * ysc) : (T)0;
       }
     }
@@ -640,66 +641,83 @@ __global__ __launch_bounds__(NTHREADS) void k_lnS_raw(const double* S, const uns
 }
 
 // ------------------------------------------------------------------ read-out (Eq. 9-10)
-// Inputs per pixel p = (j,k): S, Sx, Sy, Scx, Scy are the pass-2 outputs for V_T divided by
-// exp(m'_k); lnS_prev = ln(Lambda V_{T-1} Lambda) from the final u-update.  u/a = 1/S_prev.
-// lnS_probe (or nullptr) = ln S(V_T) as the loop's operand type forms it.
-// Writes Tx, Ty and per-block partial sums of: |row mass - a|, row mass, transport cost,
-// <f,a> + <psi,b>, column-mass error, and sum a |S_probe / S - 1| (the row-marginal error that
-// one more u-update in the operand type would make through its products alone).
-template <typename ZT>
+// The read-out's pass-2 outputs M are formed one at a time (so that they share one plane) and
+// each is consumed by one launch of k_readout<ROLE>.  M is the output for V_T divided by
+// exp(m'_k); u/a = 1/S_prev with ln S_prev = ln(Lambda V_{T-1} Lambda) from the final u-update, so
+// that a pixel's factor is scale = exp(m'_k - ln S_prev).  Roles:
+//   RO_S:   M = S.  Per-block partial sums of |row mass - a| (slot 0), the row mass (1),
+//           <f,a> + <psi,b> (3), the column-mass error (4) and, with lnS_probe = ln S(V_T) as the
+//           loop's operand type forms it, sum a |S_probe / S - 1| (5: the row-marginal error
+//           that one more u-update in the operand type would make through its products alone).
+//   RO_CX, RO_CY: M = Scx or Scy, the transport cost's x or y part (slot 2 or 6).
+//   RO_TX, RO_TY: M = Sx or Sy; T = M scale, written over M.
+enum ReadoutRole { RO_S = 0, RO_CX = 1, RO_CY = 2, RO_TX = 3, RO_TY = 4 };
+constexpr int READOUT_SLOTS = 7;
+template <int ROLE>
 __global__ __launch_bounds__(NTHREADS) void k_readout(
-    const ZT* S, const ZT* Sx, const ZT* Sy, const ZT* Scx, const ZT* Scy, const unsigned* colkey,
-    const double* lnS_prev, const double* lna, const double* lnb, const double* f, const double* psi,
-    const double* lnSp, const double* lnS_probe, int n, int np, double eps, double* Tx, double* Ty,
-    double* part /*[6][batch][blocks]*/) {
+    double* M, const unsigned* colkey, const double* lnS_prev, const double* lna, const double* lnb,
+    const double* f, const double* psi, const double* lnSp, const double* lnS_probe, int n, int np, double eps,
+    double* part /*[READOUT_SLOTS][batch][blocks]*/) {
   __shared__ double red[4];
   const int bz = blockIdx.y;
   const size_t plane = (size_t)np * np;
   const int nblk = gridDim.x;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double acc[5] = {0, 0, 0, 0, 0};
   const double inv_eps = 1.0 / eps;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
        idx += (size_t)nblk * blockDim.x) {
     const int j = (int)(idx / n), k = (int)(idx % n);
     const size_t o = bz * plane + (size_t)j * np + k;
     const size_t oa = (size_t)j * np + k;
-    const double scale = exp(key_to_shift(colkey[(size_t)bz * np + k]) - lnS_prev[o]);
-    Tx[o] = (double)Sx[o] * scale;
-    Ty[o] = (double)Sy[o] * scale;
+    const double shift = key_to_shift(colkey[(size_t)bz * np + k]);
+    const double scale = exp(shift - lnS_prev[o]);
+    if constexpr (ROLE == RO_TX || ROLE == RO_TY) {
+      M[o] = M[o] * scale;
+      continue;
+    }
     const double la = lna[oa];
-    if (la > -INFINITY) {
-      const double a = exp(la);
-      const double rm = a * (double)S[o] * scale;
-      acc[0] += fabs(rm - a);
-      acc[1] += rm;
-      acc[2] += a * scale * ((double)Scx[o] + (double)Scy[o]);
-      acc[3] += a * f[o];
-      if (lnS_probe) {
-        // ln S(V_T) in FP64 against the operand type's value
-        const double lnS64 = key_to_shift(colkey[(size_t)bz * np + k]) + log((double)S[o]);
-        const double d = lnS_probe[o] - lnS64;
-        // both -inf: no term; any other NaN (a non-finite probe) counts as the pixel's whole mass
-        const bool none = lnS_probe[o] == -INFINITY && lnS64 == -INFINITY;
-        acc[5] += none ? 0.0 : (d == d) ? a * fabs(expm1(d)) : a;
+    if constexpr (ROLE == RO_CX || ROLE == RO_CY) {
+      if (la > -INFINITY) acc[0] += exp(la) * scale * M[o];
+      continue;
+    }
+    if constexpr (ROLE == RO_S) {
+      if (la > -INFINITY) {
+        const double a = exp(la);
+        const double rm = a * M[o] * scale;
+        acc[0] += fabs(rm - a);
+        acc[1] += rm;
+        acc[2] += a * f[o];
+        if (lnS_probe) {
+          // ln S(V_T) in FP64 against the operand type's value
+          const double lnS64 = shift + log(M[o]);
+          const double d = lnS_probe[o] - lnS64;
+          // both -inf: no term; any other NaN (a non-finite probe) counts as the pixel's whole mass
+          const bool none = lnS_probe[o] == -INFINITY && lnS64 == -INFINITY;
+          acc[4] += none ? 0.0 : (d == d) ? a * fabs(expm1(d)) : a;
+        }
+      }
+      const double lb = lnb[o];
+      const double cmass = exp(psi[o] * inv_eps + lnSp[o]);
+      if (lb > -INFINITY) {
+        acc[2] += exp(lb) * psi[o];
+        acc[3] += fabs(cmass - exp(lb));
+      } else {
+        acc[3] += cmass;
       }
     }
-    const double lb = lnb[o];
-    const double cmass = exp(psi[o] * inv_eps + lnSp[o]);
-    if (lb > -INFINITY) {
-      acc[3] += exp(lb) * psi[o];
-      acc[4] += fabs(cmass - exp(lb));
-    } else {
-      acc[4] += cmass;
-    }
   }
+  if constexpr (ROLE == RO_TX || ROLE == RO_TY) return;
   const int B = gridDim.y;
-  for (int q = 0; q < 6; ++q) {
+  constexpr int NQ = ROLE == RO_S ? 5 : 1;
+  constexpr int slot_s[5] = {0, 1, 3, 4, 5};
+  for (int q = 0; q < NQ; ++q) {
+    const int sl = ROLE == RO_S ? slot_s[q] : ROLE == RO_CX ? 2 : 6;
     const double s = block_sum(acc[q], red);
-    if (threadIdx.x == 0) part[((size_t)q * B + bz) * nblk + blockIdx.x] = s;
+    if (threadIdx.x == 0) part[((size_t)sl * B + bz) * nblk + blockIdx.x] = s;
   }
 }
 
-// Deterministic final sums of the read-out partials: out[q][bz] for q in 0..4.
+// Deterministic final sums of the read-out partials: out[q][bz] for q < READOUT_SLOTS.
 __global__ void k_sum_parts(const double* part, int nblk, double* out) {
   __shared__ double red[4];
   const int q = blockIdx.x, bz = blockIdx.y, B = gridDim.y;

@@ -714,11 +714,11 @@ def test_mid_trajectory_range_losses_are_reported(n, prec, eps, T, reported):
 @pytest.mark.parametrize("n,B,prec", [(1024, 1, "f32"), (1024, 1, "bf16"), (512, 4, "f32"), (1024, 1, "f64")])
 def test_plan_memory_is_linear_in_pixels(n, B, prec):
     """O(N) memory (Sec. 4, Table 1): a plan's device memory (no tape, no output-beam workspace) is
-    at most (128 B + 28) bytes per padded pixel for 32- and 16-bit operand types: per target 15 FP64
-    planes (f, psi, ln b, ln S, ln S', phase and the read-out's 9 operand and intermediate planes,
-    which its outputs and T_x, T_y share) and two operand planes of at most 4 bytes; shared ln a,
-    Lambda and Lambda o H in FP64 and Lambda in the operand type.  FP64 plans reuse the loop's
-    buffers for the read-out: at most (120 B + 24) bytes."""
+    at most (88 B + 28) bytes per padded pixel for 32- and 16-bit operand types: per target 10 FP64
+    planes (f, psi, ln b, ln S, ln S', the read-out's three scratch planes and T_x, T_y; the phase
+    goes to the caller's array) and two operand planes of at most 4 bytes; shared ln a, Lambda and
+    Lambda o H in FP64 and Lambda in the operand type.  FP64 plans reuse the loop's buffers for the
+    read-out: at most (80 B + 24) bytes."""
     import torch
     from paper_2512_19072_amd import fot as F
     torch.cuda.synchronize()
@@ -728,7 +728,7 @@ def test_plan_memory_is_linear_in_pixels(n, B, prec):
     used = free0 - torch.cuda.mem_get_info()[0]
     plan.close()
     npad = -(-n // 256) * 256
-    per_px = (120 * B + 24) if prec == "f64" else (128 * B + 28)
+    per_px = (80 * B + 24) if prec == "f64" else (88 * B + 28)
     bound = per_px * npad * npad + (8 << 20)
     _say(f"plan {n}^2 x {B} {prec}: {used / 2**20:.1f} MiB (bound {bound / 2**20:.1f} MiB)")
     assert used <= bound
