@@ -98,14 +98,16 @@ enum {
                             largest lose accuracy: at small eps fot_solve may return
                             FOT_E_NONFINITE, or FOT_E_RANGE when the final column-marginal L1
                             exceeds 1e-6 */
-  FOT_FLAG_SMALL_TILES = 16, /* run the iteration kernels on 32 x 32 output tiles, with operands
-                            normalised in 32-wide instead of 64-wide blocks.  fot_plan chooses
-                            these tiles by itself when 64 x 64 tiles would occupy at most half of
-                            the GPU's compute units (small grids); on larger grids the flag
-                            trades speed (about 1.3x the time per iteration at 1024 x 1024) for
-                            range: the 32- and 16-bit operand types then reach about half the
-                            eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian 1024 x 1024
-                            workload).  No effect with FOT_FLAG_CFOT */
+  FOT_FLAG_SMALL_TILES = 16, /* normalise the iteration kernels' operands in 32-wide instead of
+                            64-wide blocks.  fot_plan runs the kernels on 32 x 32 output tiles,
+                            whose blocks are 32 wide anyway, when 64 x 64 tiles would occupy at
+                            most half of the GPU's compute units (small grids); on larger grids
+                            the flag keeps the 64 x 64 tiles with two blocks each and trades
+                            speed (about 1.12x the time per iteration at 1024 x 1024 and
+                            eps 2e-4) for range: the 32- and 16-bit operand types then reach
+                            about half the eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian
+                            1024 x 1024 workload).  The two tilings give bit-identical
+                            potentials.  No effect with FOT_FLAG_CFOT */
   FOT_FLAG_F64_REVERSE = 32, /* fot_backward after an FP32 solve: run the reverse half-steps with FP64
                             operands, as for the other precisions.  Without the flag they use FP32
                             operands wherever the solve held the Gibbs factor raw in FP32: on 8

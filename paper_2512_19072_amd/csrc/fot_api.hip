@@ -46,6 +46,10 @@ constexpr int READOUT_BLOCKS = 256;
 
 }  // namespace
 
+// fused-kernel tile configurations (fot_plan_s::tcfg): 64 x 64 tiles, 32 x 32 tiles (small grids,
+// 32-wide exponent blocks), 64 x 64 tiles with 32-wide exponent blocks
+enum { TCFG_LARGE = 0, TCFG_SMALL = 1, TCFG_BLOCK32 = 2 };
+
 struct fot_plan_s {
   fot_plan_desc d{};
   int n = 0, np = 0, B = 0, prec = 0, tiles = 0;
@@ -61,7 +65,7 @@ struct fot_plan_s {
   unsigned* colkey = nullptr;
   int *kexpA = nullptr, *kexpT = nullptr;   // exponent tables of the block-normalised loop operands
   int nbA = 0, nbT = 0;
-  bool t32 = false;                         // fused kernels on 32 x 32 tiles (small grids)
+  int tcfg = 0;                             // fused kernels' tiles (TCFG_*)
   int* kexpL = nullptr;                     // LN form: [np][nbA] exponents of the block-normalised Lambda
   int* probe_flag = nullptr;                // non-finite flag of the end-of-solve probe
   // range check: per wave of the fused kernels, the lowest margin and the first iteration below the
@@ -286,6 +290,19 @@ struct Ops {
   // four waves (one per SIMD), whose exponent blocks are 32 wide.  Four times the workgroups
   // and a quarter of the work each, so a launch's fixed latency (first stage, epilogue) is shorter.
   typedef Cfg<32, 32, 4, 1, 1> GS;
+  // 64 x 64 tiles with 32-wide exponent blocks (FOT_FLAG_SMALL_TILES on grids that take 64 x 64
+  // tiles): the range of the 32 x 32 tiles at close to the speed of the 64 x 64 ones.
+  typedef Cfg<64, 64, 8, 2, 1, 2> GC2;
+  // Call f with the plan's fused-kernel tile configuration (an empty tag object).
+  template <typename F>
+  static void with_cfg(const fot_plan_s* p, F&& f) {
+    if (p->tcfg == TCFG_SMALL)
+      f(GS{});
+    else if (p->tcfg == TCFG_BLOCK32)
+      f(GC2{});
+    else
+      f(GC{});
+  }
 
   static fot_status gemm_launch(fot_plan_s* p, int epi, const GemmArgs& a) {
     dim3 grid(p->np / GC::BN, p->np / GC::BM, p->B);
@@ -332,15 +349,13 @@ struct Ops {
       return true;
     } else {
       hipFuncAttributes fa{};
-      hipError_t e;
-      size_t dyn;
-      if (p->t32) {
-        e = hipFuncGetAttributes(&fa, (const void*)k_fused<T, 2, GS, FUSED_NBUF, true>);
-        dyn = fused_dyn_lds<2, GS, true>(p->np);
-      } else {
-        e = hipFuncGetAttributes(&fa, (const void*)k_fused<T, 2, GC, FUSED_NBUF, true>);
-        dyn = fused_dyn_lds<2, GC, true>(p->np);
-      }
+      hipError_t e = hipSuccess;
+      size_t dyn = 0;
+      with_cfg(p, [&](auto c) {
+        typedef decltype(c) C;
+        e = hipFuncGetAttributes(&fa, (const void*)k_fused<T, 2, C, FUSED_NBUF, true>);
+        dyn = fused_dyn_lds<2, C, true>(p->np);
+      });
       int lim = 0;
       if (e != hipSuccess || hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess) {
         (void)hipGetLastError();
@@ -370,12 +385,11 @@ struct Ops {
 
   static fot_status fill_lambda(fot_plan_s* p, double eps, bool /*unused*/) {
     if (lam_ln(p, eps)) {
-      if (p->t32)
-        hipLaunchKernelGGL((k_lambda_blocks<T, GS::BN>), dim3(p->np), dim3(64), 0, p->stream, p->n, p->np, 1.0 / eps,
-                           (T*)p->lam, p->kexpL);
-      else
-        hipLaunchKernelGGL((k_lambda_blocks<T, GC::BN>), dim3(p->np), dim3(64), 0, p->stream, p->n, p->np, 1.0 / eps,
-                           (T*)p->lam, p->kexpL);
+      with_cfg(p, [&](auto c) {
+        typedef decltype(c) C;
+        hipLaunchKernelGGL((k_lambda_blocks<T, C::BN / C::XS>), dim3(p->np), dim3(64), 0, p->stream, p->n, p->np,
+                           1.0 / eps, (T*)p->lam, p->kexpL);
+      });
     } else {
       const size_t total = p->plane;
       const int blocks = (int)((total + 255) / 256);
@@ -444,18 +458,14 @@ struct Ops {
     hipEvent_t e1 = prof ? p->prof[p->prof_used + 1] : nullptr;
     bool ln = false;
     if constexpr (sizeof(T) < 8) ln = a.kexpL != nullptr;
-    if (ln) {
-      if constexpr (sizeof(T) < 8) {
-        if (p->t32)
-          fused_launch_cfg<GS, true>(p, pass, a, e0, e1);
-        else
-          fused_launch_cfg<GC, true>(p, pass, a, e0, e1);
+    with_cfg(p, [&](auto c) {
+      typedef decltype(c) C;
+      if (ln) {
+        if constexpr (sizeof(T) < 8) fused_launch_cfg<C, true>(p, pass, a, e0, e1);
+      } else {
+        fused_launch_cfg<C, false>(p, pass, a, e0, e1);
       }
-    } else if (p->t32) {
-      fused_launch_cfg<GS, false>(p, pass, a, e0, e1);
-    } else {
-      fused_launch_cfg<GC, false>(p, pass, a, e0, e1);
-    }
+    });
     LAUNCH_CHECK();
     if (prof) p->prof_used += 2;
     return FOT_OK;
@@ -463,12 +473,11 @@ struct Ops {
 
   // Block-normalised pass-1 operand of a potential (start of a solve or of a replayed segment).
   static fot_status prep(fot_plan_s* p, const double* P, double eps) {
-    if (p->t32)
-      hipLaunchKernelGGL((k_prep_blocks<T, GS::BN>), dim3(p->np * p->np / (256 * PREP_U), p->B), dim3(256), 0, p->stream, P,
-                         p->n, p->np, 1.0 / eps, (T*)p->opA, p->kexpA);
-    else
-      hipLaunchKernelGGL((k_prep_blocks<T, GC::BN>), dim3(p->np * p->np / (256 * PREP_U), p->B), dim3(256), 0, p->stream, P,
-                         p->n, p->np, 1.0 / eps, (T*)p->opA, p->kexpA);
+    with_cfg(p, [&](auto c) {
+      typedef decltype(c) C;
+      hipLaunchKernelGGL((k_prep_blocks<T, C::BN / C::XS>), dim3(p->np * p->np / (256 * PREP_U), p->B), dim3(256), 0,
+                         p->stream, P, p->n, p->np, 1.0 / eps, (T*)p->opA, p->kexpA);
+    });
     LAUNCH_CHECK();
     return FOT_OK;
   }
@@ -720,12 +729,12 @@ struct Ops {
       const long long plane = (long long)p->plane;
       const double eps = st.eps;
       const dim3 pg(p->np * p->np / (256 * PREP_U), p->B);
-      if (st.have_operand) {
-      } else if (p->t32) {
-        hipLaunchKernelGGL((k_adj_prep<T, GS::BN>), pg, dim3(256), 0, p->stream, st.v, st.L, p->n, p->np, A, p->kexpA);
-      } else {
-        hipLaunchKernelGGL((k_adj_prep<T, GC::BN>), pg, dim3(256), 0, p->stream, st.v, st.L, p->n, p->np, A, p->kexpA);
-      }
+      if (!st.have_operand)
+        with_cfg(p, [&](auto c) {
+          typedef decltype(c) C;
+          hipLaunchKernelGGL((k_adj_prep<T, C::BN / C::XS>), pg, dim3(256), 0, p->stream, st.v, st.L, p->n, p->np, A,
+                             p->kexpA);
+        });
       LAUNCH_CHECK();
       FusedArgs a{};
       a.n = p->n;
@@ -765,13 +774,11 @@ struct Ops {
       b.adj_next_L = st.next_L;
       b.nextA = A;   // (pass 1 has consumed it)
       b.kexpN = p->kexpA;
-      if (p->t32) {
-        adj_launch_cfg<GS>(p, 1, a);
-        adj_launch_cfg<GS>(p, 2, b);
-      } else {
-        adj_launch_cfg<GC>(p, 1, a);
-        adj_launch_cfg<GC>(p, 2, b);
-      }
+      with_cfg(p, [&](auto c) {
+        typedef decltype(c) C;
+        adj_launch_cfg<C>(p, 1, a);
+        adj_launch_cfg<C>(p, 2, b);
+      });
       LAUNCH_CHECK();
       return FOT_OK;
     }
@@ -1399,15 +1406,21 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   // fused-kernel tiles: 64 x 64, or 32 x 32 when 64 x 64 tiles would occupy at most half of the
   // CUs.  Measured FP32 half-steps (pass 1 + pass 2), 32 x 32 against 64 x 64 tiles on 256 CUs:
   // 512^2 17 against 32 us, 640^2 27 against 38 us, 768^2 45 against 43 us (BF16 26 against
-  // 20 us), 1024^2 73 against 57 us.
+  // 20 us), 1024^2 73 against 57 us.  FOT_FLAG_SMALL_TILES asks for 32-wide exponent blocks: the
+  // 32 x 32 tiles where they are chosen anyway, 64 x 64 tiles with two blocks per tile otherwise.
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
       hipDeviceGetAttribute(&p->lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess)
     return bail(fail(FOT_E_HIP, "fot_plan: cannot query the device"));
-  p->t32 = (d.flags & FOT_FLAG_SMALL_TILES) ||
-           2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
-  const int tbm = p->t32 ? Ops<float>::GS::BM : Ops<float>::GC::BM;
-  const int tbn = p->t32 ? Ops<float>::GS::BN : Ops<float>::GC::BN;
+  const bool small = 2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
+  p->tcfg = small ? TCFG_SMALL : (d.flags & FOT_FLAG_SMALL_TILES) ? TCFG_BLOCK32 : TCFG_LARGE;
+  int tbm = 0, tbn = 0, txs = 1;
+  Ops<float>::with_cfg(p, [&](auto c) {
+    typedef decltype(c) C;
+    tbm = C::BM;
+    tbn = C::BN;
+    txs = C::XS;
+  });
   // one marginal-error partial per output tile of the fused pass-2 kernel
   p->tiles = (p->np / tbm) * (p->np / tbn);
   const size_t BP = (size_t)p->B * p->plane;
@@ -1438,8 +1451,8 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   p->range_spt = (p->np / 32) * (p->np / 32) * 4;
   ALLOC(p->range_slots, (size_t)2 * p->B * p->range_spt * 2);
   ALLOC(p->colkey, (size_t)p->B * p->np);
-  p->nbA = p->np / tbn;
-  p->nbT = p->np / tbm;
+  p->nbA = p->np / (tbn / txs);
+  p->nbT = p->np / (tbm / txs);
   ALLOC(p->kexpA, (size_t)p->B * p->np * p->nbA);
   ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
   if (d.precision != FOT_F64) ALLOC(p->kexpL, (size_t)p->np * p->nbA);

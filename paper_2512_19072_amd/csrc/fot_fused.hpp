@@ -467,7 +467,7 @@ template <int PASS, typename C>
 constexpr int fused_scaled_rows() { return PASS == 1 ? C::BM : C::BN; }
 template <int PASS, typename C, bool LN = false, bool TZ = false>
 inline size_t fused_dyn_lds(int np) {
-  const int xb = PASS == 1 ? C::BN : C::BM;
+  const int xb = (PASS == 1 ? C::BN : C::BM) / C::XS;
   const int lam_rows = PASS == 1 ? C::BN : C::BM;
   size_t bytes = (size_t)(np / xb) * (fused_scaled_rows<PASS, C>() + (LN ? lam_rows : 0)) * sizeof(short);
   if (TZ) bytes = (bytes + 15) / 16 * 16 + toeplitz_table_bytes(np, lam_rows);
@@ -483,7 +483,12 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   static_assert(NBUF >= 2, "at least double buffering");
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int BM = C::BM, BN = C::BN, RB = C::RB, CB = C::CB;
-  constexpr int XB = PASS == 1 ? BN : BM;         // K extent of one exponent block of this pass
+  constexpr int XB = (PASS == 1 ? BN : BM) / C::XS;   // K extent of one exponent block of this pass
+  // exponent blocks of the outputs: pass 1's (the pass-2 operand's) span XB1 rows, the next
+  // operand's (pass 2) XB2 columns; WPB1 / WPB2 waves along M / N share one
+  constexpr int XB1 = BM / C::XS, XB2 = BN / C::XS;
+  constexpr int WPB1 = XB1 / C::WTM, WPB2 = XB2 / C::WTN;
+  static_assert(XB1 % C::WTM == 0 && XB2 % C::WTN == 0, "an exponent block holds whole wave tiles");
   constexpr int SR = fused_scaled_rows<PASS, C>(); // rows whose exponents scale the sums
   constexpr int HPS = FROWB / 64;                 // fragment steps per K stage
   constexpr int EPH = 64 / (int)sizeof(T);        // K elements per fragment step (4 lane groups;
@@ -890,7 +895,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   // col0 + wn*WTN + cb*16 + r16; its true value is accd * 2^(reference exponent).  The element
   // work is written without branches (selects), so the compiler interleaves the elements.
   if constexpr (PASS == 1) {
-    // W[L][k] = accd 2^{R_L}.  Column block exponent K'[k] = max over this tile's rows of the
+    // W[L][k] = accd 2^{R_L}.  Column block exponent K'[k] = max over the tile's XB1 rows of the
     // binary exponent of W; Bt[k][L] = W 2^{-K'} in (0, 1).
     int ecol[CB];
     int mmin = INT_MAX;
@@ -940,10 +945,11 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     for (int cb = 0; cb < CB; ++cb) {
       const int lc = wn * C::WTN + cb * 16 + r16;
       const int j = col0 + lc;
-      int K = ered[0][lc];
+      const int xblk = wm / WPB1;                   // this wave's exponent block of rows
+      int K = ered[xblk * WPB1][lc];
 #pragma unroll
-      for (int w = 1; w < C::WGM; ++w) K = max(K, ered[w][lc]);
-      if (wm == 0 && g == 0 && j < n) p.kexpT[((size_t)bz * np + j) * p.nbT + tr] = K;
+      for (int w = 1; w < WPB1; ++w) K = max(K, ered[xblk * WPB1 + w][lc]);
+      if (wm % WPB1 == 0 && g == 0 && j < n) p.kexpT[((size_t)bz * np + j) * p.nbT + tr * C::XS + xblk] = K;
       if (j >= n) continue;  // padded rows of Bt stay zero
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
@@ -1034,7 +1040,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         }
     }
     if (p.adj_next_L) {
-      // next pass-1 operand: this tile's columns are one exponent block of its rows
+      // next pass-1 operand: the tile's columns are XS exponent blocks of its rows
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -1053,10 +1059,11 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         for (int e = 0; e < 4; ++e) {
           const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int i = row0 + lr;
-          int K = kred[0][lr];
+          const int xblk = wn / WPB2;               // this wave's exponent block of columns
+          int K = kred[xblk * WPB2][lr];
 #pragma unroll
-          for (int w = 1; w < C::WGN; ++w) K = max(K, kred[w][lr]);
-          if (wn == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc] = K;
+          for (int w = 1; w < WPB2; ++w) K = max(K, kred[xblk * WPB2 + w][lr]);
+          if (wn % WPB2 == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc * C::XS + xblk] = K;
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
             const int j = col0 + wn * C::WTN + cb * 16 + r16;
@@ -1124,7 +1131,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     }
 
     if (p.next_inv_eps > 0.0) {
-      // next pass-1 operand: per output row, the exponent of the max over this tile's columns
+      // next pass-1 operand: per output row, the exponent of the max over each XB2 of the tile's columns
       const double ninv = p.next_inv_eps;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -1153,10 +1160,11 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
         for (int e = 0; e < 4; ++e) {
           const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int i = row0 + lr;
-          int K = kred[0][lr];
+          const int xblk = wn / WPB2;               // this wave's exponent block of columns
+          int K = kred[xblk * WPB2][lr];
 #pragma unroll
-          for (int w = 1; w < C::WGN; ++w) K = max(K, kred[w][lr]);
-          if (wn == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc] = K;
+          for (int w = 1; w < WPB2; ++w) K = max(K, kred[xblk * WPB2 + w][lr]);
+          if (wn % WPB2 == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc * C::XS + xblk] = K;
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
             const int j = col0 + wn * C::WTN + cb * 16 + r16;

@@ -262,10 +262,11 @@ __device__ __forceinline__ void tile_of(int tiles_x, int tiles_y, int swz, int* 
 }
 
 // Tile configuration: a BM x BN output tile per workgroup of NW wave64s; every wave owns an
-// (RB*16) x (CB*16) block of 16 x 16 MFMA tiles.
-template <int BM_, int BN_, int NW_, int RB_, int CB_>
+// (RB*16) x (CB*16) block of 16 x 16 MFMA tiles.  The fused kernels normalise their operands in
+// exponent blocks of BN / XS (pass-1 operand) and BM / XS (pass-2 operand) K values.
+template <int BM_, int BN_, int NW_, int RB_, int CB_, int XS_ = 1>
 struct Cfg {
-  static constexpr int BM = BM_, BN = BN_, NW = NW_, RB = RB_, CB = CB_;
+  static constexpr int BM = BM_, BN = BN_, NW = NW_, RB = RB_, CB = CB_, XS = XS_;
   static constexpr int WTM = 16 * RB, WTN = 16 * CB;          // wave tile
   static constexpr int WGN = BN / WTN, WGM = BM / WTM;         // waves along N and M
   static constexpr int THREADS = 64 * NW;

@@ -387,9 +387,9 @@ def test_range_loss_is_reported():
 
 
 def test_small_tiles_flag_reaches_half_the_eps():
-    """FOT_FLAG_SMALL_TILES runs a 1024^2 solve on 32 x 32 tiles with 32-wide operand blocks: at
-    eps = 1e-4, where 64-wide blocks lose FP32's range (test_range_loss_is_reported), FP32
-    operands then match the oracle."""
+    """FOT_FLAG_SMALL_TILES runs a 1024^2 solve with 32-wide operand blocks (64 x 64 tiles holding
+    two blocks each): at eps = 1e-4, where 64-wide blocks lose FP32's range
+    (test_range_loss_is_reported), FP32 operands then match the oracle."""
     from paper_2512_19072_amd import fot as F
     from tests.parity_util import to_dev
     n, T, eps = 1024, 40, 1e-4
@@ -409,6 +409,28 @@ def test_small_tiles_flag_reaches_half_the_eps():
     ef, ep = gauge_rel(gpu["f"][0], ref.f, a), gauge_rel(gpu["psi"][0], ref.psi, b)
     _say(f"f {ef:.2e} psi {ep:.2e} err_b {rep.err_b[0]:.2e}")
     assert ef < 1e-6 and ep < 1e-6, (ef, ep)
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-2), ("bf16", 1e-2), ("f32", 5e-4)])
+def test_block32_tiles_match_small_tiles_bit_for_bit(prec, eps):
+    """32-wide exponent blocks on 64 x 64 tiles (FOT_FLAG_SMALL_TILES where the grid takes 64 x 64
+    tiles: four 512^2 targets) against 32 x 32 tiles (chosen for one 512^2 target): the blocks, the
+    K order of every sum and the element work are the same, so the potentials and the phase of
+    each target are bit-identical (at 5e-4 with the block-normalised Lambda as well)."""
+    import torch
+    n, T = 512, 30
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    if not (128 <= cus < 512):
+        pytest.skip(f"{cus} CUs: the two 512^2 cases would not use the two tile configurations")
+    g, G = _rand_case(n, 31)
+    _say(f"case: 32-wide blocks n={n} {prec} eps={eps}: 32 x 32 tiles (B=1) against 64 x 64 tiles (B=4)")
+    one = run_gpu(g, G, eps, T, prec)
+    four = run_gpu(g, np.stack([G] * 4), eps, T, prec, small_tiles=True)
+    assert one["status"] == four["status"], (one["status"], four["status"])
+    for b in range(4):
+        for k in ("f", "psi", "phase"):
+            same = (one[k][0] == four[k][b]) | (np.isnan(one[k][0]) & np.isnan(four[k][b]))
+            assert same.all(), (b, k, int((~same).sum()))
 
 
 def test_small_eps_beyond_the_lds_table_is_unsupported():
