@@ -102,9 +102,10 @@ enum {
                             64-wide blocks.  fot_plan runs the kernels on 32 x 32 output tiles,
                             whose blocks are 32 wide anyway, when 64 x 64 tiles would occupy at
                             most half of the GPU's compute units (small grids); on larger grids
-                            the flag keeps the 64 x 64 tiles with two blocks each and trades
-                            speed (about 1.12x the time per iteration at 1024 x 1024 and
-                            eps 2e-4) for range: the 32- and 16-bit operand types then reach
+                            the flag keeps the 64 x 64 tiles with two blocks each (up to
+                            n_p = 3584, beyond which the block-normalised Lambda's exponent table
+                            needs the 32 x 32 tiles) and trades speed (about 1.12x the time per
+                            iteration at 1024 x 1024 and eps 2e-4) for range: the 32- and 16-bit operand types then reach
                             about half the eps (FP32: 1e-4 instead of 2e-4 on the two-Gaussian
                             1024 x 1024 workload).  The two tilings give bit-identical
                             potentials.  No effect with FOT_FLAG_CFOT */

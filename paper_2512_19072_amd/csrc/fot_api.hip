@@ -1414,6 +1414,17 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
     return bail(fail(FOT_E_HIP, "fot_plan: cannot query the device"));
   const bool small = 2LL * d.batch * (p->np / Ops<float>::GC::BM) * (p->np / Ops<float>::GC::BN) <= (long long)cus;
   p->tcfg = small ? TCFG_SMALL : (d.flags & FOT_FLAG_SMALL_TILES) ? TCFG_BLOCK32 : TCFG_LARGE;
+  if (p->tcfg == TCFG_BLOCK32) {
+    // the block-normalised Lambda's exponent table takes twice the LDS with 32-wide blocks on 64 x 64
+    // tiles: where it would not fit beside the stage buffers, the 32 x 32 tiles serve the flag
+    hipFuncAttributes fa{};
+    typedef Ops<float>::GC2 C;
+    if (hipFuncGetAttributes(&fa, (const void*)k_fused<float, 2, C, FUSED_NBUF, true>) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(FOT_E_HIP, "fot_plan: cannot query the fused kernel"));
+    }
+    if (fa.sharedSizeBytes + fused_dyn_lds<2, C, true>(p->np) > (size_t)p->lds_limit) p->tcfg = TCFG_SMALL;
+  }
   int tbm = 0, tbn = 0, txs = 1;
   Ops<float>::with_cfg(p, [&](auto c) {
     typedef decltype(c) C;
