@@ -433,6 +433,29 @@ def test_block32_tiles_match_small_tiles_bit_for_bit(prec, eps):
             assert same.all(), (b, k, int((~same).sum()))
 
 
+def test_block32_tiles_with_block_normalised_lambda_at_2048():
+    """FOT_FLAG_SMALL_TILES at 2048^2 and eps = 1e-4: 64 x 64 tiles with 32-wide blocks and Lambda
+    block-normalised (its raw FP32 band is ~300 px), whose doubled exponent table still fits in
+    LDS at this n_p; FP32 potentials against the oracle after a few iterations."""
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import gauge_rel, to_dev
+    n, T, eps = 2048, 6, 1e-4
+    g, G = W.twogauss_to_shapes(n)
+    G = G if G.ndim == 2 else G[0]
+    _say(f"case: 32-wide blocks on 64 x 64 tiles, block-normalised Lambda, n={n} f32 eps={eps} T={T}")
+    plan = F.Plan(n, 1, "f32", max_iters=T, small_tiles=True)
+    _, rep, st = plan.solve(to_dev(g), to_dev(G[None]), eps, T, check=False)
+    f, psi = plan.potentials()
+    plan.close()
+    assert st == F.FOT_OK, (st, F.fot_last_error())
+    ref = O.solve_sep(g, G, eps, T)
+    a = g ** 2 / np.sum(g ** 2)
+    b = G ** 2 / np.sum(G ** 2)
+    ef, ep = gauge_rel(f.cpu().numpy()[0], ref.f, a), gauge_rel(psi.cpu().numpy()[0], ref.psi, b)
+    _say(f"f {ef:.2e} psi {ep:.2e} err_b {rep.err_b[0]:.2e}")
+    assert ef < 1e-6 and ep < 1e-6, (ef, ep)
+
+
 def test_small_eps_beyond_the_lds_table_is_unsupported():
     """At n = 8192 the block-normalised Gibbs factor's exponent table no longer fits in LDS beside
     the 64 x 64-tile stage buffers: a 32-bit solve at an eps that needs it returns
