@@ -512,8 +512,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   constexpr int LR = PASS == 1 ? BN : BM;         // Lambda rows of the tile (output columns / rows)
   __shared__ int rref[SR];                        // reference exponent of each scaled row
   __shared__ double red[C::NW];
-  __shared__ int kred[C::WGN][BM];                // pass 2: row exponents of the next operand
-  __shared__ int ered[C::WGM][BN];                // pass 1: column exponent maxima
+  // pass 2: row exponents of the next operand, [row][wave column] so that a row's entries are
+  // one vector read
+  __shared__ __attribute__((aligned(16))) int kred[BM][C::WGN];
+  __shared__ __attribute__((aligned(16))) int ered[BN][C::WGM];   // pass 1: column exponent maxima, [column][wave row]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / C::WGN, wn = wave % C::WGN;
@@ -921,7 +923,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     for (int cb = 0; cb < CB; ++cb) {
       ecol[cb] = max(ecol[cb], __shfl_xor(ecol[cb], 16, 64));
       ecol[cb] = max(ecol[cb], __shfl_xor(ecol[cb], 32, 64));
-      if (g == 0) ered[wm][wn * C::WTN + cb * 16 + r16] = ecol[cb];
+      if (g == 0) ered[wn * C::WTN + cb * 16 + r16][wm] = ecol[cb];
     }
     // pending marginal-error sum: entries beyond the prefetched ones, then per-wave sums
     double pend = 0.0;
@@ -946,9 +948,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       const int lc = wn * C::WTN + cb * 16 + r16;
       const int j = col0 + lc;
       const int xblk = wm / WPB1;                   // this wave's exponent block of rows
-      int K = ered[xblk * WPB1][lc];
+      int K = ered[lc][xblk * WPB1];
 #pragma unroll
-      for (int w = 1; w < WPB1; ++w) K = max(K, ered[xblk * WPB1 + w][lc]);
+      for (int w = 1; w < WPB1; ++w) K = max(K, ered[lc][xblk * WPB1 + w]);
       if (wm % WPB1 == 0 && g == 0 && j < n) p.kexpT[((size_t)bz * np + j) * p.nbT + tr * C::XS + xblk] = K;
       if (j >= n) continue;  // padded rows of Bt stay zero
 #pragma unroll
@@ -1049,7 +1051,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) k = max(k, block_exponent(ln_v[cb][rb][e]));
           k = row16_max(k);
-          if (r16 == 0) kred[wn][wm * C::WTM + rb * 16 + Mma<T>::row(g, e)] = k;
+          if (r16 == 0) kred[wm * C::WTM + rb * 16 + Mma<T>::row(g, e)][wn] = k;
         }
       lds_barrier();
       T* nA = (T*)p.nextA + (size_t)bz * plane;
@@ -1060,9 +1062,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int i = row0 + lr;
           const int xblk = wn / WPB2;               // this wave's exponent block of columns
-          int K = kred[xblk * WPB2][lr];
+          int K = kred[lr][xblk * WPB2];
 #pragma unroll
-          for (int w = 1; w < WPB2; ++w) K = max(K, kred[xblk * WPB2 + w][lr]);
+          for (int w = 1; w < WPB2; ++w) K = max(K, kred[lr][xblk * WPB2 + w]);
           if (wn % WPB2 == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc * C::XS + xblk] = K;
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
@@ -1141,7 +1143,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) k = max(k, block_exponent(fnew_v[cb][rb][e] * ninv));
           k = row16_max(k);   // over the 16 columns of this lane's block row
-          if (r16 == 0) kred[wn][wm * C::WTM + rb * 16 + Mma<T>::row(g, e)] = k;
+          if (r16 == 0) kred[wm * C::WTM + rb * 16 + Mma<T>::row(g, e)][wn] = k;
         }
     }
     lds_barrier();
@@ -1161,9 +1163,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           const int lr = wm * C::WTM + rb * 16 + Mma<T>::row(g, e);
           const int i = row0 + lr;
           const int xblk = wn / WPB2;               // this wave's exponent block of columns
-          int K = kred[xblk * WPB2][lr];
+          int K = kred[lr][xblk * WPB2];
 #pragma unroll
-          for (int w = 1; w < WPB2; ++w) K = max(K, kred[xblk * WPB2 + w][lr]);
+          for (int w = 1; w < WPB2; ++w) K = max(K, kred[lr][xblk * WPB2 + w]);
           if (wn % WPB2 == 0 && r16 == 0 && i < n) p.kexpN[((size_t)bz * np + i) * p.nbA + tc * C::XS + xblk] = K;
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) {
