@@ -2,8 +2,8 @@
 //
 // One half-step of Algorithm 1 (arXiv 2512.19072, Sec. 3, Eq. 7 or Eq. 8) computes, in the log
 // domain, ln S = ln(Lambda . exp(P/eps) . Lambda) and the new potential eps (ln m - ln S).
-// Every operand the per-axis GEMMs consume is stored normalised per 64-wide block of its K
-// index by an integer power of two:
+// Every operand the per-axis GEMMs consume is stored normalised per 64-wide (or 32-wide) block of
+// its K index by an integer power of two:
 //
 //   At[L][M] = exp(P_LM/eps - K[L][blk(M)] ln 2)      (pass-1 operand, max of a block in [1/2, 1])
 //   Bt[k][L] = W[L][k] 2^{-K'[k][blk(L)]}              (pass-2 operand, transposed)
@@ -18,7 +18,9 @@
 //           transcendental) and the exponent table K'.
 // At small eps Lambda itself spans more than the operand type's range; it is then stored the same
 // way, Lambda[k][M] = Lambda~[k][M] 2^{KL[k][blk(M)]} (KL <= 0), and each block's partial sum is
-// rescaled by the sum of both operands' exponents (the LN form of the kernels).
+// rescaled by the sum of both operands' exponents (the LN form of the kernels).  Raw Lambda is
+// not staged with the K stages: it depends on i - k only, and its fragments are read from a
+// Toeplitz table (one 16-byte chunk per starting distance) that each workgroup copies into LDS once.
 //   pass 2  S~ = Lambda . Bt^T, ln S = R'_k ln 2 + ln S~; epilogue updates the potential, the
 //           marginal-error partial, and writes the next pass-1 operand At and its exponents.
 #pragma once

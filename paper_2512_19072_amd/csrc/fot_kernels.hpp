@@ -12,7 +12,8 @@
 //     across workgroups with atomicMax on order-preserving integer keys of their FP32 roundings
 //     (a shift only has to keep the sums in range, so its rounding does not matter);
 //   * set-up kernels (row sums of the squared amplitudes, ln a and ln b, Lambda, initial
-//     potentials), the read-out's reductions (k_readout, k_sum_parts, fixed-order partial sums),
+//     potentials), the read-out's reductions (k_readout, one launch per pass-2 moment, and
+//     k_sum_parts: fixed-order partial sums),
 //     the trapezoid integration of the phase, and the reverse sweep's elementwise kernels.
 #pragma once
 
