@@ -474,6 +474,38 @@ def test_small_eps_beyond_the_lds_table_is_unsupported():
     assert "FOT_F64" in msg, msg
 
 
+def test_largest_grid_f32_against_f64():
+    """n = 8192, the largest grid fot_plan accepts: the Toeplitz table of the Gibbs factor no longer
+    fits in LDS beside the stage buffers, so the kernels stage it with the K stages.  Two
+    iterations at eps = 5e-2 (raw Lambda) with FP32 operands against the same solve with FP64
+    operands: potentials and phase within FP32's 1e-6 (range-normalised, gauge-fixed)."""
+    import torch
+    from paper_2512_19072_amd import fot as F
+    from tests.parity_util import gauge_rel, range_rel
+    n, T, eps = 8192, 2, 5e-2
+    _say(f"case: n={n} f32 against f64, eps={eps}, T={T}")
+    x = (torch.arange(n, dtype=torch.float64, device="cuda") - n / 2) / n
+    g = torch.exp(-(x[:, None] ** 2 + x[None, :] ** 2) / (2 * 0.15 ** 2))
+    G = torch.exp(-((x[:, None] - 0.1) ** 2 / (2 * 0.2 ** 2) + (x[None, :] + 0.05) ** 2 / (2 * 0.1 ** 2)))[None]
+    out = {}
+    for prec in ("f64", "f32"):
+        plan = F.Plan(n, 1, prec, max_iters=T)
+        ph, rep, st = plan.solve(g, G, eps, T)
+        f, psi = plan.potentials()
+        out[prec] = (f.cpu().numpy()[0], psi.cpu().numpy()[0], ph.cpu().numpy()[0], st)
+        plan.close()
+        del f, psi, ph
+        torch.cuda.empty_cache()
+    a = (g ** 2 / (g ** 2).sum()).cpu().numpy()
+    b = (G[0] ** 2 / (G[0] ** 2).sum()).cpu().numpy()
+    assert out["f32"][3] == F.FOT_OK and out["f64"][3] == F.FOT_OK
+    ef = gauge_rel(out["f32"][0], out["f64"][0], a)
+    ep = gauge_rel(out["f32"][1], out["f64"][1], b)
+    eph = range_rel(out["f32"][2], out["f64"][2])
+    _say(f"f {ef:.2e} psi {ep:.2e} phase {eph:.2e}")
+    assert ef < 1e-6 and ep < 1e-6 and eph < 1e-6, (ef, ep, eph)
+
+
 def test_u_direction_range_loss_is_reported():
     """On 129^2 at eps = 5e-4 (32-wide blocks: a quarter of the grid) the potential psi comes to
     span more than FP32 holds within one block from about the 27th iteration, so the u-updates'
