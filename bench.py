@@ -172,11 +172,11 @@ def errors_vs_oracle(out, ref, a, b):
             "transport_cost": abs(out["cost"] - ref.cost) / abs(ref.cost)}
 
 
-def adjoint_steps(F, W, torch, np, steps, warmup):
+def adjoint_steps(F, W, torch, np, steps, warmup, checkpoint_every=None):
     """The reverse-mode workload (workload 4: 512^2, 8 targets, FP32 operands, 100 iterations,
-    checkpoints every 10): `warmup` then `steps` forward solves with tape and fot_backward of
-    L = D + 1/2 sum_p a_p phi_p^2, each timed wall-clock between stream synchronisations;
-    returns the summed forward and backward seconds."""
+    checkpoints every 10, or every `checkpoint_every`): `warmup` then `steps` forward solves with
+    tape and fot_backward of L = D + 1/2 sum_p a_p phi_p^2, each timed wall-clock between stream
+    synchronisations; returns the summed forward and backward seconds."""
     wl4 = W.workload(4)
     g4, G4 = wl4.images()
     dev = torch.device("cuda", 0)
@@ -184,7 +184,7 @@ def adjoint_steps(F, W, torch, np, steps, warmup):
     G4d = torch.tensor(G4, dtype=torch.float64, device=dev)
     a4 = torch.tensor(g4 ** 2 / np.sum(g4 ** 2), dtype=torch.float64, device=dev)
     B4, n4, T4 = G4.shape[0], wl4.n, wl4.iters
-    plan = F.Plan(n4, B4, "f32", max_iters=T4, checkpoint_every=wl4.checkpoint_every)
+    plan = F.Plan(n4, B4, "f32", max_iters=T4, checkpoint_every=checkpoint_every or wl4.checkpoint_every)
     ph4 = torch.empty((B4, n4, n4), dtype=torch.float64, device=dev)
     dD = np.ones(B4)
     try:
@@ -523,6 +523,16 @@ def main():
                           "unit": "Mpixel·iter/s (targets x pixels x iterations)"}
         log(f"bench: adjoint {out['adjoint']['ms_forward']:.2f} ms forward + {out['adjoint']['ms_backward']:.2f} ms "
             f"backward per step ({B4} x {n4}^2, {T4} its)")
+        # the same with every iterate kept by the forward solve (one checkpoint segment of T
+        # iterations, the plan's segment buffers holding f, psi, ln S, ln S' of each: the backward
+        # pass replays nothing), the memory-for-time end of the checkpoint trade-off
+        tfk, tbk = adjoint_steps(F, W, torch, np, args.steps, args.warmup, checkpoint_every=T4)
+        out["adjoint"]["every_iterate_kept"] = {
+            "checkpoint_every": T4, "ms_forward": round(1e3 * tfk / args.steps, 3),
+            "ms_backward": round(1e3 * tbk / args.steps, 3), "backward_over_forward": round(tbk / tfk, 3),
+            "segment_buffers_gib": round(4 * T4 * B4 * n4 * n4 * 8 / 2 ** 30, 2)}
+        log(f"bench: adjoint with every iterate kept: {1e3 * tfk / args.steps:.2f} ms forward + "
+            f"{1e3 * tbk / args.steps:.2f} ms backward per step")
 
         # output beam and L1 intensity loss of the FP32 phase of the headline workload, and
         # Gerchberg-Saxton rounds from it (FP64 transforms on the matrix cores)
