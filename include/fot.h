@@ -218,9 +218,9 @@ fot_status fot_solve(fot_plan_t plan, const double* g, const double* G,
  * (no hipMalloc, no graph, no events); the iteration loop is launched kernel by kernel and the
  * report's timing fields are 0.
  *   desc      as for fot_plan; checkpoint_every must be 0 and FOT_FLAG_PROFILE unset
- *             (FOT_E_INVALID otherwise); a plan whose workspace exceeds 32 MiB (n_p <= 512 for one
- *             target with 32- or 16-bit operands) is rejected with FOT_E_INVALID before anything
- *             runs
+ *             (FOT_E_INVALID otherwise); a plan whose workspace exceeds 32 MiB (n_p <= 640 for one
+ *             target with FP64, FP32 or BF16x3 operands, n_p <= 512 with 16-bit ones) is rejected
+ *             with FOT_E_INVALID before anything runs
  *   stream..rep as for fot_plan / fot_solve (a cold start: u = V = 1/n^2)
  *   f_out, psi_out  device [batch][n][n] FP64 final potentials, or NULL; written also when the
  *             status is FOT_E_RANGE or FOT_E_NONFINITE

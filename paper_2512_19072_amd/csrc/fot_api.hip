@@ -58,8 +58,14 @@ struct fot_plan_s {
   int device = 0;
   int lds_limit = 0;   // LDS bytes per workgroup on the plan's device
   // FP64 state and scratch
-  double *f = nullptr, *psi = nullptr, *lna = nullptr, *lnb = nullptr, *lnS = nullptr, *lnSp = nullptr;
-  double *mrow = nullptr, *Tx = nullptr, *Ty = nullptr;
+  double *f = nullptr, *psi = nullptr, *lna = nullptr, *lnb = nullptr, *lnS = nullptr;
+  double* mrow = nullptr;
+  // T_x at column 0 ([batch][np], the one column the integration reads) and the read-out's fourth
+  // FP64 plane, which holds T_y when a solve ends; with x_alias it is the loop's operand buffers
+  // (FP32-sized operands, no tape, no schedule: one allocation, dead once the loop is done), whose
+  // padded borders are cleared again before the next solve when x_dirty
+  double *txc = nullptr, *Ty = nullptr;
+  bool x_alias = false, x_dirty = false;
   double *rowsum_g = nullptr, *rowsum_G = nullptr, *rowpart = nullptr, *partials = nullptr;
   double *hist_a = nullptr, *hist_b = nullptr, *rparts = nullptr, *rsums = nullptr;
   unsigned* colkey = nullptr;
@@ -94,7 +100,10 @@ struct fot_plan_s {
   // The phase read-out and the reverse-sweep contractions run with FP64 operands in every
   // precision (once per solve; their signed sums cancel too strongly for FP32).  For FP64 plans
   // these alias the loop's buffers, otherwise they are separate.
-  double *flam = nullptr, *flamH = nullptr, *fA = nullptr, *fB = nullptr, *fZ = nullptr;
+  // flam: Lambda's FP64 plane where one is kept (FP64 plans: the loop's own; plans with a tape: the
+  // reverse sweep's operand), else null; flamT / flamHT: Toeplitz chunk tables of Lambda and
+  // Lambda o H in FP64, which the read-out's GEMMs read (flamT follows flam's plane when it exists)
+  double *flam = nullptr, *flamT = nullptr, *flamHT = nullptr, *fA = nullptr, *fB = nullptr, *fZ = nullptr;
   double flam_eps_sep = -1.0;
   bool flamH_valid_sep = false;
   double* flam_eps = nullptr;   // -> lam_eps (FP64 plans) or flam_eps_sep
@@ -141,6 +150,7 @@ struct fot_plan_s {
   // workspace carved from a caller-independent device array instead of hipMalloc (see plan_init)
   unsigned char* arena = nullptr;
   size_t arena_cap = 0, arena_used = 0;
+  bool sizing = false;   // plan_init's sizing pass: dalloc only adds up the sizes
 };
 
 namespace {
@@ -148,6 +158,13 @@ namespace {
 fot_status dalloc(fot_plan_s* p, void** out, size_t bytes) {
   void* ptr = nullptr;
   if (bytes == 0) bytes = 16;
+  if (p->sizing) {
+    // sizing pass: the offsets are recorded, the pointers are placeholders never used
+    const size_t off = (p->arena_used + 255) & ~(size_t)255;
+    p->arena_used = off + bytes;
+    *out = (void*)(uintptr_t)(256 + off);
+    return FOT_OK;
+  }
   if (p->arena) {
     // carve 256-byte aligned pieces from the static scratch array
     const size_t off = (p->arena_used + 255) & ~(size_t)255;
@@ -629,8 +646,9 @@ struct Ops {
       auto copy = [&](const double* src, double* dst) {
         hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, p->stream, src, dst, (size_t)B * p->plane);
       };
+      // (the last V-update's ln S' is not kept: the read-out forms it again in FP64)
       double* lnS_u = last ? p->lnS : keep ? p->seg_lnS + so : nullptr;
-      double* lnS_v = last ? p->lnSp : keep ? p->seg_lnSp + so : nullptr;
+      double* lnS_v = keep ? p->seg_lnSp + so : nullptr;
       if ((s = half(p, p->psi, p->f, p->lna, 0, hist ? p->hist_a + (size_t)t * B : nullptr, lnS_u, ep, ep, nullptr,
                     t, p->range_slots + (size_t)seg * B * p->range_spt * 2)) != FOT_OK)
         return s;
@@ -646,7 +664,6 @@ struct Ops {
         return s;
       if (keep) {
         copy(p->psi, p->seg_psi + so);
-        if (last) copy(p->lnSp, p->seg_lnSp + so);
         LAUNCH_CHECK();
       }
     }
@@ -661,8 +678,9 @@ struct Ops {
   }
 
   // End-of-solve probe of the operand type's u-direction products: ln S(psi_T) formed as a u-half
-  // would form it (its update goes to read-out scratch, fA, its ln S to Ty, which the read-out
-  // reads before it writes T_y there), for the read-out to compare with the FP64 value.  The final column marginal checks
+  // would form it, for the read-out to compare with the FP64 value (the update goes to read-out
+  // scratch, fZ, which the read-out reads before it writes there; its ln S is ln a - update / eps
+  // wherever a > 0, the only pixels the comparison weighs).  The final column marginal checks
   // only the last V-half's products; a loss of range in the u-direction products (the potential
   // psi spanning more than the type holds within one operand block) would otherwise go unseen
   // while the iterates drift.  FP64 operands need no probe.  Its own range check is recorded as
@@ -678,7 +696,7 @@ struct Ops {
       fot_status s = prep(p, p->psi, eps);
       if (s != FOT_OK) return s;
       p->probing = true;
-      s = half(p, p->psi, p->fA, p->lna, 0, nullptr, p->Ty, eps, 0.0, p->probe_flag, iters,
+      s = half(p, p->psi, p->fZ, p->lna, 0, nullptr, nullptr, eps, 0.0, p->probe_flag, iters,
                p->range_slots + (size_t)seg * p->B * p->range_spt * 2);
       p->probing = false;
       return s;
@@ -868,7 +886,7 @@ struct Ops {
         if ((s = step({p->Tbx, lnSl, psiT, ep, p->lnb, plane, 1.0 / ep, 1, 1, p->psibar})) != FOT_OK) return s;
         if ((s = step({p->Tby, lnSl, psiT, ep, p->lnb, plane, 1.0 / ep, 2, 1, p->psibar})) != FOT_OK) return s;
         // psibar_{T-1} += -(V_{T-1} / eps) K((Tbx Tx + Tby Ty) / S)
-        hipLaunchKernelGGL(k_moment_weight, eg, dim3(256), 0, p->stream, p->Tbx, p->Tx, p->Tby, p->Ty, n, np,
+        hipLaunchKernelGGL(k_moment_weight, eg, dim3(256), 0, p->stream, p->Tbx, p->txc, p->Tby, p->Ty, n, np,
                            p->wtmp);
         LAUNCH_CHECK();
         if ((s = step({p->wtmp, lnSl, psi_in(i), ep, p->lnb, plane, -1.0 / ep, 0, 0, p->psiprev})) != FOT_OK) return s;
@@ -952,114 +970,132 @@ fot_status sched_check(fot_plan_s* p, const std::vector<double>& e, int iters) {
 }
 
 // ------------------------------------------------------------------ FP64 read-out and reverse sweep
-// Lambda (and Lambda o H) with FP64 elements for the read-out and the reverse sweep.
+// Lambda (and Lambda o H) with FP64 elements for the read-out and the reverse sweep: Lambda's
+// plane and its chunks where the plan keeps the plane, else Lambda's chunk table alone (the
+// read-out's GEMMs read the tables), and Lambda o H's chunk table.
 fot_status fill64(fot_plan_s* p, double eps, bool withH) {
-  if (*p->flam_eps == eps && (!withH || *p->flamH_valid)) return FOT_OK;
-  hipLaunchKernelGGL(k_fill_lambda<double>, dim3((unsigned)((p->plane + 255) / 256)), dim3(256), 0, p->stream,
-                     p->flam, withH ? p->flamH : (double*)nullptr, p->n, p->np, 1.0 / eps);
-  hipLaunchKernelGGL(k_lam_chunks<double>, dim3((2 * p->np + 255) / 256), dim3(256), 0, p->stream, p->flam, p->np);
+  const bool needL = *p->flam_eps != eps;
+  const bool needH = withH && (needL || !*p->flamH_valid);
+  if (!needL && !needH) return FOT_OK;
+  const dim3 cgrid((unsigned)((2 * p->np + 255) / 256));
+  if (needL && p->flam) {
+    hipLaunchKernelGGL(k_fill_lambda<double>, dim3((unsigned)((p->plane + 255) / 256)), dim3(256), 0, p->stream,
+                       p->flam, (double*)nullptr, p->n, p->np, 1.0 / eps);
+    hipLaunchKernelGGL(k_lam_chunks<double>, cgrid, dim3(256), 0, p->stream, p->flam, p->np);
+  }
+  const bool tabL = needL && !p->flam;
+  if (tabL || needH)
+    hipLaunchKernelGGL(k_lam_table64, cgrid, dim3(256), 0, p->stream, tabL ? p->flamT : (double*)nullptr,
+                       needH ? p->flamHT : (double*)nullptr, p->n, p->np, 1.0 / eps);
   LAUNCH_CHECK();
   *p->flam_eps = eps;
-  *p->flamH_valid = withH;
+  *p->flamH_valid = withH || (!needL && *p->flamH_valid);
   return FOT_OK;
 }
 
 fot_status rev_lambda(fot_plan_s* p, double eps) { return fill64(p, eps, false); }
 
-// Phase read-out (Eq. 9-10), final marginals, dual value and transport cost, with FP64 operands.
-fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double* lnS_probe) {
+// Phase read-out (Eq. 9-10), final marginals, dual value and transport cost, with FP64 operands,
+// in four FP64 planes (fA, fB, fZ, Ty) besides the state.  f_probe: the end-of-solve probe's
+// potential (in fZ) or null.
+fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double* f_probe) {
   typedef Ops<double> R;
   const long long plane = (long long)p->plane;
   fot_status s;
   if ((s = fill64(p, eps, true)) != FOT_OK) return s;
-  dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
-  // ln S'(f_T) = ln(Lambda . u_T . Lambda) in FP64, replacing the loop's value (computed with the
-  // operand type), so that the column marginal below is the true one of the returned plan: its
-  // L1 error then measures how well the operand type represented the last V-update's products.
-  {
-    hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->f, p->n, p->np,
-                       1.0 / eps, p->mrow, p->fA, (double*)nullptr, p->colkey, take_pending(p));
-    LAUNCH_CHECK();
-    GemmArgs gf = R::base_args(p, p->fA, plane, p->flam, 0);
-    gf.out = p->fZ;
-    gf.sOut = plane;
-    gf.mrow = p->mrow;
-    gf.colkey = p->colkey;
-    if ((s = R::gemm_launch(p, EPI_LOGROW, gf)) != FOT_OK) return s;
-    hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
-                       p->mrow, p->colkey, p->n, p->np, p->fB);
-    LAUNCH_CHECK();
-    GemmArgs gs = R::base_args(p, p->flam, 0, p->fB, plane);
-    gs.out = p->fA;
-    gs.sOut = plane;
-    if ((s = R::gemm_launch(p, EPI_RAW, gs)) != FOT_OK) return s;
-    hipLaunchKernelGGL(k_lnS_raw, dim3(READOUT_BLOCKS, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->fA,
-                       p->colkey, p->n, p->np, p->lnSp);
-    LAUNCH_CHECK();
-  }
-  // Moments of V_T (Eq. 9-10).  Each pass-2 output is consumed (k_readout) before the next is
-  // formed, so that the read-out works in three scratch planes besides T_x and T_y:
-  //   A0 = exp(psi/eps - m) -> fA, Z = ln(A0 Lambda) -> fZ (row shifts, column keys),
-  //   B0 = colexp(Z) -> fB: S = Lambda B0 and Scx = (Lambda o H) B0 -> Tx (consumed),
-  //   Bx = colexp_x(Z) -> fB: Sx = Lambda Bx -> Tx (T_x),
-  //   Zc = A0 (Lambda o H) -> fB, Bc = colexp(Zc) -> fZ: Scy = Lambda Bc -> fB (consumed),
-  //   A2 = A0 Y -> fA, Zy = A2 Lambda -> fZ, By = colexp(Zy) -> fB: Sy = Lambda By -> Ty (T_y).
-  // Ty holds the end-of-solve probe's ln S until the first k_readout has read it.
-  auto gemm = [&](const void* A, long long sA, const void* Bm, long long sB, double* out) -> fot_status {
-    GemmArgs g = R::base_args(p, A, sA, Bm, sB);
+  if (p->x_alias) p->x_dirty = true;
+  const dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
+  const dim3 rgrid(READOUT_BLOCKS, p->B), rblock(NTHREADS);
+  const void* const LAM = p->flamT;
+  const void* const LAMH = p->flamHT;
+  // GEMM operands: a batch of planes, or Lambda / Lambda o H through their chunk tables
+  auto args = [&](const void* A, const void* Bm, double* out) -> GemmArgs {
+    const bool ta = A == LAM || A == LAMH, tb = Bm == LAM || Bm == LAMH;
+    GemmArgs g = R::base_args(p, A, ta ? 0 : plane, Bm, tb ? 0 : plane);
+    g.tzA = ta ? A : nullptr;
+    g.tzB = tb ? Bm : nullptr;
     g.out = out;
     g.sOut = plane;
-    return R::gemm_launch(p, EPI_RAW, g);
+    return g;
   };
-  const dim3 rgrid(READOUT_BLOCKS, p->B), rblock(NTHREADS);
-  hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np,
-                     1.0 / eps, p->mrow, p->fA, (double*)nullptr, p->colkey, PendingSum{nullptr, 0, nullptr});
+  auto gemm = [&](const void* A, const void* Bm, double* out) -> fot_status {
+    return R::gemm_launch(p, EPI_RAW, args(A, Bm, out));
+  };
+  // Z = ln(A Lambda) with the row shifts of A's k_rowexp and the column keys gathered
+  auto gemm_log = [&](const double* A, double* out) -> fot_status {
+    GemmArgs g = args(A, LAM, out);
+    g.mrow = p->mrow;
+    g.colkey = p->colkey;
+    return R::gemm_launch(p, EPI_LOGROW, g);
+  };
+  auto rowexp = [&](const double* P, double* out, double* out2, unsigned* keys, PendingSum ps) {
+    hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, P, p->n, p->np,
+                       1.0 / eps, p->mrow, out, out2, keys, ps);
+  };
+  const PendingSum none{nullptr, 0, nullptr};
+  // ln S'(f_T) = ln(Lambda . u_T . Lambda) in FP64, not the loop's value (computed with the operand
+  // type), and with it the column-mass error of the returned plan: it then measures how well the
+  // operand type represented the last V-update's products.
+  //   A0' = exp(f/eps - m) -> fA, Z' = ln(A0' Lambda) -> Ty, B0' = colexp(Z') -> fB, S' -> fA.
+  rowexp(p->f, p->fA, nullptr, p->colkey, take_pending(p));
   LAUNCH_CHECK();
-  GemmArgs g1 = R::base_args(p, p->fA, plane, p->flam, 0);
-  g1.out = p->fZ;
-  g1.sOut = plane;
-  g1.mrow = p->mrow;
-  g1.colkey = p->colkey;
-  if ((s = R::gemm_launch(p, EPI_LOGROW, g1)) != FOT_OK) return s;
-  hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
+  if ((s = gemm_log(p->fA, p->Ty)) != FOT_OK) return s;
+  hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->Ty,
                      p->mrow, p->colkey, p->n, p->np, p->fB);
   LAUNCH_CHECK();
-  if ((s = gemm(p->flam, 0, p->fB, plane, p->Tx)) != FOT_OK) return s;
-  hipLaunchKernelGGL(k_readout<RO_S>, rgrid, rblock, 0, p->stream, p->Tx, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, p->lnSp, lnS_probe, p->n, p->np, eps, p->rparts);
+  if ((s = gemm(LAM, p->fB, p->fA)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_colerr, rgrid, rblock, 0, p->stream, (const double*)p->fA, p->colkey, p->psi, p->lnb, p->n,
+                     p->np, eps, p->rparts);
   LAUNCH_CHECK();
-  if ((s = gemm(p->flamH, 0, p->fB, plane, p->Tx)) != FOT_OK) return s;
-  hipLaunchKernelGGL(k_readout<RO_CX>, rgrid, rblock, 0, p->stream, p->Tx, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
-  hipLaunchKernelGGL((k_colexpT<double, double, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
+  // Moments of V_T (Eq. 9-10), each pass-2 output consumed (k_readout) before the next is formed:
+  //   A0 = exp(psi/eps - m) -> fA, Z = ln(A0 Lambda) -> Ty (row shifts, column keys),
+  //   B0 = colexp(Z) -> fB: S = Lambda B0 -> fA (consumed, with the probe's update in fZ), Scx =
+  //   (Lambda o H) B0 -> fA (consumed); Bx = colexp_x(Z) -> fB: Sx = Lambda Bx -> fA (T_x at column 0),
+  //   A0 again -> fA (keys kept), Zc = A0 (Lambda o H) -> fB, Bc = colexp(Zc) -> fZ: Scy = Lambda Bc
+  //   -> fB (consumed), A2 = A0 Y -> fA, Zy = A2 Lambda -> fZ, By = colexp(Zy) -> fB: Sy = Lambda By
+  //   -> Ty (T_y).
+  rowexp(p->psi, p->fA, nullptr, p->colkey, none);
+  LAUNCH_CHECK();
+  if ((s = gemm_log(p->fA, p->Ty)) != FOT_OK) return s;
+  hipLaunchKernelGGL((k_colexpT<double, double, 0>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->Ty,
                      p->mrow, p->colkey, p->n, p->np, p->fB);
   LAUNCH_CHECK();
-  if ((s = gemm(p->flam, 0, p->fB, plane, p->Tx)) != FOT_OK) return s;
-  hipLaunchKernelGGL(k_readout<RO_TX>, rgrid, rblock, 0, p->stream, p->Tx, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
+  if ((s = gemm(LAM, p->fB, p->fA)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_S>, rgrid, rblock, 0, p->stream, p->fA, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, f_probe, (double*)nullptr, p->n, p->np, eps, p->rparts);
   LAUNCH_CHECK();
-  if ((s = gemm(p->fA, plane, p->flamH, 0, p->fB)) != FOT_OK) return s;
+  if ((s = gemm(LAMH, p->fB, p->fA)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_CX>, rgrid, rblock, 0, p->stream, p->fA, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, (const double*)nullptr, (double*)nullptr, p->n, p->np, eps, p->rparts);
+  hipLaunchKernelGGL((k_colexpT<double, double, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->Ty,
+                     p->mrow, p->colkey, p->n, p->np, p->fB);
+  LAUNCH_CHECK();
+  if ((s = gemm(LAM, p->fB, p->fA)) != FOT_OK) return s;
+  hipLaunchKernelGGL(k_readout<RO_TX>, rgrid, rblock, 0, p->stream, p->fA, p->colkey, p->lnS, p->lna, p->lnb, p->f,
+                     p->psi, (const double*)nullptr, p->txc, p->n, p->np, eps, p->rparts);
+  rowexp(p->psi, p->fA, nullptr, (unsigned*)nullptr, none);
+  LAUNCH_CHECK();
+  if ((s = gemm(p->fA, LAMH, p->fB)) != FOT_OK) return s;
   hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fB,
                      p->mrow, p->colkey, p->n, p->np, p->fZ);
   LAUNCH_CHECK();
-  if ((s = gemm(p->flam, 0, p->fZ, plane, p->fB)) != FOT_OK) return s;
+  if ((s = gemm(LAM, p->fZ, p->fB)) != FOT_OK) return s;
   hipLaunchKernelGGL(k_readout<RO_CY>, rgrid, rblock, 0, p->stream, p->fB, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
+                     p->psi, (const double*)nullptr, (double*)nullptr, p->n, p->np, eps, p->rparts);
   // (the moment operand A2 with the row shifts of A0, which the column keys above refer to)
-  hipLaunchKernelGGL(k_rowexp<double>, dim3(p->np, p->B), dim3(NTHREADS), 0, p->stream, p->psi, p->n, p->np,
-                     1.0 / eps, p->mrow, (double*)nullptr, p->fA, p->colkey, PendingSum{nullptr, 0, nullptr});
+  rowexp(p->psi, nullptr, p->fA, p->colkey, none);
   LAUNCH_CHECK();
-  if ((s = gemm(p->fA, plane, p->flam, 0, p->fZ)) != FOT_OK) return s;
+  if ((s = gemm(p->fA, LAM, p->fZ)) != FOT_OK) return s;
   hipLaunchKernelGGL((k_colexpT<double, double, 2>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->fZ,
                      p->mrow, p->colkey, p->n, p->np, p->fB);
   LAUNCH_CHECK();
-  if ((s = gemm(p->flam, 0, p->fB, plane, p->Ty)) != FOT_OK) return s;
+  if ((s = gemm(LAM, p->fB, p->Ty)) != FOT_OK) return s;
   hipLaunchKernelGGL(k_readout<RO_TY>, rgrid, rblock, 0, p->stream, p->Ty, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, p->lnSp, nullptr, p->n, p->np, eps, p->rparts);
+                     p->psi, (const double*)nullptr, (double*)nullptr, p->n, p->np, eps, p->rparts);
   hipLaunchKernelGGL(k_sum_parts, dim3(READOUT_SLOTS, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS,
                      p->rsums);
-  hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->Tx, p->Ty, p->lna, p->n, p->np,
-                     p->fZ, p->rowpart);
+  hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->txc,
+                     (const double*)p->Ty, p->lna, p->n, p->np, p->fZ, p->rowpart);
   if (phase_out)
     hipLaunchKernelGGL(k_center, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, p->fZ, p->rowpart, p->n, p->np,
                        phase_out);
@@ -1257,7 +1293,7 @@ fot_status cfot_loop(fot_plan_s* p, const std::vector<double>& e, int iters) {
                        last ? p->cS : nullptr, ep)) != FOT_OK)
       return s;
     if ((s = cfot_half(p, p->cfT, p->psi, p->lnb, plane, hist ? p->hist_b + (size_t)t * B : nullptr,
-                       last ? p->lnSp : nullptr, ep)) != FOT_OK)
+                       nullptr, ep)) != FOT_OK)
       return s;
   }
   if ((s = cfot_finish_pending(p)) != FOT_OK) return s;
@@ -1291,6 +1327,14 @@ fot_status sched_loop_graph_state(fot_plan_s* p, const std::vector<double>& e, i
 template <typename H, typename L>
 fot_status solve_body(fot_plan_s* p, const std::vector<double>& e, int iters, double* phase_out) {
   constexpr bool sched = !std::is_same<H, L>::value;
+  if (p->x_dirty) {
+    // the last read-out used the operand buffers as an FP64 plane: the padded borders, which the
+    // loop kernels read as zeros and never write, are cleared again (no borders when n = n_p)
+    if (p->np > p->n &&
+        hipMemsetAsync(p->op_set[0][1], 0, 2 * (size_t)p->B * p->plane * p->esz, p->stream) != hipSuccess)
+      return fail(FOT_E_HIP, "fot_solve: memset failed");
+    p->x_dirty = false;
+  }
   if (p->ev[1]) HIP_TRY(hipEventRecord(p->ev[1], p->stream));
   const bool graph = !(p->d.flags & (FOT_FLAG_NO_GRAPH | FOT_FLAG_PROFILE)) && !p->graph_broken && p->cap;
   p->used_graph = false;
@@ -1314,7 +1358,7 @@ fot_status solve_body(fot_plan_s* p, const std::vector<double>& e, int iters, do
     s = (hipEventRecord(p->ev[2], p->stream) == hipSuccess) ? FOT_OK : fail(FOT_E_HIP, "event record");
   const bool probed = !p->cfot && sizeof(L) != 8;
   if (s == FOT_OK && probed) s = Ops<L>::probe(p, e[iters - 1], iters, sched ? 1 : 0);
-  if (s == FOT_OK) s = readout64(p, e[iters - 1], phase_out, probed ? p->Ty : nullptr);
+  if (s == FOT_OK) s = readout64(p, e[iters - 1], phase_out, probed ? p->fZ : nullptr);
   if (s == FOT_OK && p->ev[3])
     s = (hipEventRecord(p->ev[3], p->stream) == hipSuccess) ? FOT_OK : fail(FOT_E_HIP, "event record");
   activate(p, 0);
@@ -1435,83 +1479,148 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
   // one marginal-error partial per output tile of the fused pass-2 kernel
   p->tiles = (p->np / tbm) * (p->np / tbn);
   const size_t BP = (size_t)p->B * p->plane;
-  fot_status s = FOT_OK;
+  const bool tape = d.checkpoint_every > 0;
+  const size_t chunk64 = toeplitz_chunks_bytes(p->np) / sizeof(double);   // FP64 chunk table, in doubles
+  // (the read-out's fourth plane: the loop's two operand buffers where they hold 4-byte elements
+  // and nothing else needs them after the loop)
+  p->x_alias = !tape && !tail && p->esz == 4;
+  if (d.checkpoint_every > 0) p->n_ckpt = (d.max_iters + d.checkpoint_every - 1) / d.checkpoint_every;
+  const size_t kseg = tape ? (size_t)std::min(d.checkpoint_every, d.max_iters) : 0;
+  // Every device buffer of the plan, carved in order from one piece of memory (see dalloc).
+  auto carve = [&]() -> fot_status {
+    fot_status s = FOT_OK;
 #define ALLOC(ptr, cnt)                                       \
-  if ((s = dalloc_t(p, &(ptr), (cnt))) != FOT_OK) return bail(s);
+  if ((s = dalloc_t(p, &(ptr), (cnt))) != FOT_OK) return s;
 #define ALLOCV(ptr, bytes)                                    \
-  if ((s = dalloc(p, &(ptr), (bytes))) != FOT_OK) return bail(s);
-  ALLOC(p->f, BP);
-  ALLOC(p->psi, BP);
-  ALLOC(p->lna, p->plane);
-  ALLOC(p->lnb, BP);
-  ALLOC(p->lnS, BP);
-  ALLOC(p->lnSp, BP);
-  ALLOC(p->mrow, (size_t)p->B * p->np);
-  ALLOC(p->rowsum_g, (size_t)p->n);
-  ALLOC(p->rowsum_G, (size_t)p->B * p->n);
-  ALLOC(p->rowpart, (size_t)p->B * p->n);
-  ALLOC(p->partials, (size_t)p->B * p->tiles);
-  p->pending_parts = p->partials;
-  p->pending_tiles = p->tiles;
-  ALLOC(p->hist_a, (size_t)d.max_iters * p->B);
-  ALLOC(p->hist_b, (size_t)d.max_iters * p->B);
-  ALLOC(p->rparts, (size_t)READOUT_SLOTS * p->B * READOUT_BLOCKS);
-  ALLOC(p->rsums, (size_t)READOUT_SLOTS * p->B);
-  ALLOC(p->probe_flag, (size_t)1);
-  // (the most waves any iteration kernel has per target: 32 x 32 tiles of 4 waves)
-  p->range_spt = (p->np / 32) * (p->np / 32) * 4;
-  ALLOC(p->range_slots, (size_t)2 * p->B * p->range_spt * 2);
-  ALLOC(p->colkey, (size_t)p->B * p->np);
-  p->nbA = p->np / (tbn / txs);
-  p->nbT = p->np / (tbm / txs);
-  ALLOC(p->kexpA, (size_t)p->B * p->np * p->nbA);
-  ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
-  if (d.precision != FOT_F64) ALLOC(p->kexpL, (size_t)p->np * p->nbA);
-  ALLOC(p->flag, (size_t)1);
-  // (each Lambda plane is followed by its Toeplitz chunks, see toeplitz_chunks_bytes)
-  const size_t lam_bytes = p->plane * p->esz + toeplitz_chunks_bytes(p->np);
-  ALLOCV(p->lam, lam_bytes);
-  ALLOCV(p->opA, BP * p->esz);
-  ALLOCV(p->opB, BP * p->esz);
-  p->op_set[0][0] = p->lam;
-  p->op_set[0][1] = p->opA;
-  p->op_set[0][2] = p->opB;
-  if (tail) {
-    ALLOCV(p->op_set[1][0], lam_bytes);
-    ALLOCV(p->op_set[1][1], BP * p->esz);
-    ALLOCV(p->op_set[1][2], BP * p->esz);
+  if ((s = dalloc(p, &(ptr), (bytes))) != FOT_OK) return s;
+    ALLOC(p->f, BP);
+    ALLOC(p->psi, BP);
+    ALLOC(p->lna, p->plane);
+    ALLOC(p->lnb, BP);
+    ALLOC(p->lnS, BP);
+    ALLOC(p->mrow, (size_t)p->B * p->np);
+    ALLOC(p->rowsum_g, (size_t)p->n);
+    ALLOC(p->rowsum_G, (size_t)p->B * p->n);
+    ALLOC(p->rowpart, (size_t)p->B * p->n);
+    ALLOC(p->partials, (size_t)p->B * p->tiles);
+    p->pending_parts = p->partials;
+    p->pending_tiles = p->tiles;
+    ALLOC(p->hist_a, (size_t)d.max_iters * p->B);
+    ALLOC(p->hist_b, (size_t)d.max_iters * p->B);
+    ALLOC(p->rparts, (size_t)READOUT_SLOTS * p->B * READOUT_BLOCKS);
+    ALLOC(p->rsums, (size_t)READOUT_SLOTS * p->B);
+    ALLOC(p->probe_flag, (size_t)1);
+    // (the most waves any iteration kernel has per target: 32 x 32 tiles of 4 waves)
+    p->range_spt = (p->np / 32) * (p->np / 32) * 4;
+    ALLOC(p->range_slots, (size_t)2 * p->B * p->range_spt * 2);
+    ALLOC(p->colkey, (size_t)p->B * p->np);
+    p->nbA = p->np / (tbn / txs);
+    p->nbT = p->np / (tbm / txs);
+    ALLOC(p->kexpA, (size_t)p->B * p->np * p->nbA);
+    ALLOC(p->kexpT, (size_t)p->B * p->np * p->nbT);
+    if (d.precision != FOT_F64) ALLOC(p->kexpL, (size_t)p->np * p->nbA);
+    ALLOC(p->flag, (size_t)1);
+    // (each Lambda plane is followed by its Toeplitz chunks, see toeplitz_chunks_bytes)
+    const size_t lam_bytes = p->plane * p->esz + toeplitz_chunks_bytes(p->np);
+    ALLOCV(p->lam, lam_bytes);
+    // the two operand buffers as one piece (with x_alias also the read-out's FP64 plane Ty)
+    ALLOCV(p->opA, 2 * BP * p->esz);
+    p->opB = (unsigned char*)p->opA + BP * p->esz;
+    p->op_set[0][0] = p->lam;
+    p->op_set[0][1] = p->opA;
+    p->op_set[0][2] = p->opB;
+    if (tail) {
+      ALLOCV(p->op_set[1][0], lam_bytes);
+      ALLOCV(p->op_set[1][1], BP * p->esz);
+      ALLOCV(p->op_set[1][2], BP * p->esz);
+    }
+    if (d.precision == FOT_F64) ALLOCV(p->Z, BP * p->zsz);   // (the FP64 read-out's fZ)
+    if (d.precision == FOT_F64) {
+      p->flam = (double*)p->lam;
+      p->flamT = p->flam + p->plane;
+      p->fA = (double*)p->opA;
+      p->fB = (double*)p->opB;
+      p->fZ = (double*)p->Z;
+      p->flam_eps = &p->lam_eps;
+      p->flamH_valid = &p->lamH_valid;
+    } else {
+      if (tape) {
+        ALLOC(p->flam, p->plane + chunk64);
+        p->flamT = p->flam + p->plane;
+      } else {
+        p->flam = nullptr;
+        ALLOC(p->flamT, chunk64);
+      }
+      ALLOC(p->fA, BP);
+      ALLOC(p->fB, BP);
+      ALLOC(p->fZ, BP);
+      p->flam_eps = &p->flam_eps_sep;
+      p->flamH_valid = &p->flamH_valid_sep;
+    }
+    ALLOC(p->flamHT, chunk64);
+    ALLOC(p->txc, (size_t)p->B * p->np);
+    if (p->x_alias)
+      p->Ty = (double*)p->opA;
+    else
+      ALLOC(p->Ty, BP);
+    if (cN > 0) {
+      void* tw = nullptr;
+      ALLOCV(tw, sizeof(cplx) * (size_t)cfot_tw_count(cN));
+      p->ctw = (cplx*)tw;
+      ALLOC(p->clamhat, (size_t)cN);
+      ALLOC(p->cY, BP);
+      ALLOC(p->cfT, BP);
+      ALLOC(p->clnaT, p->plane);
+      ALLOC(p->cS, BP);
+      ALLOC(p->cparts, (size_t)p->B * ((p->n + 1) / 2));
+    }
+    if (tape) {
+      ALLOC(p->tape, (size_t)p->n_ckpt * BP);
+      ALLOC(p->fbar, BP);
+      ALLOC(p->psibar, BP);
+      ALLOC(p->psibar2, BP);
+      ALLOC(p->psiprev, BP);
+      ALLOC(p->lbbar, BP);
+      ALLOC(p->Tbx, BP);
+      ALLOC(p->Tby, BP);
+      ALLOC(p->wtmp, BP);
+      ALLOC(p->cbar, (size_t)p->B * p->n);
+      ALLOC(p->rsum_tmp, (size_t)p->B * p->n);
+      ALLOC(p->gsums, (size_t)2 * p->B);
+      ALLOC(p->gparts, (size_t)2 * p->B * p->n);
+      ALLOC(p->dd_dev, (size_t)p->B);
+      ALLOC(p->seg_f, kseg * BP);
+      ALLOC(p->seg_psi, kseg * BP);
+      ALLOC(p->seg_lnS, kseg * BP);
+      ALLOC(p->seg_lnSp, kseg * BP);
+    }
+#undef ALLOC
+#undef ALLOCV
+    return s;
+  };
+  fot_status s = FOT_OK;
+  if (!arena) {
+    // one hipMalloc of the exact total (a sizing pass first): no per-buffer rounding of the
+    // allocator; later buffers (the output-beam workspace) are allocated on their own
+    p->sizing = true;
+    s = carve();
+    p->sizing = false;
+    if (s != FOT_OK) return bail(s);
+    void* block = nullptr;
+    if ((s = dalloc(p, &block, p->arena_used)) != FOT_OK) return bail(s);
+    p->arena = (unsigned char*)block;
+    p->arena_cap = p->arena_used;
+    p->arena_used = 0;
+    s = carve();
+    p->arena = nullptr;
+    p->arena_cap = p->arena_used = 0;
+    if (s != FOT_OK) return bail(s);
+  } else if ((s = carve()) != FOT_OK) {
+    return bail(s);
   }
-  if (d.precision == FOT_F64) ALLOCV(p->Z, BP * p->zsz);   // (the FP64 read-out's fZ)
-  if (d.precision == FOT_F64) {
-    p->flam = (double*)p->lam;
-    p->fA = (double*)p->opA;
-    p->fB = (double*)p->opB;
-    p->fZ = (double*)p->Z;
-    p->flam_eps = &p->lam_eps;
-    p->flamH_valid = &p->lamH_valid;
-  } else {
-    ALLOC(p->flam, p->plane + toeplitz_chunks_bytes(p->np) / sizeof(double));
-    ALLOC(p->fA, BP);
-    ALLOC(p->fB, BP);
-    ALLOC(p->fZ, BP);
-    p->flam_eps = &p->flam_eps_sep;
-    p->flamH_valid = &p->flamH_valid_sep;
-  }
-  ALLOC(p->flamH, p->plane);
-  ALLOC(p->Tx, BP);
-  ALLOC(p->Ty, BP);
   if (cN > 0) {
     p->cfot = true;
     p->cN = cN;
-    void* tw = nullptr;
-    if ((s = dalloc(p, &tw, sizeof(cplx) * (size_t)cfot_tw_count(cN))) != FOT_OK) return bail(s);
-    p->ctw = (cplx*)tw;
-    ALLOC(p->clamhat, (size_t)cN);
-    ALLOC(p->cY, BP);
-    ALLOC(p->cfT, BP);
-    ALLOC(p->clnaT, p->plane);
-    ALLOC(p->cS, BP);
-    ALLOC(p->cparts, (size_t)p->B * ((p->n + 1) / 2));
     const int lds = (int)cfot_lds_bytes(cN);
     s = cfot_dispatch(cN, [&](auto nc) -> fot_status {
       constexpr int N = decltype(nc)::value;
@@ -1529,30 +1638,6 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
                        cN, p->ctw);
     if (hipGetLastError() != hipSuccess) return bail(fail(FOT_E_HIP, "fot_plan: twiddle kernel launch failed"));
   }
-  if (d.checkpoint_every > 0) {
-    p->n_ckpt = (d.max_iters + d.checkpoint_every - 1) / d.checkpoint_every;
-    const size_t kseg = (size_t)std::min(d.checkpoint_every, d.max_iters);
-    ALLOC(p->tape, (size_t)p->n_ckpt * BP);
-    ALLOC(p->fbar, BP);
-    ALLOC(p->psibar, BP);
-    ALLOC(p->psibar2, BP);
-    ALLOC(p->psiprev, BP);
-    ALLOC(p->lbbar, BP);
-    ALLOC(p->Tbx, BP);
-    ALLOC(p->Tby, BP);
-    ALLOC(p->wtmp, BP);
-    ALLOC(p->cbar, (size_t)p->B * p->n);
-    ALLOC(p->rsum_tmp, (size_t)p->B * p->n);
-    ALLOC(p->gsums, (size_t)2 * p->B);
-    ALLOC(p->gparts, (size_t)2 * p->B * p->n);
-    ALLOC(p->dd_dev, (size_t)p->B);
-    ALLOC(p->seg_f, kseg * BP);
-    ALLOC(p->seg_psi, kseg * BP);
-    ALLOC(p->seg_lnS, kseg * BP);
-    ALLOC(p->seg_lnSp, kseg * BP);
-  }
-#undef ALLOC
-#undef ALLOCV
   // the fused loop kernels never write the padded borders of their operands: zero them once
   for (int set = 0; set < (tail ? 2 : 1); ++set)
     for (int k = 1; k < 3; ++k)

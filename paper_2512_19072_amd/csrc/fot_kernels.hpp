@@ -10,10 +10,12 @@
 //     per row (k_rowexp) before the first product and per column (k_colexpT) before the second
 //     (the reverse sweep's signed contractions run on the fused kernels); the column maxima are gathered
 //     across workgroups with atomicMax on order-preserving integer keys of their FP32 roundings
-//     (a shift only has to keep the sums in range, so its rounding does not matter);
+//     (a shift only has to keep the sums in range, so its rounding does not matter).  Lambda and
+//     Lambda o H, functions of the pixel distance alone, enter it as Toeplitz chunk tables (a few
+//     KB, read through the caches) instead of n_p x n_p planes;
 //   * set-up kernels (row sums of the squared amplitudes, ln a and ln b, Lambda, initial
-//     potentials), the read-out's reductions (k_readout, one launch per pass-2 moment, and
-//     k_sum_parts: fixed-order partial sums),
+//     potentials), the read-out's reductions (k_readout, one launch per pass-2 moment, k_colerr,
+//     and k_sum_parts: fixed-order partial sums),
 //     the trapezoid integration of the phase, and the reverse sweep's elementwise kernels.
 #pragma once
 
@@ -235,6 +237,11 @@ struct GemmArgs {
   int xcd_swizzle;          // remap workgroups so each XCD works on a compact block of tiles
   int kp;                   // row pitch of A and B in elements (0: np); the K extent is nk stages
   int ldo;                  // EPI_RAW: row pitch of the output in elements (0: np)
+  // or nullptr: the operand is Lambda-like (its entry (r, k) a function of |r - k| alone) and is read
+  // from that function's Toeplitz chunks instead of A / B: chunk c holds the 16 / sizeof(T) values
+  // at distances c - (np - 1), c - (np - 1) + 1, ... (2 np chunks, see k_lam_table64); row pitch np
+  const void* tzA;
+  const void* tzB;
   // EPI_LOGROW / EPI_RAW output (Z type, [batch][np][ldo])
   void* out;
   long long sOut;
@@ -307,6 +314,18 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
   const unsigned char* Bg = Bb + (size_t)rl * pitch + (size_t)ql * 16;
   const int sofs = rl * LDS_RS + ql * 16;
   u32x4 ga[LA], gb[LB];
+  // chunk u of stage kt: row rl + u RSTEP of the tile, K values from kt KPS + ql EPC; a Toeplitz
+  // operand's row r holds at K the value at distance K - r, i.e. chunk K - r + np - 1 of its table
+  constexpr int KPS = ROWB / (int)sizeof(T), EPC = 16 / (int)sizeof(T);
+  const int tz0 = ql * EPC - rl + p.np - 1;
+  auto load_a = [&](int u, int kt) -> u32x4 {
+    if (p.tzA) return ((const u32x4*)p.tzA)[tz0 + kt * KPS - row0 - u * RSTEP];
+    return *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch + (size_t)kt * ROWB);
+  };
+  auto load_b = [&](int u, int kt) -> u32x4 {
+    if (p.tzB) return ((const u32x4*)p.tzB)[tz0 + kt * KPS - col0 - u * RSTEP];
+    return *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch + (size_t)kt * ROWB);
+  };
 
   acc_t acc[RB][CB];
 #pragma unroll
@@ -323,9 +342,9 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
     for (int j = 0; j < CB; ++j) accd[i][j] = f64x4{};
 
 #pragma unroll
-  for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch);
+  for (int u = 0; u < LA; ++u) ga[u] = load_a(u, 0);
 #pragma unroll
-  for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch);
+  for (int u = 0; u < LB; ++u) gb[u] = load_b(u, 0);
 #pragma unroll
   for (int u = 0; u < LA; ++u) *(u32x4*)(&ldsA[0][sofs + u * RSTEP * LDS_RS]) = ga[u];
 #pragma unroll
@@ -335,11 +354,10 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
     const int s = kt & 1;
     const bool more = kt + 1 < p.nk;
     if (more) {
-      const size_t ko = (size_t)(kt + 1) * ROWB;
 #pragma unroll
-      for (int u = 0; u < LA; ++u) ga[u] = *(const u32x4*)(Ag + (size_t)u * RSTEP * pitch + ko);
+      for (int u = 0; u < LA; ++u) ga[u] = load_a(u, kt + 1);
 #pragma unroll
-      for (int u = 0; u < LB; ++u) gb[u] = *(const u32x4*)(Bg + (size_t)u * RSTEP * pitch + ko);
+      for (int u = 0; u < LB; ++u) gb[u] = load_b(u, kt + 1);
     }
 #pragma unroll
     for (int h = 0; h < CHUNKS / 4; ++h) {
@@ -444,8 +462,9 @@ __global__ __launch_bounds__(C::THREADS) void k_gemm(const GemmArgs p) {
 // Row shift and shifted exponentials of a potential (pass-1 operand):
 //   m_i = max_k P_ik / eps (0 if the row has no finite entry), out_ik = exp(P_ik/eps - m_i).
 // Optionally out2_ik = out_ik * Y_k with Y_k = (k - floor(n/2)) / sqrt(n) (Eq. 10 moment).
-// Also clears the column-max keys that the following pass 1 fills.  With out = nullptr only out2 is
-// written (the same values), and the row shifts and column keys are left as they are.
+// Also clears the column-max keys that the following pass 1 fills (unless colkey is null: then out is
+// rewritten with the same values and the keys stay).  With out = nullptr only out2 is written (the
+// same values), and the row shifts and column keys are left as they are.
 //
 // Block 0 of each batch entry also finishes the marginal-error reduction of the preceding
 // potential update: red_out[bz] = sum of red_parts[bz][0..red_tiles) in index order.
@@ -473,7 +492,7 @@ __global__ __launch_bounds__(NTHREADS) void k_rowexp(const double* P, int n, int
   const size_t plane = (size_t)np * np;
   T* o = out ? out + bz * plane + (size_t)i * np : nullptr;
   T* o2 = out2 ? out2 + bz * plane + (size_t)i * np : nullptr;
-  if (o && threadIdx.x == 0) colkey[(size_t)bz * np + i] = 0u;
+  if (o && colkey && threadIdx.x == 0) colkey[(size_t)bz * np + i] = 0u;
   if (i >= n) {
     for (int k = threadIdx.x; k < np; k += blockDim.x) {
       if (o) o[k] = (T)0;
@@ -572,6 +591,25 @@ __global__ void k_fill_lambda(T* lam, T* lamH, int n, int np, double inv_eps) {
   if (lamH) store_op<T>(lamH + (size_t)i * np, k, cvt_op<T>(v * h));
 }
 
+// The same two functions of the distance d = i - k in FP64 as Toeplitz chunks (the form k_gemm
+// reads through GemmArgs::tzA / tzB): chunk c holds the values at d = c - (np - 1) and d + 1, zero
+// where |d| >= np; element for element equal to the planes k_fill_lambda writes.  One thread per
+// chunk; either table may be null.
+__global__ void k_lam_table64(double* tz, double* tzH, int n, int np, double inv_eps) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 2 * np) return;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int di = c - (np - 1) + e;
+    const double d = (double)di;
+    const double h = d * d / (2.0 * (double)n * (double)n);
+    const double v = exp(-h * inv_eps);
+    const bool in = di < np && di > -np;
+    if (tz) tz[2 * c + e] = in ? v : 0.0;
+    if (tzH) tzH[2 * c + e] = in ? v * h : 0.0;
+  }
+}
+
 // ------------------------------------------------------------------ marginals (Eq. 2)
 // Row sums of squared amplitudes (one block per row), with input validation.
 __global__ void k_rowsumsq(const double* x, int n, double* rowsum, int* flag) {
@@ -629,42 +667,39 @@ __global__ void k_fill_pot(double* pot, int n, int np, int batch, double value) 
 }
 
 // ln S from a raw pass-2 output: ln S = m'_k + ln S~ (-inf where S~ = 0), valid pixels only.
-__global__ __launch_bounds__(NTHREADS) void k_lnS_raw(const double* S, const unsigned* colkey, int n, int np,
-                                                       double* lnS) {
-  const int bz = blockIdx.y;
-  const size_t plane = (size_t)np * np;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)(idx / n), k = (int)(idx % n);
-    const size_t o = bz * plane + (size_t)j * np + k;
-    const double v = S[o];
-    lnS[o] = (v > 0.0) ? key_to_shift(colkey[(size_t)bz * np + k]) + log(v) : -INFINITY;
-  }
-}
-
 // ------------------------------------------------------------------ read-out (Eq. 9-10)
-// The read-out's pass-2 outputs M are formed one at a time (so that they share one plane) and
-// each is consumed by one launch of k_readout<ROLE>.  M is the output for V_T divided by
-// exp(m'_k); u/a = 1/S_prev with ln S_prev = ln(Lambda V_{T-1} Lambda) from the final u-update, so
-// that a pixel's factor is scale = exp(m'_k - ln S_prev).  Roles:
+// The read-out's pass-2 outputs M are formed one at a time and each is consumed by one launch of
+// k_readout<ROLE>.  M is the output for V_T divided by exp(m'_k); u/a = 1/S_prev with
+// ln S_prev = ln(Lambda V_{T-1} Lambda) from the final u-update, so that a pixel's factor is
+// scale = exp(m'_k - ln S_prev).  Roles:
 //   RO_S:   M = S.  Per-block partial sums of |row mass - a| (slot 0), the row mass (1),
-//           <f,a> + <psi,b> (3), the column-mass error (4) and, with lnS_probe = ln S(V_T) as the
-//           loop's operand type forms it, sum a |S_probe / S - 1| (5: the row-marginal error
-//           that one more u-update in the operand type would make through its products alone).
+//           <f,a> + <psi,b> (3) and, with f_probe the potential one more u-update in the loop's
+//           operand type gives (its ln S = ln a - f_probe / eps where a > 0), sum a |S_probe / S - 1|
+//           (5: the row-marginal error that this update would make through its products alone).
+//           Slot 4, the column-mass error, comes from k_colerr.
 //   RO_CX, RO_CY: M = Scx or Scy, the transport cost's x or y part (slot 2 or 6).
-//   RO_TX, RO_TY: M = Sx or Sy; T = M scale, written over M.
+//   RO_TX:  M = Sx; T_x = M scale at column 0 (the one column the integration reads) -> tcol.
+//   RO_TY:  M = Sy; T_y = M scale, written over M.
 enum ReadoutRole { RO_S = 0, RO_CX = 1, RO_CY = 2, RO_TX = 3, RO_TY = 4 };
 constexpr int READOUT_SLOTS = 7;
 template <int ROLE>
 __global__ __launch_bounds__(NTHREADS) void k_readout(
     double* M, const unsigned* colkey, const double* lnS_prev, const double* lna, const double* lnb,
-    const double* f, const double* psi, const double* lnSp, const double* lnS_probe, int n, int np, double eps,
+    const double* f, const double* psi, const double* f_probe, double* tcol, int n, int np, double eps,
     double* part /*[READOUT_SLOTS][batch][blocks]*/) {
   __shared__ double red[4];
   const int bz = blockIdx.y;
   const size_t plane = (size_t)np * np;
   const int nblk = gridDim.x;
-  double acc[5] = {0, 0, 0, 0, 0};
+  if constexpr (ROLE == RO_TX) {
+    const double shift = key_to_shift(colkey[(size_t)bz * np]);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += nblk * blockDim.x) {
+      const size_t o = bz * plane + (size_t)j * np;
+      tcol[(size_t)bz * np + j] = M[o] * exp(shift - lnS_prev[o]);
+    }
+    return;
+  }
+  double acc[4] = {0, 0, 0, 0};
   const double inv_eps = 1.0 / eps;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
        idx += (size_t)nblk * blockDim.x) {
@@ -673,7 +708,7 @@ __global__ __launch_bounds__(NTHREADS) void k_readout(
     const size_t oa = (size_t)j * np + k;
     const double shift = key_to_shift(colkey[(size_t)bz * np + k]);
     const double scale = exp(shift - lnS_prev[o]);
-    if constexpr (ROLE == RO_TX || ROLE == RO_TY) {
+    if constexpr (ROLE == RO_TY) {
       M[o] = M[o] * scale;
       continue;
     }
@@ -689,34 +724,55 @@ __global__ __launch_bounds__(NTHREADS) void k_readout(
         acc[0] += fabs(rm - a);
         acc[1] += rm;
         acc[2] += a * f[o];
-        if (lnS_probe) {
+        if (f_probe) {
           // ln S(V_T) in FP64 against the operand type's value
           const double lnS64 = shift + log(M[o]);
-          const double d = lnS_probe[o] - lnS64;
+          const double lnSq = la - f_probe[o] * inv_eps;
+          const double d = lnSq - lnS64;
           // both -inf: no term; any other NaN (a non-finite probe) counts as the pixel's whole mass
-          const bool none = lnS_probe[o] == -INFINITY && lnS64 == -INFINITY;
-          acc[4] += none ? 0.0 : (d == d) ? a * fabs(expm1(d)) : a;
+          const bool none = lnSq == -INFINITY && lnS64 == -INFINITY;
+          acc[3] += none ? 0.0 : (d == d) ? a * fabs(expm1(d)) : a;
         }
       }
       const double lb = lnb[o];
-      const double cmass = exp(psi[o] * inv_eps + lnSp[o]);
-      if (lb > -INFINITY) {
-        acc[2] += exp(lb) * psi[o];
-        acc[3] += fabs(cmass - exp(lb));
-      } else {
-        acc[3] += cmass;
-      }
+      if (lb > -INFINITY) acc[2] += exp(lb) * psi[o];
     }
   }
-  if constexpr (ROLE == RO_TX || ROLE == RO_TY) return;
+  if constexpr (ROLE == RO_TY) return;
   const int B = gridDim.y;
-  constexpr int NQ = ROLE == RO_S ? 5 : 1;
-  constexpr int slot_s[5] = {0, 1, 3, 4, 5};
+  constexpr int NQ = ROLE == RO_S ? 4 : 1;
+  constexpr int slot_s[4] = {0, 1, 3, 5};
   for (int q = 0; q < NQ; ++q) {
     const int sl = ROLE == RO_S ? slot_s[q] : ROLE == RO_CX ? 2 : 6;
     const double s = block_sum(acc[q], red);
     if (threadIdx.x == 0) part[((size_t)sl * B + bz) * nblk + blockIdx.x] = s;
   }
+}
+
+// Column-marginal L1 error of the returned plan (slot 4 of the read-out's partials): S' =
+// Lambda u_T Lambda in FP64 arrives raw (divided by exp(m'_k), the column keys), so
+// ln S' = m'_k + ln S'raw and the column mass is exp(psi/eps + ln S'); per-block sums over the
+// pixels of |mass - b|, or of the mass where b = 0.  Same grid and summation order as k_readout.
+__global__ __launch_bounds__(NTHREADS) void k_colerr(const double* S, const unsigned* colkey, const double* psi,
+                                                      const double* lnb, int n, int np, double eps,
+                                                      double* part /*[READOUT_SLOTS][batch][blocks]*/) {
+  __shared__ double red[4];
+  const int bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  const double inv_eps = 1.0 / eps;
+  double acc = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / n), k = (int)(idx % n);
+    const size_t o = bz * plane + (size_t)j * np + k;
+    const double v = S[o];
+    const double lnSp = (v > 0.0) ? key_to_shift(colkey[(size_t)bz * np + k]) + log(v) : -INFINITY;
+    const double lb = lnb[o];
+    const double cmass = exp(psi[o] * inv_eps + lnSp);
+    acc += (lb > -INFINITY) ? fabs(cmass - exp(lb)) : cmass;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[((size_t)4 * gridDim.y + bz) * gridDim.x + blockIdx.x] = s;
 }
 
 // Deterministic final sums of the read-out partials: out[q][bz] for q < READOUT_SLOTS.
@@ -729,9 +785,9 @@ __global__ void k_sum_parts(const double* part, int nblk, double* out) {
   if (threadIdx.x == 0) out[(size_t)q * B + bz] = v;
 }
 
-// Trapezoid integration (step 1/sqrt(n)): phi[j][0] from Tx along j, then along k with Ty.
-// One block per row; rowpart[bz][j] = sum_k a_jk phi_jk for the a-weighted mean.
-__global__ __launch_bounds__(NTHREADS) void k_integrate(const double* Tx, const double* Ty, const double* lna,
+// Trapezoid integration (step 1/sqrt(n)): phi[j][0] from T_x's column 0 (txc[bz][j]) along j, then
+// along k with Ty.  One block per row; rowpart[bz][j] = sum_k a_jk phi_jk for the a-weighted mean.
+__global__ __launch_bounds__(NTHREADS) void k_integrate(const double* txc, const double* Ty, const double* lna,
                                                         int n, int np, double* phi, double* rowpart) {
   __shared__ double red[4];
   __shared__ double tsum[NTHREADS];
@@ -741,7 +797,7 @@ __global__ __launch_bounds__(NTHREADS) void k_integrate(const double* Tx, const 
   // phi[j][0] = sum_{i<j} h/2 (Tx[i][0] + Tx[i+1][0])
   double c = 0.0;
   for (int i = threadIdx.x; i < j; i += blockDim.x)
-    c += hh * (Tx[bz * plane + (size_t)i * np] + Tx[bz * plane + (size_t)(i + 1) * np]);
+    c += hh * (txc[(size_t)bz * np + i] + txc[(size_t)bz * np + i + 1]);
   const double base = block_sum(c, red);
   // scan of increments d_k = h/2 (Ty[j][k-1] + Ty[j][k]) over contiguous chunks per thread
   const double* ty = Ty + bz * plane + (size_t)j * np;
@@ -882,15 +938,17 @@ __global__ __launch_bounds__(NTHREADS) void k_int_adj_col(const double* cbar, in
   }
 }
 
-// w = Tbx * Tx + Tby * Ty (padded layout, valid pixels only).
-__global__ void k_moment_weight(const double* Tbx, const double* Tx, const double* Tby, const double* Ty, int n,
+// w = Tbx * Tx + Tby * Ty (padded layout, valid pixels only).  Tbx, the adjoint of the integration,
+// is nonzero only in column 0, where T_x is given as txc[bz][j].
+__global__ void k_moment_weight(const double* Tbx, const double* txc, const double* Tby, const double* Ty, int n,
                                 int np, double* w) {
   const int bz = blockIdx.y;
   const size_t plane = (size_t)np * np;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
        idx += (size_t)gridDim.x * blockDim.x) {
-    const size_t o = bz * plane + (size_t)(idx / n) * np + (idx % n);
-    w[o] = Tbx[o] * Tx[o] + Tby[o] * Ty[o];
+    const int j = (int)(idx / n), k = (int)(idx % n);
+    const size_t o = bz * plane + (size_t)j * np + k;
+    w[o] = (k == 0 ? Tbx[o] * txc[(size_t)bz * np + j] : 0.0) + Tby[o] * Ty[o];
   }
 }
 
