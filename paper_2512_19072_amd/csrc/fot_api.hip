@@ -42,7 +42,7 @@ fot_status fail(fot_status s, const std::string& msg) {
     if (e_ != hipSuccess) return fail(FOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int READOUT_BLOCKS = 256;
+constexpr int READOUT_BLOCKS = 2048;   // (eight per CU: the reductions are latency-bound)
 
 }  // namespace
 
@@ -1050,7 +1050,7 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
   // Moments of V_T (Eq. 9-10), each pass-2 output consumed (k_readout) before the next is formed:
   //   A0 = exp(psi/eps - m) -> fA, Z = ln(A0 Lambda) -> Ty (row shifts, column keys),
   //   B0 = colexp(Z) -> fB: S = Lambda B0 -> fA (consumed, with the probe's update in fZ), Scx =
-  //   (Lambda o H) B0 -> fA (consumed); Bx = colexp_x(Z) -> fB: Sx = Lambda Bx -> fA (T_x at column 0),
+  //   (Lambda o H) B0 -> fA (consumed); T_x at column 0 from Z's column 0 (k_tx_column),
   //   A0 again -> fA (keys kept), Zc = A0 (Lambda o H) -> fB, Bc = colexp(Zc) -> fZ: Scy = Lambda Bc
   //   -> fB (consumed), A2 = A0 Y -> fA, Zy = A2 Lambda -> fZ, By = colexp(Zy) -> fB: Sy = Lambda By
   //   -> Ty (T_y).
@@ -1062,17 +1062,14 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
   LAUNCH_CHECK();
   if ((s = gemm(LAM, p->fB, p->fA)) != FOT_OK) return s;
   hipLaunchKernelGGL(k_readout<RO_S>, rgrid, rblock, 0, p->stream, p->fA, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, f_probe, (double*)nullptr, p->n, p->np, eps, p->rparts);
+                     p->psi, f_probe, p->n, p->np, eps, p->rparts);
   LAUNCH_CHECK();
   if ((s = gemm(LAMH, p->fB, p->fA)) != FOT_OK) return s;
   hipLaunchKernelGGL(k_readout<RO_CX>, rgrid, rblock, 0, p->stream, p->fA, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, (const double*)nullptr, (double*)nullptr, p->n, p->np, eps, p->rparts);
-  hipLaunchKernelGGL((k_colexpT<double, double, 1>), tgrid, dim3(NTHREADS), 0, p->stream, (const double*)p->Ty,
-                     p->mrow, p->colkey, p->n, p->np, p->fB);
-  LAUNCH_CHECK();
-  if ((s = gemm(LAM, p->fB, p->fA)) != FOT_OK) return s;
-  hipLaunchKernelGGL(k_readout<RO_TX>, rgrid, rblock, 0, p->stream, p->fA, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, (const double*)nullptr, p->txc, p->n, p->np, eps, p->rparts);
+                     p->psi, (const double*)nullptr, p->n, p->np, eps, p->rparts);
+  hipLaunchKernelGGL(k_tx_column, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->Ty,
+                     (const double*)p->mrow, (const unsigned*)p->colkey, (const double*)p->flamT,
+                     (const double*)p->lnS, p->n, p->np, p->txc);
   rowexp(p->psi, p->fA, nullptr, (unsigned*)nullptr, none);
   LAUNCH_CHECK();
   if ((s = gemm(p->fA, LAMH, p->fB)) != FOT_OK) return s;
@@ -1081,7 +1078,7 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
   LAUNCH_CHECK();
   if ((s = gemm(LAM, p->fZ, p->fB)) != FOT_OK) return s;
   hipLaunchKernelGGL(k_readout<RO_CY>, rgrid, rblock, 0, p->stream, p->fB, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, (const double*)nullptr, (double*)nullptr, p->n, p->np, eps, p->rparts);
+                     p->psi, (const double*)nullptr, p->n, p->np, eps, p->rparts);
   // (the moment operand A2 with the row shifts of A0, which the column keys above refer to)
   rowexp(p->psi, nullptr, p->fA, p->colkey, none);
   LAUNCH_CHECK();
@@ -1091,7 +1088,7 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
   LAUNCH_CHECK();
   if ((s = gemm(LAM, p->fB, p->Ty)) != FOT_OK) return s;
   hipLaunchKernelGGL(k_readout<RO_TY>, rgrid, rblock, 0, p->stream, p->Ty, p->colkey, p->lnS, p->lna, p->lnb, p->f,
-                     p->psi, (const double*)nullptr, (double*)nullptr, p->n, p->np, eps, p->rparts);
+                     p->psi, (const double*)nullptr, p->n, p->np, eps, p->rparts);
   hipLaunchKernelGGL(k_sum_parts, dim3(READOUT_SLOTS, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS,
                      p->rsums);
   hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->txc,

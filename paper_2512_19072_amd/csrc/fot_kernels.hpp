@@ -678,27 +678,19 @@ __global__ void k_fill_pot(double* pot, int n, int np, int batch, double value) 
 //           (5: the row-marginal error that this update would make through its products alone).
 //           Slot 4, the column-mass error, comes from k_colerr.
 //   RO_CX, RO_CY: M = Scx or Scy, the transport cost's x or y part (slot 2 or 6).
-//   RO_TX:  M = Sx; T_x = M scale at column 0 (the one column the integration reads) -> tcol.
 //   RO_TY:  M = Sy; T_y = M scale, written over M.
-enum ReadoutRole { RO_S = 0, RO_CX = 1, RO_CY = 2, RO_TX = 3, RO_TY = 4 };
+// (T_x is needed at column 0 only, where the integration reads it: k_tx_column.)
+enum ReadoutRole { RO_S = 0, RO_CX = 1, RO_CY = 2, RO_TY = 4 };
 constexpr int READOUT_SLOTS = 7;
 template <int ROLE>
 __global__ __launch_bounds__(NTHREADS) void k_readout(
     double* M, const unsigned* colkey, const double* lnS_prev, const double* lna, const double* lnb,
-    const double* f, const double* psi, const double* f_probe, double* tcol, int n, int np, double eps,
+    const double* f, const double* psi, const double* f_probe, int n, int np, double eps,
     double* part /*[READOUT_SLOTS][batch][blocks]*/) {
   __shared__ double red[4];
   const int bz = blockIdx.y;
   const size_t plane = (size_t)np * np;
   const int nblk = gridDim.x;
-  if constexpr (ROLE == RO_TX) {
-    const double shift = key_to_shift(colkey[(size_t)bz * np]);
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += nblk * blockDim.x) {
-      const size_t o = bz * plane + (size_t)j * np;
-      tcol[(size_t)bz * np + j] = M[o] * exp(shift - lnS_prev[o]);
-    }
-    return;
-  }
   double acc[4] = {0, 0, 0, 0};
   const double inv_eps = 1.0 / eps;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (size_t)n * n;
@@ -747,6 +739,29 @@ __global__ __launch_bounds__(NTHREADS) void k_readout(
     const double s = block_sum(acc[q], red);
     if (threadIdx.x == 0) part[((size_t)sl * B + bz) * nblk + blockIdx.x] = s;
   }
+}
+
+// T_x at column 0 (Eq. 9): Sx[j][0] = sum_L Lambda(j - L) Bx[0][L] with the moment operand's row
+// for k = 0, Bx[0][L] = X_L exp(m_L - m'_0 + Z[L][0]) (k_colexpT MODE 1 for that one column: Z =
+// ln(A0 Lambda) with the row shifts m and column keys m' of its k_rowexp / EPI_LOGROW product), then
+// scaled as T = Sx exp(m'_0 - ln S_prev).  Lambda from its FP64 Toeplitz table (element 0 of chunk
+// d + n_p - 1 is the value at distance d).  One block per row j and target.
+__global__ __launch_bounds__(NTHREADS) void k_tx_column(const double* Z, const double* mrow, const unsigned* colkey,
+                                                        const double* lamT, const double* lnS_prev, int n, int np,
+                                                        double* tcol) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, bz = blockIdx.y;
+  const size_t plane = (size_t)np * np;
+  const double mk = key_to_shift(colkey[(size_t)bz * np]);
+  const double xsc = 1.0 / sqrt((double)n);
+  double s = 0.0;
+  for (int L = threadIdx.x; L < n; L += blockDim.x) {
+    const double zz = Z[bz * plane + (size_t)L * np];
+    const double w = scaled_exp_op<double>((mrow[(size_t)bz * np + L] - mk) + zz, (double)(L - n / 2) * xsc);
+    s += lamT[2 * (j - L + np - 1)] * w;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) tcol[(size_t)bz * np + j] = s * exp(mk - lnS_prev[bz * plane + (size_t)j * np]);
 }
 
 // Column-marginal L1 error of the returned plan (slot 4 of the read-out's partials): S' =

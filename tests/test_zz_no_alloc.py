@@ -54,7 +54,9 @@ def _noalloc(F, g, G, prec, eps, T):
 
 @pytest.mark.parametrize("calls", [[(200, 2, "f32", 1e-2, 40), (96, 1, "bf16", 2e-2, 25)],
                                    # the largest FP32 grid the 32 MiB array holds for one target
-                                   [(640, 1, "f32", 1e-2, 10), (128, 1, "f16", 5e-2, 10)]])
+                                   [(640, 1, "f32", 1e-2, 10), (128, 1, "f16", 5e-2, 10)],
+                                   # and for FP64 operands
+                                   [(640, 1, "f64", 1e-2, 10), (64, 1, "bf16x3", 2e-2, 10)]])
 def test_noalloc_matches_allocated_plan(calls):
     import torch
     from paper_2512_19072_amd import fot as F
