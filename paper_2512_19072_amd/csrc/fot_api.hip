@@ -42,7 +42,12 @@ fot_status fail(fot_status s, const std::string& msg) {
     if (e_ != hipSuccess) return fail(FOT_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int READOUT_BLOCKS = 2048;   // (eight per CU: the reductions are latency-bound)
+// blocks of the read-out's per-pixel reductions: two pixels per thread up to eight blocks per CU
+// (the reductions are latency-bound), fewer on small grids
+constexpr int READOUT_BLOCKS = 2048;
+inline int readout_blocks(int n) {
+  return (int)std::min<long long>(READOUT_BLOCKS, ((long long)n * n + 2 * 256 - 1) / (2 * 256));
+}
 
 }  // namespace
 
@@ -1005,7 +1010,8 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
   if ((s = fill64(p, eps, true)) != FOT_OK) return s;
   if (p->x_alias) p->x_dirty = true;
   const dim3 tgrid(p->np / TILE, p->np / TILE, p->B);
-  const dim3 rgrid(READOUT_BLOCKS, p->B), rblock(NTHREADS);
+  const int rblocks = readout_blocks(p->n);
+  const dim3 rgrid(rblocks, p->B), rblock(NTHREADS);
   const void* const LAM = p->flamT;
   const void* const LAMH = p->flamHT;
   // GEMM operands: a batch of planes, or Lambda / Lambda o H through their chunk tables
@@ -1089,7 +1095,7 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
   if ((s = gemm(LAM, p->fB, p->Ty)) != FOT_OK) return s;
   hipLaunchKernelGGL(k_readout<RO_TY>, rgrid, rblock, 0, p->stream, p->Ty, p->colkey, p->lnS, p->lna, p->lnb, p->f,
                      p->psi, (const double*)nullptr, p->n, p->np, eps, p->rparts);
-  hipLaunchKernelGGL(k_sum_parts, dim3(READOUT_SLOTS, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, READOUT_BLOCKS,
+  hipLaunchKernelGGL(k_sum_parts, dim3(READOUT_SLOTS, p->B), dim3(NTHREADS), 0, p->stream, p->rparts, rblocks,
                      p->rsums);
   hipLaunchKernelGGL(k_integrate, dim3(p->n, p->B), dim3(NTHREADS), 0, p->stream, (const double*)p->txc,
                      (const double*)p->Ty, p->lna, p->n, p->np, p->fZ, p->rowpart);
