@@ -346,7 +346,7 @@ struct Ops {
     a.n = p->n;
     a.np = p->np;
     a.nk = (int)((size_t)p->np * sizeof(T) / ROWB);
-    a.xcd_swizzle = 1;
+    a.xcd_swizzle = XCD_BLOCKS;
     return a;
   }
 
@@ -456,14 +456,17 @@ struct Ops {
     if constexpr (!LN && !Mma<T>::PAIRED) {
       const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true>(p->np);
       const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true>(p->np);
+      // (Lambda from its table: bands of tiles per XCD, one fetch of each operand panel)
+      FusedArgs b = a;
+      b.xcd_swizzle = pass == 1 ? XCD_ROWS : XCD_COLS;
       if (pass == 1 && tz_fits<C, 1, false>(p)) {
         hipExtLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, false, true>), grid, block, t1, p->stream, e0, e1,
-                              0, a);
+                              0, b);
         return;
       }
       if (pass == 2 && tz_fits<C, 2, false>(p)) {
         hipExtLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, false, false, true>), grid, block, t2, p->stream, e0, e1,
-                              0, a);
+                              0, b);
         return;
       }
     }
@@ -563,7 +566,7 @@ struct Ops {
     a.nk = (int)((size_t)p->np * sizeof(T) / FROWB);
     a.nbA = p->nbA;
     a.nbT = p->nbT;
-    a.xcd_swizzle = 1;
+    a.xcd_swizzle = XCD_BLOCKS;
     a.band = lambda_band(p, eps);
     a.kexpL = lam_ln(p, eps) ? p->kexpL : nullptr;
     a.range_slots = range_slots;
@@ -591,7 +594,7 @@ struct Ops {
     b.nk = a.nk;
     b.nbA = p->nbA;
     b.nbT = p->nbT;
-    b.xcd_swizzle = 1;
+    b.xcd_swizzle = XCD_BLOCKS;
     b.band = a.band;
     b.kexpL = a.kexpL;
     b.range_slots = range_slots;
@@ -735,10 +738,12 @@ struct Ops {
     const uint32_t l1 = (uint32_t)fused_dyn_lds<1, C, false>(p->np), l2 = (uint32_t)fused_dyn_lds<2, C, false>(p->np);
     const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true>(p->np);
     const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true>(p->np);
+    FusedArgs b = a;   // (Lambda from its table: bands of tiles per XCD)
+    b.xcd_swizzle = pass == 1 ? XCD_ROWS : XCD_COLS;
     if (pass == 1 && tz_fits<C, 1, true>(p))
-      hipLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, true, true>), grid, block, t1, p->stream, a);
+      hipLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, true, true>), grid, block, t1, p->stream, b);
     else if (pass == 2 && tz_fits<C, 2, true>(p))
-      hipLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, false, true, true>), grid, block, t2, p->stream, a);
+      hipLaunchKernelGGL((k_fused<T, 2, C, FUSED_NBUF, false, true, true>), grid, block, t2, p->stream, b);
     else if (pass == 1)
       hipLaunchKernelGGL((k_fused<T, 1, C, FUSED_NBUF, false, true>), grid, block, l1, p->stream, a);
     else
@@ -765,7 +770,7 @@ struct Ops {
       a.nk = (int)((size_t)p->np * sizeof(T) / FROWB);
       a.nbA = p->nbA;
       a.nbT = p->nbT;
-      a.xcd_swizzle = 1;
+      a.xcd_swizzle = XCD_BLOCKS;
       a.band = raw_band(p, eps);
       a.A = A;
       a.sA = plane;
@@ -1148,7 +1153,7 @@ fot_status beam_dft(fot_plan_s* p, const double* src, double* dst, bool inverse)
   a.kp = 2 * np;
   a.nk = (int)((size_t)2 * np * sizeof(double) / ROWB);
   a.ldo = 2 * np;
-  a.xcd_swizzle = 1;
+  a.xcd_swizzle = XCD_BLOCKS;
   a.sA = 0;
   a.sB = wsz;
   a.sOut = wsz;

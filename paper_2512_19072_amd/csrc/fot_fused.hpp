@@ -1153,7 +1153,8 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
       double v = 0.0;
 #pragma unroll
       for (int w = 0; w < C::NW; ++w) v += red[w];
-      p.partials[(size_t)bz * gridDim.x * gridDim.y + blockIdx.x + gridDim.x * blockIdx.y] = v;
+      // (indexed by tile, so that the fixed-order sum does not depend on the tile mapping)
+      p.partials[(size_t)bz * gridDim.x * gridDim.y + tc + gridDim.x * tr] = v;
     }
     if (p.next_inv_eps > 0.0) {
       const double ninv = p.next_inv_eps;

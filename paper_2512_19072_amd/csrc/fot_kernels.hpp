@@ -250,14 +250,27 @@ struct GemmArgs {
 };
 
 // Map the linear workgroup id to a tile so that the workgroups that land on one XCD
-// (hardware round-robin: id % 8) cover a compact block of tiles that shares A rows and
-// B columns in that XCD's L2.
+// (hardware round-robin: id % 8) share operand panels in that XCD's L2.  swz = XCD_BLOCKS: a
+// compact block of tiles that shares A rows and B columns; XCD_ROWS / XCD_COLS: whole bands of
+// tile rows / tile columns, for products whose B / A operand (Lambda's Toeplitz table) is not a
+// panel, so that each panel of the other operand is fetched by one XCD.
+enum { XCD_NONE = 0, XCD_BLOCKS = 1, XCD_ROWS = 2, XCD_COLS = 3 };
 __device__ __forceinline__ void tile_of(int tiles_x, int tiles_y, int swz, int* tr, int* tc) {
   const int total = tiles_x * tiles_y;
   int w = blockIdx.x + tiles_x * blockIdx.y;
   if (swz && (total % 8) == 0) {
     const int per = total / 8;
     w = (w % 8) * per + (w / 8);
+  }
+  if (swz == XCD_ROWS) {
+    *tr = w / tiles_x;
+    *tc = w % tiles_x;
+    return;
+  }
+  if (swz == XCD_COLS) {
+    *tc = w / tiles_y;
+    *tr = w % tiles_y;
+    return;
   }
   const int GROUP = 4;
   const int per_group = GROUP * tiles_x;
