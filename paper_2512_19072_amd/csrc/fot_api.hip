@@ -1025,6 +1025,8 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
     GemmArgs g = R::base_args(p, A, ta ? 0 : plane, Bm, tb ? 0 : plane);
     g.tzA = ta ? A : nullptr;
     g.tzB = tb ? Bm : nullptr;
+    // (one operand a table: bands of tiles per XCD, as in the fused kernels)
+    g.xcd_swizzle = ta ? XCD_COLS : tb ? XCD_ROWS : XCD_BLOCKS;
     g.out = out;
     g.sOut = plane;
     return g;
