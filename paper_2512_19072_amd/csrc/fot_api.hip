@@ -1025,8 +1025,8 @@ fot_status readout64(fot_plan_s* p, double eps, double* phase_out, const double*
     GemmArgs g = R::base_args(p, A, ta ? 0 : plane, Bm, tb ? 0 : plane);
     g.tzA = ta ? A : nullptr;
     g.tzB = tb ? Bm : nullptr;
-    // (one operand a table: bands of tiles per XCD, as in the fused kernels)
-    g.xcd_swizzle = ta ? XCD_COLS : tb ? XCD_ROWS : XCD_BLOCKS;
+    // (the 4 x 8 blocks per XCD of base_args: bands of tiles, as in the fused kernels, measured
+    // slower here, 45.1 against 43.8 us per FP64 product at 1024^2)
     g.out = out;
     g.sOut = plane;
     return g;
