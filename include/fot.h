@@ -184,9 +184,11 @@ typedef struct {
                              the u-half, then of the V-half, per iteration); n_contract entries */
 } fot_report;
 
-/* Create a plan: validates desc, allocates O(n^2 * batch) device workspace once (no later
- * allocation in fot_solve or fot_backward), and binds it to `stream` (a hipStream_t; NULL
- * = the null stream) on the current device.  *out is set only on FOT_OK. */
+/* Create a plan: validates desc, allocates O(n^2 * batch) device workspace once, as one device
+ * allocation (no later allocation in fot_solve or fot_backward; without a tape at most
+ * (68 batch + 12) bytes per padded pixel for 32- and 16-bit operands, (64 batch + 16) for FP64,
+ * plus a few MB), and binds it to `stream` (a hipStream_t; NULL = the null stream) on the current
+ * device.  *out is set only on FOT_OK (FOT_E_NOMEM when the allocation fails). */
 fot_status fot_plan(const fot_plan_desc* desc, void* stream, fot_plan_t* out);
 
 /* Run Algorithm 1 (Sec. 3): normalise a = g^2/sum g^2 and b = G^2/sum G^2 (Eq. 2 marginals,
