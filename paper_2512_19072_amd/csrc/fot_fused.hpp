@@ -633,11 +633,13 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   for (int kk = 1; kk < NBUF - 1; ++kk)
     if (kk < nks) stage_load(kk, bufp(kk));
 
-  // pass-2 epilogue inputs, prefetched so that their latency hides behind the K loop
+  // pass-2 epilogue inputs, prefetched so that their latency hides behind the K loop (FP32: issued
+  // one step into the first stage, so that one wave's load issue overlaps the other wave's MFMAs)
   double la_v[CB][RB][4], fo_v[CB][RB][4];
   double ao_v[ADJ ? CB : 1][ADJ ? RB : 1][4], lb_v[ADJ ? CB : 1][ADJ ? RB : 1][4];
   double ln_v[ADJ ? CB : 1][ADJ ? RB : 1][4];
-  if constexpr (PASS == 2) {
+  constexpr bool LATE_PF = PASS == 2 && !ADJ && std::is_same<T, float>::value;
+  auto epi_prefetch = [&]() {
     const double* lnm = p.lnmarg + (size_t)bz * p.sMarg;
     const double* pot = p.pot + (size_t)bz * plane;
 #pragma unroll
@@ -660,7 +662,8 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           }
         }
     }
-  }
+  };
+  if constexpr (PASS == 2 && !LATE_PF) epi_prefetch();
 
   // marginal-error partials of the preceding update, summed in index order by workgroup 0;
   // the first PEND_REG per thread are read now, the sum is formed in the epilogue
@@ -819,6 +822,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
           for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) Mma<T>::sub(fa[h % PD][rb], fb[h % PD][cb], acc[par][rb][cb], q);
+      }
+      if constexpr (LATE_PF) {
+        if (jb == 0 && h == 1)
+          if (kt0 == 0) epi_prefetch();
       }
       if (first && !(kt == 0 && h == 0)) {
         // flush the previous block (other set) with its exact power-of-two scales
