@@ -417,9 +417,8 @@ struct Ops {
       const int blocks = (int)((total + 255) / 256);
       hipLaunchKernelGGL(k_fill_lambda<T>, dim3(blocks), dim3(256), 0, p->stream, (T*)p->lam, (T*)nullptr, p->n,
                          p->np, 1.0 / eps);
-      if constexpr (!Mma<T>::PAIRED)
-        hipLaunchKernelGGL(k_lam_chunks<T>, dim3((2 * p->np + 255) / 256), dim3(256), 0, p->stream, (T*)p->lam,
-                           p->np);
+      hipLaunchKernelGGL(k_lam_chunks<T>, dim3((2 * p->np + 255) / 256), dim3(256), 0, p->stream, (T*)p->lam,
+                         p->np);
     }
     LAUNCH_CHECK();
     p->lam_eps = eps;
@@ -428,34 +427,31 @@ struct Ops {
   }
 
   // Toeplitz form of Lambda's operand (k_fused<..., TZ = true>, see toeplitz_table_bytes): raw
-  // Lambda (its Toeplitz chunks are formed with it) in the plain element layout, not switched off
-  // by FOT_FLAG_STAGED_LAMBDA, and the kernel's LDS, static and dynamic, within the device's limit.
+  // Lambda (its Toeplitz chunks are formed with it; BF16x3: a table of the hi and one of the lo
+  // halves), not switched off by FOT_FLAG_STAGED_LAMBDA, and the kernel's LDS, static and dynamic,
+  // within the device's limit.
   template <typename C, int PASS, bool ADJ>
   static bool tz_fits(const fot_plan_s* p) {
-    if constexpr (Mma<T>::PAIRED) {
-      (void)p;
-      return false;
-    } else {
-      if (p->d.flags & FOT_FLAG_STAGED_LAMBDA) return false;
-      static const size_t st = [] {
-        hipFuncAttributes fa{};
-        if (hipFuncGetAttributes(&fa, (const void*)k_fused<T, PASS, C, FUSED_NBUF, false, ADJ, true>) != hipSuccess) {
-          (void)hipGetLastError();
-          return (size_t)-1;
-        }
-        return (size_t)fa.sharedSizeBytes;
-      }();
-      return st != (size_t)-1 && st + fused_dyn_lds<PASS, C, false, true>(p->np) <= (size_t)p->lds_limit;
-    }
+    if (p->d.flags & FOT_FLAG_STAGED_LAMBDA) return false;
+    static const size_t st = [] {
+      hipFuncAttributes fa{};
+      if (hipFuncGetAttributes(&fa, (const void*)k_fused<T, PASS, C, FUSED_NBUF, false, ADJ, true>) != hipSuccess) {
+        (void)hipGetLastError();
+        return (size_t)-1;
+      }
+      return (size_t)fa.sharedSizeBytes;
+    }();
+    return st != (size_t)-1 &&
+           st + fused_dyn_lds<PASS, C, false, true, Mma<T>::PAIRED>(p->np) <= (size_t)p->lds_limit;
   }
 
   template <typename C, bool LN>
   static void fused_launch_cfg(fot_plan_s* p, int pass, const FusedArgs& a, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid(p->np / C::BN, p->np / C::BM, p->B);
     const dim3 block(C::THREADS);
-    if constexpr (!LN && !Mma<T>::PAIRED) {
-      const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true>(p->np);
-      const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true>(p->np);
+    if constexpr (!LN) {
+      const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true, Mma<T>::PAIRED>(p->np);
+      const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true, Mma<T>::PAIRED>(p->np);
       // (Lambda from its table: bands of tiles per XCD, one fetch of each operand panel)
       FusedArgs b = a;
       b.xcd_swizzle = pass == 1 ? XCD_ROWS : XCD_COLS;
@@ -736,8 +732,8 @@ struct Ops {
     const dim3 grid(p->np / C::BN, p->np / C::BM, p->B);
     const dim3 block(C::THREADS);
     const uint32_t l1 = (uint32_t)fused_dyn_lds<1, C, false>(p->np), l2 = (uint32_t)fused_dyn_lds<2, C, false>(p->np);
-    const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true>(p->np);
-    const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true>(p->np);
+    const uint32_t t1 = (uint32_t)fused_dyn_lds<1, C, false, true, Mma<T>::PAIRED>(p->np);
+    const uint32_t t2 = (uint32_t)fused_dyn_lds<2, C, false, true, Mma<T>::PAIRED>(p->np);
     FusedArgs b = a;   // (Lambda from its table: bands of tiles per XCD)
     b.xcd_swizzle = pass == 1 ? XCD_ROWS : XCD_COLS;
     if (pass == 1 && tz_fits<C, 1, true>(p))
@@ -1531,7 +1527,8 @@ static fot_status plan_init(fot_plan_s* p, const fot_plan_desc& d, int cN, hipSt
     if (d.precision != FOT_F64) ALLOC(p->kexpL, (size_t)p->np * p->nbA);
     ALLOC(p->flag, (size_t)1);
     // (each Lambda plane is followed by its Toeplitz chunks, see toeplitz_chunks_bytes)
-    const size_t lam_bytes = p->plane * p->esz + toeplitz_chunks_bytes(p->np);
+    const bool paired = d.precision == FOT_BF16X3 || (tail && d.tail_precision == FOT_BF16X3);
+    const size_t lam_bytes = p->plane * p->esz + toeplitz_chunks_bytes(p->np, paired);
     ALLOCV(p->lam, lam_bytes);
     // the two operand buffers as one piece (with x_alias also the read-out's FP64 plane Ty)
     ALLOCV(p->opA, 2 * BP * p->esz);

@@ -434,9 +434,13 @@ constexpr int FUSED_NBUF = 2;   // K stages resident in LDS (one in flight while
 // fragment read 16 consecutive chunks: no bank conflicts).  The full table (2 n_p chunks, entries
 // with |d| >= n_p zero) sits in device memory right after the n_p x n_p Lambda plane it is formed
 // from (k_lam_chunks); a workgroup copies the window of at most n_p + LR chunks its tile uses
-// (LR: its Lambda rows) into LDS, in 1 KB units.
-inline size_t toeplitz_chunks_bytes(int np) { return (size_t)32 * (size_t)np; }
-inline size_t toeplitz_table_bytes(int np, int lam_rows) {
+// (LR: its Lambda rows) into LDS, in 1 KB units.  BF16x3 operands (hi/lo layout) have two tables,
+// of the hi and of the lo halves (8 halves per chunk), the lo one right after the hi one, and a
+// workgroup copies a window of each.
+__host__ __device__ inline size_t toeplitz_chunks_bytes(int np, bool paired = false) {
+  return (size_t)(paired ? 64 : 32) * (size_t)np;
+}
+__host__ __device__ inline size_t toeplitz_table_bytes(int np, int lam_rows) {
   return ((size_t)16 * (size_t)(np + lam_rows) + 1023) / 1024 * 1024;
 }
 
@@ -444,6 +448,27 @@ inline size_t toeplitz_table_bytes(int np, int lam_rows) {
 // function of i - k, padding included), written after the plane; one thread per chunk.
 template <typename T>
 __global__ void k_lam_chunks(T* lam, int np) {
+  if constexpr (Mma<T>::PAIRED) {
+    // hi/lo layout: value k of a row is half 2 (k & ~31) + (k & 31) (hi) and that + 32 (lo)
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= 2 * np) return;
+    const unsigned short* row = (const unsigned short*)lam;
+    unsigned short hv[8], lv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int d = abs(c - (np - 1) + e);
+      const int h = 2 * (d & ~31) + (d & 31);
+      hv[e] = d < np ? row[h] : (unsigned short)0;
+      lv[e] = d < np ? row[h + 32] : (unsigned short)0;
+    }
+    u32x4 wh, wl;
+    __builtin_memcpy(&wh, hv, 16);
+    __builtin_memcpy(&wl, lv, 16);
+    u32x4* t = (u32x4*)((unsigned char*)lam + (size_t)np * np * sizeof(T));
+    t[c] = wh;
+    t[2 * np + c] = wl;
+    return;
+  }
   typedef typename std::conditional<
       sizeof(T) == 2, unsigned short,
       typename std::conditional<sizeof(T) == 4, unsigned, unsigned long long>::type>::type EB;
@@ -467,12 +492,12 @@ __global__ void k_lam_chunks(T* lam, int np) {
 // Toeplitz table of Lambda, 16-byte aligned).
 template <int PASS, typename C>
 constexpr int fused_scaled_rows() { return PASS == 1 ? C::BM : C::BN; }
-template <int PASS, typename C, bool LN = false, bool TZ = false>
+template <int PASS, typename C, bool LN = false, bool TZ = false, bool PAIRED = false>
 inline size_t fused_dyn_lds(int np) {
   const int xb = (PASS == 1 ? C::BN : C::BM) / C::XS;
   const int lam_rows = PASS == 1 ? C::BN : C::BM;
   size_t bytes = (size_t)(np / xb) * (fused_scaled_rows<PASS, C>() + (LN ? lam_rows : 0)) * sizeof(short);
-  if (TZ) bytes = (bytes + 15) / 16 * 16 + toeplitz_table_bytes(np, lam_rows);
+  if (TZ) bytes = (bytes + 15) / 16 * 16 + (PAIRED ? 2 : 1) * toeplitz_table_bytes(np, lam_rows);
   return bytes;
 }
 
@@ -504,7 +529,7 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   constexpr bool NT_OPS = std::is_same<T, float>::value || std::is_same<T, double>::value;
   static_assert(HB >= 1 && XB % EPH == 0, "exponent blocks must hold whole fragment steps");
   static_assert(!PAIRED || (HB % 2 == 0 && HPS % 2 == 0), "hi/lo step pairs within a block and a stage");
-  static_assert(!TZ || (!LN && !PAIRED), "the Toeplitz table holds raw Lambda in the plain element layout");
+  static_assert(!TZ || !LN, "the Toeplitz table holds raw Lambda");
   // rows staged per K stage: both operands, or (TZ) only the operand that is not Lambda
   constexpr int SROWS = TZ ? (PASS == 1 ? BM : BN) : BM + BN;
   // K-stage buffers as distinct objects, so that the compiler can tell a direct load into one
@@ -588,8 +613,10 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   // K range starts at k_lo KPS, so the distances K - (lam0 + lr) start at d_lo = k_lo KPS - lam0 -
   // (LR - 1): the fragment of Lambda row lam0 + lr at K chunk c (K = c EPC ...) is window chunk
   // x = c EPC - k_lo KPS + LR - 1 - lr, the window has nch chunks, and every |d| is below n_p.
-  constexpr int EPC = 16 / (int)sizeof(T);        // operand elements per 16-byte chunk
+  // (BF16x3: a chunk holds 8 hi or 8 lo halves, and the lo window follows the hi one at tzlo)
+  constexpr int EPC = PAIRED ? 8 : 16 / (int)sizeof(T);   // operand elements per 16-byte chunk
   unsigned char* const tzt = (unsigned char*)dtab + ((size_t)nbk * SR * sizeof(short) + 15) / 16 * 16;
+  const int tzlo = PAIRED ? (int)toeplitz_table_bytes(np, LR) : 0;
   if constexpr (TZ) {
     const int lam0 = PASS == 1 ? col0 : row0;
     const int cbase = k_lo * KPS - lam0 - (LR - 1) + (np - 1);   // first chunk of the window (>= 0)
@@ -597,6 +624,9 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     const u32x4* chunks = (const u32x4*)((const unsigned char*)(PASS == 1 ? p.B : p.A) + plane * sizeof(T));
     for (int u = wave; u * 64 < nch; u += C::NW)   // (lanes past the window copy its last chunk again)
       dma16(chunks + min(cbase + u * 64 + lane, 2 * np - 1), tzt + u * 1024);
+    if constexpr (PAIRED)
+      for (int u = wave; u * 64 < nch; u += C::NW)
+        dma16(chunks + 2 * np + min(cbase + u * 64 + lane, 2 * np - 1), tzt + tzlo + u * 1024);
   }
 
   // exponent table of the block-normalised operand for this tile's scaled rows
@@ -729,7 +759,8 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
   const int arow = (wm * C::WTM + r16) * FROWB, brow = ((TZ ? 0 : BM) + wn * C::WTN + r16) * FROWB;
   const int sw = (g ^ r16) << 4;                  // slot of chunk 4h+g in this lane's rows, h = 0
   // TZ: table offset of this lane's Lambda fragments (pass 1: B fragment cb, pass 2: A fragment
-  // rb) at the loop's first step; each step advances K by 4 EPC values, i.e. TZSTEP bytes
+  // rb) at the loop's first step; each step advances K by 4 EPC values, i.e. TZSTEP bytes (BF16x3:
+  // each pair of steps, hi halves from the hi window and then lo halves from the lo window)
   constexpr int NTZ = PASS == 1 ? CB : RB;
   constexpr int TZSTEP = 64 * EPC;
   int tzo[NTZ];
@@ -739,12 +770,16 @@ __global__ __launch_bounds__(C::THREADS) void k_fused(const FusedArgs p) {
     tzo[q] = 16 * (g * EPC + LR - 1 - lr);
   }
   // fragment reads: step s (from the loop's first K) of stage buffer buf at slot offset so
+  auto tz_frag = [&](int off, int s) -> u32x4 {
+    if constexpr (PAIRED) return *(const u32x4*)(tzt + ((s & 1) ? tzlo : 0) + off + (s >> 1) * TZSTEP);
+    return *(const u32x4*)(tzt + off + s * TZSTEP);
+  };
   auto frag_a = [&](const unsigned char* buf, int rb, int so, int s) -> u32x4 {
-    if constexpr (TZ && PASS == 2) return *(const u32x4*)(tzt + tzo[rb] + s * TZSTEP);
+    if constexpr (TZ && PASS == 2) return tz_frag(tzo[rb], s);
     return *(const u32x4*)(&buf[arow + rb * 16 * FROWB + so]);
   };
   auto frag_b = [&](const unsigned char* buf, int cb, int so, int s) -> u32x4 {
-    if constexpr (TZ && PASS == 1) return *(const u32x4*)(tzt + tzo[cb] + s * TZSTEP);
+    if constexpr (TZ && PASS == 1) return tz_frag(tzo[cb], s);
     return *(const u32x4*)(&buf[brow + cb * 16 * FROWB + so]);
   };
   // fragments of PD consecutive steps are live: slot h % PD holds step h of the stage (the

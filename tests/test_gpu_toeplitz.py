@@ -53,6 +53,11 @@ def _same(a, b, what):
     (700, 1, "bf16", 1e-2, 20, True),      # 32 x 32 tiles on a grid that would take 64 x 64
     (1024, 1, "f32", 5e-3, 20, False),
     (1024, 1, "bf16", 5e-3, 20, False),
+    # BF16x3: the hi and the lo halves from two tables
+    (96, 2, "bf16x3", 2e-2, 30, False),
+    (300, 1, "bf16x3", 1e-2, 30, False),
+    (700, 1, "bf16x3", 1e-2, 20, True),
+    (1024, 1, "bf16x3", 5e-3, 20, False),
 ])
 def test_toeplitz_table_is_bit_identical_to_staged_lambda(n, B, prec, eps, T, small):
     g, Gs = _case(n, B, n)
