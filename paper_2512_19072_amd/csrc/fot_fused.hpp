@@ -20,7 +20,8 @@
 // way, Lambda[k][M] = Lambda~[k][M] 2^{KL[k][blk(M)]} (KL <= 0), and each block's partial sum is
 // rescaled by the sum of both operands' exponents (the LN form of the kernels).  Raw Lambda is
 // not staged with the K stages: it depends on i - k only, and its fragments are read from a
-// Toeplitz table (one 16-byte chunk per starting distance) that each workgroup copies into LDS once.
+// Toeplitz table (one 16-byte chunk per starting distance; BF16x3: one table of the hi and one of
+// the lo halves) that each workgroup copies into LDS once.
 //   pass 2  S~ = Lambda . Bt^T, ln S = R'_k ln 2 + ln S~; epilogue updates the potential, the
 //           marginal-error partial, and writes the next pass-1 operand At and its exponents.
 #pragma once
@@ -487,9 +488,9 @@ __global__ void k_lam_chunks(T* lam, int np) {
   ((u32x4*)((unsigned char*)lam + (size_t)np * np * sizeof(T)))[c] = w;
 }
 
-// Launch with dynamic LDS of fused_dyn_lds<PASS, C, LN, TZ>(np) bytes (the exponent-difference
-// table, in the LN form Lambda's exponent table for the tile's Lambda rows, and in the TZ form the
-// Toeplitz table of Lambda, 16-byte aligned).
+// Launch with dynamic LDS of fused_dyn_lds<PASS, C, LN, TZ, PAIRED>(np) bytes (the exponent-
+// difference table, in the LN form Lambda's exponent table for the tile's Lambda rows, and in the TZ
+// form the window of Lambda's Toeplitz table, 16-byte aligned; BF16x3: the hi and the lo window).
 template <int PASS, typename C>
 constexpr int fused_scaled_rows() { return PASS == 1 ? C::BM : C::BN; }
 template <int PASS, typename C, bool LN = false, bool TZ = false, bool PAIRED = false>
